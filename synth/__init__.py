@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module holds no step of the method: it only draws antenna layouts, complex int8
+voltages with injected narrowband tones, and the configuration constants that both the
+oracle and the HIP path receive as plain inputs.  It stands in for the instrument's
+post-PFB voltage dump of the paper's Sec. 2.1 (one 30 s OVRO-LWA epoch), which is not
+available here.
+
+Workload shapes follow the five configurations of the build (tiny plain method,
+instrument scale, uneven sub-bands, precision study, learned classifier):
+
+* antennas: 16 or 352 dual-polarisation antennas, uniform in a disk (Sec. 1 gives the
+  array as 352 antennas with a ~200 m core and baselines up to 2.4 km);
+* voltages: complex int8, Gaussian sigma = 8 per component, clipped to +-127;
+* tones: on-bin narrowband carriers from a point source at (l0, m0), with the
+  geometric phase of a plane wave across the array.
+
+Conventions (also listed as readings in the design notes):
+* input i belongs to antenna a = i // 2, polarisation i % 2 (0 = X, 1 = Y);
+* a voltage stream is [n_inputs][n_spec * n_fft][2] int8, (re, im) interleaved;
+* fine channel c of an n_fft-point channelizer has baseband offset (c - n_fft/2)*f_s/n_fft
+  and sky frequency nu0 + that offset (f_s = 23.9 kHz coarse channel, Sec. 2.1);
+* a tone at baseband bin k0 (signed) multiplies antenna a by exp(+2 pi i nu (x_a l0 + y_a m0)/c),
+  so that visibilities x_i conj(x_j) carry exp(+2 pi i (u l0 + v m0)).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+C_LIGHT = 299_792_458.0      # m/s
+F_COARSE = 23_900.0          # Hz, coarse (F-engine) channel width, "about 23.9 kHz" (Sec. 2.1)
+NU0 = 70.0e6                 # Hz, representative sky frequency of the coarse channel
+SIGMA = 8.0                  # voltage noise per component, LSB
+
+
+@dataclass
+class Tone:
+    k0: int          # signed baseband bin in [-n_fft/2, n_fft/2)
+    amp: float       # amplitude per component, LSB
+    l0: float
+    m0: float
+
+
+@dataclass
+class Config:
+    name: str
+    n_ant: int
+    radius_m: float
+    n_fft: int
+    n_spec: int
+    chan0: int
+    n_chan: int
+    n_pix: int
+    method: str                 # "dft" or "grid"
+    tones: list = field(default_factory=list)
+    sigma: float = SIGMA
+    seed_base: int = 1000
+    gain: float = 0.0           # requantisation gain (float32 value), per input identical
+
+    @property
+    def n_in(self) -> int:
+        return 2 * self.n_ant
+
+
+def antenna_layout(n_ant: int, radius_m: float, seed: int) -> np.ndarray:
+    """Positions uniform in a disk of the given radius, z = 0.  Returns [n_ant, 3] float64 metres."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u1 = rng.random(n_ant)
+    u2 = rng.random(n_ant)
+    r = radius_m * np.sqrt(u1)
+    th = 2.0 * np.pi * u2
+    xyz = np.zeros((n_ant, 3), dtype=np.float64)
+    xyz[:, 0] = r * np.cos(th)
+    xyz[:, 1] = r * np.sin(th)
+    return xyz
+
+
+def channel_freqs(n_fft: int, chan0: int, n_chan: int, nu0: float = NU0,
+                  f_s: float = F_COARSE) -> np.ndarray:
+    """Sky frequency of fine channels chan0 .. chan0+n_chan-1 (float64 Hz)."""
+    c = np.arange(chan0, chan0 + n_chan, dtype=np.float64)
+    return nu0 + (c - n_fft / 2) * (f_s / n_fft)
+
+
+def tone_sky_freq(k0: int, n_fft: int, nu0: float = NU0, f_s: float = F_COARSE) -> float:
+    return nu0 + k0 * (f_s / n_fft)
+
+
+def hann_power_gain(n_fft: int) -> float:
+    """Sum of squares of the periodic Hann window, 3N/8 (a config constant for gains)."""
+    return 3.0 * n_fft / 8.0
+
+
+def gain_loud_tone(n_fft: int, amp: float, sigma: float) -> np.float32:
+    """Gain that maps a tone of amplitude `amp` plus 5 sigma of noise to 127 LSB."""
+    return np.float32(127.0 / (amp * n_fft / 2 + 5.0 * sigma * math.sqrt(hann_power_gain(n_fft))))
+
+
+def gain_noise(n_fft: int, sigma: float, target: float = 8.0) -> np.float32:
+    """Gain that maps the per-component channel noise to `target` LSB rms."""
+    return np.float32(target / (sigma * math.sqrt(hann_power_gain(n_fft))))
+
+
+def approx_n_baselines_in_grid(ant_xyz: np.ndarray, nu: float, n_pix: int) -> int:
+    """Rough count of baselines inside the gridding uv box, used only to size tone amplitudes."""
+    u_max = (2 * n_pix / 2 - 4 - 1) * 0.25
+    a, b = np.tril_indices(ant_xyz.shape[0], -1)
+    u = (ant_xyz[a, 0] - ant_xyz[b, 0]) * nu / C_LIGHT
+    v = (ant_xyz[a, 1] - ant_xyz[b, 1]) * nu / C_LIGHT
+    return int(np.count_nonzero((np.abs(u) <= u_max) & (np.abs(v) <= u_max)))
+
+
+def tone_amp_for_snr(snr: float, n_fft: int, n_spec: int, n_b: int, sigma: float) -> float:
+    """Amplitude whose expected width-1 image SNR is `snr`: SNR = 2 sqrt(T N_b) A^2 N / (3 sigma^2)."""
+    return math.sqrt(snr * 3.0 * sigma ** 2 / (2.0 * n_fft * math.sqrt(n_spec * n_b)))
+
+
+def random_tones(n_tones: int, n_fft: int, chan0: int, n_chan: int, snr_lo: float, snr_hi: float,
+                 ant_xyz: np.ndarray, n_spec: int, n_pix: int, seed: int, sigma: float = SIGMA,
+                 edge: int = 17) -> list:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tones = []
+    used = set()
+    while len(tones) < n_tones:
+        c = int(rng.integers(chan0 + edge, chan0 + n_chan - edge))
+        if any(abs(c - u) < 3 for u in used):
+            continue
+        while True:
+            l0, m0 = rng.uniform(-0.9, 0.9, size=2)
+            if l0 * l0 + m0 * m0 < 0.81:
+                break
+        snr = float(rng.uniform(snr_lo, snr_hi))
+        k0 = c - n_fft // 2
+        nb = approx_n_baselines_in_grid(ant_xyz, tone_sky_freq(k0, n_fft), n_pix)
+        tones.append(Tone(k0=k0, amp=tone_amp_for_snr(snr, n_fft, n_spec, nb, sigma),
+                          l0=float(l0), m0=float(m0)))
+        used.add(c)
+    return tones
+
+
+def make_config(k: int) -> Config:
+    """Configurations 1, 2 and 4 (the uneven-sub-band set is built by `subband_configs`)."""
+    if k == 1:
+        n_fft = 4096
+        c_tone = n_fft // 2 + 256
+        cfg = Config("tiny: 16 ant x 2 pol, 4096-pt, T=16, 64 ch, DFT 64^2", 16, 100.0, n_fft, 16,
+                     c_tone - 32, 64, 64, "dft", seed_base=1000)
+        cfg.tones = [Tone(k0=256, amp=4.0, l0=0.2, m0=-0.1)]
+        cfg.gain = gain_loud_tone(n_fft, 4.0, SIGMA)
+        return cfg
+    if k == 2:
+        n_fft = 65536
+        cfg = Config("instrument: 352 ant x 2 pol, 65536-pt, T=32, 4096 ch, GRID 256^2", 352, 750.0,
+                     n_fft, 32, n_fft // 2 - 2048, 4096, 256, "grid", seed_base=2000)
+        xyz = antenna_layout(cfg.n_ant, cfg.radius_m, cfg.seed_base + 1)
+        cfg.tones = random_tones(8, n_fft, cfg.chan0, cfg.n_chan, 3.0, 20.0, xyz, cfg.n_spec,
+                                 cfg.n_pix, cfg.seed_base + 3)
+        cfg.gain = gain_noise(n_fft, SIGMA)
+        return cfg
+    if k == 4:
+        n_fft = 1 << 18
+        cfg = Config("precision: 352 ant x 2 pol, 2^18-pt, T=8, 16384 ch, GRID 512^2", 352, 750.0,
+                     n_fft, 8, n_fft // 2 - 8192, 16384, 512, "grid", seed_base=4000)
+        xyz = antenna_layout(cfg.n_ant, cfg.radius_m, cfg.seed_base + 1)
+        cfg.tones = random_tones(8, n_fft, cfg.chan0, cfg.n_chan, 3.0, 20.0, xyz, cfg.n_spec,
+                                 cfg.n_pix, cfg.seed_base + 3)
+        cfg.gain = gain_noise(n_fft, SIGMA)
+        return cfg
+    raise ValueError(f"no configuration {k}")
+
+
+SUBBAND_NT = [(1 << 14, 128), (1 << 15, 64), (1 << 16, 32), (1 << 17, 16), (1 << 18, 8)]
+SUBBAND_NPIX = [128, 256, 512]
+
+
+def subband_configs(n_sub: int = 12, n_chan: int = 1024, n_ant: int = 352):
+    """Uneven sub-bands: (N, T) and image size cycle; every sub-band holds 2^21 samples per input."""
+    out = []
+    for s in range(n_sub):
+        n_fft, n_spec = SUBBAND_NT[s % len(SUBBAND_NT)]
+        out.append(dict(n_fft=n_fft, n_spec=n_spec, chan0=n_fft // 2 - n_chan // 2, n_chan=n_chan,
+                        n_pix=SUBBAND_NPIX[s % len(SUBBAND_NPIX)],
+                        nu0=NU0 + (s - 6) * F_COARSE, gain=gain_noise(n_fft, SIGMA)))
+    return out
+
+
+def _tone_phasors(tones, ant_xyz, n_fft, nu0):
+    """Per antenna complex gain of each tone (geometric phase), float64 [n_tones, n_ant]."""
+    ph = []
+    for t in tones:
+        nu = tone_sky_freq(t.k0, n_fft, nu0)
+        turns = nu * (ant_xyz[:, 0] * t.l0 + ant_xyz[:, 1] * t.m0) / C_LIGHT
+        ph.append(np.exp(2j * np.pi * turns))
+    return np.array(ph) if ph else np.zeros((0, ant_xyz.shape[0]), np.complex128)
+
+
+def voltages(n_ant: int, n_fft: int, n_spec: int, tones, ant_xyz: np.ndarray, seed: int,
+             sigma: float = SIGMA, device: str = "cpu", nu0: float = NU0, noise: bool = True,
+             block_inputs: int = 32):
+    """Complex int8 voltages [2*n_ant, n_spec*n_fft, 2] as a torch tensor on `device`.
+
+    noise + tones are summed in float64, rounded half-to-even once and clipped to +-127.
+    The noise comes from torch's generator for `device` seeded with `seed` (Philox on GPU,
+    Mersenne Twister on CPU), drawn block by block over inputs.
+    """
+    import torch
+    n_in = 2 * n_ant
+    n_samp = n_spec * n_fft
+    out = torch.empty((n_in, n_samp, 2), dtype=torch.int8, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    ph = _tone_phasors(tones, ant_xyz, n_fft, nu0)
+    n = torch.arange(n_fft, device=device, dtype=torch.float64)
+    carriers = []
+    for t in tones:
+        arg = (2.0 * math.pi / n_fft) * ((t.k0 % n_fft) * n % n_fft)
+        carriers.append((t.amp * torch.cos(arg), t.amp * torch.sin(arg)))
+    for i0 in range(0, n_in, block_inputs):
+        i1 = min(n_in, i0 + block_inputs)
+        if noise:
+            x = torch.randn((i1 - i0, n_samp, 2), generator=gen, device=device, dtype=torch.float64)
+            x.mul_(sigma)
+        else:
+            x = torch.zeros((i1 - i0, n_samp, 2), device=device, dtype=torch.float64)
+        if tones:
+            xv = x.view(i1 - i0, n_spec, n_fft, 2)
+            ants = np.arange(i0, i1) // 2
+            for ti, (cr, ci) in enumerate(carriers):
+                g = ph[ti, ants]
+                gr = torch.tensor(g.real, device=device, dtype=torch.float64)[:, None, None]
+                gi = torch.tensor(g.imag, device=device, dtype=torch.float64)[:, None, None]
+                xv[..., 0] += cr[None, None, :] * gr - ci[None, None, :] * gi
+                xv[..., 1] += cr[None, None, :] * gi + ci[None, None, :] * gr
+        torch.round(x, out=x)
+        x.clamp_(-127.0, 127.0)
+        out[i0:i1] = x.to(torch.int8)
+        del x
+    return out
+
+
+def config_inputs(cfg: Config, device: str = "cpu", noise: bool = True):
+    """Antenna positions, voltages, channel sky frequencies and per-input gains for a config."""
+    xyz = antenna_layout(cfg.n_ant, cfg.radius_m, cfg.seed_base + 1)
+    volt = voltages(cfg.n_ant, cfg.n_fft, cfg.n_spec, cfg.tones, xyz, cfg.seed_base + 2,
+                    cfg.sigma, device=device, noise=noise)
+    freq = channel_freqs(cfg.n_fft, cfg.chan0, cfg.n_chan)
+    gain = np.full(cfg.n_in, cfg.gain, dtype=np.float32)
+    return xyz, volt, freq, gain
+
+
+def random_spectra(n_chan: int, n_in: int, n_spec: int, seed: int, sigma_q: float = 8.0,
+                   device: str = "cpu", full_range: bool = False):
+    """Random int8 correlator inputs [n_chan][n_in][2][n_spec] (Gaussian sigma_q, clipped +-127;
+    or uniform over [-128, 127] when full_range)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    if full_range:
+        return torch.randint(-128, 128, (n_chan, n_in, 2, n_spec), generator=gen,
+                             device=device, dtype=torch.int16).to(torch.int8)
+    x = torch.randn((n_chan, n_in, 2, n_spec), generator=gen, device=device) * sigma_q
+    return torch.round(x).clamp_(-127, 127).to(torch.int8)

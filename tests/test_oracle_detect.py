@@ -1,0 +1,96 @@
+"""Pins of the oracle detector (Sec. 2.4, Stage I with the width-1 matched filter)."""
+import numpy as np
+import pytest
+
+from oracle import detect as D
+
+
+def _cube_with_spectrum(spec, n_pix=8, x=4, y=4, base=None):
+    C = len(spec)
+    rng = np.random.default_rng(0)
+    cube = rng.standard_normal((C, n_pix, n_pix)) if base is None else base.copy()
+    cube[:, y, x] = spec
+    return cube
+
+
+def test_median_even_count_is_mean_of_central_pair():
+    a = np.array([[4.0, 1.0, 3.0, 2.0], [1.0, 1.0, 5.0, 9.0]])
+    np.testing.assert_allclose(D.median_even_mean(a, axis=1), [2.5, 3.0])
+    np.testing.assert_allclose(D.median_even_mean(np.array([[3.0, 1.0, 2.0]]), axis=1), [2.0])
+
+
+def test_mad_constant_normalises_gaussian_noise():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(2_000_000)
+    mad = D.median_even_mean(np.abs(x - D.median_even_mean(x[None], 1)[0])[None], 1)[0]
+    assert abs(D.MAD_K * mad - 1.0) < 0.003
+    # 1/Phi^-1(3/4)
+    from scipy.stats import norm
+    assert abs(D.MAD_K - 1.0 / norm.ppf(0.75)) < 1e-14
+
+
+def test_hand_computed_spike_snr():
+    # sorted spectrum [-1,-1,-1,1,1,1,1,11]: median = (1 + 1)/2 = 1;
+    # |x - 1| sorted [0,0,0,0,2,2,2,10]: MAD = (0 + 2)/2 = 1; spike SNR = (11 - 1)/k
+    spec = np.array([1, -1, 1, -1, 1, -1, 1, 11], float)
+    rec, snr, valid = D.detect(_cube_with_spectrum(spec), tau=5.0)
+    mine = rec[(rec["x"] == 4) & (rec["y"] == 4)]
+    assert len(mine) == 1 and mine["c"][0] == 7
+    assert abs(mine["snr"][0] - 10 / D.MAD_K) < 1e-12
+    np.testing.assert_allclose(snr[:, 4, 4], (spec - 1) / D.MAD_K)
+
+
+def test_nms_plateau_keeps_lower_channel_and_chain_keeps_top():
+    spec = np.zeros(16)
+    spec[::2] = 1
+    spec[1::2] = -1
+    spec[5] = spec[6] = 20           # plateau -> channel 5
+    spec[10], spec[11], spec[12] = 12, 15, 18   # rising chain -> channel 12
+    rec, snr, _ = D.detect(_cube_with_spectrum(spec), tau=5.0)
+    mine = rec[(rec["x"] == 4) & (rec["y"] == 4)]
+    assert list(mine["c"]) == [5, 12]
+
+
+def test_horizon_mask_integer_rule():
+    m = D.horizon_mask(8)
+    assert m[4, 4] and m[4, 1] and not m[4, 0] and not m[0, 0] and not m[0, 4]
+    assert m.sum() == sum(1 for y in range(8) for x in range(8) if (x - 4) ** 2 + (y - 4) ** 2 < 16)
+
+
+def test_zero_mad_pixel_gives_nothing():
+    spec = np.zeros(10)
+    spec[3] = 100.0
+    rec, _, valid = D.detect(_cube_with_spectrum(spec), tau=5.0)
+    assert not valid[4, 4]
+    assert len(rec[(rec["x"] == 4) & (rec["y"] == 4)]) == 0
+
+
+def test_gaussian_noise_false_positive_rate():
+    # P(z >= 5) = 2.87e-7; over ~0.8M searchable voxels we expect ~0.2 false positives.
+    rng = np.random.default_rng(7)
+    cube = rng.standard_normal((4096, 16, 16))
+    rec, snr, valid = D.detect(cube, tau=5.0)
+    assert len(rec) <= 4
+    s = snr[:, valid]
+    assert abs(s.std() - 1.0) < 0.01
+
+
+def test_per_image_mode_recovers_weak_spike():
+    rng = np.random.default_rng(3)
+    cube = rng.standard_normal((256, 16, 16))
+    cube[100, 6, 9] += 8.0
+    for mode in ("per_pixel", "per_image"):
+        rec, snr, _ = D.detect(cube, tau=5.0, mode=mode)
+        hit = rec[(rec["x"] == 9) & (rec["y"] == 6) & (rec["c"] == 100)]
+        assert len(hit) == 1 and 6.5 < hit["snr"][0] < 9.5
+
+
+def test_records_sorted_by_y_x_c():
+    rng = np.random.default_rng(4)
+    cube = rng.standard_normal((64, 16, 16))
+    for (c, y, x) in [(10, 9, 3), (5, 3, 9), (40, 3, 9), (7, 3, 4)]:
+        cube[c, y, x] += 30
+    rec, _, _ = D.detect(cube, tau=5.0)
+    keys = list(zip(rec["y"], rec["x"], rec["c"]))
+    assert keys == sorted(keys)
+    assert {(3, 4, 7), (3, 9, 5), (3, 9, 40), (9, 3, 10)} <= set(keys)
