@@ -1,0 +1,187 @@
+/*
+ * nbsi.h - C ABI of the MI355X (gfx950) narrowband spectral-imaging library.
+ *
+ * The calls follow the paper's statement of the problem (arXiv 2606.04304, Sec. 2.1-2.4):
+ * upchannelise coarse-channel voltages, cross-correlate every baseline per fine channel,
+ * image every fine channel over the visible hemisphere, and search the spectral cube for
+ * narrowband outliers.
+ *
+ * Conventions shared by every call
+ *  - Array arguments are DEVICE pointers unless the name ends in _host.  The caller owns all
+ *    buffers; the library never frees or keeps them beyond the work it enqueues.
+ *  - Every call first validates its arguments on the host.  On a bad argument it returns a
+ *    negative status and enqueues nothing.  Otherwise it enqueues its kernels asynchronously
+ *    on the context's stream and returns NBSI_OK (nbsi_detect alone blocks, to return the
+ *    candidate count).
+ *  - Device pointers must be 16-byte aligned.  No C++ exception crosses this interface.
+ *  - A context is not thread-safe; use one context per host thread / stream.  Scratch memory
+ *    is owned by the context, grown on demand and released by nbsi_destroy.
+ *  - Complex numbers are stored as (re, im) pairs.  Input i belongs to antenna i / 2 and
+ *    polarisation i % 2 (0 = X, 1 = Y).
+ */
+#ifndef NBSI_H
+#define NBSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NBSI_OK 0
+#define NBSI_EINVAL (-1)       /* bad shape, null or misaligned pointer, bad enum */
+#define NBSI_EOVERFLOW (-2)    /* a result could not fit its type (e.g. n_spec > 65535) */
+#define NBSI_ENOMEM (-3)       /* scratch allocation failed */
+#define NBSI_EHIP (-4)         /* a HIP runtime call failed (detail in nbsi_last_error) */
+#define NBSI_ETRUNC (-5)       /* output buffer too short; *n_out holds the true count */
+#define NBSI_EUNSUPPORTED (-6) /* valid request this build does not implement */
+
+#define NBSI_MAX_SPEC 65535    /* int32 visibilities are exact up to this many spectra */
+
+/* imaging methods */
+#define NBSI_IMAGE_DFT 0       /* direct Fourier sum over every imaged baseline */
+#define NBSI_IMAGE_GRID 1      /* ES-kernel gridding on a 2x oversampled grid + 2D FFT */
+
+/* visibility input types of nbsi_image */
+#define NBSI_VIS_I32 0
+#define NBSI_VIS_F32 1
+
+/* gridding arithmetic of nbsi_image (accumulation is FP32 in every mode) */
+#define NBSI_PREC_FP32 0
+#define NBSI_PREC_FP16 1
+#define NBSI_PREC_BF16 2
+
+/* detector noise models */
+#define NBSI_DETECT_PER_PIXEL 0
+#define NBSI_DETECT_PER_IMAGE 1
+
+typedef struct nbsi_ctx nbsi_ctx;
+typedef struct nbsi_image_plan nbsi_image_plan;
+
+/* One candidate (Sec. 2.4: sky position, detection frequency, effective width, SNR). */
+typedef struct {
+    int32_t x;      /* pixel column (l) */
+    int32_t y;      /* pixel row (m) */
+    int32_t c;      /* channel index within the cube */
+    int32_t width;  /* matched-filter width in channels */
+    float snr;
+} nbsi_cand;
+
+int nbsi_version(void);
+const char *nbsi_strerror(int status);
+
+/* Create a context on HIP device `device` that enqueues on `stream` (a hipStream_t; NULL =
+ * the default stream).  Returns NBSI_EHIP if the device cannot be used. */
+int nbsi_create(nbsi_ctx **ctx, int device, void *stream);
+int nbsi_destroy(nbsi_ctx *ctx);
+int nbsi_set_stream(nbsi_ctx *ctx, void *stream);
+/* Human-readable detail of the last failure on this context ("" if none). */
+const char *nbsi_last_error(const nbsi_ctx *ctx);
+/* Wait for all work enqueued by this context. */
+int nbsi_synchronize(nbsi_ctx *ctx);
+
+/*
+ * Host-only argument checks, also run first by each call below.  They need no GPU.
+ * nbsi_check_channelize: n_fft a power of two in [2^8, 2^18]; 1 <= n_spec <= NBSI_MAX_SPEC;
+ *   n_chan >= 1, 0 <= chan0, chan0 + n_chan <= n_fft, n_chan <= 16384 (the kept band must fit
+ *   one on-chip sub-transform); n_in >= 1.
+ * nbsi_check_correlate: n_in >= 1, n_chan >= 1, 1 <= n_spec <= NBSI_MAX_SPEC.
+ * nbsi_check_image: n_ant >= 2, n_chan >= 1, n_pix even in [8, 1024], method and precision
+ *   valid, 0 <= uv_min <= uv_max.
+ * nbsi_check_detect: n_chan >= 3, n_pix even in [8, 1024], mode valid, max_out >= 0.
+ */
+int nbsi_check_channelize(int n_in, int n_fft, int n_spec, int chan0, int n_chan);
+int nbsi_check_correlate(int n_chan, int n_in, int n_spec);
+int nbsi_check_image(int n_chan, int n_ant, int n_pix, int method, int precision,
+                     double uv_min, double uv_max);
+int nbsi_check_detect(int n_chan, int n_pix, int mode, int max_out);
+
+/*
+ * Upchannelisation and requantisation (Sec. 2.1: an FFT over the time samples of each
+ * coarse channel raises the spectral resolution; the selected fine channels form a batch).
+ *   volt   [n_in][n_spec * n_fft][2] int8: complex voltages, time-contiguous per input.
+ *   gain   [n_in] float32: per-input requantisation gain g_i.
+ * For input i and spectrum s (samples s*n_fft .. s*n_fft + n_fft - 1):
+ *   X[k] = sum_n w[n] x[n] exp(-2 pi i k n / n_fft), w[n] = 1/2 - 1/2 cos(2 pi n / n_fft)
+ *   (periodic Hann), no 1/N scaling.  Fine channel c holds bin k = (c + n_fft/2) mod n_fft
+ *   (fftshift), and channels chan0 .. chan0 + n_chan - 1 are kept.
+ * Outputs (either may be NULL, not both), correlator layout [n_chan][n_in][2][n_spec]
+ * (for each channel and input: n_spec real parts, then n_spec imaginary parts):
+ *   spec_f float32: g_i * X, computed in float32;
+ *   spec_q int8:    clamp(round-half-even(g_i * X), -127, 127), the float32 value of spec_f.
+ */
+int nbsi_channelize(nbsi_ctx *ctx, const int8_t *volt, int n_in, int n_fft, int n_spec,
+                    int chan0, int n_chan, const float *gain, int8_t *spec_q, float *spec_f);
+
+/*
+ * Full cross-correlation (Sec. 2.1, the X-engine): for every channel and every pair i >= j,
+ *   V_ij = sum_{s < n_spec} q_i,s conj(q_j,s)
+ * on int8 matrix cores with int32 accumulation, exact for n_spec <= NBSI_MAX_SPEC (any int8,
+ * including -128).
+ *   spec_q [n_chan][n_in][2][n_spec] int8 (nbsi_channelize layout).
+ *   vis    [n_chan][n_in (n_in + 1) / 2][2] int32, packed lower triangle t(i, j) = i(i+1)/2 + j.
+ */
+int nbsi_correlate(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, int n_spec,
+                   int32_t *vis);
+
+/* The same product from float32 spectra (the plain FP32 path): vis in float32, same layout. */
+int nbsi_correlate_f32(nbsi_ctx *ctx, const float *spec_f, int n_chan, int n_in, int n_spec,
+                       float *vis);
+
+/*
+ * Imaging geometry (Sec. 2.2: all-sky images of every fine channel over the visible
+ * hemisphere).  A plan fixes the antennas, the channel frequencies, the image size and the
+ * method; it is built on the host, uploaded once, and reused by nbsi_image.
+ *   ant_xyz_host [n_ant][3] float64 metres (z is ignored: coplanar array).
+ *   freq_hz_host [n_chan] float64 sky frequency of each channel.
+ * Baseline a > b has (u, v) = ((x_a - x_b) * nu / c, (y_a - y_b) * nu / c) wavelengths.
+ * Imaged set B per channel: pairs with uv_min <= |uv| <= uv_max, and for NBSI_IMAGE_GRID also
+ * |u|, |v| <= (2 n_pix / 2 - 4 - 1) / 4 (every tap of the width-8 kernel stays on the 2x grid).
+ */
+int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
+                           const double *freq_hz_host, int n_chan, int n_pix, int method,
+                           double uv_min, double uv_max, nbsi_image_plan **plan);
+int nbsi_image_plan_destroy(nbsi_image_plan *plan);
+/* Copy |B| per channel into n_b_host[n_chan] (blocks until the plan is built). */
+int nbsi_image_plan_nbase(nbsi_image_plan *plan, int64_t *n_b_host);
+
+/*
+ * Dirty image of every channel (Stokes I, natural weighting):
+ *   I(l, m) = (1/|B|) sum_{b in B} Re[V_I,b exp(-2 pi i (u_b l + v_b m))],
+ *   V_I = (V_XX + V_YY) / 2 of antennas a > b (autos and cross-hands unused),
+ *   l = (x - n_pix/2) * 2/n_pix, m = (y - n_pix/2) * 2/n_pix.
+ *   vis  [n_chan][n_in (n_in+1)/2][2] int32 (NBSI_VIS_I32) or float32 (NBSI_VIS_F32),
+ *        n_in = 2 n_ant.
+ *   img  [n_chan][n_pix][n_pix] float32, row y <-> m, column x <-> l.
+ * NBSI_IMAGE_DFT evaluates the sum directly (float64 phases).  NBSI_IMAGE_GRID grids with the
+ * exponential-of-semicircle kernel (width 8, beta = 2.30 * 8) onto a 2 n_pix square grid,
+ * transforms it with a 2D FFT and divides by the kernel's Fourier transform; `precision`
+ * selects the gridding arithmetic (FP32, FP16 or BF16 products, FP32 accumulation) and
+ * applies to NBSI_IMAGE_GRID only.  uv coordinates are float64 on the GPU.
+ */
+int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int vis_dtype,
+               int precision, float *img);
+
+/*
+ * Narrowband search of a cube (Sec. 2.4, Stage I with the width-1 matched filter):
+ *   NBSI_DETECT_PER_PIXEL: SNR_p[c] = (I_p[c] - med_c I_p) / (k MAD_c I_p)
+ *   NBSI_DETECT_PER_IMAGE: z = (I - med) / (k MAD) over each channel image, then
+ *                          SNR_p[c] = z_p[c] - med_c z_p
+ *   with k = 1.482602218505602, the median of an even count the mean of the central pair,
+ *   over pixels with (x - n/2)^2 + (y - n/2)^2 < (n/2)^2 (the visible hemisphere).
+ * A voxel is a candidate when SNR >= thresh and it has the highest SNR within +-1 channel
+ * (non-maximum suppression, ties keep the lower channel).  Pixels with MAD = 0 are skipped.
+ *   img     [n_chan][n_pix][n_pix] float32.
+ *   snr     optional [n_chan][n_pix][n_pix] float32 SNR cube (0 outside the searched pixels).
+ *   out     [max_out] candidates sorted by (y, x, c); n_out (HOST) receives the true count.
+ * Returns NBSI_ETRUNC when the count exceeds max_out (the first max_out are written).
+ * Blocks until the count is known.
+ */
+int nbsi_detect(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode, float thresh,
+                float *snr, nbsi_cand *out, int max_out, int *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBSI_H */

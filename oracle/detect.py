@@ -46,6 +46,16 @@ def median_even_mean(a: np.ndarray, axis: int) -> np.ndarray:
     return 0.5 * (lo + hi)
 
 
+def per_pixel_snr(flat: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """SNR of spectra flat [C][P] under the per-pixel noise model, and the pixels with MAD > 0."""
+    med = median_even_mean(flat, axis=0)                  # per pixel
+    mad = median_even_mean(np.abs(flat - med[None, :]), axis=0)
+    good = mad > 0
+    snr = np.zeros_like(flat)
+    snr[:, good] = (flat[:, good] - med[None, good]) / (MAD_K * mad[None, good])
+    return snr, good
+
+
 def snr_cube(cube: np.ndarray, mode: str = "per_pixel") -> tuple[np.ndarray, np.ndarray]:
     """SNR for every voxel of cube [C][N][N] (float64) and the boolean searchable-pixel mask."""
     cube = np.asarray(cube, dtype=np.float64)
@@ -53,11 +63,7 @@ def snr_cube(cube: np.ndarray, mode: str = "per_pixel") -> tuple[np.ndarray, np.
     mask = horizon_mask(n_pix)
     flat = cube.reshape(n_chan, -1)[:, mask.ravel()]          # [C][P_in]
     if mode == "per_pixel":
-        med = median_even_mean(flat, axis=0)                  # per pixel
-        mad = median_even_mean(np.abs(flat - med[None, :]), axis=0)
-        good = mad > 0
-        snr = np.zeros_like(flat)
-        snr[:, good] = (flat[:, good] - med[None, good]) / (MAD_K * mad[None, good])
+        snr, good = per_pixel_snr(flat)
     elif mode == "per_image":
         med_c = median_even_mean(flat, axis=1)                # per channel image
         mad_c = median_even_mean(np.abs(flat - med_c[:, None]), axis=1)

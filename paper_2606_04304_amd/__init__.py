@@ -1,0 +1,278 @@
+"""Python binding of libnbsi (include/nbsi.h): argument marshalling only.
+
+Every function has the name of the C entry point it wraps and enqueues that entry point on
+torch's current HIP stream.  Tensors must be on the context's device, contiguous and of the
+documented dtype; outputs are allocated with torch when not supplied.  All computation runs
+in the HIP kernels of libnbsi.so; if the library is missing this module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnbsi.so")
+
+NBSI_OK = 0
+NBSI_EINVAL = -1
+NBSI_EOVERFLOW = -2
+NBSI_ENOMEM = -3
+NBSI_EHIP = -4
+NBSI_ETRUNC = -5
+NBSI_EUNSUPPORTED = -6
+NBSI_MAX_SPEC = 65535
+NBSI_IMAGE_DFT = 0
+NBSI_IMAGE_GRID = 1
+NBSI_VIS_I32 = 0
+NBSI_VIS_F32 = 1
+NBSI_PREC_FP32 = 0
+NBSI_PREC_FP16 = 1
+NBSI_PREC_BF16 = 2
+NBSI_DETECT_PER_PIXEL = 0
+NBSI_DETECT_PER_IMAGE = 1
+
+EXPORTS = [
+    "nbsi_version", "nbsi_strerror", "nbsi_create", "nbsi_destroy", "nbsi_set_stream",
+    "nbsi_last_error", "nbsi_synchronize", "nbsi_check_channelize", "nbsi_check_correlate",
+    "nbsi_check_image", "nbsi_check_detect", "nbsi_channelize", "nbsi_correlate",
+    "nbsi_correlate_f32", "nbsi_image_plan_create", "nbsi_image_plan_destroy",
+    "nbsi_image_plan_nbase", "nbsi_image", "nbsi_detect",
+]
+
+CAND_DTYPE = np.dtype([("x", np.int32), ("y", np.int32), ("c", np.int32), ("width", np.int32),
+                       ("snr", np.float32)])
+
+
+class NbsiError(RuntimeError):
+    def __init__(self, status: int, detail: str = ""):
+        self.status = status
+        msg = lib().nbsi_strerror(status).decode()
+        super().__init__(f"{msg} ({status}){': ' + detail if detail else ''}")
+
+
+_lib = None
+
+
+def lib():
+    """Load libnbsi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.nbsi_version.restype = I
+        L.nbsi_strerror.argtypes = [I]
+        L.nbsi_strerror.restype = ctypes.c_char_p
+        L.nbsi_create.argtypes = [ctypes.POINTER(P), I, P]
+        L.nbsi_destroy.argtypes = [P]
+        L.nbsi_set_stream.argtypes = [P, P]
+        L.nbsi_last_error.argtypes = [P]
+        L.nbsi_last_error.restype = ctypes.c_char_p
+        L.nbsi_synchronize.argtypes = [P]
+        L.nbsi_check_channelize.argtypes = [I, I, I, I, I]
+        L.nbsi_check_correlate.argtypes = [I, I, I]
+        L.nbsi_check_image.argtypes = [I, I, I, I, I, D, D]
+        L.nbsi_check_detect.argtypes = [I, I, I, I]
+        L.nbsi_channelize.argtypes = [P, P, I, I, I, I, I, P, P, P]
+        L.nbsi_correlate.argtypes = [P, P, I, I, I, P]
+        L.nbsi_correlate_f32.argtypes = [P, P, I, I, I, P]
+        L.nbsi_image_plan_create.argtypes = [P, P, I, P, I, I, I, D, D, ctypes.POINTER(P)]
+        L.nbsi_image_plan_destroy.argtypes = [P]
+        L.nbsi_image_plan_nbase.argtypes = [P, P]
+        L.nbsi_image.argtypes = [P, P, P, I, I, P]
+        L.nbsi_detect.argtypes = [P, P, I, I, I, ctypes.c_float, P, P, I, P]
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(status: int, ctx=None):
+    if status != NBSI_OK:
+        detail = lib().nbsi_last_error(ctx._h).decode() if ctx is not None and ctx._h else ""
+        raise NbsiError(status, detail)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, dtype, name, device):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name}: expected a contiguous {dtype} tensor")
+    if t.device != device:
+        raise ValueError(f"{name}: tensor on {t.device}, context on {device}")
+
+
+class Context:
+    """nbsi_create / nbsi_destroy around one HIP device; calls enqueue on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        _check(lib().nbsi_create(ctypes.byref(h), int(device), None))
+        self._h = h
+
+    def _sync_stream(self):
+        torch = _torch()
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        lib().nbsi_set_stream(self._h, ctypes.c_void_p(s))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nbsi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = {}
+
+
+def nbsi_create(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def nbsi_channelize(volt, n_fft: int, n_spec: int, chan0: int, n_chan: int, gain,
+                    want_q: bool = True, want_f: bool = False, spec_q=None, spec_f=None,
+                    ctx: Context | None = None):
+    """volt [n_in][n_spec*n_fft][2] int8, gain [n_in] float32 -> (spec_q, spec_f), each
+    [n_chan][n_in][2][n_spec] (int8 / float32) or None."""
+    torch = _torch()
+    ctx = ctx or nbsi_create(volt.device.index or 0)
+    _need(volt, torch.int8, "volt", ctx.device)
+    _need(gain, torch.float32, "gain", ctx.device)
+    n_in = volt.shape[0]
+    if want_q and spec_q is None:
+        spec_q = torch.empty((n_chan, n_in, 2, n_spec), dtype=torch.int8, device=ctx.device)
+    if want_f and spec_f is None:
+        spec_f = torch.empty((n_chan, n_in, 2, n_spec), dtype=torch.float32, device=ctx.device)
+    ctx._sync_stream()
+    _check(lib().nbsi_channelize(ctx._h, _ptr(volt), n_in, n_fft, n_spec, chan0, n_chan, _ptr(gain),
+                                 _ptr(spec_q) if want_q else None, _ptr(spec_f) if want_f else None),
+           ctx)
+    return (spec_q if want_q else None), (spec_f if want_f else None)
+
+
+def nbsi_correlate(spec_q, vis=None, ctx: Context | None = None):
+    """spec_q [n_chan][n_in][2][n_spec] int8 -> vis [n_chan][n_in(n_in+1)/2][2] int32."""
+    torch = _torch()
+    ctx = ctx or nbsi_create(spec_q.device.index or 0)
+    _need(spec_q, torch.int8, "spec_q", ctx.device)
+    n_chan, n_in, two, n_spec = spec_q.shape
+    if vis is None:
+        vis = torch.empty((n_chan, n_in * (n_in + 1) // 2, 2), dtype=torch.int32, device=ctx.device)
+    ctx._sync_stream()
+    _check(lib().nbsi_correlate(ctx._h, _ptr(spec_q), n_chan, n_in, n_spec, _ptr(vis)), ctx)
+    return vis
+
+
+def nbsi_correlate_f32(spec_f, vis=None, ctx: Context | None = None):
+    torch = _torch()
+    ctx = ctx or nbsi_create(spec_f.device.index or 0)
+    _need(spec_f, torch.float32, "spec_f", ctx.device)
+    n_chan, n_in, two, n_spec = spec_f.shape
+    if vis is None:
+        vis = torch.empty((n_chan, n_in * (n_in + 1) // 2, 2), dtype=torch.float32, device=ctx.device)
+    ctx._sync_stream()
+    _check(lib().nbsi_correlate_f32(ctx._h, _ptr(spec_f), n_chan, n_in, n_spec, _ptr(vis)), ctx)
+    return vis
+
+
+class ImagePlan:
+    """nbsi_image_plan_create / destroy."""
+
+    def __init__(self, ant_xyz, freq_hz, n_pix: int, method: int = NBSI_IMAGE_GRID,
+                 uv_min: float = 0.0, uv_max: float = float("inf"), ctx: Context | None = None):
+        self.ctx = ctx or nbsi_create(0)
+        self.ant_xyz = np.ascontiguousarray(ant_xyz, dtype=np.float64)
+        self.freq = np.ascontiguousarray(freq_hz, dtype=np.float64)
+        self.n_ant = self.ant_xyz.shape[0]
+        self.n_chan = self.freq.size
+        self.n_pix = int(n_pix)
+        self.method = int(method)
+        h = ctypes.c_void_p()
+        self.ctx._sync_stream()
+        _check(lib().nbsi_image_plan_create(
+            self.ctx._h, self.ant_xyz.ctypes.data_as(ctypes.c_void_p), self.n_ant,
+            self.freq.ctypes.data_as(ctypes.c_void_p), self.n_chan, self.n_pix, self.method,
+            float(uv_min), float(uv_max), ctypes.byref(h)), self.ctx)
+        self._h = h
+
+    def n_baselines(self) -> np.ndarray:
+        out = np.empty(self.n_chan, dtype=np.int64)
+        _check(lib().nbsi_image_plan_nbase(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nbsi_image_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nbsi_image_plan_create(ant_xyz, freq_hz, n_pix, method=NBSI_IMAGE_GRID, uv_min=0.0,
+                           uv_max=float("inf"), ctx=None) -> ImagePlan:
+    return ImagePlan(ant_xyz, freq_hz, n_pix, method, uv_min, uv_max, ctx)
+
+
+def nbsi_image(plan: ImagePlan, vis, precision: int = NBSI_PREC_FP32, img=None):
+    """vis int32 or float32 [n_chan][nprod][2] -> img [n_chan][n_pix][n_pix] float32."""
+    torch = _torch()
+    ctx = plan.ctx
+    if vis.dtype == torch.int32:
+        vt = NBSI_VIS_I32
+    elif vis.dtype == torch.float32:
+        vt = NBSI_VIS_F32
+    else:
+        raise TypeError("vis must be int32 or float32")
+    _need(vis, vis.dtype, "vis", ctx.device)
+    n_in = 2 * plan.n_ant
+    if tuple(vis.shape) != (plan.n_chan, n_in * (n_in + 1) // 2, 2):
+        raise ValueError(f"vis shape {tuple(vis.shape)} does not match the plan")
+    if img is None:
+        img = torch.empty((plan.n_chan, plan.n_pix, plan.n_pix), dtype=torch.float32, device=ctx.device)
+    ctx._sync_stream()
+    _check(lib().nbsi_image(ctx._h, plan._h, _ptr(vis), vt, int(precision), _ptr(img)), ctx)
+    return img
+
+
+def nbsi_detect(img, mode: int = NBSI_DETECT_PER_PIXEL, thresh: float = 5.0, want_snr: bool = False,
+                max_out: int = 1 << 20, ctx: Context | None = None):
+    """img [n_chan][n_pix][n_pix] float32 -> (candidates as a numpy structured array sorted by
+    (y, x, c), snr cube or None).  Blocks until the candidate count is known."""
+    torch = _torch()
+    ctx = ctx or nbsi_create(img.device.index or 0)
+    _need(img, torch.float32, "img", ctx.device)
+    n_chan, n_pix, _ = img.shape
+    snr = torch.empty_like(img) if want_snr else None
+    out = torch.empty((max(1, max_out), 5), dtype=torch.int32, device=ctx.device)
+    n_out = ctypes.c_int(0)
+    ctx._sync_stream()
+    st = lib().nbsi_detect(ctx._h, _ptr(img), n_chan, n_pix, int(mode), float(thresh), _ptr(snr),
+                           _ptr(out), int(max_out), ctypes.byref(n_out))
+    if st not in (NBSI_OK, NBSI_ETRUNC):
+        _check(st, ctx)
+    n = min(n_out.value, max_out)
+    rec = out[:n].cpu().numpy().view(CAND_DTYPE).reshape(-1)
+    return rec, snr, n_out.value

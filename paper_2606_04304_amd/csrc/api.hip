@@ -1,0 +1,442 @@
+// Host side of the C ABI: validation, context and scratch management, imaging plans.
+#include "internal.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+int channelize_log_m(int log_n, int n_chan);
+int detect_ppw(int n_chan);
+
+namespace {
+
+constexpr double C_LIGHT = 299792458.0;
+constexpr int GRID_CELLS = 256 * 32;  // LDS cells of one gridding workgroup (see image.hip)
+constexpr size_t IMAGE_SCRATCH_CAP = (size_t)2 << 30;
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+bool is_pow2(long n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(long n) {
+    int l = 0;
+    while ((1L << l) < n) l++;
+    return l;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; i++) {
+        double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= n; k++) {
+                const double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            dp = n * (z * p0 - p1) / (z * z - 1.0);
+            const double dz = p0 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
+int nbsi_fail(nbsi_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->last_error = msg;
+    return code;
+}
+
+int nbsi_scratch(nbsi_ctx *ctx, int slot, size_t bytes, void **ptr) {
+    if (bytes == 0) bytes = 256;
+    if (ctx->scratch_size[slot] < bytes) {
+        if (ctx->scratch[slot]) {
+            // the old buffer may still be read by queued work of this stream
+            if (hipStreamSynchronize(ctx->stream) != hipSuccess) return nbsi_fail(ctx, NBSI_EHIP, "stream sync failed");
+            (void)hipFree(ctx->scratch[slot]);
+            ctx->scratch[slot] = nullptr;
+            ctx->scratch_size[slot] = 0;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess || !p)
+            return nbsi_fail(ctx, NBSI_ENOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
+        ctx->scratch[slot] = p;
+        ctx->scratch_size[slot] = bytes;
+    }
+    *ptr = ctx->scratch[slot];
+    return NBSI_OK;
+}
+
+extern "C" {
+
+int nbsi_version(void) { return 1; }
+
+const char *nbsi_strerror(int status) {
+    switch (status) {
+        case NBSI_OK: return "ok";
+        case NBSI_EINVAL: return "invalid argument";
+        case NBSI_EOVERFLOW: return "result would overflow its type";
+        case NBSI_ENOMEM: return "out of device memory";
+        case NBSI_EHIP: return "HIP runtime error";
+        case NBSI_ETRUNC: return "output truncated";
+        case NBSI_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+int nbsi_check_channelize(int n_in, int n_fft, int n_spec, int chan0, int n_chan) {
+    if (n_in < 1 || n_chan < 1) return NBSI_EINVAL;
+    if (!is_pow2(n_fft) || n_fft < 256 || n_fft > (1 << 18)) return NBSI_EINVAL;
+    if (n_spec < 1) return NBSI_EINVAL;
+    if (n_spec > NBSI_MAX_SPEC) return NBSI_EOVERFLOW;
+    if (chan0 < 0 || chan0 + (long)n_chan > n_fft || n_chan > 16384) return NBSI_EINVAL;
+    if ((long)n_in * n_spec > 0x7fffffffL) return NBSI_EINVAL;
+    return NBSI_OK;
+}
+
+int nbsi_check_correlate(int n_chan, int n_in, int n_spec) {
+    if (n_chan < 1 || n_in < 1 || n_spec < 1) return NBSI_EINVAL;
+    if (n_spec > NBSI_MAX_SPEC) return NBSI_EOVERFLOW;
+    if (n_in > 8192) return NBSI_EINVAL;
+    return NBSI_OK;
+}
+
+int nbsi_check_image(int n_chan, int n_ant, int n_pix, int method, int precision, double uv_min,
+                     double uv_max) {
+    if (n_chan < 1 || n_ant < 2 || n_ant > 4096) return NBSI_EINVAL;
+    if (n_pix < 8 || n_pix > 1024 || (n_pix & 7)) return NBSI_EINVAL;
+    if (method != NBSI_IMAGE_DFT && method != NBSI_IMAGE_GRID) return NBSI_EINVAL;
+    if (method == NBSI_IMAGE_GRID && (!is_pow2(n_pix) || n_pix < 64)) return NBSI_EINVAL;
+    if (precision != NBSI_PREC_FP32 && precision != NBSI_PREC_FP16 && precision != NBSI_PREC_BF16)
+        return NBSI_EINVAL;
+    if (!(uv_min >= 0.0) || !(uv_max >= uv_min)) return NBSI_EINVAL;
+    return NBSI_OK;
+}
+
+int nbsi_check_detect(int n_chan, int n_pix, int mode, int max_out) {
+    if (n_chan < 3 || n_chan > 32768) return NBSI_EINVAL;
+    if (n_pix < 8 || n_pix > 1024 || (n_pix & 7)) return NBSI_EINVAL;
+    if (mode != NBSI_DETECT_PER_PIXEL && mode != NBSI_DETECT_PER_IMAGE) return NBSI_EINVAL;
+    if (max_out < 0) return NBSI_EINVAL;
+    return NBSI_OK;
+}
+
+int nbsi_create(nbsi_ctx **out, int device, void *stream) {
+    if (!out) return NBSI_EINVAL;
+    *out = nullptr;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) return NBSI_EHIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return NBSI_EHIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return NBSI_EUNSUPPORTED;
+    nbsi_ctx *ctx = new (std::nothrow) nbsi_ctx();
+    if (!ctx) return NBSI_ENOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)stream;
+    DeviceGuard g(device);
+    if (!g.ok || hipMalloc(&ctx->d_counter, 256) != hipSuccess) {
+        delete ctx;
+        return NBSI_EHIP;
+    }
+    *out = ctx;
+    return NBSI_OK;
+}
+
+int nbsi_destroy(nbsi_ctx *ctx) {
+    if (!ctx) return NBSI_EINVAL;
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int s = 0; s < 8; s++)
+        if (ctx->scratch[s]) (void)hipFree(ctx->scratch[s]);
+    if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+    delete ctx;
+    return NBSI_OK;
+}
+
+int nbsi_set_stream(nbsi_ctx *ctx, void *stream) {
+    if (!ctx) return NBSI_EINVAL;
+    ctx->stream = (hipStream_t)stream;
+    return NBSI_OK;
+}
+
+const char *nbsi_last_error(const nbsi_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int nbsi_synchronize(nbsi_ctx *ctx) {
+    if (!ctx) return NBSI_EINVAL;
+    DeviceGuard g(ctx->device);
+    NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return NBSI_OK;
+}
+
+int nbsi_channelize(nbsi_ctx *ctx, const int8_t *volt, int n_in, int n_fft, int n_spec, int chan0,
+                    int n_chan, const float *gain, int8_t *spec_q, float *spec_f) {
+    if (!ctx) return NBSI_EINVAL;
+    int rc = nbsi_check_channelize(n_in, n_fft, n_spec, chan0, n_chan);
+    if (rc) return nbsi_fail(ctx, rc, "nbsi_channelize: bad shape");
+    if (!volt || !gain || (!spec_q && !spec_f)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_channelize: null pointer");
+    if (!aligned16(volt) || !aligned16(gain) || (spec_q && !aligned16(spec_q)) || (spec_f && !aligned16(spec_f)))
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_channelize: pointers must be 16-byte aligned");
+    DeviceGuard g(ctx->device);
+    const int log_n = ilog2(n_fft);
+    const int klo = (chan0 + n_fft / 2) & (n_fft - 1);
+    const size_t cells = (size_t)n_in * n_spec * n_chan;
+    void *sq = nullptr, *sf = nullptr;
+    if (spec_q && (rc = nbsi_scratch(ctx, SLOT_CHAN_STAGE_Q, cells * 2, &sq))) return rc;
+    if (spec_f && (rc = nbsi_scratch(ctx, SLOT_CHAN_STAGE_F, cells * 8, &sf))) return rc;
+    NBSI_TRY_HIP(ctx, launch_channelize(volt, n_in, log_n, n_spec, klo, n_chan, gain, (int8_t *)sq, (float *)sf,
+                                        ctx->stream));
+    if (spec_q) NBSI_TRY_HIP(ctx, launch_corner_turn_q((int8_t *)sq, n_in, n_spec, n_chan, spec_q, ctx->stream));
+    if (spec_f) NBSI_TRY_HIP(ctx, launch_corner_turn_f((float *)sf, n_in, n_spec, n_chan, spec_f, ctx->stream));
+    return NBSI_OK;
+}
+
+int nbsi_correlate(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, int n_spec, int32_t *vis) {
+    if (!ctx) return NBSI_EINVAL;
+    int rc = nbsi_check_correlate(n_chan, n_in, n_spec);
+    if (rc) return nbsi_fail(ctx, rc, "nbsi_correlate: bad shape");
+    if (!spec_q || !vis) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate: null pointer");
+    if (!aligned16(spec_q) || !aligned16(vis)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate: misaligned pointer");
+    DeviceGuard g(ctx->device);
+    NBSI_TRY_HIP(ctx, launch_correlate_i8(spec_q, n_chan, n_in, n_spec, vis, ctx->stream));
+    return NBSI_OK;
+}
+
+int nbsi_correlate_f32(nbsi_ctx *ctx, const float *spec_f, int n_chan, int n_in, int n_spec, float *vis) {
+    if (!ctx) return NBSI_EINVAL;
+    int rc = nbsi_check_correlate(n_chan, n_in, n_spec);
+    if (rc == NBSI_EOVERFLOW) rc = NBSI_OK;  // float accumulation has no int32 bound
+    if (rc) return nbsi_fail(ctx, rc, "nbsi_correlate_f32: bad shape");
+    if (!spec_f || !vis) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_f32: null pointer");
+    if (!aligned16(spec_f) || !aligned16(vis))
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_f32: misaligned pointer");
+    DeviceGuard g(ctx->device);
+    NBSI_TRY_HIP(ctx, launch_correlate_f32(spec_f, n_chan, n_in, n_spec, vis, ctx->stream));
+    return NBSI_OK;
+}
+
+int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const double *freq_hz_host,
+                           int n_chan, int n_pix, int method, double uv_min, double uv_max,
+                           nbsi_image_plan **out) {
+    if (!ctx || !out) return NBSI_EINVAL;
+    *out = nullptr;
+    int rc = nbsi_check_image(n_chan, n_ant, n_pix, method, NBSI_PREC_FP32, uv_min, uv_max);
+    if (rc) return nbsi_fail(ctx, rc, "nbsi_image_plan_create: bad shape or parameters");
+    if (!ant_xyz_host || !freq_hz_host) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_plan_create: null pointer");
+    double nu_min = freq_hz_host[0], nu_max = freq_hz_host[0];
+    for (int c = 0; c < n_chan; c++) {
+        if (!(freq_hz_host[c] > 0.0) || !isfinite(freq_hz_host[c]))
+            return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_plan_create: frequencies must be positive");
+        nu_min = std::min(nu_min, freq_hz_host[c]);
+        nu_max = std::max(nu_max, freq_hz_host[c]);
+    }
+    DeviceGuard g(ctx->device);
+    nbsi_image_plan *p = new (std::nothrow) nbsi_image_plan();
+    if (!p) return NBSI_ENOMEM;
+    p->device = ctx->device;
+    p->n_ant = n_ant;
+    p->n_chan = n_chan;
+    p->n_pix = n_pix;
+    p->method = method;
+    p->uv_min = uv_min;
+    p->uv_max = uv_max;
+
+    // Candidate pairs: every pair that can be in B for some channel frequency (1e-9 slack; the
+    // kernels apply the exact per-channel test).
+    const double slack = 1e-9;
+    const double U = (double)(n_pix - 5) * 0.25;
+    const int M = 2 * n_pix;
+    std::vector<int2> pairs;
+    std::vector<int> lo_row, hi_row;
+    for (int a = 0; a < n_ant; a++)
+        for (int b = 0; b < a; b++) {
+            const double dx = ant_xyz_host[3 * a] - ant_xyz_host[3 * b];
+            const double dy = ant_xyz_host[3 * a + 1] - ant_xyz_host[3 * b + 1];
+            const double r = sqrt(dx * dx + dy * dy);
+            if (r * nu_max / C_LIGHT < uv_min * (1 - slack) - 1e-12) continue;
+            if (r * nu_min / C_LIGHT > uv_max * (1 + slack) + 1e-12) continue;
+            if (method == NBSI_IMAGE_GRID) {
+                if (fabs(dx) * nu_min / C_LIGHT > U * (1 + slack)) continue;
+                if (fabs(dy) * nu_min / C_LIGHT > U * (1 + slack)) continue;
+                const double v1 = dy * nu_min / C_LIGHT * 4.0 + M / 2, v2 = dy * nu_max / C_LIGHT * 4.0 + M / 2;
+                lo_row.push_back(std::max(0, (int)floor(std::min(v1, v2)) - 4));
+                hi_row.push_back(std::min(M - 1, (int)floor(std::max(v1, v2)) + 5));
+            }
+            pairs.push_back(make_int2(a, b));
+        }
+    p->n_pairs = (int)pairs.size();
+
+    std::vector<int> band_off, band_items;
+    std::vector<float> corr;
+    if (method == NBSI_IMAGE_GRID) {
+        p->band_rows = GRID_CELLS / M;
+        p->n_bands = M / p->band_rows;
+        std::vector<std::vector<int>> bins(p->n_bands);
+        for (int k = 0; k < p->n_pairs; k++)
+            for (int bnd = lo_row[k] / p->band_rows; bnd <= hi_row[k] / p->band_rows; bnd++) bins[bnd].push_back(k);
+        band_off.push_back(0);
+        for (int bnd = 0; bnd < p->n_bands; bnd++) {
+            band_items.insert(band_items.end(), bins[bnd].begin(), bins[bnd].end());
+            band_off.push_back((int)band_items.size());
+        }
+        p->n_band_items = (int)band_items.size();
+        // 1 / Fourier transform of the ES kernel at image column x, frequency (x - n/2)/M cycles
+        // per cell: Phi(f) = 4 int_{-1}^{1} phi(z) cos(8 pi z f) dz.
+        std::vector<double> gx, gw;
+        gauss_legendre(200, gx, gw);
+        const double beta = 2.30 * 8.0;
+        corr.resize(n_pix);
+        for (int x = 0; x < n_pix; x++) {
+            const double f = (double)(x - n_pix / 2) / (double)M;
+            double s = 0.0;
+            for (size_t q = 0; q < gx.size(); q++) {
+                const double z = gx[q];
+                s += gw[q] * exp(beta * (sqrt(1.0 - z * z) - 1.0)) * cos(8.0 * M_PI * z * f);
+            }
+            corr[x] = (float)(1.0 / (4.0 * s));
+        }
+    }
+
+    auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
+        if (bytes == 0) bytes = 16;
+        if (hipMalloc(dst, bytes) != hipSuccess) return false;
+        return src ? hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess : true;
+    };
+    bool ok = up((void **)&p->d_xyz, ant_xyz_host, sizeof(double) * 3 * n_ant) &&
+              up((void **)&p->d_freq, freq_hz_host, sizeof(double) * n_chan) &&
+              up((void **)&p->d_nb, nullptr, sizeof(int) * n_chan) &&
+              up((void **)&p->d_pairs, pairs.data(), sizeof(int2) * pairs.size());
+    if (ok && method == NBSI_IMAGE_GRID)
+        ok = up((void **)&p->d_band_off, band_off.data(), sizeof(int) * band_off.size()) &&
+             up((void **)&p->d_band_items, band_items.data(), sizeof(int) * band_items.size()) &&
+             up((void **)&p->d_corr, corr.data(), sizeof(float) * corr.size());
+    if (!ok) {
+        nbsi_image_plan_destroy(p);
+        return nbsi_fail(ctx, NBSI_ENOMEM, "nbsi_image_plan_create: device allocation failed");
+    }
+    hipError_t e = launch_image_count(p, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        nbsi_image_plan_destroy(p);
+        return nbsi_fail(ctx, NBSI_EHIP, std::string("nbsi_image_plan_create: ") + hipGetErrorString(e));
+    }
+    *out = p;
+    return NBSI_OK;
+}
+
+int nbsi_image_plan_destroy(nbsi_image_plan *p) {
+    if (!p) return NBSI_EINVAL;
+    DeviceGuard g(p->device);
+    void *bufs[] = {p->d_xyz, p->d_freq, p->d_nb, p->d_pairs, p->d_band_off, p->d_band_items, p->d_corr};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+    return NBSI_OK;
+}
+
+int nbsi_image_plan_nbase(nbsi_image_plan *p, int64_t *n_b_host) {
+    if (!p || !n_b_host) return NBSI_EINVAL;
+    DeviceGuard g(p->device);
+    std::vector<int> nb(p->n_chan);
+    if (hipMemcpy(nb.data(), p->d_nb, sizeof(int) * p->n_chan, hipMemcpyDeviceToHost) != hipSuccess) return NBSI_EHIP;
+    for (int c = 0; c < p->n_chan; c++) n_b_host[c] = nb[c];
+    return NBSI_OK;
+}
+
+int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int vis_dtype, int precision,
+               float *img) {
+    if (!ctx) return NBSI_EINVAL;
+    if (!plan || !vis || !img) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image: null pointer");
+    if (plan->device != ctx->device) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image: plan built on another device");
+    if (vis_dtype != NBSI_VIS_I32 && vis_dtype != NBSI_VIS_F32) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image: bad vis_dtype");
+    if (precision != NBSI_PREC_FP32 && precision != NBSI_PREC_FP16 && precision != NBSI_PREC_BF16)
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image: bad precision");
+    if (!aligned16(vis) || !aligned16(img)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image: misaligned pointer");
+    DeviceGuard g(ctx->device);
+    if (plan->method == NBSI_IMAGE_DFT) {
+        NBSI_TRY_HIP(ctx, launch_image_dft(plan, vis, vis_dtype, img, ctx->stream));
+        return NBSI_OK;
+    }
+    // gridding: channel chunks bound the intermediate to IMAGE_SCRATCH_CAP bytes
+    const size_t per_chan = (size_t)plan->n_pix * 2 * plan->n_pix * sizeof(float2);
+    int chunk = (int)std::max<size_t>(1, std::min<size_t>(plan->n_chan, IMAGE_SCRATCH_CAP / per_chan));
+    void *inter = nullptr;
+    int rc = nbsi_scratch(ctx, SLOT_IMG_INTER, per_chan * chunk, &inter);
+    if (rc) return rc;
+    const size_t nprod = (size_t)(2 * plan->n_ant) * (2 * plan->n_ant + 1) / 2;
+    const size_t vis_chan_bytes = nprod * 8;  // int2 or float2
+    for (int c0 = 0; c0 < plan->n_chan; c0 += chunk) {
+        nbsi_image_plan sub = *plan;
+        sub.n_chan = std::min(chunk, plan->n_chan - c0);
+        sub.d_freq = plan->d_freq + c0;
+        sub.d_nb = plan->d_nb + c0;
+        NBSI_TRY_HIP(ctx, launch_image_grid(&sub, (const char *)vis + vis_chan_bytes * c0, vis_dtype, precision,
+                                            (float2 *)inter, img + (size_t)c0 * plan->n_pix * plan->n_pix,
+                                            ctx->stream));
+    }
+    return NBSI_OK;
+}
+
+int nbsi_detect(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode, float thresh, float *snr,
+                nbsi_cand *out, int max_out, int *n_out) {
+    if (!ctx) return NBSI_EINVAL;
+    int rc = nbsi_check_detect(n_chan, n_pix, mode, max_out);
+    if (rc) return nbsi_fail(ctx, rc, "nbsi_detect: bad shape");
+    if (!img || !n_out || (max_out > 0 && !out)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_detect: null pointer");
+    if (!aligned16(img) || (snr && !aligned16(snr)) || (out && !aligned16(out)))
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_detect: misaligned pointer");
+    DeviceGuard g(ctx->device);
+    void *stats = nullptr;
+    if ((rc = nbsi_scratch(ctx, SLOT_DET_STATS, sizeof(float2) * n_chan, &stats))) return rc;
+    NBSI_TRY_HIP(ctx, launch_detect_stats(img, n_chan, n_pix, mode, (float *)stats, ctx->stream));
+    int cap = (int)std::max<size_t>(65536, ctx->scratch_size[SLOT_DET_CAND] / sizeof(nbsi_cand));
+    int count = 0;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        void *cand = nullptr;
+        if ((rc = nbsi_scratch(ctx, SLOT_DET_CAND, sizeof(nbsi_cand) * (size_t)cap, &cand))) return rc;
+        NBSI_TRY_HIP(ctx, hipMemsetAsync(ctx->d_counter, 0, sizeof(int), ctx->stream));
+        NBSI_TRY_HIP(ctx, launch_detect_scan(img, n_chan, n_pix, mode, (const float *)stats, thresh, snr,
+                                             (nbsi_cand *)cand, cap, ctx->d_counter, ctx->stream));
+        NBSI_TRY_HIP(ctx, hipMemcpyAsync(&count, ctx->d_counter, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (count <= cap) break;
+        if (count > (1 << 24)) return nbsi_fail(ctx, NBSI_EOVERFLOW, "nbsi_detect: more than 2^24 candidates");
+        cap = count;
+    }
+    *n_out = count;
+    const int n_write = std::min(count, max_out);
+    if (count > 0 && n_write > 0) {
+        int n_pow2 = 1;
+        while (n_pow2 < count) n_pow2 <<= 1;
+        void *keys = nullptr;
+        if ((rc = nbsi_scratch(ctx, SLOT_DET_KEYS, sizeof(unsigned long long) * n_pow2, &keys))) return rc;
+        NBSI_TRY_HIP(ctx, launch_detect_sort((nbsi_cand *)ctx->scratch[SLOT_DET_CAND], count,
+                                             (unsigned long long *)keys, n_chan, n_pix, out, n_write, ctx->stream));
+        NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return count > max_out ? NBSI_ETRUNC : NBSI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,268 @@
+// Full cross-correlation (the paper's Sec. 2.1 X-engine) on gfx950 matrix cores.
+//
+// For one channel, stack the spectra as a real int8 matrix Y with 2 n_in rows (row 2i = Re q_i,
+// row 2i+1 = Im q_i) and n_spec columns, and form the Gram matrix G = Y Y^T with
+// v_mfma_i32_32x32x32_i8 (int32 accumulation, exact).  Every 2x2 block of G is one visibility:
+//     Re V_ij = G[2i, 2j] + G[2i+1, 2j+1],   Im V_ij = G[2i+1, 2j] - G[2i, 2j+1]
+// so no int8 value is ever negated (-128 is safe) and all four products of a block are useful.
+// Only lower-triangle blocks of G are computed.
+//
+// Tiling: a workgroup (4 waves) owns a 128 x 128 block of G (64 x 64 visibilities) and loops
+// over K = n_spec in 64-byte LDS stages; each wave owns 64 x 64 of G (2 x 2 MFMA tiles).
+// The epilogue swaps accumulators with the neighbouring lane (DPP) to assemble complex
+// visibilities and writes packed-triangle rows of 16 consecutive baselines (128 B) per lane
+// group.  Block index -> (channel, tile pair) keeps every tile pair of a channel on one XCD so
+// partial cache lines at tile edges merge in that XCD's L2.
+#include "internal.h"
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr int TILE = 128;        // G rows / cols per workgroup tile
+constexpr int KC = 64;           // K bytes per LDS stage
+constexpr int LDS_STRIDE = KC + 16;  // padded row stride (bytes) against bank conflicts
+
+__device__ __forceinline__ void tile_pair(int pair, int &I, int &J) {
+    int a = (int)((sqrtf(8.f * (float)pair + 1.f) - 1.f) * 0.5f);
+    while ((a + 1) * (a + 2) / 2 <= pair) a++;
+    while (a * (a + 1) / 2 > pair) a--;
+    I = a;
+    J = pair - a * (a + 1) / 2;
+}
+
+// Stage rows [r0, r0 + TILE) x bytes [k0, k0 + KC) of Y (row stride T bytes) into LDS, zero-padded.
+__device__ __forceinline__ void stage_rows(int8_t *s, const int8_t *__restrict__ Y, int rows, int T,
+                                           int r0, int k0, int t) {
+    for (int e = t; e < TILE * (KC / 16); e += 256) {
+        const int rl = e / (KC / 16), vq = e % (KC / 16);
+        const int r = r0 + rl, k = k0 + vq * 16;
+        v4i val = {0, 0, 0, 0};
+        if (r < rows) {
+            const int8_t *src = Y + (size_t)r * T + k;
+            if ((T & 15) == 0) {
+                if (k < T) val = *reinterpret_cast<const v4i *>(src);
+            } else {
+                int8_t tmp[16];
+#pragma unroll
+                for (int b = 0; b < 16; b++) tmp[b] = (k + b < T) ? src[b] : (int8_t)0;
+                val = *reinterpret_cast<v4i *>(tmp);
+            }
+        }
+        *reinterpret_cast<v4i *>(s + rl * LDS_STRIDE + vq * 16) = val;
+    }
+}
+
+__device__ __forceinline__ int swap_lanes(int x) {
+    // quad_perm [1, 0, 3, 2]: exchange with the neighbouring lane
+    return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);
+}
+
+// Combine a 32 x 32 tile of G (rows R0.., cols C0.., both even) into visibilities and store.
+__device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, int lane, int n_in,
+                                               int2 *__restrict__ vc) {
+    int par[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) par[r] = swap_lanes(a[r]);
+    const int p = lane & 1, h = lane >> 5, cl = lane & 31;
+    const int b = (C0 >> 1) + (cl >> 1);
+#pragma unroll
+    for (int qq = 0; qq < 4; qq++) {
+        const int ia = (R0 >> 1) + 4 * qq + 2 * h + p;
+        int re, im;
+        if (p == 0) {  // column 2b: own rows 2a, 2a+1 at regs 4qq, 4qq+1
+            re = a[4 * qq] + par[4 * qq + 1];
+            im = a[4 * qq + 1] - par[4 * qq];
+        } else {       // column 2b+1: rows 2a, 2a+1 at regs 4qq+2, 4qq+3
+            re = par[4 * qq + 2] + a[4 * qq + 3];
+            im = par[4 * qq + 3] - a[4 * qq + 2];
+        }
+        if (ia < n_in && b <= ia) {
+            vc[(size_t)ia * (ia + 1) / 2 + b] = make_int2(re, im);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void correlate_i8_kernel(const int8_t *__restrict__ q, int n_chan,
+                                                           int n_in, int T, int n_pairs,
+                                                           int32_t *__restrict__ vis) {
+    __shared__ __attribute__((aligned(16))) int8_t sA[TILE * LDS_STRIDE];
+    __shared__ __attribute__((aligned(16))) int8_t sB[TILE * LDS_STRIDE];
+    const int id = blockIdx.x;
+    const int xcd = id & 7, rest = id >> 3;
+    const int pair = rest % n_pairs;
+    const int c = (rest / n_pairs) * 8 + xcd;
+    if (c >= n_chan) return;
+    int I, J;
+    tile_pair(pair, I, J);
+    const int rows = 2 * n_in;
+    const int8_t *Y = q + (size_t)c * rows * T;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int wr = wave >> 1, wc = wave & 1;
+    const bool diag = (I == J);
+    const bool active = !(diag && wr < wc);
+
+    v16i acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+        for (int ni = 0; ni < 2; ni++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[mi][ni][r] = 0;
+
+    const int8_t *sBr = diag ? sA : sB;
+    for (int k0 = 0; k0 < T; k0 += KC) {
+        __syncthreads();
+        stage_rows(sA, Y, rows, T, I * TILE, k0, t);
+        if (!diag) stage_rows(sB, Y, rows, T, J * TILE, k0, t);
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 32) {
+                const int koff = kk + (lane >> 5) * 16;
+                v4i a[2], b[2];
+#pragma unroll
+                for (int mi = 0; mi < 2; mi++)
+                    a[mi] = *reinterpret_cast<const v4i *>(sA + (wr * 64 + mi * 32 + (lane & 31)) * LDS_STRIDE + koff);
+#pragma unroll
+                for (int ni = 0; ni < 2; ni++)
+                    b[ni] = *reinterpret_cast<const v4i *>(sBr + (wc * 64 + ni * 32 + (lane & 31)) * LDS_STRIDE + koff);
+#pragma unroll
+                for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ni++)
+                        acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+            }
+        }
+    }
+    if (!active) return;
+    const size_t nprod = (size_t)n_in * (n_in + 1) / 2;
+    int2 *vc = reinterpret_cast<int2 *>(vis) + (size_t)c * nprod;
+#pragma unroll
+    for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+        for (int ni = 0; ni < 2; ni++) {
+            const int R0 = I * TILE + wr * 64 + mi * 32;
+            const int C0 = J * TILE + wc * 64 + ni * 32;
+            if (R0 < rows && C0 <= R0 + 31) store_tile_i32(acc[mi][ni], R0, C0, lane, n_in, vc);
+        }
+}
+
+// ---- plain FP32 path: the same Gram formulation on v_mfma_f32_32x32x2_f32 ----
+typedef float v16f __attribute__((ext_vector_type(16)));
+constexpr int KCF = 16;  // K floats per LDS stage
+constexpr int LDS_STRIDE_F = KCF + 1;
+
+__device__ __forceinline__ float swap_lanes_f(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, true));
+}
+
+__global__ __launch_bounds__(256) void correlate_f32_kernel(const float *__restrict__ q, int n_chan,
+                                                            int n_in, int T, int n_pairs,
+                                                            float *__restrict__ vis) {
+    __shared__ float sA[TILE * LDS_STRIDE_F];
+    __shared__ float sB[TILE * LDS_STRIDE_F];
+    const int id = blockIdx.x;
+    const int xcd = id & 7, rest = id >> 3;
+    const int pair = rest % n_pairs;
+    const int c = (rest / n_pairs) * 8 + xcd;
+    if (c >= n_chan) return;
+    int I, J;
+    tile_pair(pair, I, J);
+    const int rows = 2 * n_in;
+    const float *Y = q + (size_t)c * rows * T;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int wr = wave >> 1, wc = wave & 1;
+    const bool diag = (I == J);
+    const bool active = !(diag && wr < wc);
+    v16f acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+        for (int ni = 0; ni < 2; ni++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[mi][ni][r] = 0.f;
+    const float *sBr = diag ? sA : sB;
+    for (int k0 = 0; k0 < T; k0 += KCF) {
+        __syncthreads();
+        for (int e = t; e < TILE * KCF; e += 256) {
+            const int rl = e / KCF, kk = e % KCF;
+            const int r = I * TILE + rl, k = k0 + kk;
+            sA[rl * LDS_STRIDE_F + kk] = (r < rows && k < T) ? Y[(size_t)r * T + k] : 0.f;
+            if (!diag) {
+                const int r2 = J * TILE + rl;
+                sB[rl * LDS_STRIDE_F + kk] = (r2 < rows && k < T) ? Y[(size_t)r2 * T + k] : 0.f;
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int kk = 0; kk < KCF; kk += 2) {
+                const int koff = kk + (lane >> 5);
+                float a[2], b[2];
+#pragma unroll
+                for (int mi = 0; mi < 2; mi++) a[mi] = sA[(wr * 64 + mi * 32 + (lane & 31)) * LDS_STRIDE_F + koff];
+#pragma unroll
+                for (int ni = 0; ni < 2; ni++) b[ni] = sBr[(wc * 64 + ni * 32 + (lane & 31)) * LDS_STRIDE_F + koff];
+#pragma unroll
+                for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+                    for (int ni = 0; ni < 2; ni++)
+                        acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+            }
+        }
+    }
+    if (!active) return;
+    const size_t nprod = (size_t)n_in * (n_in + 1) / 2;
+    float2 *vc = reinterpret_cast<float2 *>(vis) + (size_t)c * nprod;
+    const int p = lane & 1, h = lane >> 5, cl = lane & 31;
+#pragma unroll
+    for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+        for (int ni = 0; ni < 2; ni++) {
+            const int R0 = I * TILE + wr * 64 + mi * 32;
+            const int C0 = J * TILE + wc * 64 + ni * 32;
+            if (!(R0 < rows && C0 <= R0 + 31)) continue;
+            const v16f &a = acc[mi][ni];
+            float par[16];
+#pragma unroll
+            for (int r = 0; r < 16; r++) par[r] = swap_lanes_f(a[r]);
+            const int b = (C0 >> 1) + (cl >> 1);
+#pragma unroll
+            for (int qq = 0; qq < 4; qq++) {
+                const int ia = (R0 >> 1) + 4 * qq + 2 * h + p;
+                float re, im;
+                if (p == 0) {
+                    re = a[4 * qq] + par[4 * qq + 1];
+                    im = a[4 * qq + 1] - par[4 * qq];
+                } else {
+                    re = par[4 * qq + 2] + a[4 * qq + 3];
+                    im = par[4 * qq + 3] - a[4 * qq + 2];
+                }
+                if (ia < n_in && b <= ia) vc[(size_t)ia * (ia + 1) / 2 + b] = make_float2(re, im);
+            }
+        }
+}
+
+}  // namespace
+
+hipError_t launch_correlate_i8(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis,
+                               hipStream_t st) {
+    const int n_tiles = (2 * n_in + TILE - 1) / TILE;
+    const int n_pairs = n_tiles * (n_tiles + 1) / 2;
+    const size_t groups = (size_t)((n_chan + 7) / 8) * 8 * n_pairs;
+    hipLaunchKernelGGL(correlate_i8_kernel, dim3((unsigned)groups), dim3(256), 0, st, q, n_chan, n_in,
+                       n_spec, n_pairs, vis);
+    return hipGetLastError();
+}
+
+hipError_t launch_correlate_f32(const float *q, int n_chan, int n_in, int n_spec, float *vis,
+                                hipStream_t st) {
+    const int n_tiles = (2 * n_in + TILE - 1) / TILE;
+    const int n_pairs = n_tiles * (n_tiles + 1) / 2;
+    const size_t groups = (size_t)((n_chan + 7) / 8) * 8 * n_pairs;
+    hipLaunchKernelGGL(correlate_f32_kernel, dim3((unsigned)groups), dim3(256), 0, st, q, n_chan, n_in,
+                       n_spec, n_pairs, vis);
+    return hipGetLastError();
+}

@@ -1,0 +1,384 @@
+// All-sky imaging of every fine channel (the paper's Sec. 2.2), gfx950.
+//
+// I(l, m) = (1/|B|) sum_{b in B} Re[V_I,b exp(-2 pi i (u_b l + v_b m))],  V_I = (V_XX + V_YY)/2.
+// Baseline coordinates and the membership test of B are float64 and written with explicit
+// rounding intrinsics (no contraction), so the set B is decided identically everywhere.
+//
+// DFT method: one workgroup per (channel, image row); baselines are staged in LDS in chunks,
+// phases are float64 turns reduced to [0, 1) before a float32 sincospi.
+//
+// GRID method (NUFFT type 1 with the exponential-of-semicircle kernel, width 8, beta = 18.4,
+// on a 2x oversampled M = 2 n_pix grid, cell du = 1/4 wavelength):
+//   pass A, one workgroup per (channel, band of grid rows): grid the band's baselines into LDS
+//     (float32 accumulation; FP32, FP16 or BF16 products), FFT every row along u, keep the
+//     n_pix central outputs (image columns) and write them column-major to an intermediate;
+//   pass B, one workgroup per (channel, band of image columns): FFT along v, keep the n_pix
+//     central outputs (image rows), divide by the kernel's Fourier transform in l and m, scale
+//     by 1/|B| and write the real part.
+// The grid never leaves LDS; the only HBM round trip is the n_pix x M intermediate.
+#include "internal.h"
+#include "fft_dev.h"
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+namespace {
+
+constexpr double C_LIGHT = 299792458.0;
+
+struct UV {
+    double u, v;
+};
+
+__device__ __forceinline__ UV baseline_uv(const double *__restrict__ xyz, int a, int b, double nu) {
+    const double dx = __dsub_rn(xyz[3 * a], xyz[3 * b]);
+    const double dy = __dsub_rn(xyz[3 * a + 1], xyz[3 * b + 1]);
+    UV r;
+    r.u = __ddiv_rn(__dmul_rn(dx, nu), C_LIGHT);
+    r.v = __ddiv_rn(__dmul_rn(dy, nu), C_LIGHT);
+    return r;
+}
+
+// Membership of the imaged set B (see nbsi_image_plan_create).
+__device__ __forceinline__ bool in_set(UV w, int grid_n_pix, double uv_min, double uv_max) {
+    const double r = __dsqrt_rn(__dadd_rn(__dmul_rn(w.u, w.u), __dmul_rn(w.v, w.v)));
+    if (r < uv_min || r > uv_max) return false;
+    if (grid_n_pix > 0) {
+        const double U = (double)(grid_n_pix - 5) * 0.25;
+        if (fabs(w.u) > U || fabs(w.v) > U) return false;
+    }
+    return true;
+}
+
+// Stokes I of pair (a, b), a > b: (V[t(2a, 2b)] + V[t(2a+1, 2b+1)]) / 2.
+template <typename VT>
+__device__ __forceinline__ float2 stokes_i(const VT *__restrict__ vc, int a, int b);
+
+template <>
+__device__ __forceinline__ float2 stokes_i<int2>(const int2 *__restrict__ vc, int a, int b) {
+    const size_t txx = (size_t)(2 * a) * (2 * a + 1) / 2 + 2 * b;
+    const size_t tyy = (size_t)(2 * a + 1) * (2 * a + 2) / 2 + 2 * b + 1;
+    const int2 x = vc[txx], y = vc[tyy];
+    return make_float2((float)(0.5 * ((double)x.x + (double)y.x)), (float)(0.5 * ((double)x.y + (double)y.y)));
+}
+
+template <>
+__device__ __forceinline__ float2 stokes_i<float2>(const float2 *__restrict__ vc, int a, int b) {
+    const size_t txx = (size_t)(2 * a) * (2 * a + 1) / 2 + 2 * b;
+    const size_t tyy = (size_t)(2 * a + 1) * (2 * a + 2) / 2 + 2 * b + 1;
+    const float2 x = vc[txx], y = vc[tyy];
+    return make_float2(0.5f * (x.x + y.x), 0.5f * (x.y + y.y));
+}
+
+// ---- |B| per channel ----
+__global__ __launch_bounds__(256) void count_kernel(const double *__restrict__ xyz, const double *__restrict__ freq,
+                                                    const int2 *__restrict__ pairs, int n_pairs, int grid_n_pix,
+                                                    double uv_min, double uv_max, int *__restrict__ nb) {
+    __shared__ int part[256];
+    const int c = blockIdx.x;
+    const double nu = freq[c];
+    int cnt = 0;
+    for (int k = threadIdx.x; k < n_pairs; k += 256) {
+        const int2 p = pairs[k];
+        cnt += in_set(baseline_uv(xyz, p.x, p.y, nu), grid_n_pix, uv_min, uv_max) ? 1 : 0;
+    }
+    part[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nb[c] = part[0];
+}
+
+// ---- direct Fourier imager ----
+template <typename VT>
+__global__ __launch_bounds__(256) void dft_kernel(const VT *__restrict__ vis, const double *__restrict__ xyz,
+                                                  const double *__restrict__ freq, const int2 *__restrict__ pairs,
+                                                  int n_pairs, int n_ant, int n_pix, double uv_min, double uv_max,
+                                                  const int *__restrict__ nb, float *__restrict__ img) {
+    __shared__ double su[256], sv[256];
+    __shared__ float2 sval[256];
+    __shared__ int sok[256];
+    const int c = blockIdx.y;
+    const int y = blockIdx.x;
+    const int t = threadIdx.x;
+    const double nu = freq[c];
+    const size_t nprod = (size_t)(2 * n_ant) * (2 * n_ant + 1) / 2;
+    const VT *vc = vis + (size_t)c * nprod;
+    const double m = (double)(y - n_pix / 2) * (2.0 / (double)n_pix);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < n_pairs; k0 += 256) {
+        __syncthreads();
+        const int k = k0 + t;
+        int ok = 0;
+        if (k < n_pairs) {
+            const int2 p = pairs[k];
+            const UV w = baseline_uv(xyz, p.x, p.y, nu);
+            ok = in_set(w, 0, uv_min, uv_max);
+            su[t] = w.u;
+            sv[t] = w.v;
+            sval[t] = ok ? stokes_i<VT>(vc, p.x, p.y) : make_float2(0.f, 0.f);
+        }
+        sok[t] = ok;
+        __syncthreads();
+        const int kn = min(256, n_pairs - k0);
+        for (int q = 0; q < kn; q++) {
+            if (!sok[q]) continue;
+            const double uq = su[q], vq = sv[q];
+            const float2 val = sval[q];
+#pragma unroll
+            for (int xi = 0; xi < 4; xi++) {
+                const int x = t + 256 * xi;
+                if (x < n_pix) {
+                    const double l = (double)(x - n_pix / 2) * (2.0 / (double)n_pix);
+                    const double turns = uq * l + vq * m;
+                    const double frac = turns - floor(turns);
+                    float sn, cs;
+                    sincospif(2.0f * (float)frac, &sn, &cs);
+                    acc[xi] += val.x * cs + val.y * sn;
+                }
+            }
+        }
+    }
+    const int n = nb[c];
+    const float inv = n > 0 ? (float)(1.0 / (double)n) : 0.f;
+#pragma unroll
+    for (int xi = 0; xi < 4; xi++) {
+        const int x = t + 256 * xi;
+        if (x < n_pix) img[((size_t)c * n_pix + y) * n_pix + x] = acc[xi] * inv;
+    }
+}
+
+// ---- gridding ----
+constexpr int GE = 32;                 // complex values per thread in the banded FFTs
+constexpr int GRID_CELLS = 256 * GE;   // LDS grid cells per workgroup (64 KB)
+constexpr float ES_BETA = 2.30f * 8.0f;
+
+__device__ __forceinline__ float es_kernel(float z) {
+    // exp(beta (sqrt(1 - z^2) - 1)) for |z| <= 1, else 0
+    const float q = 1.f - z * z;
+    return q > 0.f ? expf(ES_BETA * (sqrtf(q) - 1.f)) : 0.f;
+}
+
+template <int PREC>
+__device__ __forceinline__ float2 grid_product(float2 val, float wu, float wv) {
+    if constexpr (PREC == NBSI_PREC_FP16) {
+        const __half2 v2 = __floats2half2_rn(val.x, val.y);
+        const __half w = __float2half_rn(wu * 1.0f);
+        const __half w2 = __float2half_rn(wv);
+        const __half ww = __hmul(w, w2);
+        const __half2 r = __hmul2(v2, __halves2half2(ww, ww));
+        return __half22float2(r);
+    } else if constexpr (PREC == NBSI_PREC_BF16) {
+        const __hip_bfloat16 vr = __float2bfloat16(val.x), vi = __float2bfloat16(val.y);
+        const __hip_bfloat16 ww = __hmul(__float2bfloat16(wu), __float2bfloat16(wv));
+        return make_float2(__bfloat162float(__hmul(vr, ww)), __bfloat162float(__hmul(vi, ww)));
+    } else {
+        const float ww = wu * wv;
+        return make_float2(val.x * ww, val.y * ww);
+    }
+}
+
+// Batched Stockham FFT over `nrows` rows of length 2^log_l stored row-major in LDS (nrows *
+// 2^log_l == 256 * GE).  Radix-16 passes, with one smaller first pass when log_l % 4 != 0.
+template <int R, int E>
+__device__ __forceinline__ void batched_pass(float2 *buf, int t, int log_l, int ns, const TwiddleTable &tw,
+                                             int log_tab) {
+    const int L = 1 << log_l;
+    const int log_r = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+    const int per_row = L / R;  // butterflies per row
+    float2 v[E];
+#pragma unroll
+    for (int b = 0; b < E / R; b++) {
+        const int g = t + 256 * b;
+        const int row = g >> (log_l - log_r), j = g & (per_row - 1);
+#pragma unroll
+        for (int r = 0; r < R; r++) v[b * R + r] = buf[row * L + j + r * per_row];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / R; b++) {
+        const int g = t + 256 * b;
+        const int row = g >> (log_l - log_r), j = g & (per_row - 1);
+        const int k = j & (ns - 1);
+        if (ns > 1) {
+            const int sh = log_tab - (31 - __clz(ns * R));
+#pragma unroll
+            for (int r = 1; r < R; r++) v[b * R + r] = cmul(v[b * R + r], tw((k * r) << sh));
+        }
+        dft_r<R>(v + b * R);
+        const int base = row * L + (j / ns) * ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; r++) buf[base + r * ns] = v[b * R + r];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void batched_fft(float2 *buf, int t, int log_l, const TwiddleTable &tw, int log_tab) {
+    int ns = 1;
+    const int rem = log_l % 4;
+    if (rem == 1) { batched_pass<2, GE>(buf, t, log_l, ns, tw, log_tab); ns = 2; }
+    else if (rem == 2) { batched_pass<4, GE>(buf, t, log_l, ns, tw, log_tab); ns = 4; }
+    else if (rem == 3) { batched_pass<8, GE>(buf, t, log_l, ns, tw, log_tab); ns = 8; }
+    for (int p = 0; p < log_l / 4; p++) {
+        batched_pass<16, GE>(buf, t, log_l, ns, tw, log_tab);
+        ns *= 16;
+    }
+}
+
+template <typename VT, int PREC>
+__global__ __launch_bounds__(256) void grid_rows_kernel(
+    const VT *__restrict__ vis, const double *__restrict__ xyz, const double *__restrict__ freq,
+    const int2 *__restrict__ pairs, const int *__restrict__ band_off, const int *__restrict__ band_items,
+    int n_ant, int n_pix, int log_m, int band_rows, double uv_min, double uv_max, float2 *__restrict__ inter) {
+    __shared__ float2 grid[GRID_CELLS];
+    __shared__ float2 tw_lo[64], tw_hi[64];
+    __shared__ float vscale;
+    const int band = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
+    const int M = 1 << log_m;
+    const int row0 = band * band_rows;
+    const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_m, t, 256);
+    float *gf = reinterpret_cast<float *>(grid);
+    for (int e = t; e < GRID_CELLS; e += 256) grid[e] = make_float2(0.f, 0.f);
+    const size_t nprod = (size_t)(2 * n_ant) * (2 * n_ant + 1) / 2;
+    const VT *vc = vis + (size_t)c * nprod;
+    const double nu = freq[c];
+    const int k_begin = band_off[band], k_end = band_off[band + 1];
+    if constexpr (PREC == NBSI_PREC_FP16) {
+        // Scale this workgroup's visibilities by a power of two so the largest |V_I| it grids
+        // maps below 2^14: every FP16 product (kernel weights <= 1) stays finite.
+        __shared__ float red[256];
+        float mx = 0.f;
+        for (int k = k_begin + t; k < k_end; k += 256) {
+            const int2 p = pairs[band_items[k]];
+            if (!in_set(baseline_uv(xyz, p.x, p.y, nu), n_pix, uv_min, uv_max)) continue;
+            const float2 val = stokes_i<VT>(vc, p.x, p.y);
+            mx = fmaxf(mx, fmaxf(fabsf(val.x), fabsf(val.y)));
+        }
+        red[t] = mx;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (t < s) red[t] = fmaxf(red[t], red[t + s]);
+            __syncthreads();
+        }
+        if (t == 0) {
+            int e2 = 0;
+            frexpf(fmaxf(red[0], 1e-30f), &e2);
+            vscale = ldexpf(1.f, 14 - e2);
+        }
+    }
+    __syncthreads();
+    // 8 threads per baseline: thread tap = t % 8 handles grid column floor(cu) - 3 + tap
+    for (int k = k_begin + t / 8; k < k_end; k += 32) {
+        const int2 p = pairs[band_items[k]];
+        const UV w = baseline_uv(xyz, p.x, p.y, nu);
+        if (!in_set(w, n_pix, uv_min, uv_max)) continue;
+        float2 val = stokes_i<VT>(vc, p.x, p.y);
+        if constexpr (PREC == NBSI_PREC_FP16) val = make_float2(val.x * vscale, val.y * vscale);
+        const double cu = w.u * 4.0 + (double)(M / 2), cv = w.v * 4.0 + (double)(M / 2);
+        const double fu = floor(cu), fv = floor(cv);
+        const int tap = t & 7;
+        const int gu = (int)fu - 3 + tap;
+        const float wu = es_kernel((float)((double)gu - cu) * 0.25f);
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const int gv = (int)fv - 3 + j;
+            const int lr = gv - row0;
+            if (lr < 0 || lr >= band_rows) continue;
+            const float wv = es_kernel((float)((double)gv - cv) * 0.25f);
+            const float2 add = grid_product<PREC>(val, wu, wv);
+            atomicAdd(&gf[2 * (lr * M + gu)], add.x);
+            atomicAdd(&gf[2 * (lr * M + gu) + 1], add.y);
+        }
+    }
+    __syncthreads();
+    batched_fft(grid, t, log_m, tw, log_m);
+    // keep image columns x: FFT index (x - n/2) mod M, times (-1)^(x - n/2); undo the FP16 scale
+    const float unscale = (PREC == NBSI_PREC_FP16) ? 1.f / vscale : 1.f;
+    for (int e = t; e < n_pix * band_rows; e += 256) {
+        const int lr = e % band_rows, x = e / band_rows;
+        const int xp = x - n_pix / 2;
+        const float2 f = grid[lr * M + (xp & (M - 1))];
+        const float sgn = (xp & 1) ? -unscale : unscale;
+        inter[((size_t)c * n_pix + x) * M + row0 + lr] = make_float2(f.x * sgn, f.y * sgn);
+    }
+}
+
+__global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict__ inter, int n_pix, int log_m,
+                                                        int band_cols, const float *__restrict__ corr,
+                                                        const int *__restrict__ nb, float *__restrict__ img) {
+    __shared__ float2 buf[GRID_CELLS];
+    __shared__ float2 tw_lo[64], tw_hi[64];
+    const int xb = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
+    const int M = 1 << log_m;
+    const int x0 = xb * band_cols;
+    const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_m, t, 256);
+    for (int e = t; e < band_cols * M; e += 256) {
+        const int xl = e / M, g = e % M;
+        buf[e] = inter[((size_t)c * n_pix + x0 + xl) * M + g];
+    }
+    __syncthreads();
+    batched_fft(buf, t, log_m, tw, log_m);
+    const int n = nb[c];
+    const float inv = n > 0 ? (float)(1.0 / (double)n) : 0.f;
+    for (int e = t; e < n_pix * band_cols; e += 256) {
+        const int xl = e % band_cols, y = e / band_cols;
+        const int yp = y - n_pix / 2;
+        const float2 f = buf[xl * M + (yp & (M - 1))];
+        const float sgn = (yp & 1) ? -1.f : 1.f;
+        img[((size_t)c * n_pix + y) * n_pix + x0 + xl] = f.x * sgn * corr[x0 + xl] * corr[y] * inv;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_image_count(const nbsi_image_plan *p, hipStream_t st) {
+    hipLaunchKernelGGL(count_kernel, dim3(p->n_chan), dim3(256), 0, st, p->d_xyz, p->d_freq, p->d_pairs,
+                       p->n_pairs, p->method == NBSI_IMAGE_GRID ? p->n_pix : 0, p->uv_min, p->uv_max,
+                       p->d_nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_dtype, float *img,
+                            hipStream_t st) {
+    dim3 grid(p->n_pix, p->n_chan);
+    if (vis_dtype == NBSI_VIS_I32)
+        hipLaunchKernelGGL(dft_kernel<int2>, grid, dim3(256), 0, st, (const int2 *)vis, p->d_xyz, p->d_freq,
+                           p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, p->d_nb, img);
+    else
+        hipLaunchKernelGGL(dft_kernel<float2>, grid, dim3(256), 0, st, (const float2 *)vis, p->d_xyz,
+                           p->d_freq, p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max,
+                           p->d_nb, img);
+    return hipGetLastError();
+}
+
+template <typename VT, int PREC>
+static void launch_rows(const nbsi_image_plan *p, const VT *vis, float2 *inter, int log_m, hipStream_t st) {
+    hipLaunchKernelGGL((grid_rows_kernel<VT, PREC>), dim3(p->n_bands, p->n_chan), dim3(256), 0, st, vis,
+                       p->d_xyz, p->d_freq, p->d_pairs, p->d_band_off, p->d_band_items, p->n_ant, p->n_pix,
+                       log_m, p->band_rows, p->uv_min, p->uv_max, inter);
+}
+
+hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype, int precision,
+                             float2 *inter, float *img, hipStream_t st) {
+    const int M = 2 * p->n_pix;
+    const int log_m = 31 - __builtin_clz(M);
+    if (vis_dtype == NBSI_VIS_I32) {
+        const int2 *v = (const int2 *)vis;
+        if (precision == NBSI_PREC_FP16) launch_rows<int2, NBSI_PREC_FP16>(p, v, inter, log_m, st);
+        else if (precision == NBSI_PREC_BF16) launch_rows<int2, NBSI_PREC_BF16>(p, v, inter, log_m, st);
+        else launch_rows<int2, NBSI_PREC_FP32>(p, v, inter, log_m, st);
+    } else {
+        const float2 *v = (const float2 *)vis;
+        if (precision == NBSI_PREC_FP16) launch_rows<float2, NBSI_PREC_FP16>(p, v, inter, log_m, st);
+        else if (precision == NBSI_PREC_BF16) launch_rows<float2, NBSI_PREC_BF16>(p, v, inter, log_m, st);
+        else launch_rows<float2, NBSI_PREC_FP32>(p, v, inter, log_m, st);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int band_cols = GRID_CELLS / M;
+    hipLaunchKernelGGL(grid_cols_kernel, dim3(p->n_pix / band_cols, p->n_chan), dim3(256), 0, st, inter,
+                       p->n_pix, log_m, band_cols, p->d_corr, p->d_nb, img);
+    return hipGetLastError();
+}

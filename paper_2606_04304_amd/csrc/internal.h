@@ -1,0 +1,86 @@
+// Internal declarations shared by the host API and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "nbsi.h"
+
+struct nbsi_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    // grow-only scratch slots, each owned by one stage
+    void *scratch[8] = {nullptr};
+    size_t scratch_size[8] = {0};
+    int *d_counter = nullptr;  // small device counters (detector)
+};
+
+enum ScratchSlot {
+    SLOT_CHAN_STAGE_Q = 0,  // channelizer staging, int8
+    SLOT_CHAN_STAGE_F = 1,  // channelizer staging, float32
+    SLOT_IMG_INTER = 2,     // imager: row-transformed grid
+    SLOT_DET_CAND = 3,      // detector: unsorted candidates
+    SLOT_DET_KEYS = 4,      // detector: sort keys
+    SLOT_DET_STATS = 5,     // detector: per-channel / per-pixel statistics
+    SLOT_IMG_BL = 6,        // imager: per-channel baseline values
+};
+
+struct nbsi_image_plan {
+    int device = 0;
+    int n_ant = 0, n_chan = 0, n_pix = 0, method = 0;
+    double uv_min = 0, uv_max = 0;
+    // device arrays
+    double *d_xyz = nullptr;      // [n_ant][3]
+    double *d_freq = nullptr;     // [n_chan]
+    int *d_nb = nullptr;          // [n_chan] |B| per channel
+    int2 *d_pairs = nullptr;      // candidate pairs (a, b), a > b
+    int n_pairs = 0;
+    // gridding: candidate pairs binned by bands of grid rows (CSR over bands)
+    int band_rows = 0, n_bands = 0;
+    int *d_band_off = nullptr;    // [n_bands + 1]
+    int *d_band_items = nullptr;  // indices into d_pairs
+    int n_band_items = 0;
+    float *d_corr = nullptr;      // [n_pix] 1 / (kernel Fourier transform) per image column
+};
+
+#define NBSI_TRY_HIP(ctx, call)                                                        \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            (ctx)->last_error = std::string(#call) + ": " + hipGetErrorString(e_);    \
+            return NBSI_EHIP;                                                          \
+        }                                                                              \
+    } while (0)
+
+int nbsi_scratch(nbsi_ctx *ctx, int slot, size_t bytes, void **ptr);
+int nbsi_fail(nbsi_ctx *ctx, int code, const std::string &msg);
+
+// ---- launchers (each returns hipError_t of the launch) ----
+hipError_t launch_channelize(const int8_t *volt, int n_in, int log_n, int n_spec, int klo,
+                             int n_chan, const float *gain, int8_t *stage_q, float *stage_f,
+                             hipStream_t st);
+hipError_t launch_corner_turn_q(const int8_t *stage, int n_in, int n_spec, int n_chan,
+                                int8_t *out, hipStream_t st);
+hipError_t launch_corner_turn_f(const float *stage, int n_in, int n_spec, int n_chan, float *out,
+                                hipStream_t st);
+hipError_t launch_correlate_i8(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis,
+                               hipStream_t st);
+hipError_t launch_correlate_f32(const float *q, int n_chan, int n_in, int n_spec, float *vis,
+                                hipStream_t st);
+hipError_t launch_image_count(const nbsi_image_plan *p, hipStream_t st);
+hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_dtype, float *img,
+                            hipStream_t st);
+hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype,
+                             int precision, float2 *inter, float *img, hipStream_t st);
+hipError_t launch_detect_stats(const float *img, int n_chan, int n_pix, int mode, float *stats,
+                               hipStream_t st);
+hipError_t launch_detect_scan(const float *img, int n_chan, int n_pix, int mode,
+                              const float *stats, float thresh, float *snr, nbsi_cand *cand,
+                              int cap, int *counter, hipStream_t st);
+hipError_t launch_detect_sort(nbsi_cand *cand, int n, unsigned long long *keys, int n_chan,
+                              int n_pix, nbsi_cand *out, int n_out, hipStream_t st);
