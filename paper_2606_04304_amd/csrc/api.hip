@@ -15,7 +15,7 @@ namespace {
 
 constexpr double C_LIGHT = 299792458.0;
 constexpr int GRID_CELLS = 256 * 32;  // LDS cells of one gridding workgroup (see image.hip)
-constexpr size_t IMAGE_SCRATCH_CAP = (size_t)2 << 30;
+constexpr size_t IMAGE_CHUNK_BYTES = (size_t)128 << 20;
 
 struct DeviceGuard {
     int prev = -1;
@@ -269,6 +269,7 @@ int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
     const double U = (double)(n_pix - 5) * 0.25;
     const int M = 2 * n_pix;
     std::vector<int2> pairs;
+    std::vector<double2> dxy;
     std::vector<int> lo_row, hi_row;
     for (int a = 0; a < n_ant; a++)
         for (int b = 0; b < a; b++) {
@@ -285,6 +286,7 @@ int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
                 hi_row.push_back(std::min(M - 1, (int)floor(std::max(v1, v2)) + 5));
             }
             pairs.push_back(make_int2(a, b));
+            dxy.push_back(make_double2(dx, dy));
         }
     p->n_pairs = (int)pairs.size();
 
@@ -298,6 +300,10 @@ int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
             for (int bnd = lo_row[k] / p->band_rows; bnd <= hi_row[k] / p->band_rows; bnd++) bins[bnd].push_back(k);
         band_off.push_back(0);
         for (int bnd = 0; bnd < p->n_bands; bnd++) {
+            // sorted by x separation: the grid column u / du + M/2 = dx nu / (c du) + M/2 is then
+            // non-decreasing along the list for every channel frequency
+            std::stable_sort(bins[bnd].begin(), bins[bnd].end(),
+                             [&](int a, int b) { return dxy[a].x < dxy[b].x; });
             band_items.insert(band_items.end(), bins[bnd].begin(), bins[bnd].end());
             band_off.push_back((int)band_items.size());
         }
@@ -327,7 +333,8 @@ int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
     bool ok = up((void **)&p->d_xyz, ant_xyz_host, sizeof(double) * 3 * n_ant) &&
               up((void **)&p->d_freq, freq_hz_host, sizeof(double) * n_chan) &&
               up((void **)&p->d_nb, nullptr, sizeof(int) * n_chan) &&
-              up((void **)&p->d_pairs, pairs.data(), sizeof(int2) * pairs.size());
+              up((void **)&p->d_pairs, pairs.data(), sizeof(int2) * pairs.size()) &&
+              up((void **)&p->d_dxy, dxy.data(), sizeof(double2) * dxy.size());
     if (ok && method == NBSI_IMAGE_GRID)
         ok = up((void **)&p->d_band_off, band_off.data(), sizeof(int) * band_off.size()) &&
              up((void **)&p->d_band_items, band_items.data(), sizeof(int) * band_items.size()) &&
@@ -349,7 +356,7 @@ int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
 int nbsi_image_plan_destroy(nbsi_image_plan *p) {
     if (!p) return NBSI_EINVAL;
     DeviceGuard g(p->device);
-    void *bufs[] = {p->d_xyz, p->d_freq, p->d_nb, p->d_pairs, p->d_band_off, p->d_band_items, p->d_corr};
+    void *bufs[] = {p->d_xyz, p->d_freq, p->d_nb, p->d_pairs, p->d_dxy, p->d_band_off, p->d_band_items, p->d_corr};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -379,12 +386,16 @@ int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int 
         NBSI_TRY_HIP(ctx, launch_image_dft(plan, vis, vis_dtype, img, ctx->stream));
         return NBSI_OK;
     }
-    // gridding: channel chunks bound the intermediate to IMAGE_SCRATCH_CAP bytes
+    // Gridding runs over chunks of channels small enough for the row-transformed intermediate
+    // (n_pix x 2 n_pix complex per channel) to stay in the 256 MB last-level cache between the
+    // row and column passes.
     const size_t per_chan = (size_t)plan->n_pix * 2 * plan->n_pix * sizeof(float2);
-    int chunk = (int)std::max<size_t>(1, std::min<size_t>(plan->n_chan, IMAGE_SCRATCH_CAP / per_chan));
-    void *inter = nullptr;
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>(plan->n_chan, IMAGE_CHUNK_BYTES / per_chan));
+    void *inter = nullptr, *cvis = nullptr;
     int rc = nbsi_scratch(ctx, SLOT_IMG_INTER, per_chan * chunk, &inter);
     if (rc) return rc;
+    if ((rc = nbsi_scratch(ctx, SLOT_IMG_BL, sizeof(float2) * (size_t)chunk * std::max(1, plan->n_pairs), &cvis)))
+        return rc;
     const size_t nprod = (size_t)(2 * plan->n_ant) * (2 * plan->n_ant + 1) / 2;
     const size_t vis_chan_bytes = nprod * 8;  // int2 or float2
     for (int c0 = 0; c0 < plan->n_chan; c0 += chunk) {
@@ -393,8 +404,8 @@ int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int 
         sub.d_freq = plan->d_freq + c0;
         sub.d_nb = plan->d_nb + c0;
         NBSI_TRY_HIP(ctx, launch_image_grid(&sub, (const char *)vis + vis_chan_bytes * c0, vis_dtype, precision,
-                                            (float2 *)inter, img + (size_t)c0 * plan->n_pix * plan->n_pix,
-                                            ctx->stream));
+                                            (float2 *)cvis, (float2 *)inter,
+                                            img + (size_t)c0 * plan->n_pix * plan->n_pix, ctx->stream));
     }
     return NBSI_OK;
 }

@@ -16,6 +16,7 @@
 #include "internal.h"
 #include "fft_dev.h"
 
+
 namespace {
 
 constexpr int E = 16;  // complex values per thread
@@ -28,14 +29,50 @@ struct Plan {
     static constexpr int NPASS16 = (LOGM % 4 == 0) ? LOGM / 4 - 1 : LOGM / 4;
 };
 
-template <int LOGM>
+// W_16^e = exp(-2 pi i e / 16)
+__device__ __forceinline__ float2 w16(int e) {
+    constexpr float c[16] = {1.f, 0.92387953251128675613f, 0.70710678118654752440f, 0.38268343236508977173f,
+                             0.f, -0.38268343236508977173f, -0.70710678118654752440f, -0.92387953251128675613f,
+                             -1.f, -0.92387953251128675613f, -0.70710678118654752440f, -0.38268343236508977173f,
+                             0.f, 0.38268343236508977173f, 0.70710678118654752440f, 0.92387953251128675613f};
+    return make_float2(c[e & 15], -c[(e + 12) & 15]);  // sin(2 pi e/16) = cos(2 pi (e - 4)/16)
+}
+
+// One radix-16 Stockham pass for one butterfly per thread (j = t).  The twiddles w^r,
+// w = W_{16 ns}^{j mod ns}, come from one table entry: w^1..w^7 by a running product and
+// w^8..w^15 from w^8 = ((w^2)^2)^2, so no chain is longer than about ten roundings.
+__device__ __forceinline__ void pass16(float2 *v, int t, int ns, int log_n, const TwiddleTable &tw) {
+    if (ns > 1) {
+        const int k = t & (ns - 1);
+        const int sh = log_n - (31 - __clz(ns * 16));
+        const float2 w = tw(k << sh);
+        float2 cur = w;
+#pragma unroll
+        for (int r = 1; r < 8; r++) {
+            v[r] = cmul(v[r], cur);
+            cur = cmul(cur, w);
+        }
+        const float2 w2 = cmul(w, w), w4 = cmul(w2, w2);
+        cur = cmul(w4, w4);
+#pragma unroll
+        for (int r = 8; r < 16; r++) {
+            v[r] = cmul(v[r], cur);
+            cur = cmul(cur, w);
+        }
+    }
+    dft16(v);
+}
+
+template <int LOGM, int G>
 __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(
     const int8_t *__restrict__ volt, int log_n, int n_spec, int klo, int n_chan,
     const float *__restrict__ gain, int8_t *__restrict__ stage_q, float2 *__restrict__ stage_f) {
     using PL = Plan<LOGM>;
     constexpr int M = PL::M, NT = PL::NT, R0 = PL::R0;
-    __shared__ float2 buf[M];
-    __shared__ float2 tw_lo[512], tw_hi[512];
+    __shared__ float2 buf[padded_size(M)];
+    // dynamic LDS: two-level table of W_N (2^lo_bits + 2^(log_n - lo_bits) entries), then
+    // [P][16][2] accumulation twiddles W_N^{p (NT r + M j_sel)}
+    extern __shared__ float2 dyn[];
 
     const int t = threadIdx.x;
     const int s = blockIdx.x % n_spec;
@@ -44,50 +81,82 @@ __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(
     const int P = N >> LOGM;
     const int log_p = log_n - LOGM;
 
+    const int lo_bits = (log_n + 1) >> 1;
+    float2 *tw_lo = dyn, *tw_hi = dyn + (1 << lo_bits);
+    float2 *acc_tw = tw_hi + (1 << (log_n - lo_bits));
     const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_n, t, NT);
     __syncthreads();
+    // Kept output of residue k1 = t + NT r is k = k1 + M j with j = jl (k1 >= klo mod M) or
+    // jl + 1 (k1 < klo mod M), so W_N^{p k} = W_N^{p t} * W_N^{p (NT r + M j)}.
+    const int rl = klo & (M - 1), jl = klo >> LOGM;
+    if (P > 1) {
+        for (int e = t; e < P * 32; e += NT) {
+            const int p = e >> 5, r = (e >> 1) & 15, sel = e & 1;
+            const int j = (jl + sel) & (P - 1);
+            acc_tw[e] = tw((p * (NT * r + M * j)) & (N - 1));
+        }
+    }
+    __syncthreads();
 
+    // raw buffer over this spectrum's samples: one per-thread offset plus scalar offsets per
+    // element, with hardware range checking (reads past the spectrum return 0)
     const int16_t *x = reinterpret_cast<const int16_t *>(volt) + ((size_t)i * n_spec + s) * (size_t)N;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<int16_t *>(x), (short)0, N * 2, 0x00020000);
+    const int voff = (t << log_p) * 2;
 
-    // kept outputs owned by this thread: register e = r (final radix-16 pass) holds k1 = t + r*NT
-    int kfull[E];
-    bool kept[E];
+    unsigned kept = 0, sel = 0;
 #pragma unroll
     for (int r = 0; r < E; r++) {
         const int k1 = t + r * NT;
-        const int d = (k1 - klo) & (M - 1);
-        kept[r] = d < n_chan;
-        kfull[r] = (klo + d) & (N - 1);
+        if (((k1 - klo) & (M - 1)) < n_chan) kept |= 1u << r;
+        if (k1 < rl) sel |= 1u << r;
     }
 
     float2 acc[E];
 #pragma unroll
     for (int r = 0; r < E; r++) acc[r] = make_float2(0.f, 0.f);
 
-    for (int p = 0; p < P; p++) {
-        float2 v[E];
-        // first pass inputs: element m = j + r*M/R0, j = t + NT*b; sample n = p + P*m
+    for (int p0 = 0; p0 < P; p0 += G) {
+        // raw samples of G consecutive sub-transforms: element m = t + NT b + (M/R0) r
+        int raw[E];
 #pragma unroll
-        for (int b = 0; b < E / R0; b++) {
+        for (int b = 0; b < E / R0; b++)
 #pragma unroll
             for (int r = 0; r < R0; r++) {
-                const int m = t + NT * b + r * (M / R0);
-                const int n = p + (m << log_p);
-                const int16_t raw = x[n];
-                const float w = 0.5f - 0.5f * tw(n).x;   // periodic Hann: cos(2 pi n / N)
-                v[b * R0 + r] = make_float2(w * (float)(int8_t)(raw & 0xff), w * (float)(int8_t)(raw >> 8));
+                const int soff = 2 * (p0 + ((NT * b + r * (M / R0)) << log_p));
+                if constexpr (G == 2) raw[b * R0 + r] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0);
+                else raw[b * R0 + r] = (int)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(rsrc, voff, soff, 0);
             }
-        }
-        stockham_regs<R0, E>(v, t, NT, LOGM, 1, tw, log_n);
-        int ns = R0;
-        if constexpr (PL::NPASS16 > 0) {
+#pragma unroll 1
+        for (int g = 0; g < G; g++) {
+            const int p = p0 + g;
+            float2 v[E];
+            // window w[n] = 1/2 - 1/2 cos(2 pi n / N), n = p + P t + (N/16) b + (N/R0) r:
+            // cos from W_N^{p + P t} times the constant W_16^{b + (16/R0) r}
+            const float2 wb = tw(p + (t << log_p));
+#pragma unroll
+            for (int b = 0; b < E / R0; b++)
+#pragma unroll
+                for (int r = 0; r < R0; r++) {
+                    const float2 wc = w16(b + (16 / R0) * r);
+                    const float cs = wb.x * wc.x - wb.y * wc.y;
+                    const float w = 0.5f - 0.5f * cs;
+                    const int sample = (G == 2) ? (raw[b * R0 + r] >> (16 * g)) : raw[b * R0 + r];
+                    const float re = (float)(int8_t)(sample & 0xff), im = (float)(int8_t)((sample >> 8) & 0xff);
+                    v[b * R0 + r] = make_float2(w * re, w * im);
+                }
+            // first pass (radix R0, no twiddles)
+#pragma unroll
+            for (int b = 0; b < E / R0; b++) dft_r<R0>(v + b * R0);
             __syncthreads();  // buf free (previous sub-transform done reading)
             stockham_store<R0, E>(buf, v, t, NT, 1);
             __syncthreads();
+            int ns = R0;
 #pragma unroll
             for (int pass = 0; pass < PL::NPASS16; pass++) {
                 stockham_load<16, E>(buf, v, t, NT, LOGM);
-                stockham_regs<16, E>(v, t, NT, LOGM, ns, tw, log_n);
+                pass16(v, t, ns, log_n, tw);
                 if (pass + 1 < PL::NPASS16) {
                     __syncthreads();
                     stockham_store<16, E>(buf, v, t, NT, ns);
@@ -95,33 +164,37 @@ __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(
                 }
                 ns *= 16;
             }
-        }
-        // v[r] = Y_p[t + r*NT]
-        if (P == 1) {
+            // v[r] = Y_p[t + r NT]
+            if (P == 1) {
 #pragma unroll
-            for (int r = 0; r < E; r++) acc[r] = v[r];
-        } else {
+                for (int r = 0; r < E; r++) acc[r] = v[r];
+            } else {
+                const float2 bp = tw((p * t) & (N - 1));
+                const float2 *row = acc_tw + p * 32;
+                // every register accumulates (branch-free); only kept outputs are stored
 #pragma unroll
-            for (int r = 0; r < E; r++) {
-                if (kept[r]) acc[r] = cadd(acc[r], cmul(v[r], tw((p * kfull[r]) & (N - 1))));
+                for (int r = 0; r < E; r++) {
+                    const float2 tr = cmul(bp, row[2 * r + ((sel >> r) & 1)]);
+                    acc[r] = cadd(acc[r], cmul(v[r], tr));
+                }
             }
         }
     }
 
     const float g = gain[i];
-    const size_t row = ((size_t)i * n_spec + s) * (size_t)n_chan;
+    const size_t rowo = ((size_t)i * n_spec + s) * (size_t)n_chan;
 #pragma unroll
     for (int r = 0; r < E; r++) {
-        if (!kept[r]) continue;
+        if (!(kept & (1u << r))) continue;
         const int k1 = t + r * NT;
         const int d = (k1 - klo) & (M - 1);
         const float2 gx = make_float2(acc[r].x * g, acc[r].y * g);
-        if (stage_f) stage_f[row + d] = gx;
+        if (stage_f) stage_f[rowo + d] = gx;
         if (stage_q) {
             const float qr = fminf(fmaxf(rintf(gx.x), -127.f), 127.f);
             const float qi = fminf(fmaxf(rintf(gx.y), -127.f), 127.f);
             const int16_t packed = (int16_t)(((int)qi << 8) | ((int)qr & 0xff));
-            reinterpret_cast<int16_t *>(stage_q)[row + d] = packed;
+            reinterpret_cast<int16_t *>(stage_q)[rowo + d] = packed;
         }
     }
 }
@@ -184,8 +257,16 @@ template <int LOGM>
 hipError_t launch_logm(const int8_t *volt, int n_in, int log_n, int n_spec, int klo, int n_chan,
                        const float *gain, int8_t *stage_q, float *stage_f, hipStream_t st) {
     dim3 grid((unsigned)n_in * (unsigned)n_spec);
-    hipLaunchKernelGGL(channelize_kernel<LOGM>, grid, dim3((1 << LOGM) / 16), 0, st, volt, log_n,
-                       n_spec, klo, n_chan, gain, stage_q, reinterpret_cast<float2 *>(stage_f));
+    const int P = 1 << (log_n - LOGM);
+    float2 *sf = reinterpret_cast<float2 *>(stage_f);
+    const int lo_bits = (log_n + 1) >> 1;
+    const size_t lds = sizeof(float2) * ((1 << lo_bits) + (1 << (log_n - lo_bits)) + (P > 1 ? 32 * P : 0));
+    if (P >= 2)
+        hipLaunchKernelGGL((channelize_kernel<LOGM, 2>), grid, dim3((1 << LOGM) / 16), lds, st, volt, log_n, n_spec,
+                           klo, n_chan, gain, stage_q, sf);
+    else
+        hipLaunchKernelGGL((channelize_kernel<LOGM, 1>), grid, dim3((1 << LOGM) / 16), lds, st, volt, log_n, n_spec,
+                           klo, n_chan, gain, stage_q, sf);
     return hipGetLastError();
 }
 

@@ -2,14 +2,14 @@
 // width-1 matched filter), gfx950.
 //
 // Per-pixel kernel: a workgroup stages the spectra of PPW neighbouring pixels in LDS (one
-// read of the cube), and one wave per pixel computes the exact median and MAD by radix
-// selection on order-preserving integer keys of the float32 values (4 digit passes of 8 bits,
-// histograms in LDS), then scores every channel and keeps threshold crossings that survive
-// +-1 channel non-maximum suppression (ties keep the lower channel).  Candidates are appended
+// read of the cube), and one wave per pixel computes the exact median and MAD by selection
+// (value-range histograms in LDS refined until a few candidates remain, then ranked), scores
+// every channel and keeps threshold crossings that survive +-1 channel non-maximum
+// suppression (ties keep the lower channel).  Candidates are appended
 // with a global atomic counter and sorted afterwards by (y, x, c) with a bitonic network.
 //
 // Per-image mode first computes each channel image's median and MAD over the visible
-// hemisphere (radix selection over the image in global memory, one workgroup per channel),
+// hemisphere (the same selection over the image in global memory, one wave per channel),
 // then runs the per-pixel kernel on the standardised values with only the spectral median
 // removed.
 #include "internal.h"
@@ -18,13 +18,6 @@ namespace {
 
 constexpr float MAD_K = 1.482602218505602f;
 
-__device__ __forceinline__ unsigned fkey(float f) {
-    unsigned u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float funkey(unsigned u) {
-    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
 
 __device__ __forceinline__ bool in_horizon(int x, int y, int n) {
     const int h = n / 2, dx = x - h, dy = y - h;
@@ -52,72 +45,169 @@ __device__ __forceinline__ unsigned wave_min_u(unsigned v) {
     return v;
 }
 
-// Value whose key is the rank-th smallest (0-based) of keyfn(i), i < n, for one wave.
-// hist: this wave's 256 LDS counters.  Every wave of the block calls this the same number of
-// times, so the block barriers inside are uniform.
-template <typename KeyFn>
-__device__ unsigned wave_select(KeyFn keyfn, int n, int rank, unsigned *hist, int lane) {
-    unsigned prefix = 0, pmask = 0;
+__device__ __forceinline__ float wave_min_f(float v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// Bin of x in [lo, hi] split into 256 equal parts: non-decreasing in x, safe for a zero-width
+// or denormal range (an infinite scale sends everything above lo to the last bin).
+__device__ __forceinline__ int value_bin(float x, float lo, float scale) {
+    const float t = (x - lo) * scale;
+    return t >= 256.f ? 255 : (t > 0.f ? (int)t : 0);
+}
+
+// The rank-th smallest (0-based) of val(i), i < n, for one wave (exact order statistic).
+// NaN values are ignored (they never fall inside a range), so callers can mask entries out.
+// Values are binned by value over the current range [lo, hi] into 256 LDS counters; the bin
+// index is a non-decreasing function of the value, so the bin holding the rank-th value is
+// found from the cumulative counts, and the range shrinks to that bin's own min and max until
+// at most 64 values remain, which are ranked directly.  `hist` is this wave's 256 counters and
+// `pool` its 64 floats of LDS; every wave of the block makes the same calls (uniform barriers).
+template <typename ValFn>
+__device__ float wave_kth(ValFn val, int n, int rank, unsigned *hist, float *pool, int lane) {
+    float lo = INFINITY, hi = -INFINITY;
+    for (int i = lane; i < n; i += 64) {
+        const float x = val(i);
+        lo = fminf(lo, x);
+        hi = fmaxf(hi, x);
+    }
+    lo = wave_min_f(lo);
+    hi = wave_max_f(hi);
     int k = rank;
-    for (int shift = 24; shift >= 0; shift -= 8) {
+    float result = lo;
+    bool done = false;
+    for (int iter = 0; iter < 40; iter++) {
+        // counts of in-range values (ties at the bounds included)
+        int cnt_in = 0;
+        if (!done) {
+            if (!(hi > lo)) {
+                result = lo;
+                done = true;
+            }
+        }
+        // the loop structure (and its barriers) is identical in every wave
+        const float scale = done ? 0.f : 256.f / (hi - lo);
 #pragma unroll
         for (int b = 0; b < 4; b++) hist[lane * 4 + b] = 0;
         __syncthreads();
-        for (int i = lane; i < n; i += 64) {
-            const unsigned key = keyfn(i);
-            if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        if (!done) {
+            for (int i = lane; i < n; i += 64) {
+                const float x = val(i);
+                if (x >= lo && x <= hi) atomicAdd(&hist[value_bin(x, lo, scale)], 1u);
+            }
         }
         __syncthreads();
-        int cnt[4], s = 0;
+        int c4[4], s4 = 0;
 #pragma unroll
         for (int b = 0; b < 4; b++) {
-            cnt[b] = (int)hist[lane * 4 + b];
-            s += cnt[b];
+            c4[b] = (int)hist[lane * 4 + b];
+            s4 += c4[b];
         }
-        const int incl = wave_inclusive_scan(s, lane);
-        const int excl = incl - s;
-        int digit = 0, below = 0;
-        const bool mine = (excl <= k) && (k < incl);
+        const int incl = wave_inclusive_scan(s4, lane);
+        const int excl = incl - s4;
+        int bsel = 0, below = 0;
+        const bool mine = !done && (excl <= k) && (k < incl);
         if (mine) {
             int run = excl;
 #pragma unroll
             for (int b = 0; b < 4; b++) {
-                if (k >= run && k < run + cnt[b]) {
-                    digit = lane * 4 + b;
+                if (k >= run && k < run + c4[b]) {
+                    bsel = lane * 4 + b;
                     below = run;
+                    cnt_in = c4[b];
                 }
-                run += cnt[b];
+                run += c4[b];
             }
         }
         const unsigned long long ball = __ballot(mine);
         const int src = ball ? (int)(__ffsll((long long)ball) - 1) : 0;
-        digit = __shfl(digit, src, 64);
+        bsel = __shfl(bsel, src, 64);
         below = __shfl(below, src, 64);
-        prefix |= (unsigned)digit << shift;
-        pmask |= 0xffu << shift;
-        k -= below;
+        cnt_in = __shfl(cnt_in, src, 64);
+        // min / max of the selected bin, and (when small) its values into the pool
+        float nlo = INFINITY, nhi = -INFINITY;
+        int slot_base = 0;
+        if (!done) {
+            for (int i0 = 0; i0 < n; i0 += 64) {
+                const int i = i0 + lane;
+                bool in = false;
+                float x = 0.f;
+                if (i < n) {
+                    x = val(i);
+                    in = x >= lo && x <= hi && value_bin(x, lo, scale) == bsel;
+                }
+                if (in) {
+                    nlo = fminf(nlo, x);
+                    nhi = fmaxf(nhi, x);
+                }
+                if (cnt_in <= 64) {
+                    const unsigned long long bm = __ballot(in);
+                    if (in) pool[slot_base + __popcll(bm & ((1ull << lane) - 1ull))] = x;
+                    slot_base += __popcll(bm);
+                }
+            }
+            nlo = wave_min_f(nlo);
+            nhi = wave_max_f(nhi);
+        }
         __syncthreads();
+        if (!done) {
+            k -= below;
+            if (cnt_in <= 64) {
+                // exact rank within the pool
+                float mine_v = 0.f;
+                bool hit = false;
+                if (lane < cnt_in) {
+                    mine_v = pool[lane];
+                    int less = 0, eq = 0;
+                    for (int j = 0; j < cnt_in; j++) {
+                        const float y = pool[j];
+                        less += y < mine_v;
+                        eq += y == mine_v;
+                    }
+                    hit = (less <= k) && (k < less + eq);
+                }
+                const unsigned long long hb = __ballot(hit);
+                const int hsrc = hb ? (int)(__ffsll((long long)hb) - 1) : 0;
+                result = __shfl(mine_v, hsrc, 64);
+                done = true;
+            } else {
+                lo = nlo;
+                hi = nhi;
+            }
+        }
+        __syncthreads();
+        // all waves leave together once every wave is done
+        if (__syncthreads_and(done ? 1 : 0)) break;
     }
-    return prefix;
+    return result;
 }
 
-// Median of keyfn over n values (mean of the central pair for even n), as float.
-template <typename KeyFn>
-__device__ float wave_median(KeyFn keyfn, int n, unsigned *hist, int lane) {
-    const unsigned klo = wave_select(keyfn, n, (n - 1) / 2, hist, lane);
-    if (n & 1) return funkey(klo);
-    // rank n/2: equal to klo when more than n/2 keys are <= klo, else the next larger key
+// Median of the n_valid non-NaN values among val(i), i < n (mean of the central pair for even
+// n_valid).
+template <typename ValFn>
+__device__ float wave_median(ValFn val, int n, int n_valid, unsigned *hist, float *pool, int lane) {
+    const float vlo = wave_kth(val, n, (n_valid - 1) / 2, hist, pool, lane);
+    if (n_valid & 1) return vlo;
+    // rank n_valid/2: vlo itself when more than n_valid/2 values are <= vlo, else the next
+    // larger value
     int le = 0;
-    unsigned nxt = 0xffffffffu;
+    float nxt = INFINITY;
     for (int i = lane; i < n; i += 64) {
-        const unsigned key = keyfn(i);
-        le += key <= klo;
-        if (key > klo) nxt = min(nxt, key);
+        const float x = val(i);
+        le += x <= vlo;
+        if (x > vlo) nxt = fminf(nxt, x);
     }
     le = wave_sum(le);
-    nxt = wave_min_u(nxt);
-    const unsigned khi = (le >= n / 2 + 1) ? klo : nxt;
-    return 0.5f * (funkey(klo) + funkey(khi));
+    nxt = wave_min_f(nxt);
+    const float vhi = (le >= n_valid / 2 + 1) ? vlo : nxt;
+    return 0.5f * (vlo + vhi);
 }
 
 // stats: per-channel (median, k * MAD) for PER_IMAGE mode, else unused.
@@ -128,6 +218,7 @@ __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
     int n_groups) {
     extern __shared__ float spec[];  // [PPW][n_chan]
     __shared__ unsigned hist_all[PPW][256];
+    __shared__ float pool_all[PPW][64];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     // XCD-aware order: consecutive pixel groups of one XCD share cache lines of the cube rows
     const int id = blockIdx.x;
@@ -156,13 +247,14 @@ __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
     const bool active = grp_ok && in_horizon(x, y, n_pix);
     float *s = spec + wave * n_chan;
     unsigned *hist = hist_all[wave];
-    auto key_x = [&](int i) { return fkey(s[i]); };
-    const float med = wave_median(key_x, n_chan, hist, lane);
+    float *pool = pool_all[wave];
+    auto val_x = [&](int i) { return s[i]; };
+    const float med = wave_median(val_x, n_chan, n_chan, hist, pool, lane);
     float scale = 1.f;  // SNR = (x - med) / scale
     bool ok = active;
     if (mode == NBSI_DETECT_PER_PIXEL) {
-        auto key_d = [&](int i) { return fkey(fabsf(s[i] - med)); };
-        const float mad = wave_median(key_d, n_chan, hist, lane);
+        auto val_d = [&](int i) { return fabsf(s[i] - med); };
+        const float mad = wave_median(val_d, n_chan, n_chan, hist, pool, lane);
         scale = MAD_K * mad;
         ok = ok && mad > 0.f;
     }
@@ -189,56 +281,24 @@ __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
     }
 }
 
-// Per-channel median and k*MAD over the visible hemisphere (PER_IMAGE mode).
+// Per-channel median and k*MAD over the visible hemisphere (PER_IMAGE mode); pixels outside
+// the hemisphere read as NaN and are ignored by the selection.
 __global__ __launch_bounds__(64) void image_stats_kernel(const float *__restrict__ img, int n_pix,
                                                          float2 *__restrict__ stats) {
     __shared__ unsigned hist[256];
+    __shared__ float pool[64];
     const int c = blockIdx.x, lane = threadIdx.x;
     const float *im = img + (size_t)c * n_pix * n_pix;
-    int n_in = 0;
-    for (int i = lane; i < n_pix * n_pix; i += 64) n_in += in_horizon(i % n_pix, i / n_pix, n_pix);
-    n_in = wave_sum(n_in);
-    // scan the full image; pixels outside the hemisphere get the largest key
     const int n_all = n_pix * n_pix;
-    auto key_x = [&](int i) -> unsigned {
-        const int y = i / n_pix, x = i % n_pix;
-        return in_horizon(x, y, n_pix) ? fkey(im[i]) : 0xffffffffu;
+    int n_in = 0;
+    for (int i = lane; i < n_all; i += 64) n_in += in_horizon(i % n_pix, i / n_pix, n_pix);
+    n_in = wave_sum(n_in);
+    auto val_x = [&](int i) -> float { return in_horizon(i % n_pix, i / n_pix, n_pix) ? im[i] : NAN; };
+    const float med = wave_median(val_x, n_all, n_in, hist, pool, lane);
+    auto val_d = [&](int i) -> float {
+        return in_horizon(i % n_pix, i / n_pix, n_pix) ? fabsf(im[i] - med) : NAN;
     };
-    // the n_in smallest keys are exactly the in-horizon pixels
-    const unsigned klo = wave_select(key_x, n_all, (n_in - 1) / 2, hist, lane);
-    float med;
-    {
-        int le = 0;
-        unsigned nxt = 0xffffffffu;
-        for (int i = lane; i < n_all; i += 64) {
-            const unsigned key = key_x(i);
-            le += key <= klo;
-            if (key > klo) nxt = min(nxt, key);
-        }
-        le = wave_sum(le);
-        nxt = wave_min_u(nxt);
-        const unsigned khi = (n_in & 1) ? klo : ((le >= n_in / 2 + 1) ? klo : nxt);
-        med = 0.5f * (funkey(klo) + funkey(khi));
-    }
-    auto key_d = [&](int i) -> unsigned {
-        const int y = i / n_pix, x = i % n_pix;
-        return in_horizon(x, y, n_pix) ? fkey(fabsf(im[i] - med)) : 0xffffffffu;
-    };
-    const unsigned dlo = wave_select(key_d, n_all, (n_in - 1) / 2, hist, lane);
-    float mad;
-    {
-        int le = 0;
-        unsigned nxt = 0xffffffffu;
-        for (int i = lane; i < n_all; i += 64) {
-            const unsigned key = key_d(i);
-            le += key <= dlo;
-            if (key > dlo) nxt = min(nxt, key);
-        }
-        le = wave_sum(le);
-        nxt = wave_min_u(nxt);
-        const unsigned dhi = (n_in & 1) ? dlo : ((le >= n_in / 2 + 1) ? dlo : nxt);
-        mad = 0.5f * (funkey(dlo) + funkey(dhi));
-    }
+    const float mad = wave_median(val_d, n_all, n_in, hist, pool, lane);
     if (lane == 0) stats[c] = make_float2(med, MAD_K * mad);
 }
 

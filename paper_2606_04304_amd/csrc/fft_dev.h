@@ -142,6 +142,11 @@ __device__ __forceinline__ void stockham_regs(float2 *v, int t, int nt, int log_
     (void)log_l;
 }
 
+// LDS layout of transform buffers: one pad element after every 32, so the strided Stockham
+// writes (stride = ns * R elements) spread over the 64 LDS banks instead of piling onto a few.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int padded_size(int n) { return n + n / 32; }
+
 // Write the pass outputs of stockham_regs to LDS (row of length L starting at buf).
 template <int R, int E>
 __device__ __forceinline__ void stockham_store(float2 *buf, const float2 *v, int t, int nt, int ns) {
@@ -150,7 +155,7 @@ __device__ __forceinline__ void stockham_store(float2 *buf, const float2 *v, int
         const int j = t + nt * b;
         const int base = (j / ns) * ns * R + (j & (ns - 1));
 #pragma unroll
-        for (int r = 0; r < R; r++) buf[base + r * ns] = v[b * R + r];
+        for (int r = 0; r < R; r++) buf[pidx(base + r * ns)] = v[b * R + r];
     }
 }
 
@@ -162,6 +167,6 @@ __device__ __forceinline__ void stockham_load(const float2 *buf, float2 *v, int 
     for (int b = 0; b < E / R; b++) {
         const int j = t + nt * b;
 #pragma unroll
-        for (int r = 0; r < R; r++) v[b * R + r] = buf[j + r * stride];
+        for (int r = 0; r < R; r++) v[b * R + r] = buf[pidx(j + r * stride)];
     }
 }

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void dft_kernel(const VT *__restrict__ vis, co
 
 // ---- gridding ----
 constexpr int GE = 32;                 // complex values per thread in the banded FFTs
-constexpr int GRID_CELLS = 256 * GE;   // LDS grid cells per workgroup (64 KB)
+constexpr int GRID_CELLS = 256 * GE;   // grid cells per workgroup (64 KB, 66 KB padded)
 constexpr float ES_BETA = 2.30f * 8.0f;
 
 __device__ __forceinline__ float es_kernel(float z) {
@@ -180,13 +180,14 @@ __device__ __forceinline__ float2 grid_product(float2 val, float wu, float wv) {
     }
 }
 
-// Batched Stockham FFT over `nrows` rows of length 2^log_l stored row-major in LDS (nrows *
-// 2^log_l == 256 * GE).  Radix-16 passes, with one smaller first pass when log_l % 4 != 0.
+// Batched Stockham FFT over rows of length 2^log_l stored row-major in LDS (padded layout,
+// see pidx), 256 * GE elements in all.  Radix-16 passes, with one smaller first pass when
+// log_l % 4 != 0.
 template <int R, int E>
 __device__ __forceinline__ void batched_pass(float2 *buf, int t, int log_l, int ns, const TwiddleTable &tw,
                                              int log_tab) {
     const int L = 1 << log_l;
-    const int log_r = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
+    constexpr int log_r = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
     const int per_row = L / R;  // butterflies per row
     float2 v[E];
 #pragma unroll
@@ -194,7 +195,7 @@ __device__ __forceinline__ void batched_pass(float2 *buf, int t, int log_l, int 
         const int g = t + 256 * b;
         const int row = g >> (log_l - log_r), j = g & (per_row - 1);
 #pragma unroll
-        for (int r = 0; r < R; r++) v[b * R + r] = buf[row * L + j + r * per_row];
+        for (int r = 0; r < R; r++) v[b * R + r] = buf[pidx(row * L + j + r * per_row)];
     }
     __syncthreads();
 #pragma unroll
@@ -204,13 +205,18 @@ __device__ __forceinline__ void batched_pass(float2 *buf, int t, int log_l, int 
         const int k = j & (ns - 1);
         if (ns > 1) {
             const int sh = log_tab - (31 - __clz(ns * R));
+            const float2 w = tw(k << sh);
+            float2 cur = w;
 #pragma unroll
-            for (int r = 1; r < R; r++) v[b * R + r] = cmul(v[b * R + r], tw((k * r) << sh));
+            for (int r = 1; r < R; r++) {
+                v[b * R + r] = cmul(v[b * R + r], cur);
+                cur = cmul(cur, w);
+            }
         }
         dft_r<R>(v + b * R);
-        const int base = row * L + (j / ns) * ns * R + k;
+        const int base = row * L + ((j >> (31 - __clz(ns))) << (31 - __clz(ns * R))) + k;
 #pragma unroll
-        for (int r = 0; r < R; r++) buf[base + r * ns] = v[b * R + r];
+        for (int r = 0; r < R; r++) buf[pidx(base + r * ns)] = v[b * R + r];
     }
     __syncthreads();
 }
@@ -227,96 +233,179 @@ __device__ __forceinline__ void batched_fft(float2 *buf, int t, int log_l, const
     }
 }
 
-template <typename VT, int PREC>
+// Stokes I of every candidate pair of every channel of a chunk, 0 outside the imaged set B:
+// the scattered visibility reads happen here, with one thread per (channel, pair).
+template <typename VT>
+__global__ __launch_bounds__(256) void stokes_gather_kernel(const VT *__restrict__ vis, const double *__restrict__ xyz,
+                                                            const double *__restrict__ freq, const int2 *__restrict__ pairs,
+                                                            int n_pairs, int n_ant, int grid_n_pix, double uv_min,
+                                                            double uv_max, float2 *__restrict__ cvis) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (k >= n_pairs) return;
+    const int2 p = pairs[k];
+    const size_t nprod = (size_t)(2 * n_ant) * (2 * n_ant + 1) / 2;
+    const bool ok = in_set(baseline_uv(xyz, p.x, p.y, freq[c]), grid_n_pix, uv_min, uv_max);
+    cvis[(size_t)c * n_pairs + k] = ok ? stokes_i<VT>(vis + (size_t)c * nprod, p.x, p.y) : make_float2(0.f, 0.f);
+}
+
+// Gridding without atomics: every thread owns a fixed rectangle of 32 grid cells of the band
+// (CPT consecutive columns x RPT rows) and sums the contributions of the baselines whose
+// 8 x 8 kernel footprint covers it.  The band's baselines are sorted by x separation, hence
+// by grid column for every channel (u is proportional to dx), and are staged in LDS with
+// their 8 + 8 kernel weights, so a thread finds its few baselines by binary search.  The sum
+// order is fixed, so the result is deterministic.
+constexpr int STAGE_CAP = 768;  // baselines staged per round (reuses the grid's LDS)
+
+template <int LOGM, int PREC>
 __global__ __launch_bounds__(256) void grid_rows_kernel(
-    const VT *__restrict__ vis, const double *__restrict__ xyz, const double *__restrict__ freq,
-    const int2 *__restrict__ pairs, const int *__restrict__ band_off, const int *__restrict__ band_items,
-    int n_ant, int n_pix, int log_m, int band_rows, double uv_min, double uv_max, float2 *__restrict__ inter) {
-    __shared__ float2 grid[GRID_CELLS];
+    const float2 *__restrict__ cvis, const double2 *__restrict__ dxy, const double *__restrict__ freq,
+    const int *__restrict__ band_off, const int *__restrict__ band_items, int n_pairs, int n_pix,
+    float2 *__restrict__ inter) {
+    constexpr int M = 1 << LOGM;
+    constexpr int R = GRID_CELLS / M;               // band rows
+    constexpr int CPT = (M >= 256) ? M / 256 : 1;   // owned columns per thread
+    constexpr int COLT = M / CPT;                   // threads across the columns
+    constexpr int RPT = R / (256 / COLT);           // owned rows per thread
+    static_assert(CPT * RPT == GE, "32 cells per thread");
+    __shared__ float2 grid[padded_size(GRID_CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
     __shared__ float vscale;
+    // staging view of the grid's LDS: gu0, gv0 (int), value (float2), wu[8], wv[8] (float)
+    int *s_gu = reinterpret_cast<int *>(grid);
+    int *s_gv = s_gu + STAGE_CAP;
+    float2 *s_val = reinterpret_cast<float2 *>(s_gv + STAGE_CAP);
+    float *s_wu = reinterpret_cast<float *>(s_val + STAGE_CAP);
+    float *s_wv = s_wu + 8 * STAGE_CAP;
+
     const int band = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
-    const int M = 1 << log_m;
-    const int row0 = band * band_rows;
-    const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_m, t, 256);
-    float *gf = reinterpret_cast<float *>(grid);
-    for (int e = t; e < GRID_CELLS; e += 256) grid[e] = make_float2(0.f, 0.f);
-    const size_t nprod = (size_t)(2 * n_ant) * (2 * n_ant + 1) / 2;
-    const VT *vc = vis + (size_t)c * nprod;
-    const double nu = freq[c];
+    const int row0 = band * R;
+    const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, LOGM, t, 256);
+    const float2 *cv_c = cvis + (size_t)c * n_pairs;
     const int k_begin = band_off[band], k_end = band_off[band + 1];
     if constexpr (PREC == NBSI_PREC_FP16) {
         // Scale this workgroup's visibilities by a power of two so the largest |V_I| it grids
         // maps below 2^14: every FP16 product (kernel weights <= 1) stays finite.
-        __shared__ float red[256];
         float mx = 0.f;
-        for (int k = k_begin + t; k < k_end; k += 256) {
-            const int2 p = pairs[band_items[k]];
-            if (!in_set(baseline_uv(xyz, p.x, p.y, nu), n_pix, uv_min, uv_max)) continue;
-            const float2 val = stokes_i<VT>(vc, p.x, p.y);
+        for (int i = k_begin + t; i < k_end; i += 256) {
+            const float2 val = cv_c[band_items[i]];
             mx = fmaxf(mx, fmaxf(fabsf(val.x), fabsf(val.y)));
         }
-        red[t] = mx;
+        reinterpret_cast<float *>(grid)[t] = mx;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
-            if (t < s) red[t] = fmaxf(red[t], red[t + s]);
+            if (t < s) reinterpret_cast<float *>(grid)[t] = fmaxf(reinterpret_cast<float *>(grid)[t],
+                                                                  reinterpret_cast<float *>(grid)[t + s]);
             __syncthreads();
         }
         if (t == 0) {
             int e2 = 0;
-            frexpf(fmaxf(red[0], 1e-30f), &e2);
+            frexpf(fmaxf(reinterpret_cast<float *>(grid)[0], 1e-30f), &e2);
             vscale = ldexpf(1.f, 14 - e2);
         }
+        __syncthreads();
     }
-    __syncthreads();
-    // 8 threads per baseline: thread tap = t % 8 handles grid column floor(cu) - 3 + tap
-    for (int k = k_begin + t / 8; k < k_end; k += 32) {
-        const int2 p = pairs[band_items[k]];
-        const UV w = baseline_uv(xyz, p.x, p.y, nu);
-        if (!in_set(w, n_pix, uv_min, uv_max)) continue;
-        float2 val = stokes_i<VT>(vc, p.x, p.y);
-        if constexpr (PREC == NBSI_PREC_FP16) val = make_float2(val.x * vscale, val.y * vscale);
-        const double cu = w.u * 4.0 + (double)(M / 2), cv = w.v * 4.0 + (double)(M / 2);
-        const double fu = floor(cu), fv = floor(cv);
-        const int tap = t & 7;
-        const int gu = (int)fu - 3 + tap;
-        const float wu = es_kernel((float)((double)gu - cu) * 0.25f);
+    const int col0 = (t % COLT) * CPT;
+    const int rown = (t / COLT) * RPT;  // first owned row within the band
+    float2 acc[CPT][RPT];
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
-            const int gv = (int)fv - 3 + j;
-            const int lr = gv - row0;
-            if (lr < 0 || lr >= band_rows) continue;
-            const float wv = es_kernel((float)((double)gv - cv) * 0.25f);
-            const float2 add = grid_product<PREC>(val, wu, wv);
-            atomicAdd(&gf[2 * (lr * M + gu)], add.x);
-            atomicAdd(&gf[2 * (lr * M + gu) + 1], add.y);
+    for (int q = 0; q < CPT; q++)
+#pragma unroll
+        for (int r = 0; r < RPT; r++) acc[q][r] = make_float2(0.f, 0.f);
+
+    // grid position u / du + M/2 with du = 1/4 wavelength (the membership of B was decided by
+    // the gather kernel; baselines outside B carry a zero value)
+    const double sc = freq[c] / C_LIGHT * 4.0;
+    for (int k0 = k_begin; k0 < k_end; k0 += STAGE_CAP) {
+        const int nk = min(STAGE_CAP, k_end - k0);
+        __syncthreads();
+        for (int i = t; i < nk; i += 256) {
+            const int k = band_items[k0 + i];
+            float2 val = cv_c[k];
+            if constexpr (PREC == NBSI_PREC_FP16) val = make_float2(val.x * vscale, val.y * vscale);
+            const double2 d = dxy[k];
+            const double cu = d.x * sc + (double)(M / 2), cvv = d.y * sc + (double)(M / 2);
+            const double fu = floor(cu), fv = floor(cvv);
+            const float ou = (float)(cu - fu), ov = (float)(cvv - fv);  // in [0, 1)
+            s_gu[i] = (int)fu - 3;
+            s_gv[i] = (int)fv - 3;
+            s_val[i] = val;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                s_wu[8 * i + j] = es_kernel(((float)(j - 3) - ou) * 0.25f);
+                s_wv[8 * i + j] = es_kernel(((float)(j - 3) - ov) * 0.25f);
+            }
+        }
+        __syncthreads();
+        // first staged baseline whose footprint can reach column col0: gu0 >= col0 - 7
+        int lo = 0, hi = nk;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_gu[mid] < col0 - 7) lo = mid + 1;
+            else hi = mid;
+        }
+        for (int i = lo; i < nk; i++) {
+            const int gu0 = s_gu[i];
+            if (gu0 > col0 + CPT - 1) break;
+            const int dr0 = row0 + rown - s_gv[i];  // owned row r sits at footprint row dr0 + r
+            if (dr0 + RPT <= 0 || dr0 >= 8) continue;
+            const float2 val = s_val[i];
+#pragma unroll
+            for (int q = 0; q < CPT; q++) {
+                const int dq = col0 + q - gu0;
+                if (dq < 0 || dq >= 8) continue;
+                const float wu = s_wu[8 * i + dq];
+#pragma unroll
+                for (int r = 0; r < RPT; r++) {
+                    const int dr = dr0 + r;
+                    if (dr >= 0 && dr < 8) {
+                        const float2 add = grid_product<PREC>(val, wu, s_wv[8 * i + dr]);
+                        acc[q][r] = cadd(acc[q][r], add);
+                    }
+                }
+            }
         }
     }
     __syncthreads();
-    batched_fft(grid, t, log_m, tw, log_m);
+#pragma unroll
+    for (int q = 0; q < CPT; q++)
+#pragma unroll
+        for (int r = 0; r < RPT; r++) grid[pidx((rown + r) * M + col0 + q)] = acc[q][r];
+    __syncthreads();
+    batched_fft(grid, t, LOGM, tw, LOGM);
     // keep image columns x: FFT index (x - n/2) mod M, times (-1)^(x - n/2); undo the FP16 scale
     const float unscale = (PREC == NBSI_PREC_FP16) ? 1.f / vscale : 1.f;
-    for (int e = t; e < n_pix * band_rows; e += 256) {
-        const int lr = e % band_rows, x = e / band_rows;
+    constexpr int half = R / 2;  // two rows per float4 store
+    for (int e = t; e < n_pix * half; e += 256) {
+        const int lr = 2 * (e % half), x = e / half;
         const int xp = x - n_pix / 2;
-        const float2 f = grid[lr * M + (xp & (M - 1))];
+        const int col = xp & (M - 1);
         const float sgn = (xp & 1) ? -unscale : unscale;
-        inter[((size_t)c * n_pix + x) * M + row0 + lr] = make_float2(f.x * sgn, f.y * sgn);
+        const float2 f0 = grid[pidx(lr * M + col)], f1 = grid[pidx((lr + 1) * M + col)];
+        float4 o = make_float4(f0.x * sgn, f0.y * sgn, f1.x * sgn, f1.y * sgn);
+        *reinterpret_cast<float4 *>(inter + ((size_t)c * n_pix + x) * M + row0 + lr) = o;
     }
 }
 
 __global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict__ inter, int n_pix, int log_m,
                                                         int band_cols, const float *__restrict__ corr,
                                                         const int *__restrict__ nb, float *__restrict__ img) {
-    __shared__ float2 buf[GRID_CELLS];
+    __shared__ float2 buf[padded_size(GRID_CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
     const int xb = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
     const int M = 1 << log_m;
     const int x0 = xb * band_cols;
     const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_m, t, 256);
-    for (int e = t; e < band_cols * M; e += 256) {
-        const int xl = e / M, g = e % M;
-        buf[e] = inter[((size_t)c * n_pix + x0 + xl) * M + g];
+    // the band's columns are contiguous in the intermediate: 16 float4 loads per thread in flight
+    const float4 *src = reinterpret_cast<const float4 *>(inter + ((size_t)c * n_pix + x0) * M);
+    float4 r[GRID_CELLS / 2 / 256];
+#pragma unroll
+    for (int q = 0; q < GRID_CELLS / 2 / 256; q++) r[q] = src[t + 256 * q];
+#pragma unroll
+    for (int q = 0; q < GRID_CELLS / 2 / 256; q++) {
+        const int e = 2 * (t + 256 * q);  // two consecutive elements never straddle a pad
+        buf[pidx(e)] = make_float2(r[q].x, r[q].y);
+        buf[pidx(e + 1)] = make_float2(r[q].z, r[q].w);
     }
     __syncthreads();
     batched_fft(buf, t, log_m, tw, log_m);
@@ -325,7 +414,7 @@ __global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict
     for (int e = t; e < n_pix * band_cols; e += 256) {
         const int xl = e % band_cols, y = e / band_cols;
         const int yp = y - n_pix / 2;
-        const float2 f = buf[xl * M + (yp & (M - 1))];
+        const float2 f = buf[pidx(xl * M + (yp & (M - 1)))];
         const float sgn = (yp & 1) ? -1.f : 1.f;
         img[((size_t)c * n_pix + y) * n_pix + x0 + xl] = f.x * sgn * corr[x0 + xl] * corr[y] * inv;
     }
@@ -353,28 +442,35 @@ hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_d
     return hipGetLastError();
 }
 
-template <typename VT, int PREC>
-static void launch_rows(const nbsi_image_plan *p, const VT *vis, float2 *inter, int log_m, hipStream_t st) {
-    hipLaunchKernelGGL((grid_rows_kernel<VT, PREC>), dim3(p->n_bands, p->n_chan), dim3(256), 0, st, vis,
-                       p->d_xyz, p->d_freq, p->d_pairs, p->d_band_off, p->d_band_items, p->n_ant, p->n_pix,
-                       log_m, p->band_rows, p->uv_min, p->uv_max, inter);
-}
-
 hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype, int precision,
-                             float2 *inter, float *img, hipStream_t st) {
+                             float2 *cvis, float2 *inter, float *img, hipStream_t st) {
     const int M = 2 * p->n_pix;
     const int log_m = 31 - __builtin_clz(M);
-    if (vis_dtype == NBSI_VIS_I32) {
-        const int2 *v = (const int2 *)vis;
-        if (precision == NBSI_PREC_FP16) launch_rows<int2, NBSI_PREC_FP16>(p, v, inter, log_m, st);
-        else if (precision == NBSI_PREC_BF16) launch_rows<int2, NBSI_PREC_BF16>(p, v, inter, log_m, st);
-        else launch_rows<int2, NBSI_PREC_FP32>(p, v, inter, log_m, st);
-    } else {
-        const float2 *v = (const float2 *)vis;
-        if (precision == NBSI_PREC_FP16) launch_rows<float2, NBSI_PREC_FP16>(p, v, inter, log_m, st);
-        else if (precision == NBSI_PREC_BF16) launch_rows<float2, NBSI_PREC_BF16>(p, v, inter, log_m, st);
-        else launch_rows<float2, NBSI_PREC_FP32>(p, v, inter, log_m, st);
+    dim3 gg((p->n_pairs + 255) / 256, p->n_chan);
+    if (vis_dtype == NBSI_VIS_I32)
+        hipLaunchKernelGGL(stokes_gather_kernel<int2>, gg, dim3(256), 0, st, (const int2 *)vis, p->d_xyz, p->d_freq,
+                           p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, cvis);
+    else
+        hipLaunchKernelGGL(stokes_gather_kernel<float2>, gg, dim3(256), 0, st, (const float2 *)vis, p->d_xyz,
+                           p->d_freq, p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, cvis);
+    dim3 gr(p->n_bands, p->n_chan);
+#define NBSI_ROWS(LM, PR)                                                                                  \
+    hipLaunchKernelGGL((grid_rows_kernel<LM, PR>), gr, dim3(256), 0, st, cvis, p->d_dxy, p->d_freq,          \
+                       p->d_band_off, p->d_band_items, p->n_pairs, p->n_pix, inter)
+#define NBSI_ROWS_P(LM)                                                        \
+    if (precision == NBSI_PREC_FP16) NBSI_ROWS(LM, NBSI_PREC_FP16);             \
+    else if (precision == NBSI_PREC_BF16) NBSI_ROWS(LM, NBSI_PREC_BF16);        \
+    else NBSI_ROWS(LM, NBSI_PREC_FP32)
+    switch (log_m) {
+        case 7: NBSI_ROWS_P(7); break;
+        case 8: NBSI_ROWS_P(8); break;
+        case 9: NBSI_ROWS_P(9); break;
+        case 10: NBSI_ROWS_P(10); break;
+        case 11: NBSI_ROWS_P(11); break;
+        default: return hipErrorInvalidValue;
     }
+#undef NBSI_ROWS_P
+#undef NBSI_ROWS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int band_cols = GRID_CELLS / M;

@@ -39,6 +39,7 @@ struct nbsi_image_plan {
     double *d_freq = nullptr;     // [n_chan]
     int *d_nb = nullptr;          // [n_chan] |B| per channel
     int2 *d_pairs = nullptr;      // candidate pairs (a, b), a > b
+    double2 *d_dxy = nullptr;     // (x_a - x_b, y_a - y_b) metres of each candidate pair
     int n_pairs = 0;
     // gridding: candidate pairs binned by bands of grid rows (CSR over bands)
     int band_rows = 0, n_bands = 0;
@@ -76,7 +77,7 @@ hipError_t launch_image_count(const nbsi_image_plan *p, hipStream_t st);
 hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_dtype, float *img,
                             hipStream_t st);
 hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype,
-                             int precision, float2 *inter, float *img, hipStream_t st);
+                             int precision, float2 *cvis, float2 *inter, float *img, hipStream_t st);
 hipError_t launch_detect_stats(const float *img, int n_chan, int n_pix, int mode, float *stats,
                                hipStream_t st);
 hipError_t launch_detect_scan(const float *img, int n_chan, int n_pix, int mode,
