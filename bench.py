@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-path", action="store_true")
     ap.add_argument("--stages", default="all", help="profiling aid: all | correlate")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -158,6 +160,16 @@ def main():
         nb.nbsi_correlate(spec_q, vis=vis, ctx=ctx)
         if ev is not None:
             ev[1].record()
+
+    if args.calibrate:
+        # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy calibration done (3 x 1 GiB)")
 
     run = step if args.stages == "all" else corr_only
     n_ev = 5 if args.stages == "all" else 2

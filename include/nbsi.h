@@ -180,6 +180,46 @@ int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int 
 int nbsi_detect(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode, float thresh,
                 float *snr, nbsi_cand *out, int max_out, int *n_out);
 
+/*
+ * Batched sub-bands (Sec. 2.1: the band is processed as independent batches of fine channels;
+ * Sec. 2.6: re-processing with other FFT lengths and integrations).  Each sub-band is one coarse
+ * channel's voltages with its own FFT length, integration count, kept channels and image size;
+ * nbsi_batch_run channelizes, correlates and images all of them (each stage one persistent launch
+ * over a task table spanning the sub-bands, grouped only where kernel shapes differ), with the
+ * same results as the per-sub-band calls above (bit-identical spectra, visibilities and images).
+ */
+typedef struct {
+    const int8_t *volt;          /* [n_in][n_spec * n_fft][2] int8, n_in = 2 n_ant */
+    const float *gain;           /* [n_in] requantisation gains */
+    int n_fft, n_spec, chan0, n_chan;
+    const double *freq_hz_host;  /* [n_chan] sky frequency of each kept channel (host) */
+    int n_pix;                   /* image size (NBSI_IMAGE_GRID) */
+    int8_t *spec_q;              /* out [n_chan][n_in][2][n_spec] */
+    int32_t *vis;                /* out [n_chan][n_in (n_in+1)/2][2] */
+    float *img;                  /* out [n_chan][n_pix][n_pix] */
+} nbsi_subband;
+
+typedef struct nbsi_batch nbsi_batch;
+
+#define NBSI_BATCH_GRAPH 1     /* capture the launches into a hipGraph on the first run, replay after */
+#define NBSI_BATCH_AUTOTUNE 2  /* time correlator variants and gridding tiles per shape at plan time */
+#define NBSI_BATCH_GRID_TALL 4 /* grid with the 32-cell-per-thread tile everywhere (no gridding tuning) */
+
+/*
+ * Plan a batch: validates every sub-band, builds its imaging plan, allocates the batch's
+ * scratch (staging, Stokes-I gathers, row-transform intermediates; kept until destroy) and the
+ * task tables.  With NBSI_BATCH_AUTOTUNE the plan runs the stages once to time the candidates
+ * (this writes the sub-bands' outputs); choices are read from and added to the text file
+ * tune_cache_path (may be NULL).  The batch runs on its own stream, ordered after and before the
+ * context's stream with events.  Not thread-safe; one batch at a time per context.
+ */
+int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const nbsi_subband *sb, int n_sb,
+                    int precision, int flags, const char *tune_cache_path, nbsi_batch **plan);
+int nbsi_batch_run(nbsi_batch *plan);
+/* JSON text of the per-sub-band choices (correlator variant, gridding tile) into buf[len]. */
+int nbsi_batch_describe(const nbsi_batch *plan, char *buf, int len);
+int nbsi_batch_destroy(nbsi_batch *plan);
+
 #ifdef __cplusplus
 }
 #endif

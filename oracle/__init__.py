@@ -46,6 +46,7 @@ def lib():
         L.orc_correlate.argtypes = [P, i32, i32, i32, P]
         L.orc_count_baselines.argtypes = [i32, i32, P, P, i32, f64, f64, P]
         L.orc_image_dft.argtypes = [P, i32, i32, P, P, i32, i32, f64, f64, P]
+        L.orc_image_dft_pixels.argtypes = [P, i32, i32, P, P, i32, i32, f64, f64, P, i32, P]
         L.orc_set_threads.argtypes = [i32]
         L.orc_num_threads.restype = i32
         _lib = L
@@ -144,6 +145,22 @@ def image_dft(vis: np.ndarray, ant_xyz, freq, n_pix: int, grid_n_pix: int = 0,
     if rc != 0:
         raise MemoryError("orc_image_dft failed")
     return img
+
+
+def image_dft_pixels(vis: np.ndarray, ant_xyz, freq, n_pix: int, pix_xy, grid_n_pix: int = 0,
+                     uv_min: float = 0.0, uv_max: float = np.inf) -> np.ndarray:
+    """The direct Fourier image at the listed pixels only: pix_xy [n][2] (x, y) -> [n_chan][n]."""
+    v = np.ascontiguousarray(vis, dtype=np.float64)
+    xyz = np.ascontiguousarray(ant_xyz, dtype=np.float64)
+    f = np.ascontiguousarray(freq, dtype=np.float64)
+    pix = np.ascontiguousarray(pix_xy, dtype=np.int32)
+    out = np.empty((v.shape[0], pix.shape[0]), dtype=np.float64)
+    rc = lib().orc_image_dft_pixels(_p(v), v.shape[0], xyz.shape[0], _p(xyz), _p(f), n_pix,
+                                    int(grid_n_pix), float(uv_min), float(uv_max), _p(pix),
+                                    pix.shape[0], _p(out))
+    if rc != 0:
+        raise MemoryError("orc_image_dft_pixels failed")
+    return out
 
 
 def tri_index(i, j):

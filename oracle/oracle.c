@@ -303,3 +303,59 @@ int orc_image_dft(const double *vis, int n_chan, int n_ant, const double *xyz, c
     free(bu); free(bv); free(vr); free(vi);
     return 0;
 }
+
+/*
+ * The same direct Fourier sum evaluated only at a list of pixels (x, y) (for spot checks of
+ * large images): out [n_chan][n_list].
+ */
+int orc_image_dft_pixels(const double *vis, int n_chan, int n_ant, const double *xyz,
+                         const double *freq, int n_pix, int grid_n_pix, double uv_min,
+                         double uv_max, const int32_t *pix_xy, int n_list, double *out) {
+    const int n_in = 2 * n_ant;
+    const long nprod = (long)n_in * (n_in + 1) / 2;
+    const long nbl = (long)n_ant * (n_ant - 1) / 2;
+    int err = 0;
+#pragma omp parallel for schedule(dynamic)
+    for (int c = 0; c < n_chan; c++) {
+        double *bu = (double *)malloc(sizeof(double) * nbl);
+        double *bv = (double *)malloc(sizeof(double) * nbl);
+        double *vr = (double *)malloc(sizeof(double) * nbl);
+        double *vi = (double *)malloc(sizeof(double) * nbl);
+        if (!bu || !bv || !vr || !vi) {
+            free(bu); free(bv); free(vr); free(vi);
+#pragma omp atomic write
+            err = -2;
+            continue;
+        }
+        const double *vc = vis + (long)c * nprod * 2;
+        long nb = 0;
+        for (int a = 0; a < n_ant; a++)
+            for (int b = 0; b < a; b++) {
+                double u, v;
+                baseline_uv(xyz, a, b, freq[c], &u, &v);
+                if (!in_set(u, v, grid_n_pix, uv_min, uv_max)) continue;
+                long txx = (long)(2 * a) * (2 * a + 1) / 2 + 2 * b;
+                long tyy = (long)(2 * a + 1) * (2 * a + 2) / 2 + 2 * b + 1;
+                bu[nb] = u;
+                bv[nb] = v;
+                vr[nb] = 0.5 * (vc[2 * txx] + vc[2 * tyy]);
+                vi[nb] = 0.5 * (vc[2 * txx + 1] + vc[2 * tyy + 1]);
+                nb++;
+            }
+        for (int q = 0; q < n_list; q++) {
+            int x = pix_xy[2 * q], y = pix_xy[2 * q + 1];
+            double l = (x - n_pix / 2) * (2.0 / n_pix);
+            double m = (y - n_pix / 2) * (2.0 / n_pix);
+            double acc = 0.0;
+            for (long b = 0; b < nb; b++) {
+                double turns = bu[b] * l + bv[b] * m;
+                double frac = turns - floor(turns);
+                double th = ORC_TWO_PI * frac;
+                acc += vr[b] * cos(th) + vi[b] * sin(th);
+            }
+            out[(long)c * n_list + q] = nb > 0 ? acc / (double)nb : 0.0;
+        }
+        free(bu); free(bv); free(vr); free(vi);
+    }
+    return err;
+}

@@ -38,8 +38,12 @@ EXPORTS = [
     "nbsi_last_error", "nbsi_synchronize", "nbsi_check_channelize", "nbsi_check_correlate",
     "nbsi_check_image", "nbsi_check_detect", "nbsi_channelize", "nbsi_correlate",
     "nbsi_correlate_f32", "nbsi_image_plan_create", "nbsi_image_plan_destroy",
-    "nbsi_image_plan_nbase", "nbsi_image", "nbsi_detect",
+    "nbsi_image_plan_nbase", "nbsi_image", "nbsi_detect", "nbsi_batch_plan", "nbsi_batch_run",
+    "nbsi_batch_describe", "nbsi_batch_destroy",
 ]
+NBSI_BATCH_GRAPH = 1
+NBSI_BATCH_AUTOTUNE = 2
+NBSI_BATCH_GRID_TALL = 4
 
 CAND_DTYPE = np.dtype([("x", np.int32), ("y", np.int32), ("c", np.int32), ("width", np.int32),
                        ("snr", np.float32)])
@@ -85,6 +89,10 @@ def lib():
         L.nbsi_image_plan_nbase.argtypes = [P, P]
         L.nbsi_image.argtypes = [P, P, P, I, I, P]
         L.nbsi_detect.argtypes = [P, P, I, I, I, ctypes.c_float, P, P, I, P]
+        L.nbsi_batch_plan.argtypes = [P, P, I, P, I, I, I, ctypes.c_char_p, ctypes.POINTER(P)]
+        L.nbsi_batch_run.argtypes = [P]
+        L.nbsi_batch_describe.argtypes = [P, ctypes.c_char_p, I]
+        L.nbsi_batch_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -276,3 +284,100 @@ def nbsi_detect(img, mode: int = NBSI_DETECT_PER_PIXEL, thresh: float = 5.0, wan
     n = min(n_out.value, max_out)
     rec = out[:n].cpu().numpy().view(CAND_DTYPE).reshape(-1)
     return rec, snr, n_out.value
+
+
+class NbsiSubband(ctypes.Structure):
+    """nbsi_subband: one sub-band of a batch (device pointers, host frequency list)."""
+    _fields_ = [("volt", ctypes.c_void_p), ("gain", ctypes.c_void_p), ("n_fft", ctypes.c_int),
+                ("n_spec", ctypes.c_int), ("chan0", ctypes.c_int), ("n_chan", ctypes.c_int),
+                ("freq_hz_host", ctypes.c_void_p), ("n_pix", ctypes.c_int), ("spec_q", ctypes.c_void_p),
+                ("vis", ctypes.c_void_p), ("img", ctypes.c_void_p)]
+
+
+class Batch:
+    """nbsi_batch_plan / run / describe / destroy.
+
+    subbands: list of dicts with volt [n_in][n_spec*n_fft][2] int8 and gain [n_in] float32 device
+    tensors, n_fft, n_spec, chan0, n_chan, freq_hz (host array of n_chan) and n_pix.  The output
+    tensors spec_q, vis and img are allocated here (or taken from the dict) and kept on the
+    object; every run() rewrites them."""
+
+    def __init__(self, ant_xyz, subbands, precision: int = NBSI_PREC_FP32, graph: bool = True,
+                 autotune: bool = False, tune_cache: str | None = None, ctx: Context | None = None,
+                 grid_tall: bool = False):
+        torch = _torch()
+        self.ctx = ctx or nbsi_create(0)
+        dev = self.ctx.device
+        self.ant_xyz = np.ascontiguousarray(ant_xyz, dtype=np.float64)
+        n_ant = self.ant_xyz.shape[0]
+        n_in = 2 * n_ant
+        self.subbands = []
+        arr = (NbsiSubband * len(subbands))()
+        for i, sbd in enumerate(subbands):
+            d = dict(sbd)
+            _need(d["volt"], torch.int8, "volt", dev)
+            _need(d["gain"], torch.float32, "gain", dev)
+            if d["volt"].shape[0] != n_in or d["gain"].numel() != n_in:
+                raise ValueError(f"sub-band {i}: volt/gain do not have 2 n_ant = {n_in} inputs")
+            C, T, n_pix = int(d["n_chan"]), int(d["n_spec"]), int(d["n_pix"])
+            d["freq_hz"] = np.ascontiguousarray(d["freq_hz"], dtype=np.float64)
+            if d["freq_hz"].size != C:
+                raise ValueError(f"sub-band {i}: freq_hz needs n_chan entries")
+            if d.get("spec_q") is None:
+                d["spec_q"] = torch.empty((C, n_in, 2, T), dtype=torch.int8, device=dev)
+            if d.get("vis") is None:
+                d["vis"] = torch.empty((C, n_in * (n_in + 1) // 2, 2), dtype=torch.int32, device=dev)
+            if d.get("img") is None:
+                d["img"] = torch.empty((C, n_pix, n_pix), dtype=torch.float32, device=dev)
+            _need(d["spec_q"], torch.int8, "spec_q", dev)
+            _need(d["vis"], torch.int32, "vis", dev)
+            _need(d["img"], torch.float32, "img", dev)
+            arr[i] = NbsiSubband(d["volt"].data_ptr(), d["gain"].data_ptr(), int(d["n_fft"]), T,
+                                 int(d["chan0"]), C, d["freq_hz"].ctypes.data, n_pix,
+                                 d["spec_q"].data_ptr(), d["vis"].data_ptr(), d["img"].data_ptr())
+            self.subbands.append(d)
+        flags = ((NBSI_BATCH_GRAPH if graph else 0) | (NBSI_BATCH_AUTOTUNE if autotune else 0)
+                 | (NBSI_BATCH_GRID_TALL if grid_tall else 0))
+        h = ctypes.c_void_p()
+        self.ctx._sync_stream()
+        _check(lib().nbsi_batch_plan(self.ctx._h, self.ant_xyz.ctypes.data_as(ctypes.c_void_p), n_ant, arr,
+                                     len(subbands), int(precision), flags,
+                                     tune_cache.encode() if tune_cache else None, ctypes.byref(h)), self.ctx)
+        self._h = h
+
+    def run(self):
+        self.ctx._sync_stream()
+        _check(lib().nbsi_batch_run(self._h), self.ctx)
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().nbsi_batch_describe(self._h, buf, len(buf)))
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nbsi_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nbsi_batch_plan(ant_xyz, subbands, precision=NBSI_PREC_FP32, graph=True, autotune=False, tune_cache=None,
+                    ctx=None) -> Batch:
+    return Batch(ant_xyz, subbands, precision, graph, autotune, tune_cache, ctx)
+
+
+def nbsi_batch_run(batch: Batch) -> None:
+    batch.run()
+
+
+def nbsi_batch_describe(batch: Batch) -> str:
+    return batch.describe()
+
+
+def nbsi_batch_destroy(batch: Batch) -> None:
+    batch.close()

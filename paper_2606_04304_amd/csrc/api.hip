@@ -14,7 +14,6 @@ int detect_ppw(int n_chan);
 namespace {
 
 constexpr double C_LIGHT = 299792458.0;
-constexpr int GRID_CELLS = 256 * 32;  // LDS cells of one gridding workgroup (see image.hip)
 constexpr size_t IMAGE_CHUNK_BYTES = (size_t)128 << 20;
 
 struct DeviceGuard {
@@ -237,9 +236,11 @@ int nbsi_correlate_f32(nbsi_ctx *ctx, const float *spec_f, int n_chan, int n_in,
     return NBSI_OK;
 }
 
-int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const double *freq_hz_host,
-                           int n_chan, int n_pix, int method, double uv_min, double uv_max,
-                           nbsi_image_plan **out) {
+}  // extern "C"
+
+// Build an imaging plan; ge selects the gridding tile (256 ge grid cells per workgroup).
+int image_plan_build(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const double *freq_hz_host, int n_chan,
+                     int n_pix, int method, double uv_min, double uv_max, int ge, nbsi_image_plan **out) {
     if (!ctx || !out) return NBSI_EINVAL;
     *out = nullptr;
     int rc = nbsi_check_image(n_chan, n_ant, n_pix, method, NBSI_PREC_FP32, uv_min, uv_max);
@@ -260,6 +261,7 @@ int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
     p->n_chan = n_chan;
     p->n_pix = n_pix;
     p->method = method;
+    p->ge = ge;
     p->uv_min = uv_min;
     p->uv_max = uv_max;
 
@@ -293,7 +295,7 @@ int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
     std::vector<int> band_off, band_items;
     std::vector<float> corr;
     if (method == NBSI_IMAGE_GRID) {
-        p->band_rows = GRID_CELLS / M;
+        p->band_rows = 256 * ge / M;
         p->n_bands = M / p->band_rows;
         std::vector<std::vector<int>> bins(p->n_bands);
         for (int k = 0; k < p->n_pairs; k++)
@@ -351,6 +353,14 @@ int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
     }
     *out = p;
     return NBSI_OK;
+}
+
+extern "C" {
+
+int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const double *freq_hz_host,
+                           int n_chan, int n_pix, int method, double uv_min, double uv_max,
+                           nbsi_image_plan **out) {
+    return image_plan_build(ctx, ant_xyz_host, n_ant, freq_hz_host, n_chan, n_pix, method, uv_min, uv_max, 16, out);
 }
 
 int nbsi_image_plan_destroy(nbsi_image_plan *p) {

@@ -1,0 +1,580 @@
+// Batched execution of uneven sub-bands (the paper's batch-by-batch processing of the band,
+// Sec. 2.1, with variable FFT lengths and integrations as in its follow-up, Sec. 2.6):
+// channelize -> corner turn -> correlate -> image for every sub-band, each stage one
+// persistent launch over a task table spanning the sub-bands (grouped only where kernel
+// shapes differ), the whole sequence captured once into a hipGraph and replayed.
+// An autotuner times the correlator variants (128 x 128 tiles vs whole-channel panels) and the
+// gridding tile height (16 or 32 cells per thread) on each sub-band's real shape and caches
+// the choices in a text file.
+#include "internal.h"
+
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <functional>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+int correlate_batch_tasks(const CorrJob &jb, int variant);
+hipError_t correlate_batch_prepare(int variant, int n_in);
+
+struct nbsi_batch {
+    nbsi_ctx *ctx = nullptr;
+    int device = 0, n_sb = 0, n_ant = 0, n_in = 0, precision = 0, flags = 0;
+    std::vector<nbsi_subband> sb;
+    std::vector<nbsi_image_plan *> plans;
+    std::vector<int> corr_variant, grid_ge;
+    std::vector<void *> owned;  // device allocations of the batch
+    std::vector<int8_t *> stage;
+    std::vector<float2 *> cvis, inter;
+
+    struct Launch {  // one persistent launch: kind, shape key, job array on the device
+        int kind;    // 0 channelize, 1 corner turn, 2 correlate, 3 gather, 4 rows, 5 cols
+        int a = 0, b = 0;  // kind-specific shape (log_m/g, variant, log_m/ge)
+        int n_jobs = 0, n_tasks = 0, n_groups = 0, max_dyn = 0;
+        void *d_jobs = nullptr;
+        int *d_task0 = nullptr;
+        int8_t **d_outs = nullptr;
+    };
+    std::vector<Launch> launches;
+
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool captured = false;
+    std::string desc;
+};
+
+namespace {
+
+int n_cu(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 256;
+    return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+}
+
+template <typename T>
+int upload(nbsi_batch *b, const std::vector<T> &v, T **out) {
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * std::max<size_t>(1, v.size())) != hipSuccess) return NBSI_ENOMEM;
+    b->owned.push_back(p);
+    if (!v.empty() && hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return NBSI_EHIP;
+    *out = (T *)p;
+    return NBSI_OK;
+}
+
+int alloc(nbsi_batch *b, size_t bytes, void **out) {
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(256, bytes)) != hipSuccess) return NBSI_ENOMEM;
+    b->owned.push_back(p);
+    *out = p;
+    return NBSI_OK;
+}
+
+// ---- tuning cache: one "key value" pair per line ----
+std::map<std::string, int> read_cache(const char *path) {
+    std::map<std::string, int> m;
+    if (!path) return m;
+    FILE *f = fopen(path, "r");
+    if (!f) return m;
+    char key[256];
+    int val;
+    while (fscanf(f, "%255s %d", key, &val) == 2) m[key] = val;
+    fclose(f);
+    return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, int> &m) {
+    if (!path) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    for (auto &kv : m) fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    fclose(f);
+}
+
+std::string corr_key(int n_in, int n_spec) {
+    return "corr_n_in=" + std::to_string(n_in) + ",n_spec=" + std::to_string(n_spec);
+}
+std::string grid_key(int n_ant, int n_pix, int n_chan) {
+    return "grid_n_ant=" + std::to_string(n_ant) + ",n_pix=" + std::to_string(n_pix) + ",n_chan=" +
+           std::to_string(n_chan);
+}
+
+double time_ms(hipStream_t st, const std::function<hipError_t()> &fn, int reps) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    if (fn() != hipSuccess) return 1e30;  // warm-up
+    (void)hipEventRecord(a, st);
+    for (int r = 0; r < reps; r++)
+        if (fn() != hipSuccess) return 1e30;
+    (void)hipEventRecord(b, st);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+hipError_t enqueue_channelize_one(nbsi_batch *b, int s, hipStream_t st) {
+    const nbsi_subband &x = b->sb[s];
+    const int log_n = 31 - __builtin_clz(x.n_fft);
+    const int klo = (x.chan0 + x.n_fft / 2) & (x.n_fft - 1);
+    hipError_t e = launch_channelize(x.volt, b->n_in, log_n, x.n_spec, klo, x.n_chan, x.gain, b->stage[s], nullptr, st);
+    if (e != hipSuccess) return e;
+    return launch_corner_turn_q(b->stage[s], b->n_in, x.n_spec, x.n_chan, x.spec_q, st);
+}
+
+// Every stage of every sub-band, as the grouped persistent launches.
+hipError_t enqueue_all(nbsi_batch *b, hipStream_t st) {
+    for (const auto &L : b->launches) {
+        hipError_t e = hipSuccess;
+        switch (L.kind) {
+            case 0:
+                e = launch_channelize_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, L.b, L.max_dyn,
+                                            L.n_groups, st);
+                break;
+            case 1:
+                e = launch_corner_turn_q_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.d_task0, L.n_tasks, L.d_outs,
+                                               b->n_in, L.n_groups, st);
+                break;
+            case 2:
+                e = launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->n_in, L.n_groups,
+                                           st);
+                break;
+            case 3: e = launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.n_groups, st); break;
+            case 4:
+                e = launch_image_batch_rows((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->precision, L.b,
+                                            L.n_groups, st);
+                break;
+            case 5:
+                e = launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.b, L.n_groups, st);
+                break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int build_launches(nbsi_batch *b) {
+    const int cus = n_cu(b->device);
+    // channelize: group by (log_m, g)
+    std::map<std::pair<int, int>, std::vector<int>> cg;
+    for (int s = 0; s < b->n_sb; s++) {
+        const int log_n = 31 - __builtin_clz(b->sb[s].n_fft);
+        const int lm = channelize_log_m(log_n, b->sb[s].n_chan);
+        cg[{lm, (log_n - lm) >= 1 ? 2 : 1}].push_back(s);
+    }
+    for (auto &kv : cg) {
+        std::vector<ChanJob> jobs;
+        int tasks = 0, max_dyn = 0;
+        for (int s : kv.second) {
+            const nbsi_subband &x = b->sb[s];
+            const int log_n = 31 - __builtin_clz(x.n_fft);
+            ChanJob j{x.volt, x.gain, b->stage[s], nullptr, log_n, x.n_spec, (x.chan0 + x.n_fft / 2) & (x.n_fft - 1),
+                      x.n_chan, tasks};
+            jobs.push_back(j);
+            tasks += b->n_in * x.n_spec;
+            max_dyn = std::max(max_dyn, channelize_dyn_elems(log_n, kv.first.first));
+        }
+        nbsi_batch::Launch L;
+        L.kind = 0;
+        L.a = kv.first.first;
+        L.b = kv.first.second;
+        L.n_jobs = (int)jobs.size();
+        L.n_tasks = tasks;
+        L.max_dyn = max_dyn;
+        L.n_groups = std::min(tasks, cus * 4);
+        int rc = upload(b, jobs, (ChanJob **)&L.d_jobs);
+        if (rc) return rc;
+        b->launches.push_back(L);
+    }
+    // corner turn: one launch over every sub-band
+    {
+        std::vector<ChanJob> jobs;
+        std::vector<int> t0;
+        std::vector<int8_t *> outs;
+        int tasks = 0;
+        for (int s = 0; s < b->n_sb; s++) {
+            const nbsi_subband &x = b->sb[s];
+            jobs.push_back(ChanJob{x.volt, x.gain, b->stage[s], nullptr, 0, x.n_spec, 0, x.n_chan, tasks});
+            t0.push_back(tasks);
+            outs.push_back(x.spec_q);
+            tasks += corner_turn_tasks(b->n_in, x.n_spec, x.n_chan);
+        }
+        nbsi_batch::Launch L;
+        L.kind = 1;
+        L.n_jobs = b->n_sb;
+        L.n_tasks = tasks;
+        L.n_groups = std::min(tasks, cus * 8);
+        int rc = upload(b, jobs, (ChanJob **)&L.d_jobs);
+        if (!rc) rc = upload(b, t0, &L.d_task0);
+        if (!rc) rc = upload(b, outs, &L.d_outs);
+        if (rc) return rc;
+        b->launches.push_back(L);
+    }
+    // correlate: group by variant
+    std::map<int, std::vector<int>> kg;
+    for (int s = 0; s < b->n_sb; s++) kg[b->corr_variant[s]].push_back(s);
+    for (auto &kv : kg) {
+        std::vector<CorrJob> jobs;
+        int tasks = 0;
+        for (int s : kv.second) {
+            const nbsi_subband &x = b->sb[s];
+            CorrJob j{x.spec_q, x.vis, b->n_in, x.n_spec, x.n_chan, tasks};
+            jobs.push_back(j);
+            tasks += correlate_batch_tasks(j, kv.first);
+        }
+        hipError_t e = correlate_batch_prepare(kv.first, b->n_in);
+        if (e != hipSuccess) return NBSI_EHIP;
+        nbsi_batch::Launch L;
+        L.kind = 2;
+        L.a = kv.first;
+        L.n_jobs = (int)jobs.size();
+        L.n_tasks = tasks;
+        L.n_groups = std::min(tasks, cus * (kv.first == CORR_VARIANT_TILED ? 6 : 3));
+        int rc = upload(b, jobs, (CorrJob **)&L.d_jobs);
+        if (rc) return rc;
+        b->launches.push_back(L);
+    }
+    // imager: gather over all; rows grouped by (log_m, ge); columns grouped by ge
+    std::vector<ImgJob> base(b->n_sb);
+    for (int s = 0; s < b->n_sb; s++) {
+        const nbsi_image_plan *p = b->plans[s];
+        ImgJob &j = base[s];
+        j.vis = b->sb[s].vis;
+        j.xyz = p->d_xyz;
+        j.freq = p->d_freq;
+        j.pairs = p->d_pairs;
+        j.dxy = p->d_dxy;
+        j.band_off = p->d_band_off;
+        j.band_items = p->d_band_items;
+        j.nb = p->d_nb;
+        j.corr = p->d_corr;
+        j.cvis = b->cvis[s];
+        j.inter = b->inter[s];
+        j.img = b->sb[s].img;
+        j.n_pairs = p->n_pairs;
+        j.n_ant = p->n_ant;
+        j.n_pix = p->n_pix;
+        j.log_m = 31 - __builtin_clz(2 * p->n_pix);
+        j.n_bands = p->n_bands;
+        j.n_chan = p->n_chan;
+        j.uv_min = p->uv_min;
+        j.uv_max = p->uv_max;
+    }
+    {
+        std::vector<ImgJob> jobs = base;
+        int tasks = 0;
+        for (auto &j : jobs) {
+            j.gather_task0 = tasks;
+            tasks += j.n_chan * ((j.n_pairs + 255) / 256);
+        }
+        nbsi_batch::Launch L;
+        L.kind = 3;
+        L.n_jobs = (int)jobs.size();
+        L.n_tasks = tasks;
+        L.n_groups = std::min(tasks, cus * 8);
+        int rc = upload(b, jobs, (ImgJob **)&L.d_jobs);
+        if (rc) return rc;
+        b->launches.push_back(L);
+    }
+    std::map<std::pair<int, int>, std::vector<int>> rg;
+    std::map<int, std::vector<int>> og;
+    for (int s = 0; s < b->n_sb; s++) {
+        rg[{base[s].log_m, b->grid_ge[s]}].push_back(s);
+        og[b->grid_ge[s]].push_back(s);
+    }
+    for (auto &kv : rg) {
+        std::vector<ImgJob> jobs;
+        int tasks = 0;
+        for (int s : kv.second) {
+            ImgJob j = base[s];
+            j.rows_task0 = tasks;
+            tasks += j.n_chan * j.n_bands;
+            jobs.push_back(j);
+        }
+        nbsi_batch::Launch L;
+        L.kind = 4;
+        L.a = kv.first.first;
+        L.b = kv.first.second;
+        L.n_jobs = (int)jobs.size();
+        L.n_tasks = tasks;
+        L.n_groups = std::min(tasks, cus * (kv.first.second == 32 ? 2 : 4));
+        int rc = upload(b, jobs, (ImgJob **)&L.d_jobs);
+        if (rc) return rc;
+        b->launches.push_back(L);
+    }
+    for (auto &kv : og) {
+        std::vector<ImgJob> jobs;
+        int tasks = 0;
+        for (int s : kv.second) {
+            ImgJob j = base[s];
+            j.cols_task0 = tasks;
+            const int band_cols = 256 * kv.first / (2 * j.n_pix);
+            tasks += j.n_chan * (j.n_pix / band_cols);
+            jobs.push_back(j);
+        }
+        nbsi_batch::Launch L;
+        L.kind = 5;
+        L.b = kv.first;
+        L.n_jobs = (int)jobs.size();
+        L.n_tasks = tasks;
+        L.n_groups = std::min(tasks, cus * (kv.first == 32 ? 2 : 4));
+        int rc = upload(b, jobs, (ImgJob **)&L.d_jobs);
+        if (rc) return rc;
+        b->launches.push_back(L);
+    }
+    return NBSI_OK;
+}
+
+void free_batch(nbsi_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto *p : b->plans)
+        if (p) nbsi_image_plan_destroy(p);
+    for (void *p : b->owned) (void)hipFree(p);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const nbsi_subband *sb, int n_sb,
+                    int precision, int flags, const char *tune_cache_path, nbsi_batch **out) {
+    if (!ctx || !out) return NBSI_EINVAL;
+    *out = nullptr;
+    if (!sb || n_sb < 1 || n_sb > 4096 || !ant_xyz_host || n_ant < 2)
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_batch_plan: bad arguments");
+    if (precision != NBSI_PREC_FP32 && precision != NBSI_PREC_FP16 && precision != NBSI_PREC_BF16)
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_batch_plan: bad precision");
+    const int n_in = 2 * n_ant;
+    for (int s = 0; s < n_sb; s++) {
+        const nbsi_subband &x = sb[s];
+        int rc = nbsi_check_channelize(n_in, x.n_fft, x.n_spec, x.chan0, x.n_chan);
+        if (!rc) rc = nbsi_check_image(x.n_chan, n_ant, x.n_pix, NBSI_IMAGE_GRID, precision, 0.0, INFINITY);
+        if (rc) return nbsi_fail(ctx, rc, "nbsi_batch_plan: sub-band " + std::to_string(s) + " has a bad shape");
+        if (!x.volt || !x.gain || !x.freq_hz_host || !x.spec_q || !x.vis || !x.img)
+            return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_batch_plan: sub-band " + std::to_string(s) + " null pointer");
+        const void *ptrs[] = {x.volt, x.gain, x.spec_q, x.vis, x.img};
+        for (const void *p : ptrs)
+            if ((uintptr_t)p & 15u)
+                return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_batch_plan: sub-band " + std::to_string(s) + " misaligned");
+    }
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != ctx->device) (void)hipSetDevice(ctx->device);
+    nbsi_batch *b = new (std::nothrow) nbsi_batch();
+    if (!b) return NBSI_ENOMEM;
+    b->ctx = ctx;
+    b->device = ctx->device;
+    b->n_sb = n_sb;
+    b->n_ant = n_ant;
+    b->n_in = n_in;
+    b->precision = precision;
+    b->flags = flags;
+    b->sb.assign(sb, sb + n_sb);
+    int rc = NBSI_OK;
+    auto fail = [&](int code, const std::string &msg) {
+        free_batch(b);
+        if (prev >= 0 && prev != ctx->device) (void)hipSetDevice(prev);
+        return nbsi_fail(ctx, code, "nbsi_batch_plan: " + msg);
+    };
+    // a dedicated stream of default priority (graph capture cannot use the null stream)
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
+        return fail(NBSI_EHIP, "stream/event creation failed");
+    std::map<std::string, int> cache = read_cache(tune_cache_path);
+    bool cache_dirty = false;
+    // per sub-band scratch, default choices
+    for (int s = 0; s < n_sb; s++) {
+        const nbsi_subband &x = b->sb[s];
+        void *st = nullptr;
+        if ((rc = alloc(b, (size_t)n_in * x.n_spec * x.n_chan * 2, &st))) return fail(rc, "out of memory");
+        b->stage.push_back((int8_t *)st);
+        b->corr_variant.push_back(correlate_default_variant(n_in, x.n_spec));
+        b->grid_ge.push_back(16);
+    }
+    const bool tune = (flags & NBSI_BATCH_AUTOTUNE) != 0;
+    // channelize every sub-band once (the tuner needs real spectra and visibilities)
+    if (tune) {
+        for (int s = 0; s < n_sb; s++)
+            if (enqueue_channelize_one(b, s, b->stream) != hipSuccess) return fail(NBSI_EHIP, "channelize failed");
+    }
+    // correlator variant per shape
+    for (int s = 0; s < n_sb; s++) {
+        const nbsi_subband &x = b->sb[s];
+        const std::string key = corr_key(n_in, x.n_spec);
+        auto it = cache.find(key);
+        if (it != cache.end() && correlate_variant_valid(n_in, x.n_spec, it->second)) {
+            b->corr_variant[s] = it->second;
+        } else if (tune) {
+            double best = 1e30;
+            int best_v = b->corr_variant[s];
+            for (int v : {CORR_VARIANT_TILED, CORR_VARIANT_CHAN32, CORR_VARIANT_CHAN64}) {
+                if (!correlate_variant_valid(n_in, x.n_spec, v)) continue;
+                const double ms = time_ms(
+                    b->stream, [&]() { return launch_correlate_variant(x.spec_q, x.n_chan, n_in, x.n_spec, x.vis, v, b->stream); },
+                    2);
+                if (ms < best) {
+                    best = ms;
+                    best_v = v;
+                }
+            }
+            b->corr_variant[s] = best_v;
+            cache[key] = best_v;
+            cache_dirty = true;
+        }
+        if (tune && launch_correlate_variant(x.spec_q, x.n_chan, n_in, x.n_spec, x.vis, b->corr_variant[s],
+                                             b->stream) != hipSuccess)
+            return fail(NBSI_EHIP, "correlate failed");
+    }
+    // imaging plans and the gridding tile height per sub-band
+    for (int s = 0; s < n_sb; s++) {
+        const nbsi_subband &x = b->sb[s];
+        const std::string key = grid_key(n_ant, x.n_pix, x.n_chan);
+        auto it = cache.find(key);
+        int ge = 16;
+        if (flags & NBSI_BATCH_GRID_TALL) {
+            ge = 32;
+        } else if (it != cache.end() && (it->second == 16 || it->second == 32)) {
+            ge = it->second;
+        } else if (tune) {
+            double best = 1e30;
+            for (int g : {16, 32}) {
+                nbsi_image_plan *p = nullptr;
+                if (image_plan_build(ctx, ant_xyz_host, n_ant, x.freq_hz_host, x.n_chan, x.n_pix, NBSI_IMAGE_GRID, 0.0,
+                                     INFINITY, g, &p))
+                    return fail(NBSI_EHIP, "plan failed");
+                const size_t per_chan = (size_t)x.n_pix * 2 * x.n_pix * sizeof(float2);
+                void *cv = nullptr, *in = nullptr;
+                if (hipMalloc(&cv, sizeof(float2) * (size_t)x.n_chan * std::max(1, p->n_pairs)) != hipSuccess ||
+                    hipMalloc(&in, per_chan * x.n_chan) != hipSuccess) {
+                    if (cv) (void)hipFree(cv);
+                    nbsi_image_plan_destroy(p);
+                    return fail(NBSI_ENOMEM, "out of memory while tuning");
+                }
+                const double ms = time_ms(
+                    b->stream,
+                    [&]() {
+                        return launch_image_grid(p, x.vis, NBSI_VIS_I32, precision, (float2 *)cv, (float2 *)in, x.img,
+                                                 b->stream);
+                    },
+                    2);
+                (void)hipStreamSynchronize(b->stream);
+                (void)hipFree(cv);
+                (void)hipFree(in);
+                nbsi_image_plan_destroy(p);
+                if (ms < best) {
+                    best = ms;
+                    ge = g;
+                }
+            }
+            cache[key] = ge;
+            cache_dirty = true;
+        }
+        b->grid_ge[s] = ge;
+        nbsi_image_plan *p = nullptr;
+        if ((rc = image_plan_build(ctx, ant_xyz_host, n_ant, x.freq_hz_host, x.n_chan, x.n_pix, NBSI_IMAGE_GRID, 0.0,
+                                   INFINITY, ge, &p)))
+            return fail(rc, "plan failed");
+        b->plans.push_back(p);
+        void *cv = nullptr, *in = nullptr;
+        if ((rc = alloc(b, sizeof(float2) * (size_t)x.n_chan * std::max(1, p->n_pairs), &cv))) return fail(rc, "oom");
+        if ((rc = alloc(b, (size_t)x.n_pix * 2 * x.n_pix * sizeof(float2) * x.n_chan, &in))) return fail(rc, "oom");
+        b->cvis.push_back((float2 *)cv);
+        b->inter.push_back((float2 *)in);
+    }
+    if (cache_dirty) write_cache(tune_cache_path, cache);
+    if ((rc = build_launches(b))) return fail(rc, "launch tables failed");
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(NBSI_EHIP, "stream sync failed");
+    // description of the choices (JSON)
+    std::string d = "{\"subbands\": [";
+    for (int s = 0; s < n_sb; s++) {
+        char tmp[256];
+        snprintf(tmp, sizeof tmp, "%s{\"n_fft\": %d, \"n_spec\": %d, \"n_chan\": %d, \"n_pix\": %d, \"corr_variant\": \"%s\", \"grid_ge\": %d}",
+                 s ? ", " : "", b->sb[s].n_fft, b->sb[s].n_spec, b->sb[s].n_chan, b->sb[s].n_pix,
+                 b->corr_variant[s] == CORR_VARIANT_TILED ? "tiled128" : (b->corr_variant[s] == CORR_VARIANT_CHAN32 ? "channel32" : "channel64"),
+                 b->grid_ge[s]);
+        d += tmp;
+    }
+    d += "], \"launches\": " + std::to_string(b->launches.size()) + "}";
+    b->desc = d;
+    if (prev >= 0 && prev != ctx->device) (void)hipSetDevice(prev);
+    *out = b;
+    return NBSI_OK;
+}
+
+int nbsi_batch_run(nbsi_batch *b) {
+    if (!b) return NBSI_EINVAL;
+    nbsi_ctx *ctx = b->ctx;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != b->device) (void)hipSetDevice(b->device);
+    auto done = [&](int code) {
+        if (prev >= 0 && prev != b->device) (void)hipSetDevice(prev);
+        return code;
+    };
+    // order after the caller's stream, run on the batch stream, then order the caller after it
+    if (hipEventRecord(b->ev_in, ctx->stream) != hipSuccess || hipStreamWaitEvent(b->stream, b->ev_in, 0) != hipSuccess)
+        return done(nbsi_fail(ctx, NBSI_EHIP, "nbsi_batch_run: event ordering failed"));
+    if (b->flags & NBSI_BATCH_GRAPH) {
+        if (!b->captured) {
+            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return done(nbsi_fail(ctx, NBSI_EHIP, "nbsi_batch_run: capture failed to start"));
+            const hipError_t e = enqueue_all(b, b->stream);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess || !g)
+                return done(nbsi_fail(ctx, NBSI_EHIP, "nbsi_batch_run: capture failed"));
+            b->graph = g;
+            if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+                return done(nbsi_fail(ctx, NBSI_EHIP, "nbsi_batch_run: graph instantiation failed"));
+            b->captured = true;
+        }
+        if (hipGraphLaunch(b->exec, b->stream) != hipSuccess)
+            return done(nbsi_fail(ctx, NBSI_EHIP, "nbsi_batch_run: graph launch failed"));
+    } else {
+        if (enqueue_all(b, b->stream) != hipSuccess) return done(nbsi_fail(ctx, NBSI_EHIP, "nbsi_batch_run: launch failed"));
+    }
+    if (hipEventRecord(b->ev_out, b->stream) != hipSuccess || hipStreamWaitEvent(ctx->stream, b->ev_out, 0) != hipSuccess)
+        return done(nbsi_fail(ctx, NBSI_EHIP, "nbsi_batch_run: event ordering failed"));
+    return done(NBSI_OK);
+}
+
+int nbsi_batch_describe(const nbsi_batch *b, char *buf, int len) {
+    if (!b || !buf || len <= 0) return NBSI_EINVAL;
+    const int n = (int)b->desc.size();
+    if (n + 1 > len) {
+        memcpy(buf, b->desc.data(), len - 1);
+        buf[len - 1] = 0;
+        return NBSI_ETRUNC;
+    }
+    memcpy(buf, b->desc.c_str(), n + 1);
+    return NBSI_OK;
+}
+
+int nbsi_batch_destroy(nbsi_batch *b) {
+    if (!b) return NBSI_EINVAL;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    const int dev = b->device;
+    if (prev != dev) (void)hipSetDevice(dev);
+    free_batch(b);
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+    return NBSI_OK;
+}
+
+}  // extern "C"

@@ -63,32 +63,21 @@ __device__ __forceinline__ void pass16(float2 *v, int t, int ns, int log_n, cons
     dft16(v);
 }
 
-template <int LOGM, int G>
-__global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(
-    const int8_t *__restrict__ volt, int log_n, int n_spec, int klo, int n_chan,
-    const float *__restrict__ gain, int8_t *__restrict__ stage_q, float2 *__restrict__ stage_f) {
+// Build the transform tables of one sub-band in LDS: the two-level table of W_N and the
+// [P][16][2] accumulation twiddles W_N^{p (NT r + M j_sel)}.  The kept output of residue
+// k1 = t + NT r is k = k1 + M j with j = jl (k1 >= klo mod M) or jl + 1 (k1 < klo mod M), so
+// W_N^{p k} = W_N^{p t} * W_N^{p (NT r + M j)}.
+template <int LOGM>
+__device__ __forceinline__ TwiddleTable chan_tables(float2 *dyn, int log_n, int klo, int t) {
     using PL = Plan<LOGM>;
-    constexpr int M = PL::M, NT = PL::NT, R0 = PL::R0;
-    __shared__ float2 buf[padded_size(M)];
-    // dynamic LDS: two-level table of W_N (2^lo_bits + 2^(log_n - lo_bits) entries), then
-    // [P][16][2] accumulation twiddles W_N^{p (NT r + M j_sel)}
-    extern __shared__ float2 dyn[];
-
-    const int t = threadIdx.x;
-    const int s = blockIdx.x % n_spec;
-    const int i = blockIdx.x / n_spec;
-    const int N = 1 << log_n;
-    const int P = N >> LOGM;
-    const int log_p = log_n - LOGM;
-
+    constexpr int M = PL::M, NT = PL::NT;
+    const int N = 1 << log_n, P = N >> LOGM;
     const int lo_bits = (log_n + 1) >> 1;
     float2 *tw_lo = dyn, *tw_hi = dyn + (1 << lo_bits);
     float2 *acc_tw = tw_hi + (1 << (log_n - lo_bits));
     const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_n, t, NT);
     __syncthreads();
-    // Kept output of residue k1 = t + NT r is k = k1 + M j with j = jl (k1 >= klo mod M) or
-    // jl + 1 (k1 < klo mod M), so W_N^{p k} = W_N^{p t} * W_N^{p (NT r + M j)}.
-    const int rl = klo & (M - 1), jl = klo >> LOGM;
+    const int jl = klo >> LOGM;
     if (P > 1) {
         for (int e = t; e < P * 32; e += NT) {
             const int p = e >> 5, r = (e >> 1) & 15, sel = e & 1;
@@ -97,10 +86,34 @@ __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(
         }
     }
     __syncthreads();
+    return tw;
+}
 
+// size in float2 of the dynamic LDS of one sub-band's tables
+__host__ __device__ inline int chan_dyn_elems(int log_n, int log_m) {
+    const int lo_bits = (log_n + 1) >> 1;
+    const int P = 1 << (log_n - log_m);
+    return (1 << lo_bits) + (1 << (log_n - lo_bits)) + (P > 1 ? 32 * P : 0);
+}
+
+// One spectrum (input i, spectrum s) of one sub-band: window, P sub-transforms, twiddled
+// accumulation of the kept band, gain, float32 and int8 outputs to the staging arrays.
+template <int LOGM, int G>
+__device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, int s, float2 *buf, const float2 *dyn,
+                                                    const TwiddleTable &tw) {
+    using PL = Plan<LOGM>;
+    constexpr int M = PL::M, NT = PL::NT, R0 = PL::R0;
+    const int t = threadIdx.x;
+    const int log_n = jb.log_n, n_spec = jb.n_spec, klo = jb.klo, n_chan = jb.n_chan;
+    const int N = 1 << log_n;
+    const int P = N >> LOGM;
+    const int log_p = log_n - LOGM;
+    const int lo_bits = (log_n + 1) >> 1;
+    const float2 *acc_tw = dyn + (1 << lo_bits) + (1 << (log_n - lo_bits));
+    const int rl = klo & (M - 1);
     // raw buffer over this spectrum's samples: one per-thread offset plus scalar offsets per
     // element, with hardware range checking (reads past the spectrum return 0)
-    const int16_t *x = reinterpret_cast<const int16_t *>(volt) + ((size_t)i * n_spec + s) * (size_t)N;
+    const int16_t *x = reinterpret_cast<const int16_t *>(jb.volt) + ((size_t)i * n_spec + s) * (size_t)N;
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<int16_t *>(x), (short)0, N * 2, 0x00020000);
     const int voff = (t << log_p) * 2;
@@ -181,7 +194,7 @@ __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(
         }
     }
 
-    const float g = gain[i];
+    const float g = jb.gain[i];
     const size_t rowo = ((size_t)i * n_spec + s) * (size_t)n_chan;
 #pragma unroll
     for (int r = 0; r < E; r++) {
@@ -189,24 +202,53 @@ __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(
         const int k1 = t + r * NT;
         const int d = (k1 - klo) & (M - 1);
         const float2 gx = make_float2(acc[r].x * g, acc[r].y * g);
-        if (stage_f) stage_f[rowo + d] = gx;
-        if (stage_q) {
+        if (jb.stage_f) jb.stage_f[rowo + d] = gx;
+        if (jb.stage_q) {
             const float qr = fminf(fmaxf(rintf(gx.x), -127.f), 127.f);
             const float qi = fminf(fmaxf(rintf(gx.y), -127.f), 127.f);
             const int16_t packed = (int16_t)(((int)qi << 8) | ((int)qr & 0xff));
-            reinterpret_cast<int16_t *>(stage_q)[rowo + d] = packed;
+            reinterpret_cast<int16_t *>(jb.stage_q)[rowo + d] = packed;
         }
     }
 }
 
-// [n_in][n_spec][C] complex int8 -> [C][n_in][2][n_spec] int8, through a 64 x 64 LDS tile.
-__global__ __launch_bounds__(256) void corner_turn_q_kernel(const int16_t *__restrict__ stage, int n_in,
-                                                            int n_spec, int n_chan,
-                                                            int8_t *__restrict__ out) {
-    __shared__ int16_t tile[64][65];
-    const int i = blockIdx.y;
-    const int n_cb = (n_chan + 63) / 64;
-    const int cb = blockIdx.x % n_cb, sb = blockIdx.x / n_cb;
+template <int LOGM, int G>
+__global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(ChanJob jb) {
+    __shared__ float2 buf[padded_size(1 << LOGM)];
+    extern __shared__ float2 dyn[];  // tables (chan_tables)
+    const TwiddleTable tw = chan_tables<LOGM>(dyn, jb.log_n, jb.klo, threadIdx.x);
+    channelize_spectrum<LOGM, G>(jb, blockIdx.x / jb.n_spec, blockIdx.x % jb.n_spec, buf, dyn, tw);
+}
+
+// Persistent form over several sub-bands: jobs[j] owns tasks [task0, task0 + n_in n_spec);
+// each workgroup walks tasks with stride gridDim.x and rebuilds the tables when it crosses
+// into another sub-band.
+template <int LOGM, int G>
+__global__ __launch_bounds__((1 << LOGM) / 16) void channelize_batch_kernel(const ChanJob *__restrict__ jobs,
+                                                                            int n_jobs, int n_tasks) {
+    __shared__ float2 buf[padded_size(1 << LOGM)];
+    extern __shared__ float2 dyn[];
+    int cur = -1;
+    TwiddleTable tw{};
+    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
+        const ChanJob jb = jobs[j];
+        if (j != cur) {
+            __syncthreads();  // every thread is done with the previous tables
+            tw = chan_tables<LOGM>(dyn, jb.log_n, jb.klo, threadIdx.x);
+            cur = j;
+        }
+        const int local = task - jb.task0;
+        channelize_spectrum<LOGM, G>(jb, local / jb.n_spec, local % jb.n_spec, buf, dyn, tw);
+    }
+}
+
+// [n_in][n_spec][C] complex int8 -> [C][n_in][2][n_spec] int8, through a 64 x 64 LDS tile:
+// tile (i, channel block cb, spectrum block sb).
+__device__ __forceinline__ void corner_turn_q_tile(const int16_t *__restrict__ stage, int n_in, int n_spec,
+                                                   int n_chan, int8_t *__restrict__ out, int i, int cb, int sb,
+                                                   int16_t (*tile)[65]) {
     const int c0 = cb * 64, s0 = sb * 64;
     const int t = threadIdx.x;
     for (int e = t; e < 64 * 64; e += 256) {
@@ -224,6 +266,31 @@ __global__ __launch_bounds__(256) void corner_turn_q_kernel(const int16_t *__res
             const int8_t b = comp ? (int8_t)(v >> 8) : (int8_t)(v & 0xff);
             out[(((size_t)c * n_in + i) * 2 + comp) * n_spec + s] = b;
         }
+    }
+}
+
+__global__ __launch_bounds__(256) void corner_turn_q_kernel(const int16_t *__restrict__ stage, int n_in,
+                                                            int n_spec, int n_chan,
+                                                            int8_t *__restrict__ out) {
+    __shared__ int16_t tile[64][65];
+    const int n_cb = (n_chan + 63) / 64;
+    corner_turn_q_tile(stage, n_in, n_spec, n_chan, out, blockIdx.y, blockIdx.x % n_cb, blockIdx.x / n_cb, tile);
+}
+
+__global__ __launch_bounds__(256) void corner_turn_q_batch_kernel(const ChanJob *__restrict__ jobs, int n_jobs,
+                                                                  const int *__restrict__ task0, int n_tasks,
+                                                                  int8_t *const *__restrict__ outs, int n_in) {
+    __shared__ int16_t tile[64][65];
+    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        int j = 0;
+        while (j + 1 < n_jobs && task0[j + 1] <= task) j++;
+        const ChanJob jb = jobs[j];
+        const int local = task - task0[j];
+        const int n_cb = (jb.n_chan + 63) / 64, n_sb = (jb.n_spec + 63) / 64;
+        const int i = local / (n_cb * n_sb), rem = local % (n_cb * n_sb);
+        __syncthreads();
+        corner_turn_q_tile(reinterpret_cast<const int16_t *>(jb.stage_q), n_in, jb.n_spec, jb.n_chan, outs[j], i,
+                           rem % n_cb, rem / n_cb, tile);
     }
 }
 
@@ -254,19 +321,22 @@ __global__ __launch_bounds__(256) void corner_turn_f_kernel(const float2 *__rest
 }
 
 template <int LOGM>
-hipError_t launch_logm(const int8_t *volt, int n_in, int log_n, int n_spec, int klo, int n_chan,
-                       const float *gain, int8_t *stage_q, float *stage_f, hipStream_t st) {
-    dim3 grid((unsigned)n_in * (unsigned)n_spec);
-    const int P = 1 << (log_n - LOGM);
-    float2 *sf = reinterpret_cast<float2 *>(stage_f);
-    const int lo_bits = (log_n + 1) >> 1;
-    const size_t lds = sizeof(float2) * ((1 << lo_bits) + (1 << (log_n - lo_bits)) + (P > 1 ? 32 * P : 0));
+hipError_t launch_logm(const ChanJob &jb, int n_in, hipStream_t st) {
+    dim3 grid((unsigned)n_in * (unsigned)jb.n_spec);
+    const int P = 1 << (jb.log_n - LOGM);
+    const size_t lds = sizeof(float2) * chan_dyn_elems(jb.log_n, LOGM);
     if (P >= 2)
-        hipLaunchKernelGGL((channelize_kernel<LOGM, 2>), grid, dim3((1 << LOGM) / 16), lds, st, volt, log_n, n_spec,
-                           klo, n_chan, gain, stage_q, sf);
+        hipLaunchKernelGGL((channelize_kernel<LOGM, 2>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
     else
-        hipLaunchKernelGGL((channelize_kernel<LOGM, 1>), grid, dim3((1 << LOGM) / 16), lds, st, volt, log_n, n_spec,
-                           klo, n_chan, gain, stage_q, sf);
+        hipLaunchKernelGGL((channelize_kernel<LOGM, 1>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+    return hipGetLastError();
+}
+
+template <int LOGM, int G>
+hipError_t launch_batch_logm(const ChanJob *d_jobs, int n_jobs, int n_tasks, size_t lds, int n_groups,
+                             hipStream_t st) {
+    hipLaunchKernelGGL((channelize_batch_kernel<LOGM, G>), dim3(n_groups), dim3((1 << LOGM) / 16), lds, st, d_jobs,
+                       n_jobs, n_tasks);
     return hipGetLastError();
 }
 
@@ -284,16 +354,44 @@ int channelize_log_m(int log_n, int n_chan) {
 hipError_t launch_channelize(const int8_t *volt, int n_in, int log_n, int n_spec, int klo,
                              int n_chan, const float *gain, int8_t *stage_q, float *stage_f,
                              hipStream_t st) {
+    ChanJob jb{volt, gain, stage_q, reinterpret_cast<float2 *>(stage_f), log_n, n_spec, klo, n_chan, 0};
     switch (channelize_log_m(log_n, n_chan)) {
-        case 8: return launch_logm<8>(volt, n_in, log_n, n_spec, klo, n_chan, gain, stage_q, stage_f, st);
-        case 9: return launch_logm<9>(volt, n_in, log_n, n_spec, klo, n_chan, gain, stage_q, stage_f, st);
-        case 10: return launch_logm<10>(volt, n_in, log_n, n_spec, klo, n_chan, gain, stage_q, stage_f, st);
-        case 11: return launch_logm<11>(volt, n_in, log_n, n_spec, klo, n_chan, gain, stage_q, stage_f, st);
-        case 12: return launch_logm<12>(volt, n_in, log_n, n_spec, klo, n_chan, gain, stage_q, stage_f, st);
-        case 13: return launch_logm<13>(volt, n_in, log_n, n_spec, klo, n_chan, gain, stage_q, stage_f, st);
-        case 14: return launch_logm<14>(volt, n_in, log_n, n_spec, klo, n_chan, gain, stage_q, stage_f, st);
+        case 8: return launch_logm<8>(jb, n_in, st);
+        case 9: return launch_logm<9>(jb, n_in, st);
+        case 10: return launch_logm<10>(jb, n_in, st);
+        case 11: return launch_logm<11>(jb, n_in, st);
+        case 12: return launch_logm<12>(jb, n_in, st);
+        case 13: return launch_logm<13>(jb, n_in, st);
+        case 14: return launch_logm<14>(jb, n_in, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Jobs that share one sub-transform size and load grouping (log_m, g) run in one persistent
+// launch; d_jobs holds them with consecutive task ranges.
+hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_tasks, int log_m, int g,
+                                   int max_dyn_elems, int n_groups, hipStream_t st) {
+    const size_t lds = sizeof(float2) * (size_t)max_dyn_elems;
+#define NBSI_CB(LM)                                                                      \
+    case LM:                                                                             \
+        return g == 2 ? launch_batch_logm<LM, 2>(d_jobs, n_jobs, n_tasks, lds, n_groups, st) \
+                      : launch_batch_logm<LM, 1>(d_jobs, n_jobs, n_tasks, lds, n_groups, st);
+    switch (log_m) {
+        NBSI_CB(8) NBSI_CB(9) NBSI_CB(10) NBSI_CB(11) NBSI_CB(12) NBSI_CB(13) NBSI_CB(14)
+        default: return hipErrorInvalidValue;
+    }
+#undef NBSI_CB
+}
+
+int channelize_dyn_elems(int log_n, int log_m) { return chan_dyn_elems(log_n, log_m); }
+
+int corner_turn_tasks(int n_in, int n_spec, int n_chan) { return n_in * ((n_chan + 63) / 64) * ((n_spec + 63) / 64); }
+
+hipError_t launch_corner_turn_q_batch(const ChanJob *d_jobs, int n_jobs, const int *d_task0, int n_tasks,
+                                      int8_t *const *d_outs, int n_in, int n_groups, hipStream_t st) {
+    hipLaunchKernelGGL(corner_turn_q_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, d_task0, n_tasks,
+                       d_outs, n_in);
+    return hipGetLastError();
 }
 
 hipError_t launch_corner_turn_q(const int8_t *stage, int n_in, int n_spec, int n_chan, int8_t *out,

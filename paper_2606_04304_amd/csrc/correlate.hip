@@ -84,16 +84,9 @@ __device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, in
     }
 }
 
-__global__ __launch_bounds__(256) void correlate_i8_kernel(const int8_t *__restrict__ q, int n_chan,
-                                                           int n_in, int T, int n_pairs,
-                                                           int32_t *__restrict__ vis) {
-    __shared__ __attribute__((aligned(16))) int8_t sA[TILE * LDS_STRIDE];
-    __shared__ __attribute__((aligned(16))) int8_t sB[TILE * LDS_STRIDE];
-    const int id = blockIdx.x;
-    const int xcd = id & 7, rest = id >> 3;
-    const int pair = rest % n_pairs;
-    const int c = (rest / n_pairs) * 8 + xcd;
-    if (c >= n_chan) return;
+// One 128 x 128 tile pair (I, J) of channel c: K loop through LDS, MFMA, epilogue.
+__device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int n_in, int T, int c, int pair,
+                                               int32_t *__restrict__ vis, int8_t *sA, int8_t *sB) {
     int I, J;
     tile_pair(pair, I, J);
     const int rows = 2 * n_in;
@@ -147,6 +140,115 @@ __global__ __launch_bounds__(256) void correlate_i8_kernel(const int8_t *__restr
             const int C0 = J * TILE + wc * 64 + ni * 32;
             if (R0 < rows && C0 <= R0 + 31) store_tile_i32(acc[mi][ni], R0, C0, lane, n_in, vc);
         }
+}
+
+__global__ __launch_bounds__(256) void correlate_i8_kernel(const int8_t *__restrict__ q, int n_chan,
+                                                           int n_in, int T, int n_pairs,
+                                                           int32_t *__restrict__ vis) {
+    __shared__ __attribute__((aligned(16))) int8_t sA[TILE * LDS_STRIDE];
+    __shared__ __attribute__((aligned(16))) int8_t sB[TILE * LDS_STRIDE];
+    const int id = blockIdx.x;
+    const int xcd = id & 7, rest = id >> 3;
+    const int pair = rest % n_pairs;
+    const int c = (rest / n_pairs) * 8 + xcd;
+    if (c >= n_chan) return;
+    correlate_tile(q, n_in, T, c, pair, vis, sA, sB);
+}
+
+// Persistent form over several sub-bands: task -> (job, channel group of 8, tile pair, XCD lane)
+// in the same XCD-preserving order as the single-band launch.
+__global__ __launch_bounds__(256) void correlate_i8_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
+                                                                 int n_tasks) {
+    __shared__ __attribute__((aligned(16))) int8_t sA[TILE * LDS_STRIDE];
+    __shared__ __attribute__((aligned(16))) int8_t sB[TILE * LDS_STRIDE];
+    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
+        const CorrJob jb = jobs[j];
+        const int local = task - jb.task0;
+        const int n_tiles = (2 * jb.n_in + TILE - 1) / TILE;
+        const int n_pairs = n_tiles * (n_tiles + 1) / 2;
+        const int xcd = local & 7, rest = local >> 3;
+        const int pair = rest % n_pairs;
+        const int c = (rest / n_pairs) * 8 + xcd;
+        __syncthreads();  // LDS tiles of the previous task are no longer read
+        if (c < jb.n_chan) correlate_tile(jb.q, jb.n_in, jb.n_spec, c, pair, jb.vis, sA, sB);
+    }
+}
+
+// Short integrations (n_spec <= 64): one workgroup per channel keeps the channel's whole
+// int8 matrix Y (2 n_in rows x n_spec, zero-padded to 32 or 64) in LDS and each wave walks a
+// 32-row panel of G across every column tile at or left of the diagonal, so the packed
+// triangle rows of its 16 inputs are written as consecutive 128-byte segments by one wave
+// (whole cache lines form in L2 promptly).  At these sizes the write of the visibilities is
+// the bound, not the matrix cores.
+template <int KP>  // padded K: 32 or 64
+__device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, int n_in, int T, int c,
+                                                  int32_t *__restrict__ vis, int8_t *sY) {
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int rows = 2 * n_in;
+    const int n_panels = (rows + 31) / 32;
+    const int rows_pad = n_panels * 32;
+    const int8_t *Y = q + (size_t)c * rows * T;
+    // stage Y: 16-byte vectors when rows are whole vectors, else bytes, zero-padded
+    if (T == KP) {
+        const v4i *src = reinterpret_cast<const v4i *>(Y);
+        v4i *dst = reinterpret_cast<v4i *>(sY);
+        const int nv = rows * KP / 16;
+        for (int e = t; e < nv; e += 256) dst[e] = src[e];
+        for (int e = nv + t; e < rows_pad * KP / 16; e += 256) dst[e] = v4i{0, 0, 0, 0};
+    } else {
+        for (int e = t; e < rows_pad * KP; e += 256) {
+            const int r = e / KP, k = e % KP;
+            sY[e] = (r < rows && k < T) ? Y[(size_t)r * T + k] : (int8_t)0;
+        }
+    }
+    __syncthreads();
+    const size_t nprod = (size_t)n_in * (n_in + 1) / 2;
+    int2 *vc = reinterpret_cast<int2 *>(vis) + (size_t)c * nprod;
+    const int koff = (lane >> 5) * 16;
+    const int rl = lane & 31;
+    // panel I (32 rows of G, 16 inputs) goes to wave I % 4, reversed on every other block of
+    // four, so the waves get similar numbers of tiles (panel I has I + 1 of them)
+    for (int I = 0; I < n_panels; I++) {
+        const int pos = I & 3;
+        if ((((I >> 2) & 1) ? 3 - pos : pos) != wave) continue;
+        v4i a[KP / 32];
+#pragma unroll
+        for (int kk = 0; kk < KP / 32; kk++)
+            a[kk] = *reinterpret_cast<const v4i *>(sY + (I * 32 + rl) * KP + kk * 32 + koff);
+        for (int J = 0; J <= I; J++) {
+            v16i acc;
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[r] = 0;
+#pragma unroll
+            for (int kk = 0; kk < KP / 32; kk++) {
+                const v4i b = *reinterpret_cast<const v4i *>(sY + (J * 32 + rl) * KP + kk * 32 + koff);
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[kk], b, acc, 0, 0, 0);
+            }
+            store_tile_i32(acc, I * 32, J * 32, lane, n_in, vc);
+        }
+    }
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void correlate_i8_chan_kernel(const int8_t *__restrict__ q, int n_chan,
+                                                                int n_in, int T, int32_t *__restrict__ vis) {
+    extern __shared__ __attribute__((aligned(16))) int8_t sY[];  // [rows_pad][KP]
+    correlate_channel<KP>(q, n_in, T, blockIdx.x, vis, sY);
+}
+
+template <int KP>
+__global__ __launch_bounds__(256) void correlate_i8_chan_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
+                                                                      int n_tasks) {
+    extern __shared__ __attribute__((aligned(16))) int8_t sY[];
+    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
+        const CorrJob jb = jobs[j];
+        __syncthreads();  // the previous channel's matrix is no longer read
+        correlate_channel<KP>(jb.q, jb.n_in, jb.n_spec, task - jb.task0, jb.vis, sY);
+    }
 }
 
 // ---- plain FP32 path: the same Gram formulation on v_mfma_f32_32x32x2_f32 ----
@@ -249,11 +351,88 @@ __global__ __launch_bounds__(256) void correlate_f32_kernel(const float *__restr
 
 hipError_t launch_correlate_i8(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis,
                                hipStream_t st) {
-    const int n_tiles = (2 * n_in + TILE - 1) / TILE;
-    const int n_pairs = n_tiles * (n_tiles + 1) / 2;
-    const size_t groups = (size_t)((n_chan + 7) / 8) * 8 * n_pairs;
-    hipLaunchKernelGGL(correlate_i8_kernel, dim3((unsigned)groups), dim3(256), 0, st, q, n_chan, n_in,
-                       n_spec, n_pairs, vis);
+    return launch_correlate_variant(q, n_chan, n_in, n_spec, vis, correlate_default_variant(n_in, n_spec), st);
+}
+
+size_t correlate_chan_lds(int n_in, int variant) {
+    const int kp = variant == CORR_VARIANT_CHAN64 ? 64 : 32;
+    return (size_t)((2 * n_in + 31) / 32) * 32 * kp;
+}
+
+// Tasks of a batched correlator launch for one job and variant.
+int correlate_batch_tasks(const CorrJob &jb, int variant) {
+    if (variant == CORR_VARIANT_TILED) {
+        const int n_tiles = (2 * jb.n_in + TILE - 1) / TILE;
+        return ((jb.n_chan + 7) / 8) * 8 * (n_tiles * (n_tiles + 1) / 2);
+    }
+    return jb.n_chan;
+}
+
+// The whole-channel kernels hold the channel's matrix in LDS; they serve short integrations.
+bool correlate_variant_valid(int n_in, int n_spec, int variant) {
+    if (variant == CORR_VARIANT_TILED) return true;
+    if (variant == CORR_VARIANT_CHAN32) return n_spec <= 32 && correlate_chan_lds(n_in, variant) <= 96 * 1024;
+    if (variant == CORR_VARIANT_CHAN64) return n_spec <= 64 && correlate_chan_lds(n_in, variant) <= 96 * 1024;
+    return false;
+}
+
+int correlate_default_variant(int n_in, int n_spec) {
+    if (correlate_variant_valid(n_in, n_spec, CORR_VARIANT_CHAN32)) return CORR_VARIANT_CHAN32;
+    if (correlate_variant_valid(n_in, n_spec, CORR_VARIANT_CHAN64)) return CORR_VARIANT_CHAN64;
+    return CORR_VARIANT_TILED;
+}
+
+// Raise the dynamic-LDS limit of the whole-channel batched kernels once, outside any graph capture.
+hipError_t correlate_batch_prepare(int variant, int n_in) {
+    if (variant == CORR_VARIANT_TILED) return hipSuccess;
+    const int lds = (int)correlate_chan_lds(n_in, variant);
+    return variant == CORR_VARIANT_CHAN32
+               ? hipFuncSetAttribute((const void *)correlate_i8_chan_batch_kernel<32>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds)
+               : hipFuncSetAttribute((const void *)correlate_i8_chan_batch_kernel<64>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in,
+                                  int n_groups, hipStream_t st) {
+    if (variant == CORR_VARIANT_TILED) {
+        hipLaunchKernelGGL(correlate_i8_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+        return hipGetLastError();
+    }
+    const size_t lds = correlate_chan_lds(n_in, variant);
+    if (variant == CORR_VARIANT_CHAN32)
+        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<32>, dim3(n_groups), dim3(256), lds, st, d_jobs, n_jobs,
+                           n_tasks);
+    else
+        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<64>, dim3(n_groups), dim3(256), lds, st, d_jobs, n_jobs,
+                           n_tasks);
+    return hipGetLastError();
+}
+
+// Single-band launch of one variant (the default path and the autotuner's candidates).
+hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
+                                    hipStream_t st) {
+    if (variant == CORR_VARIANT_TILED) {
+        const int n_tiles = (2 * n_in + TILE - 1) / TILE;
+        const int n_pairs = n_tiles * (n_tiles + 1) / 2;
+        const size_t groups = (size_t)((n_chan + 7) / 8) * 8 * n_pairs;
+        hipLaunchKernelGGL(correlate_i8_kernel, dim3((unsigned)groups), dim3(256), 0, st, q, n_chan, n_in, n_spec,
+                           n_pairs, vis);
+        return hipGetLastError();
+    }
+    const size_t lds = correlate_chan_lds(n_in, variant);
+    hipError_t e;
+    if (variant == CORR_VARIANT_CHAN32) {
+        e = hipFuncSetAttribute((const void *)correlate_i8_chan_kernel<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(correlate_i8_chan_kernel<32>, dim3(n_chan), dim3(256), lds, st, q, n_chan, n_in, n_spec, vis);
+    } else {
+        e = hipFuncSetAttribute((const void *)correlate_i8_chan_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(correlate_i8_chan_kernel<64>, dim3(n_chan), dim3(256), lds, st, q, n_chan, n_in, n_spec, vis);
+    }
     return hipGetLastError();
 }
 

@@ -163,10 +163,14 @@ __device__ __forceinline__ void stockham_store(float2 *buf, const float2 *v, int
 template <int R, int E>
 __device__ __forceinline__ void stockham_load(const float2 *buf, float2 *v, int t, int nt, int log_l) {
     const int stride = (1 << log_l) / R;
+    // for strides that are multiples of 32 the pad of j + r*stride is pad(j) + r*stride/32, so
+    // one base address serves all R loads
+    const int pstride = (stride & 31) ? 0 : stride + (stride >> 5);
 #pragma unroll
     for (int b = 0; b < E / R; b++) {
         const int j = t + nt * b;
+        const int pj = pidx(j);
 #pragma unroll
-        for (int r = 0; r < R; r++) v[b * R + r] = buf[pidx(j + r * stride)];
+        for (int r = 0; r < R; r++) v[b * R + r] = pstride ? buf[pj + r * pstride] : buf[pidx(j + r * stride)];
     }
 }

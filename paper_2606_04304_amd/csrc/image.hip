@@ -151,14 +151,25 @@ __global__ __launch_bounds__(256) void dft_kernel(const VT *__restrict__ vis, co
 }
 
 // ---- gridding ----
-constexpr int GE = 32;                 // complex values per thread in the banded FFTs
-constexpr int GRID_CELLS = 256 * GE;   // grid cells per workgroup (64 KB, 66 KB padded)
+// Gridding tile: a workgroup of 256 threads holds GE complex cells per thread, i.e. a band of
+// 256 GE / M grid rows (GE = 16: 32 KB of LDS, four workgroups per CU; GE = 32: 64 KB, two).
+// The plan fixes GE (the autotuner chooses it per image size).
+template <int GE>
+struct Tile {
+    static constexpr int CELLS = 256 * GE;
+};
 constexpr float ES_BETA = 2.30f * 8.0f;
 
 __device__ __forceinline__ float es_kernel(float z) {
     // exp(beta (sqrt(1 - z^2) - 1)) for |z| <= 1, else 0
     const float q = 1.f - z * z;
     return q > 0.f ? expf(ES_BETA * (sqrtf(q) - 1.f)) : 0.f;
+}
+
+// The same kernel with hardware exp2 and square root (about 2 ulp), used per grid cell.
+__device__ __forceinline__ float es_kernel_fast(float z) {
+    const float q = 1.f - z * z;
+    return q > 0.f ? __builtin_amdgcn_exp2f(ES_BETA * 1.44269504088896341f * (__builtin_sqrtf(q) - 1.f)) : 0.f;
 }
 
 template <int PREC>
@@ -221,6 +232,7 @@ __device__ __forceinline__ void batched_pass(float2 *buf, int t, int log_l, int 
     __syncthreads();
 }
 
+template <int GE>
 __device__ __forceinline__ void batched_fft(float2 *buf, int t, int log_l, const TwiddleTable &tw, int log_tab) {
     int ns = 1;
     const int rem = log_l % 4;
@@ -236,12 +248,10 @@ __device__ __forceinline__ void batched_fft(float2 *buf, int t, int log_l, const
 // Stokes I of every candidate pair of every channel of a chunk, 0 outside the imaged set B:
 // the scattered visibility reads happen here, with one thread per (channel, pair).
 template <typename VT>
-__global__ __launch_bounds__(256) void stokes_gather_kernel(const VT *__restrict__ vis, const double *__restrict__ xyz,
-                                                            const double *__restrict__ freq, const int2 *__restrict__ pairs,
-                                                            int n_pairs, int n_ant, int grid_n_pix, double uv_min,
-                                                            double uv_max, float2 *__restrict__ cvis) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    const int c = blockIdx.y;
+__device__ __forceinline__ void stokes_gather(const VT *__restrict__ vis, const double *__restrict__ xyz,
+                                              const double *__restrict__ freq, const int2 *__restrict__ pairs,
+                                              int n_pairs, int n_ant, int grid_n_pix, double uv_min, double uv_max,
+                                              float2 *__restrict__ cvis, int c, int k) {
     if (k >= n_pairs) return;
     const int2 p = pairs[k];
     const size_t nprod = (size_t)(2 * n_ant) * (2 * n_ant + 1) / 2;
@@ -249,58 +259,69 @@ __global__ __launch_bounds__(256) void stokes_gather_kernel(const VT *__restrict
     cvis[(size_t)c * n_pairs + k] = ok ? stokes_i<VT>(vis + (size_t)c * nprod, p.x, p.y) : make_float2(0.f, 0.f);
 }
 
-// Gridding without atomics: every thread owns a fixed rectangle of 32 grid cells of the band
+template <typename VT>
+__global__ __launch_bounds__(256) void stokes_gather_kernel(const VT *__restrict__ vis, const double *__restrict__ xyz,
+                                                            const double *__restrict__ freq, const int2 *__restrict__ pairs,
+                                                            int n_pairs, int n_ant, int grid_n_pix, double uv_min,
+                                                            double uv_max, float2 *__restrict__ cvis) {
+    stokes_gather<VT>(vis, xyz, freq, pairs, n_pairs, n_ant, grid_n_pix, uv_min, uv_max, cvis, blockIdx.y,
+                      blockIdx.x * 256 + threadIdx.x);
+}
+
+// Gridding without atomics: every thread owns a fixed rectangle of GE grid cells of the band
 // (CPT consecutive columns x RPT rows) and sums the contributions of the baselines whose
 // 8 x 8 kernel footprint covers it.  The band's baselines are sorted by x separation, hence
-// by grid column for every channel (u is proportional to dx), and are staged in LDS with
-// their 8 + 8 kernel weights, so a thread finds its few baselines by binary search.  The sum
-// order is fixed, so the result is deterministic.
-constexpr int STAGE_CAP = 768;  // baselines staged per round (reuses the grid's LDS)
+// by grid column for every channel (u is proportional to dx), and are staged in LDS (cell
+// index and fractional offset per axis, value), so a thread finds its few baselines by binary
+// search and evaluates the kernel weights of its own cells in registers, without branches.
+// The sum order is fixed, so the result is deterministic.
+constexpr int STAGE_CAP = 1024;  // baselines staged per round (reuses the grid's LDS)
 
-template <int LOGM, int PREC>
-__global__ __launch_bounds__(256) void grid_rows_kernel(
-    const float2 *__restrict__ cvis, const double2 *__restrict__ dxy, const double *__restrict__ freq,
-    const int *__restrict__ band_off, const int *__restrict__ band_items, int n_pairs, int n_pix,
-    float2 *__restrict__ inter) {
+template <int LOGM, int PREC, int GE>
+__device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const double2 *__restrict__ dxy,
+                                          const double *__restrict__ freq, const int *__restrict__ band_off,
+                                          const int *__restrict__ band_items, int n_pairs, int n_pix,
+                                          float2 *__restrict__ inter, int band, int c, float2 *grid,
+                                          float2 *tw_lo, float2 *tw_hi, float &vscale) {
     constexpr int M = 1 << LOGM;
+    constexpr int GRID_CELLS = Tile<GE>::CELLS;
     constexpr int R = GRID_CELLS / M;               // band rows
     constexpr int CPT = (M >= 256) ? M / 256 : 1;   // owned columns per thread
     constexpr int COLT = M / CPT;                   // threads across the columns
     constexpr int RPT = R / (256 / COLT);           // owned rows per thread
-    static_assert(CPT * RPT == GE, "32 cells per thread");
-    __shared__ float2 grid[padded_size(GRID_CELLS)];
-    __shared__ float2 tw_lo[64], tw_hi[64];
-    __shared__ float vscale;
-    // staging view of the grid's LDS: gu0, gv0 (int), value (float2), wu[8], wv[8] (float)
+    static_assert(CPT * RPT == GE, "GE cells per thread");
+    static_assert(STAGE_CAP * 24 <= (int)sizeof(float2) * padded_size(GRID_CELLS), "staging fits");
+    // staging view of the grid's LDS: cell gu0, gv0 (int), fraction ou, ov (float), value (float2)
     int *s_gu = reinterpret_cast<int *>(grid);
     int *s_gv = s_gu + STAGE_CAP;
-    float2 *s_val = reinterpret_cast<float2 *>(s_gv + STAGE_CAP);
-    float *s_wu = reinterpret_cast<float *>(s_val + STAGE_CAP);
-    float *s_wv = s_wu + 8 * STAGE_CAP;
+    float *s_ou = reinterpret_cast<float *>(s_gv + STAGE_CAP);
+    float *s_ov = s_ou + STAGE_CAP;
+    float2 *s_val = reinterpret_cast<float2 *>(s_ov + STAGE_CAP);
 
-    const int band = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
+    const int t = threadIdx.x;
     const int row0 = band * R;
+    __syncthreads();  // the previous task of a persistent workgroup no longer reads the LDS
     const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, LOGM, t, 256);
     const float2 *cv_c = cvis + (size_t)c * n_pairs;
     const int k_begin = band_off[band], k_end = band_off[band + 1];
     if constexpr (PREC == NBSI_PREC_FP16) {
         // Scale this workgroup's visibilities by a power of two so the largest |V_I| it grids
         // maps below 2^14: every FP16 product (kernel weights <= 1) stays finite.
+        float *red = reinterpret_cast<float *>(grid);
         float mx = 0.f;
         for (int i = k_begin + t; i < k_end; i += 256) {
             const float2 val = cv_c[band_items[i]];
             mx = fmaxf(mx, fmaxf(fabsf(val.x), fabsf(val.y)));
         }
-        reinterpret_cast<float *>(grid)[t] = mx;
+        red[t] = mx;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
-            if (t < s) reinterpret_cast<float *>(grid)[t] = fmaxf(reinterpret_cast<float *>(grid)[t],
-                                                                  reinterpret_cast<float *>(grid)[t + s]);
+            if (t < s) red[t] = fmaxf(red[t], red[t + s]);
             __syncthreads();
         }
         if (t == 0) {
             int e2 = 0;
-            frexpf(fmaxf(reinterpret_cast<float *>(grid)[0], 1e-30f), &e2);
+            frexpf(fmaxf(red[0], 1e-30f), &e2);
             vscale = ldexpf(1.f, 14 - e2);
         }
         __syncthreads();
@@ -326,15 +347,11 @@ __global__ __launch_bounds__(256) void grid_rows_kernel(
             const double2 d = dxy[k];
             const double cu = d.x * sc + (double)(M / 2), cvv = d.y * sc + (double)(M / 2);
             const double fu = floor(cu), fv = floor(cvv);
-            const float ou = (float)(cu - fu), ov = (float)(cvv - fv);  // in [0, 1)
             s_gu[i] = (int)fu - 3;
             s_gv[i] = (int)fv - 3;
+            s_ou[i] = (float)(cu - fu);  // in [0, 1)
+            s_ov[i] = (float)(cvv - fv);
             s_val[i] = val;
-#pragma unroll
-            for (int j = 0; j < 8; j++) {
-                s_wu[8 * i + j] = es_kernel(((float)(j - 3) - ou) * 0.25f);
-                s_wv[8 * i + j] = es_kernel(((float)(j - 3) - ov) * 0.25f);
-            }
         }
         __syncthreads();
         // first staged baseline whose footprint can reach column col0: gu0 >= col0 - 7
@@ -347,23 +364,21 @@ __global__ __launch_bounds__(256) void grid_rows_kernel(
         for (int i = lo; i < nk; i++) {
             const int gu0 = s_gu[i];
             if (gu0 > col0 + CPT - 1) break;
-            const int dr0 = row0 + rown - s_gv[i];  // owned row r sits at footprint row dr0 + r
+            const int gv0 = s_gv[i];
+            const int dr0 = row0 + rown - gv0;  // footprint row of owned row 0
             if (dr0 + RPT <= 0 || dr0 >= 8) continue;
+            const float ou = s_ou[i], ov = s_ov[i];
             const float2 val = s_val[i];
+            // cell offsets from the baseline's grid position, in cells: (j - 3) - o
+            float wu[CPT], wv[RPT];
 #pragma unroll
-            for (int q = 0; q < CPT; q++) {
-                const int dq = col0 + q - gu0;
-                if (dq < 0 || dq >= 8) continue;
-                const float wu = s_wu[8 * i + dq];
+            for (int q = 0; q < CPT; q++) wu[q] = es_kernel_fast(((float)(col0 + q - gu0 - 3) - ou) * 0.25f);
 #pragma unroll
-                for (int r = 0; r < RPT; r++) {
-                    const int dr = dr0 + r;
-                    if (dr >= 0 && dr < 8) {
-                        const float2 add = grid_product<PREC>(val, wu, s_wv[8 * i + dr]);
-                        acc[q][r] = cadd(acc[q][r], add);
-                    }
-                }
-            }
+            for (int r = 0; r < RPT; r++) wv[r] = es_kernel_fast(((float)(dr0 + r - 3) - ov) * 0.25f);
+#pragma unroll
+            for (int q = 0; q < CPT; q++)
+#pragma unroll
+                for (int r = 0; r < RPT; r++) acc[q][r] = cadd(acc[q][r], grid_product<PREC>(val, wu[q], wv[r]));
         }
     }
     __syncthreads();
@@ -372,7 +387,7 @@ __global__ __launch_bounds__(256) void grid_rows_kernel(
 #pragma unroll
         for (int r = 0; r < RPT; r++) grid[pidx((rown + r) * M + col0 + q)] = acc[q][r];
     __syncthreads();
-    batched_fft(grid, t, LOGM, tw, LOGM);
+    batched_fft<GE>(grid, t, LOGM, tw, LOGM);
     // keep image columns x: FFT index (x - n/2) mod M, times (-1)^(x - n/2); undo the FP16 scale
     const float unscale = (PREC == NBSI_PREC_FP16) ? 1.f / vscale : 1.f;
     constexpr int half = R / 2;  // two rows per float4 store
@@ -387,17 +402,48 @@ __global__ __launch_bounds__(256) void grid_rows_kernel(
     }
 }
 
-__global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict__ inter, int n_pix, int log_m,
-                                                        int band_cols, const float *__restrict__ corr,
-                                                        const int *__restrict__ nb, float *__restrict__ img) {
-    __shared__ float2 buf[padded_size(GRID_CELLS)];
+template <int LOGM, int PREC, int GE>
+__global__ __launch_bounds__(256) void grid_rows_kernel(
+    const float2 *__restrict__ cvis, const double2 *__restrict__ dxy, const double *__restrict__ freq,
+    const int *__restrict__ band_off, const int *__restrict__ band_items, int n_pairs, int n_pix,
+    float2 *__restrict__ inter) {
+    __shared__ float2 grid[padded_size(Tile<GE>::CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
-    const int xb = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
+    __shared__ float vscale;
+    grid_rows<LOGM, PREC, GE>(cvis, dxy, freq, band_off, band_items, n_pairs, n_pix, inter, blockIdx.x, blockIdx.y, grid,
+                          tw_lo, tw_hi, vscale);
+}
+
+// Persistent gridding over the sub-bands of one image size: task -> (job, channel, band).
+template <int LOGM, int PREC, int GE>
+__global__ __launch_bounds__(256) void grid_rows_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
+                                                              int n_tasks) {
+    __shared__ float2 grid[padded_size(Tile<GE>::CELLS)];
+    __shared__ float2 tw_lo[64], tw_hi[64];
+    __shared__ float vscale;
+    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].rows_task0 <= task) j++;
+        const ImgJob &jb = jobs[j];
+        const int local = task - jb.rows_task0;
+        grid_rows<LOGM, PREC, GE>(jb.cvis, jb.dxy, jb.freq, jb.band_off, jb.band_items, jb.n_pairs, jb.n_pix, jb.inter,
+                              local % jb.n_bands, local / jb.n_bands, grid, tw_lo, tw_hi, vscale);
+    }
+}
+
+template <int GE>
+__device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, int n_pix, int log_m, int band_cols,
+                                          const float *__restrict__ corr, const int *__restrict__ nb,
+                                          float *__restrict__ img, int xb, int c, float2 *buf, float2 *tw_lo,
+                                          float2 *tw_hi) {
+    const int t = threadIdx.x;
+    __syncthreads();  // the previous task of a persistent workgroup no longer reads the LDS
     const int M = 1 << log_m;
     const int x0 = xb * band_cols;
     const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_m, t, 256);
     // the band's columns are contiguous in the intermediate: 16 float4 loads per thread in flight
     const float4 *src = reinterpret_cast<const float4 *>(inter + ((size_t)c * n_pix + x0) * M);
+    constexpr int GRID_CELLS = Tile<GE>::CELLS;
     float4 r[GRID_CELLS / 2 / 256];
 #pragma unroll
     for (int q = 0; q < GRID_CELLS / 2 / 256; q++) r[q] = src[t + 256 * q];
@@ -408,7 +454,7 @@ __global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict
         buf[pidx(e + 1)] = make_float2(r[q].z, r[q].w);
     }
     __syncthreads();
-    batched_fft(buf, t, log_m, tw, log_m);
+    batched_fft<GE>(buf, t, log_m, tw, log_m);
     const int n = nb[c];
     const float inv = n > 0 ? (float)(1.0 / (double)n) : 0.f;
     for (int e = t; e < n_pix * band_cols; e += 256) {
@@ -417,6 +463,45 @@ __global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict
         const float2 f = buf[pidx(xl * M + (yp & (M - 1)))];
         const float sgn = (yp & 1) ? -1.f : 1.f;
         img[((size_t)c * n_pix + y) * n_pix + x0 + xl] = f.x * sgn * corr[x0 + xl] * corr[y] * inv;
+    }
+}
+
+template <int GE>
+__global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict__ inter, int n_pix, int log_m,
+                                                        int band_cols, const float *__restrict__ corr,
+                                                        const int *__restrict__ nb, float *__restrict__ img) {
+    __shared__ float2 buf[padded_size(Tile<GE>::CELLS)];
+    __shared__ float2 tw_lo[64], tw_hi[64];
+    grid_cols<GE>(inter, n_pix, log_m, band_cols, corr, nb, img, blockIdx.x, blockIdx.y, buf, tw_lo, tw_hi);
+}
+
+template <int GE>
+__global__ __launch_bounds__(256) void grid_cols_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
+                                                              int n_tasks) {
+    __shared__ float2 buf[padded_size(Tile<GE>::CELLS)];
+    __shared__ float2 tw_lo[64], tw_hi[64];
+    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].cols_task0 <= task) j++;
+        const ImgJob &jb = jobs[j];
+        const int band_cols = Tile<GE>::CELLS / (1 << jb.log_m);
+        const int n_xb = jb.n_pix / band_cols;
+        const int local = task - jb.cols_task0;
+        grid_cols<GE>(jb.inter, jb.n_pix, jb.log_m, band_cols, jb.corr, jb.nb, jb.img, local % n_xb, local / n_xb, buf,
+                  tw_lo, tw_hi);
+    }
+}
+
+__global__ __launch_bounds__(256) void stokes_gather_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
+                                                                  int n_tasks) {
+    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].gather_task0 <= task) j++;
+        const ImgJob &jb = jobs[j];
+        const int local = task - jb.gather_task0;
+        const int nblk = (jb.n_pairs + 255) / 256;
+        stokes_gather<int2>(reinterpret_cast<const int2 *>(jb.vis), jb.xyz, jb.freq, jb.pairs, jb.n_pairs, jb.n_ant,
+                            jb.n_pix, jb.uv_min, jb.uv_max, jb.cvis, local / nblk, (local % nblk) * 256 + threadIdx.x);
     }
 }
 
@@ -442,20 +527,12 @@ hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_d
     return hipGetLastError();
 }
 
-hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype, int precision,
-                             float2 *cvis, float2 *inter, float *img, hipStream_t st) {
-    const int M = 2 * p->n_pix;
-    const int log_m = 31 - __builtin_clz(M);
-    dim3 gg((p->n_pairs + 255) / 256, p->n_chan);
-    if (vis_dtype == NBSI_VIS_I32)
-        hipLaunchKernelGGL(stokes_gather_kernel<int2>, gg, dim3(256), 0, st, (const int2 *)vis, p->d_xyz, p->d_freq,
-                           p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, cvis);
-    else
-        hipLaunchKernelGGL(stokes_gather_kernel<float2>, gg, dim3(256), 0, st, (const float2 *)vis, p->d_xyz,
-                           p->d_freq, p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, cvis);
+template <int GE>
+static hipError_t launch_grid_ge(const nbsi_image_plan *p, int precision, float2 *cvis, float2 *inter, float *img,
+                                 int log_m, hipStream_t st) {
     dim3 gr(p->n_bands, p->n_chan);
-#define NBSI_ROWS(LM, PR)                                                                                  \
-    hipLaunchKernelGGL((grid_rows_kernel<LM, PR>), gr, dim3(256), 0, st, cvis, p->d_dxy, p->d_freq,          \
+#define NBSI_ROWS(LM, PR)                                                                                   \
+    hipLaunchKernelGGL((grid_rows_kernel<LM, PR, GE>), gr, dim3(256), 0, st, cvis, p->d_dxy, p->d_freq,     \
                        p->d_band_off, p->d_band_items, p->n_pairs, p->n_pix, inter)
 #define NBSI_ROWS_P(LM)                                                        \
     if (precision == NBSI_PREC_FP16) NBSI_ROWS(LM, NBSI_PREC_FP16);             \
@@ -473,8 +550,68 @@ hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_
 #undef NBSI_ROWS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int band_cols = GRID_CELLS / M;
-    hipLaunchKernelGGL(grid_cols_kernel, dim3(p->n_pix / band_cols, p->n_chan), dim3(256), 0, st, inter,
+    const int band_cols = Tile<GE>::CELLS / (1 << log_m);
+    hipLaunchKernelGGL(grid_cols_kernel<GE>, dim3(p->n_pix / band_cols, p->n_chan), dim3(256), 0, st, inter,
                        p->n_pix, log_m, band_cols, p->d_corr, p->d_nb, img);
+    return hipGetLastError();
+}
+
+hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype, int precision,
+                             float2 *cvis, float2 *inter, float *img, hipStream_t st) {
+    const int M = 2 * p->n_pix;
+    const int log_m = 31 - __builtin_clz(M);
+    dim3 gg((p->n_pairs + 255) / 256, p->n_chan);
+    if (vis_dtype == NBSI_VIS_I32)
+        hipLaunchKernelGGL(stokes_gather_kernel<int2>, gg, dim3(256), 0, st, (const int2 *)vis, p->d_xyz, p->d_freq,
+                           p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, cvis);
+    else
+        hipLaunchKernelGGL(stokes_gather_kernel<float2>, gg, dim3(256), 0, st, (const float2 *)vis, p->d_xyz,
+                           p->d_freq, p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, cvis);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return p->ge == 32 ? launch_grid_ge<32>(p, precision, cvis, inter, img, log_m, st)
+                       : launch_grid_ge<16>(p, precision, cvis, inter, img, log_m, st);
+}
+
+hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, int n_groups, hipStream_t st) {
+    hipLaunchKernelGGL(stokes_gather_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+    return hipGetLastError();
+}
+
+template <int GE>
+static hipError_t launch_batch_rows_ge(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision,
+                                       int n_groups, hipStream_t st) {
+#define NBSI_BR(LM, PR)                                                                                        \
+    hipLaunchKernelGGL((grid_rows_batch_kernel<LM, PR, GE>), dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, \
+                       n_tasks)
+#define NBSI_BR_P(LM)                                                    \
+    if (precision == NBSI_PREC_FP16) NBSI_BR(LM, NBSI_PREC_FP16);         \
+    else if (precision == NBSI_PREC_BF16) NBSI_BR(LM, NBSI_PREC_BF16);    \
+    else NBSI_BR(LM, NBSI_PREC_FP32)
+    switch (log_m) {
+        case 7: NBSI_BR_P(7); break;
+        case 8: NBSI_BR_P(8); break;
+        case 9: NBSI_BR_P(9); break;
+        case 10: NBSI_BR_P(10); break;
+        case 11: NBSI_BR_P(11); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef NBSI_BR_P
+#undef NBSI_BR
+    return hipGetLastError();
+}
+
+hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision, int ge,
+                                   int n_groups, hipStream_t st) {
+    return ge == 32 ? launch_batch_rows_ge<32>(d_jobs, n_jobs, n_tasks, log_m, precision, n_groups, st)
+                    : launch_batch_rows_ge<16>(d_jobs, n_jobs, n_tasks, log_m, precision, n_groups, st);
+}
+
+hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int ge, int n_groups,
+                                   hipStream_t st) {
+    if (ge == 32)
+        hipLaunchKernelGGL(grid_cols_batch_kernel<32>, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+    else
+        hipLaunchKernelGGL(grid_cols_batch_kernel<16>, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
     return hipGetLastError();
 }

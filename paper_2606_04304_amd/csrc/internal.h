@@ -30,6 +30,7 @@ enum ScratchSlot {
     SLOT_IMG_BL = 6,        // imager: per-channel baseline values
 };
 
+
 struct nbsi_image_plan {
     int device = 0;
     int n_ant = 0, n_chan = 0, n_pix = 0, method = 0;
@@ -41,8 +42,9 @@ struct nbsi_image_plan {
     int2 *d_pairs = nullptr;      // candidate pairs (a, b), a > b
     double2 *d_dxy = nullptr;     // (x_a - x_b, y_a - y_b) metres of each candidate pair
     int n_pairs = 0;
-    // gridding: candidate pairs binned by bands of grid rows (CSR over bands)
-    int band_rows = 0, n_bands = 0;
+    // gridding: candidate pairs binned by bands of grid rows (CSR over bands); a workgroup
+    // holds 256 * ge grid cells (ge = 16 or 32), i.e. band_rows = 256 ge / (2 n_pix) rows
+    int ge = 16, band_rows = 0, n_bands = 0;
     int *d_band_off = nullptr;    // [n_bands + 1]
     int *d_band_items = nullptr;  // indices into d_pairs
     int n_band_items = 0;
@@ -59,12 +61,69 @@ struct nbsi_image_plan {
     } while (0)
 
 int nbsi_scratch(nbsi_ctx *ctx, int slot, size_t bytes, void **ptr);
+int image_plan_build(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const double *freq_hz_host, int n_chan,
+                     int n_pix, int method, double uv_min, double uv_max, int ge, nbsi_image_plan **out);
 int nbsi_fail(nbsi_ctx *ctx, int code, const std::string &msg);
+
+// One sub-band's channelizer parameters (device-visible; also the task descriptor of the
+// persistent batched launch).
+struct ChanJob {
+    const int8_t *volt;
+    const float *gain;
+    int8_t *stage_q;
+    float2 *stage_f;
+    int log_n, n_spec, klo, n_chan;
+    int task0;  // first task of this sub-band in a batched launch
+};
+
+// One sub-band's correlator parameters (task descriptor of the persistent batched launch).
+struct CorrJob {
+    const int8_t *q;
+    int32_t *vis;
+    int n_in, n_spec, n_chan;
+    int task0;
+};
+enum { CORR_VARIANT_TILED = 0, CORR_VARIANT_CHAN32 = 1, CORR_VARIANT_CHAN64 = 2 };
+int correlate_batch_tasks(const CorrJob &jb, int variant);
+int correlate_default_variant(int n_in, int n_spec);
+bool correlate_variant_valid(int n_in, int n_spec, int variant);
+hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
+                                    hipStream_t st);
+hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in,
+                                  int n_groups, hipStream_t st);
+
+// One sub-band's gridding imager parameters (task descriptor of the persistent launches).
+struct ImgJob {
+    const int32_t *vis;
+    const double *xyz, *freq;
+    const int2 *pairs;
+    const double2 *dxy;
+    const int *band_off, *band_items, *nb;
+    const float *corr;
+    float2 *cvis, *inter;
+    float *img;
+    int n_pairs, n_ant, n_pix, log_m, n_bands, n_chan;
+    double uv_min, uv_max;
+    int gather_task0, rows_task0, cols_task0;
+};
+hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, int n_groups, hipStream_t st);
+hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision, int ge,
+                                   int n_groups, hipStream_t st);
+hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int ge, int n_groups,
+                                   hipStream_t st);
+
+int channelize_log_m(int log_n, int n_chan);
+int channelize_dyn_elems(int log_n, int log_m);
+int corner_turn_tasks(int n_in, int n_spec, int n_chan);
+hipError_t launch_corner_turn_q_batch(const ChanJob *d_jobs, int n_jobs, const int *d_task0, int n_tasks,
+                                      int8_t *const *d_outs, int n_in, int n_groups, hipStream_t st);
 
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_channelize(const int8_t *volt, int n_in, int log_n, int n_spec, int klo,
                              int n_chan, const float *gain, int8_t *stage_q, float *stage_f,
                              hipStream_t st);
+hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_tasks, int log_m, int g,
+                                   int max_dyn_elems, int n_groups, hipStream_t st);
 hipError_t launch_corner_turn_q(const int8_t *stage, int n_in, int n_spec, int n_chan,
                                 int8_t *out, hipStream_t st);
 hipError_t launch_corner_turn_f(const float *stage, int n_in, int n_spec, int n_chan, float *out,
