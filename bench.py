@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-path", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven-sub-band leg (batched graph vs per-sub-band launches)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="profiling aid: run only the uneven-sub-band leg and print its figures")
     ap.add_argument("--stages", default="all", help="profiling aid: all | correlate")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -55,17 +59,19 @@ def source_digest(files):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_src, launch_algo_bytes):
-    """HBM bytes per launch from the committed counter summary, if it was taken on this source."""
+def traffic_from_profile(kernel: str, source: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary (profiles/traffic.json:
+    FETCH_SIZE and WRITE_SIZE scaled by a plain copy's counts), or None when the summary was taken
+    on other source code than the current `source` file."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    ent = d.get(kernel_src["name"])
-    if not ent or ent.get("source_sha") != source_digest(kernel_src["files"]):
+    ent = d.get("kernels", {}).get(kernel)
+    if not ent or ent.get("source_sha") != source_digest([source]):
         return None
-    return ent.get("hbm_bytes_per_launch")
+    return int(ent["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(cfg, xyz, freq, volt_dev, gain, q_dev, img_dev):
@@ -106,6 +112,81 @@ def cpu_baseline(cfg, xyz, freq, volt_dev, gain, q_dev, img_dev):
             "stage_seconds": {k: round(v, 3) for k, v in t.items()}, "step_seconds": round(step, 3)}
 
 
+def batched_leg(args, nb, torch, ctx, dev, synth):
+    """Twelve uneven sub-bands of 352 antennas (FFT lengths 2^14..2^18, 8..128 spectra, 1024
+    channels each, images 128^2..512^2): channelize + correlate + image of all of them, once as
+    per-sub-band library calls and once as one batch (grouped persistent launches replayed from a
+    captured hipGraph), with default tiles and with autotuned tiles."""
+    n_ant = 352
+    n_in = 2 * n_ant
+    nprod = n_in * (n_in + 1) // 2
+    xyz = synth.antenna_layout(n_ant, 750.0, 3001)
+    subs = []
+    for i, c in enumerate(synth.subband_configs(12, 1024, n_ant)):
+        tones = synth.random_tones(1, c["n_fft"], c["chan0"], c["n_chan"], 5.0, 20.0, xyz, c["n_spec"],
+                                   c["n_pix"], seed=3100 + i)
+        v = synth.voltages(n_ant, c["n_fft"], c["n_spec"], tones, xyz, 3200 + i, device="cuda", nu0=c["nu0"])
+        g = torch.full((n_in,), float(c["gain"]), dtype=torch.float32, device=dev)
+        subs.append(dict(volt=v, gain=g, n_fft=c["n_fft"], n_spec=c["n_spec"], chan0=c["chan0"],
+                         n_chan=c["n_chan"], n_pix=c["n_pix"],
+                         freq_hz=synth.channel_freqs(c["n_fft"], c["chan0"], c["n_chan"], c["nu0"])))
+    log("[bench] sub-band inputs ready")
+    plans = [nb.nbsi_image_plan_create(xyz, d["freq_hz"], d["n_pix"], nb.NBSI_IMAGE_GRID, ctx=ctx) for d in subs]
+    outs = [(torch.empty((d["n_chan"], n_in, 2, d["n_spec"]), dtype=torch.int8, device=dev),
+             torch.empty((d["n_chan"], nprod, 2), dtype=torch.int32, device=dev),
+             torch.empty((d["n_chan"], d["n_pix"], d["n_pix"]), dtype=torch.float32, device=dev)) for d in subs]
+
+    def per_subband():
+        for d, p, (q, vis, img) in zip(subs, plans, outs):
+            nb.nbsi_channelize(d["volt"], d["n_fft"], d["n_spec"], d["chan0"], d["n_chan"], d["gain"],
+                               spec_q=q, ctx=ctx)
+            nb.nbsi_correlate(q, vis=vis, ctx=ctx)
+            nb.nbsi_image(p, vis, img=img)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    k = max(2, args.steps // 2)
+    ms_per = timed(per_subband, k)
+    log(f"[bench] per-sub-band launches: {ms_per:.2f} ms")
+    batch = nb.Batch(xyz, subs, graph=True, ctx=ctx)
+    ms_batch = timed(batch.run, k)
+    log(f"[bench] batched graph (default tiles): {ms_batch:.2f} ms")
+    same = all(torch.equal(bd["vis"], o[1]) and torch.equal(bd["img"], o[2])
+               for bd, o in zip(batch.subbands, outs))
+    launches = batch.describe()
+    batch.close()
+    tuned = nb.Batch(xyz, subs, graph=True, autotune=True, ctx=ctx)
+    ms_tuned = timed(tuned.run, k)
+    desc = json.loads(tuned.describe())
+    log(f"[bench] batched graph (autotuned): {ms_tuned:.2f} ms")
+    tuned.close()
+    n_ch = sum(d["n_chan"] for d in subs)
+    ops = sum(8.0 * nprod * d["n_spec"] * d["n_chan"] for d in subs)
+    return {
+        "workload": "12 sub-bands x 1024 channels, 352 ant x 2 pol, FFT 2^14..2^18, T 128..8, "
+                    "GRID 128^2..512^2 (channelize + correlate + image)",
+        "per_subband_ms": round(ms_per, 3), "batched_graph_ms": round(ms_batch, 3),
+        "batched_graph_autotuned_ms": round(ms_tuned, 3),
+        "speedup_batched": round(ms_per / ms_batch, 3), "speedup_autotuned": round(ms_per / ms_tuned, 3),
+        "fine_channels_per_s_autotuned": round(n_ch / (ms_tuned * 1e-3), 1),
+        "correlated_tops_autotuned": round(ops / (ms_tuned * 1e-3) / 1e12, 3),
+        "batched_equals_per_subband": bool(same),
+        "launches": json.loads(launches)["launches"],
+        "autotuned_choices": [(s["n_fft"], s["n_spec"], s["n_pix"], s["corr_variant"], s["grid_ge"])
+                              for s in desc["subbands"]],
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -118,6 +199,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.batch_only:
+        print(json.dumps(batched_leg(args, nb, torch, nb.nbsi_create(0), dev, synth)))
+        return
     cfg = synth.make_config(2)
     log(f"[bench] generating inputs: {cfg.name}")
     xyz = synth.antenna_layout(cfg.n_ant, cfg.radius_m, cfg.seed_base + 1)
@@ -196,16 +280,29 @@ def main():
         print(json.dumps({"correlate_ms": stage_ms["correlate"], "tops": ops / stage_ms["correlate"] / 1e9}))
         return
 
-    # roofline of the correlator (one kernel per call: the events bracket exactly that launch)
+    # roofline of the correlator (one kernel per call: the events bracket exactly that launch,
+    # on the stream the library launches on, which is torch's current stream)
+    corr_kernel = nb.nbsi_correlate_kernel(n_in, T)
     corr_bytes = C * (2 * n_in * T) + C * nprod * 8          # int8 spectra in + int32 vis out
     achieved = corr_bytes / (stage_ms["correlate"] * 1e-3) / 1e9
-    corr_src = {"name": "correlate_i8_kernel", "files": ["paper_2606_04304_amd/csrc/correlate.hip"]}
-    traffic = traffic_from_profile(corr_src, corr_bytes)
-    roofline = {"kernel": "correlate_i8_kernel", "bound": "hbm", "achieved": round(achieved, 1),
+    traffic = traffic_from_profile(corr_kernel, "paper_2606_04304_amd/csrc/correlate.hip")
+    roofline = {"kernel": corr_kernel, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "algorithmic_bytes_per_launch": corr_bytes,
                 "mfma_frac": round(ops / (stage_ms["correlate"] * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4)}
+    # every stage against the HBM roofline with its algorithmic bytes (reads + writes once)
+    stage_bytes = {
+        # voltages in; int16 staging written, read back and written as int8 by the corner turn
+        "channelize": n_in * T * cfg.n_fft * 2 + 3 * C * n_in * T * 2,
+        "correlate": corr_bytes,
+        # XX and YY of every imaged baseline in, the image out
+        "image": int(plan.n_baselines().sum()) * 16 + C * n_pix * n_pix * 4,
+        "detect": C * n_pix * n_pix * 4,
+    }
+    stage_roof = {k: {"algorithmic_bytes": int(v), "gbs": round(v / (stage_ms[k] * 1e-3) / 1e9, 1),
+                      "frac_of_hbm": round(v / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                  for k, v in stage_bytes.items()}
 
     comp = {
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
@@ -213,6 +310,7 @@ def main():
         "imaged_channels_per_s_imager": round(C / (stage_ms["image"] * 1e-3), 1),
         "imaged_channels_per_s_end_to_end": round(C / (ms_step * 1e-3), 1),
         "candidates": int(n_cand),
+        "stage_hbm_roofline": stage_roof,
     }
 
     # ---- plain FP32 path on the same GPU: float spectra, FP32 correlator, float vis ----
@@ -263,6 +361,11 @@ def main():
             "channelize": round(s2["channelize"] / stage_ms["channelize"], 3),
         }
         log("[bench] fp32 path timed")
+
+    if not args.no_batch:
+        del volt
+        torch.cuda.empty_cache()
+        comp["batched_subbands"] = batched_leg(args, nb, torch, ctx, dev, synth)
 
     out = {
         "metric": "correlated fine-channel TOPS + imaged channels/s @256^2 vs plain FP32 path",

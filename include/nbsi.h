@@ -124,6 +124,11 @@ int nbsi_channelize(nbsi_ctx *ctx, const int8_t *volt, int n_in, int n_fft, int 
 int nbsi_correlate(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, int n_spec,
                    int32_t *vis);
 
+/* Name of the kernel nbsi_correlate runs for this shape (a static string; host only):
+ * "correlate_i8_chan_kernel<32>" / "<64>" (short integrations: one workgroup holds a whole
+ * channel) or "correlate_i8_kernel" (128 x 128 tiles). */
+const char *nbsi_correlate_kernel(int n_in, int n_spec);
+
 /* The same product from float32 spectra (the plain FP32 path): vis in float32, same layout. */
 int nbsi_correlate_f32(nbsi_ctx *ctx, const float *spec_f, int n_chan, int n_in, int n_spec,
                        float *vis);
@@ -219,6 +224,56 @@ int nbsi_batch_run(nbsi_batch *plan);
 /* JSON text of the per-sub-band choices (correlator variant, gridding tile) into buf[len]. */
 int nbsi_batch_describe(const nbsi_batch *plan, char *buf, int len);
 int nbsi_batch_destroy(nbsi_batch *plan);
+
+
+/*
+ * Learned candidate classifier (stands in for the paper's Stage II screen of Stage I
+ * candidates, Sec. 2.4, which rejects extended, horizon-hugging and image-wide structures; the
+ * network itself is not in the paper).  A candidate is scored from a stamp of the detector's SNR
+ * cube: 33 channels (c - 16 .. c + 16) by 9 x 9 pixels centred on (c, y, x), zero outside the
+ * cube, FP16, layout [33][9][9].  Network: conv3x3(33->32)-ReLU-conv3x3(32->64)-ReLU-
+ * conv3x3(64->32)-ReLU, zero padding 1, global average pool, linear(32->1) -> logit (label 1 =
+ * sky-localised narrowband tone).  Loss: mean binary cross-entropy on the logit.  Products run
+ * on FP16 matrix cores with FP32 accumulation; master weights, Adam moments and gradients are
+ * FP32.  Parameters are one float vector of NBSI_NET_NPARAM entries in the order
+ *   W1[32][33][3][3], b1[32], W2[64][32][3][3], b2[64], W3[32][64][3][3], b3[32], w4[32], b4[1]
+ * (a convolution is a cross-correlation: Z[o][y][x] = b[o] + sum W[o][i][dy][dx] X[i][y+dy-1][x+dx-1]).
+ * All calls are asynchronous on the context's stream unless stated otherwise.
+ */
+#define NBSI_STAMP_CHANNELS 33
+#define NBSI_STAMP_PIXELS 9
+#define NBSI_NET_NPARAM 46529
+#define NBSI_NET_MAX_BATCH 8192
+
+typedef struct nbsi_net nbsi_net;
+
+/* Stamps of cube [n_chan][n_pix][n_pix] float32 (device) around cands[n] (device, nbsi_cand)
+ * into stamps [n][33][9][9] (device, FP16 bits, round to nearest even, saturating at +-65504). */
+int nbsi_stamps(nbsi_ctx *ctx, const float *cube, int n_chan, int n_pix, const nbsi_cand *cands, int n,
+                uint16_t *stamps);
+/* Network with the given parameters (host, NBSI_NET_NPARAM floats) and device buffers for
+ * batches of up to max_batch stamps (<= NBSI_NET_MAX_BATCH).  Adam state starts at zero. */
+int nbsi_net_create(nbsi_ctx *ctx, const float *params_host, int max_batch, nbsi_net **net);
+int nbsi_net_destroy(nbsi_net *net);
+/* Replace the parameters (host) and reset Adam's moments and step count; blocking. */
+int nbsi_net_set_params(nbsi_net *net, const float *params_host);
+/* Copy the FP32 master parameters to the host; blocking. */
+int nbsi_net_get_params(nbsi_net *net, float *params_host);
+/* Logits of a batch: stamps [n_stamps][33][9][9] FP16 (device, 8-byte aligned); the batch is
+ * stamps index[0..n) (device int32; out-of-range entries read as empty stamps) or, with
+ * index NULL, the first n stamps (n <= n_stamps).  logits: device float [n]. */
+int nbsi_net_forward(nbsi_net *net, const uint16_t *stamps, int n_stamps, const int32_t *index, int n, float *logits);
+/* Mean loss and gradient of a batch: labels (device float, 0 or 1) are indexed like the stamps;
+ * loss: device float [1] or NULL; grad: device float [NBSI_NET_NPARAM] or NULL (the network's
+ * own gradient buffer, used by nbsi_net_adam with grad NULL). */
+int nbsi_net_grad(nbsi_net *net, const uint16_t *stamps, int n_stamps, const int32_t *index, const float *labels, int n,
+                  float *loss, float *grad);
+/* One Adam step (Kingma & Ba) on the master parameters with the device gradient grad (NULL: the
+ * network's own buffer); the step count advances by one. */
+int nbsi_net_adam(nbsi_net *net, const float *grad, float lr, float beta1, float beta2, float eps);
+/* nbsi_net_grad into the network's buffer, then nbsi_net_adam(lr, 0.9, 0.999, 1e-8). */
+int nbsi_net_train_step(nbsi_net *net, const uint16_t *stamps, int n_stamps, const int32_t *index, const float *labels,
+                        int n, float lr, float *loss);
 
 #ifdef __cplusplus
 }

@@ -169,3 +169,4 @@ def tri_index(i, j):
 
 
 from . import detect  # noqa: E402  (numpy detector oracle)
+from . import net  # noqa: E402  (numpy classifier oracle)

@@ -39,8 +39,14 @@ EXPORTS = [
     "nbsi_check_image", "nbsi_check_detect", "nbsi_channelize", "nbsi_correlate",
     "nbsi_correlate_f32", "nbsi_image_plan_create", "nbsi_image_plan_destroy",
     "nbsi_image_plan_nbase", "nbsi_image", "nbsi_detect", "nbsi_batch_plan", "nbsi_batch_run",
-    "nbsi_batch_describe", "nbsi_batch_destroy",
+    "nbsi_batch_describe", "nbsi_batch_destroy", "nbsi_stamps", "nbsi_net_create", "nbsi_net_destroy",
+    "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
+    "nbsi_net_train_step", "nbsi_correlate_kernel",
 ]
+NBSI_STAMP_CHANNELS = 33
+NBSI_STAMP_PIXELS = 9
+NBSI_NET_NPARAM = 46529
+NBSI_NET_MAX_BATCH = 8192
 NBSI_BATCH_GRAPH = 1
 NBSI_BATCH_AUTOTUNE = 2
 NBSI_BATCH_GRID_TALL = 4
@@ -93,6 +99,18 @@ def lib():
         L.nbsi_batch_run.argtypes = [P]
         L.nbsi_batch_describe.argtypes = [P, ctypes.c_char_p, I]
         L.nbsi_batch_destroy.argtypes = [P]
+        L.nbsi_correlate_kernel.argtypes = [I, I]
+        L.nbsi_correlate_kernel.restype = ctypes.c_char_p
+        F = ctypes.c_float
+        L.nbsi_stamps.argtypes = [P, P, I, I, P, I, P]
+        L.nbsi_net_create.argtypes = [P, P, I, ctypes.POINTER(P)]
+        L.nbsi_net_destroy.argtypes = [P]
+        L.nbsi_net_set_params.argtypes = [P, P]
+        L.nbsi_net_get_params.argtypes = [P, P]
+        L.nbsi_net_forward.argtypes = [P, P, I, P, I, P]
+        L.nbsi_net_grad.argtypes = [P, P, I, P, P, I, P, P]
+        L.nbsi_net_adam.argtypes = [P, P, F, F, F, F]
+        L.nbsi_net_train_step.argtypes = [P, P, I, P, P, I, F, P]
         _lib = L
     return _lib
 
@@ -188,6 +206,11 @@ def nbsi_correlate(spec_q, vis=None, ctx: Context | None = None):
     ctx._sync_stream()
     _check(lib().nbsi_correlate(ctx._h, _ptr(spec_q), n_chan, n_in, n_spec, _ptr(vis)), ctx)
     return vis
+
+
+def nbsi_correlate_kernel(n_in: int, n_spec: int) -> str:
+    """Name of the kernel nbsi_correlate runs for this shape."""
+    return lib().nbsi_correlate_kernel(int(n_in), int(n_spec)).decode()
 
 
 def nbsi_correlate_f32(spec_f, vis=None, ctx: Context | None = None):
@@ -381,3 +404,111 @@ def nbsi_batch_describe(batch: Batch) -> str:
 
 def nbsi_batch_destroy(batch: Batch) -> None:
     batch.close()
+
+
+def nbsi_stamps(cube, cands, stamps=None, ctx: Context | None = None):
+    """cube [n_chan][n_pix][n_pix] float32, cands: int32 device tensor [n][5] (nbsi_cand records,
+    as nbsi_detect returns them) -> stamps [n][33][9][9] float16."""
+    torch = _torch()
+    ctx = ctx or nbsi_create(cube.device.index or 0)
+    _need(cube, torch.float32, "cube", ctx.device)
+    _need(cands, torch.int32, "cands", ctx.device)
+    if cands.dim() != 2 or cands.shape[1] != 5:
+        raise ValueError("cands must be [n][5] int32 records (x, y, c, width, snr bits)")
+    n = cands.shape[0]
+    if stamps is None:
+        stamps = torch.empty((n, NBSI_STAMP_CHANNELS, NBSI_STAMP_PIXELS, NBSI_STAMP_PIXELS), dtype=torch.float16,
+                             device=ctx.device)
+    _need(stamps, torch.float16, "stamps", ctx.device)
+    ctx._sync_stream()
+    _check(lib().nbsi_stamps(ctx._h, _ptr(cube), cube.shape[0], cube.shape[1], _ptr(cands), n, _ptr(stamps)), ctx)
+    return stamps
+
+
+class Net:
+    """nbsi_net_*: the candidate classifier with its FP32 master parameters and Adam state."""
+
+    def __init__(self, params, max_batch: int = 1024, ctx: Context | None = None):
+        self.ctx = ctx or nbsi_create(0)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != NBSI_NET_NPARAM:
+            raise ValueError(f"params must have {NBSI_NET_NPARAM} entries")
+        self.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        self.ctx._sync_stream()
+        _check(lib().nbsi_net_create(self.ctx._h, p.ctypes.data_as(ctypes.c_void_p), self.max_batch,
+                                     ctypes.byref(h)), self.ctx)
+        self._h = h
+
+    def _stamps(self, stamps, index, n):
+        torch = _torch()
+        _need(stamps, torch.float16, "stamps", self.ctx.device)
+        if index is not None:
+            _need(index, torch.int32, "index", self.ctx.device)
+            n = index.numel() if n is None else n
+        else:
+            n = stamps.shape[0] if n is None else n
+        return n
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self.ctx._sync_stream()
+        _check(lib().nbsi_net_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p)), self.ctx)
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(NBSI_NET_NPARAM, dtype=np.float32)
+        self.ctx._sync_stream()
+        _check(lib().nbsi_net_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p)), self.ctx)
+        return out
+
+    def forward(self, stamps, index=None, n=None, logits=None):
+        torch = _torch()
+        n = self._stamps(stamps, index, n)
+        if logits is None:
+            logits = torch.empty(n, dtype=torch.float32, device=self.ctx.device)
+        self.ctx._sync_stream()
+        _check(lib().nbsi_net_forward(self._h, _ptr(stamps), stamps.shape[0], _ptr(index), n, _ptr(logits)),
+               self.ctx)
+        return logits
+
+    def grad(self, stamps, labels, index=None, n=None, grad=None):
+        """(loss tensor [1], gradient tensor [NBSI_NET_NPARAM]) of a batch."""
+        torch = _torch()
+        n = self._stamps(stamps, index, n)
+        _need(labels, torch.float32, "labels", self.ctx.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.ctx.device)
+        if grad is None:
+            grad = torch.empty(NBSI_NET_NPARAM, dtype=torch.float32, device=self.ctx.device)
+        self.ctx._sync_stream()
+        _check(lib().nbsi_net_grad(self._h, _ptr(stamps), stamps.shape[0], _ptr(index), _ptr(labels), n, _ptr(loss),
+                                   _ptr(grad)), self.ctx)
+        return loss, grad
+
+    def adam(self, grad=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.ctx._sync_stream()
+        _check(lib().nbsi_net_adam(self._h, _ptr(grad), float(lr), float(beta1), float(beta2), float(eps)),
+               self.ctx)
+
+    def train_step(self, stamps, labels, index=None, n=None, lr=1e-3, loss=None):
+        torch = _torch()
+        n = self._stamps(stamps, index, n)
+        _need(labels, torch.float32, "labels", self.ctx.device)
+        self.ctx._sync_stream()
+        _check(lib().nbsi_net_train_step(self._h, _ptr(stamps), stamps.shape[0], _ptr(index), _ptr(labels), n,
+                                         float(lr), _ptr(loss)), self.ctx)
+        return loss
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nbsi_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nbsi_net_create(params, max_batch=1024, ctx=None) -> Net:
+    return Net(params, max_batch, ctx)

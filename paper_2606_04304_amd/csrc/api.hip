@@ -143,6 +143,14 @@ int nbsi_check_detect(int n_chan, int n_pix, int mode, int max_out) {
     return NBSI_OK;
 }
 
+const char *nbsi_correlate_kernel(int n_in, int n_spec) {
+    switch (correlate_default_variant(n_in, n_spec)) {
+        case CORR_VARIANT_CHAN32: return "correlate_i8_chan_kernel<32>";
+        case CORR_VARIANT_CHAN64: return "correlate_i8_chan_kernel<64>";
+        default: return "correlate_i8_kernel";
+    }
+}
+
 int nbsi_create(nbsi_ctx **out, int device, void *stream) {
     if (!out) return NBSI_EINVAL;
     *out = nullptr;

@@ -263,3 +263,144 @@ def random_spectra(n_chan: int, n_in: int, n_spec: int, seed: int, sigma_q: floa
                              device=device, dtype=torch.int16).to(torch.int8)
     x = torch.randn((n_chan, n_in, 2, n_spec), generator=gen, device=device) * sigma_q
     return torch.round(x).clamp_(-127, 127).to(torch.int8)
+
+
+# ---------------------------------------------------------------------------------------------
+# Learned-classifier inputs: initial weights and injected sky tones, RFI and broadband spikes
+# ---------------------------------------------------------------------------------------------
+NET_SHAPES = [(32, 33), (64, 32), (32, 64)]  # (out, in) channels of the three 3 x 3 convolutions
+
+
+def net_init(seed: int) -> np.ndarray:
+    """Initial classifier parameters (flat float32, the documented order): convolution and
+    linear weights uniform in +-sqrt(6 / fan_in) (He), biases zero."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for co, ci in NET_SHAPES:
+        lim = math.sqrt(6.0 / (ci * 9))
+        parts.append(rng.uniform(-lim, lim, size=co * ci * 9))
+        parts.append(np.zeros(co))
+    parts.append(rng.uniform(-math.sqrt(6.0 / 32), math.sqrt(6.0 / 32), size=32))
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
+
+
+@dataclass
+class Source:
+    c: int        # fine channel
+    l: float
+    m: float
+    amp: float    # image-plane peak (visibility amplitude on every baseline)
+
+
+KIND_TONE, KIND_RFI, KIND_SPIKE, KIND_NOISE = 0, 1, 2, 3
+
+
+def pixel_lm(x: float, y: float, n_pix: int):
+    return (x - n_pix / 2) * 2.0 / n_pix, (y - n_pix / 2) * 2.0 / n_pix
+
+
+def classifier_scene(rng: np.random.Generator, n_chan: int, n_pix: int, sigma_img: float,
+                     n_tone: int, n_rfi: int, n_spike: int):
+    """Random injections for one cube, as (kind, centre (c, x, y), [Source]) triples.
+
+    * tone: one channel, a point source anywhere with l^2 + m^2 < 0.8^2, SNR 5-20;
+    * RFI: near the horizon (0.88 < sqrt(l^2 + m^2) < 0.96), 3-6 point components within
+      2.5 pixels of a centre, present in 1-8 consecutive channels and drifting by 0.5-1.5
+      pixels per channel, SNR 6-30 per component;
+    * broadband spike: one point source anywhere with l^2 + m^2 < 0.9^2 in 12-33 consecutive
+      channels at a steady SNR 6-20.
+    Injections keep 40 channels or 12 pixels from each other so stamps do not mix them."""
+    taken = []
+
+    def free(c0, c1, x, y):
+        for (a0, a1, xx, yy) in taken:
+            if c0 <= a1 + 40 and a0 <= c1 + 40 and abs(x - xx) < 12 and abs(y - yy) < 12:
+                return False
+        return 20 <= c0 and c1 < n_chan - 20
+
+    out = []
+
+    def place(kind, n_ch, r_lo, r_hi):
+        for _ in range(200):
+            c0 = int(rng.integers(20, n_chan - 20 - n_ch))
+            r = math.sqrt(rng.uniform(r_lo * r_lo, r_hi * r_hi))
+            th = rng.uniform(0, 2 * math.pi)
+            x = n_pix / 2 + r * math.cos(th) * n_pix / 2
+            y = n_pix / 2 + r * math.sin(th) * n_pix / 2
+            if free(c0, c0 + n_ch - 1, x, y):
+                taken.append((c0, c0 + n_ch - 1, x, y))
+                return c0, x, y
+        return None
+
+    for _ in range(n_tone):
+        p = place(KIND_TONE, 1, 0.0, 0.8)
+        if p:
+            c0, x, y = p
+            l, m = pixel_lm(x, y, n_pix)
+            out.append((KIND_TONE, (c0, x, y), [Source(c0, l, m, rng.uniform(5, 20) * sigma_img)]))
+    for _ in range(n_rfi):
+        n_ch = int(rng.integers(1, 9))
+        p = place(KIND_RFI, n_ch, 0.88, 0.96)
+        if p:
+            c0, x, y = p
+            comps = [(rng.uniform(-2.5, 2.5), rng.uniform(-2.5, 2.5), rng.uniform(6, 30))
+                     for _ in range(int(rng.integers(3, 7)))]
+            th = rng.uniform(0, 2 * math.pi)
+            step = rng.uniform(0.5, 1.5)
+            srcs = []
+            for k in range(n_ch):
+                for (dx, dy, snr) in comps:
+                    l, m = pixel_lm(x + dx + k * step * math.cos(th), y + dy + k * step * math.sin(th), n_pix)
+                    srcs.append(Source(c0 + k, l, m, snr * sigma_img))
+            out.append((KIND_RFI, (c0, x, y), srcs))
+    for _ in range(n_spike):
+        n_ch = int(rng.integers(12, 34))
+        p = place(KIND_SPIKE, n_ch, 0.0, 0.9)
+        if p:
+            c0, x, y = p
+            l, m = pixel_lm(x, y, n_pix)
+            amp = rng.uniform(6, 20) * sigma_img
+            out.append((KIND_SPIKE, (c0, x, y), [Source(c0 + k, l, m, amp) for k in range(n_ch)]))
+    return out
+
+
+def add_sources(vis_f, ant_xyz: np.ndarray, freq: np.ndarray, sources, chunk: int = 64):
+    """Add point sources to float32 visibilities vis_f [n_chan][n_in (n_in+1)/2][2] (torch, in
+    place): the XX and YY products of every antenna pair a > b receive
+    amp exp(+2 pi i nu ((x_a - x_b) l + (y_a - y_b) m) / c), the autocorrelations amp."""
+    import torch
+    dev = vis_f.device
+    n_ant = ant_xyz.shape[0]
+    a, b = np.tril_indices(n_ant)          # a >= b
+    dx = torch.tensor(ant_xyz[a, 0] - ant_xyz[b, 0], dtype=torch.float64, device=dev)
+    dy = torch.tensor(ant_xyz[a, 1] - ant_xyz[b, 1], dtype=torch.float64, device=dev)
+    idx = []
+    for p in (0, 1):
+        i, j = 2 * a + p, 2 * b + p
+        idx.append(torch.tensor(i * (i + 1) // 2 + j, dtype=torch.long, device=dev))
+    # sources sharing a channel go to different passes, so no pass adds twice to one product
+    # (the sums are then independent of scheduling)
+    passes, seen = [], {}
+    for src in sources:
+        k = seen.get(src.c, 0)
+        seen[src.c] = k + 1
+        while len(passes) <= k:
+            passes.append([])
+        passes[k].append(src)
+    flat = vis_f.view(-1, 2)
+    for group in passes:
+        for s0 in range(0, len(group), chunk):
+            grp = group[s0:s0 + chunk]
+            ch = torch.tensor([s.c for s in grp], dtype=torch.long, device=dev)
+            nu = torch.tensor([freq[s.c] for s in grp], dtype=torch.float64, device=dev)
+            l = torch.tensor([s.l for s in grp], dtype=torch.float64, device=dev)
+            m = torch.tensor([s.m for s in grp], dtype=torch.float64, device=dev)
+            amp = torch.tensor([s.amp for s in grp], dtype=torch.float64, device=dev)
+            turns = (nu / C_LIGHT)[:, None] * (dx[None, :] * l[:, None] + dy[None, :] * m[:, None])
+            turns = turns - torch.floor(turns)
+            upd = torch.stack([amp[:, None] * torch.cos(2 * math.pi * turns),
+                               amp[:, None] * torch.sin(2 * math.pi * turns)], dim=-1).float()
+            for ix in idx:
+                rows = (ch[:, None] * vis_f.shape[1] + ix[None, :]).reshape(-1)
+                flat.index_copy_(0, rows, flat.index_select(0, rows) + upd.reshape(-1, 2))
