@@ -153,6 +153,15 @@ def scores(net: Net, stamps, batch: int | None = None) -> np.ndarray:
     return out.cpu().numpy()
 
 
+def operating_point(logits: np.ndarray, labels: np.ndarray, keep: float = 0.95) -> float:
+    """Logit threshold that accepts the fraction `keep` of the positive examples (chosen on data
+    held out from training)."""
+    pos = np.sort(np.asarray(logits)[np.asarray(labels) > 0.5])
+    if pos.size == 0:
+        return 0.0
+    return float(pos[int(np.floor((1.0 - keep) * pos.size))]) - 1e-6
+
+
 def precision_recall(accept: np.ndarray, labels: np.ndarray, tone_ids: np.ndarray, tones_injected: int):
     """Precision over the accepted candidates; recall over the injected tones (a tone is
     recovered when any of its candidates is accepted)."""

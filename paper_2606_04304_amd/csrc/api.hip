@@ -14,7 +14,6 @@ int detect_ppw(int n_chan);
 namespace {
 
 constexpr double C_LIGHT = 299792458.0;
-constexpr size_t IMAGE_CHUNK_BYTES = (size_t)128 << 20;
 
 struct DeviceGuard {
     int prev = -1;

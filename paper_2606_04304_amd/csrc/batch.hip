@@ -16,6 +16,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 int correlate_batch_tasks(const CorrJob &jb, int variant);
@@ -29,11 +30,14 @@ struct nbsi_batch {
     std::vector<int> corr_variant, grid_ge;
     std::vector<void *> owned;  // device allocations of the batch
     std::vector<int8_t *> stage;
-    std::vector<float2 *> cvis, inter;
+    std::vector<float2 *> cvis;
+    float2 *inter = nullptr;       // one imaging chunk's row-pass intermediate
+    int *d_counters = nullptr;     // one work-queue counter per launch
 
     struct Launch {  // one persistent launch: kind, shape key, job array on the device
         int kind;    // 0 channelize, 1 corner turn, 2 correlate, 3 gather, 4 rows, 5 cols
         int a = 0, b = 0;  // kind-specific shape (log_m/g, variant, log_m/ge)
+        int counter = 0;   // index into d_counters
         int n_jobs = 0, n_tasks = 0, n_groups = 0, max_dyn = 0;
         void *d_jobs = nullptr;
         int *d_task0 = nullptr;
@@ -50,6 +54,11 @@ struct nbsi_batch {
 };
 
 namespace {
+
+__global__ void zero_counters_kernel(int *c, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = 0;
+}
 
 int n_cu(int device) {
     hipDeviceProp_t prop;
@@ -131,30 +140,37 @@ hipError_t enqueue_channelize_one(nbsi_batch *b, int s, hipStream_t st) {
     return launch_corner_turn_q(b->stage[s], b->n_in, x.n_spec, x.n_chan, x.spec_q, st);
 }
 
-// Every stage of every sub-band, as the grouped persistent launches.
+// Every stage of every sub-band, as the grouped persistent launches (the work-queue counters are
+// zeroed by a kernel first, so a captured graph resets them on every replay).
 hipError_t enqueue_all(nbsi_batch *b, hipStream_t st) {
+    const int n_l = (int)b->launches.size();
+    hipLaunchKernelGGL(zero_counters_kernel, dim3((n_l + 255) / 256), dim3(256), 0, st, b->d_counters, n_l);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     for (const auto &L : b->launches) {
         hipError_t e = hipSuccess;
+        int *ctr = b->d_counters + L.counter;
         switch (L.kind) {
             case 0:
-                e = launch_channelize_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, L.b, L.max_dyn,
+                e = launch_channelize_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.a, L.b, L.max_dyn,
                                             L.n_groups, st);
                 break;
             case 1:
-                e = launch_corner_turn_q_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.d_task0, L.n_tasks, L.d_outs,
+                e = launch_corner_turn_q_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.d_task0, L.n_tasks, ctr, L.d_outs,
                                                b->n_in, L.n_groups, st);
                 break;
             case 2:
-                e = launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->n_in, L.n_groups,
-                                           st);
+                e = launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.a, b->n_in,
+                                           L.n_groups, st);
                 break;
-            case 3: e = launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.n_groups, st); break;
+            case 3:
+                e = launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.n_groups, st);
+                break;
             case 4:
-                e = launch_image_batch_rows((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->precision, L.b,
+                e = launch_image_batch_rows((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.a, b->precision, L.b,
                                             L.n_groups, st);
                 break;
             case 5:
-                e = launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.b, L.n_groups, st);
+                e = launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.b, L.n_groups, st);
                 break;
         }
         if (e != hipSuccess) return e;
@@ -164,12 +180,13 @@ hipError_t enqueue_all(nbsi_batch *b, hipStream_t st) {
 
 int build_launches(nbsi_batch *b) {
     const int cus = n_cu(b->device);
-    // channelize: group by (log_m, g)
-    std::map<std::pair<int, int>, std::vector<int>> cg;
+    // channelize: one launch per (sub-transform size, load grouping, FFT length): the table LDS is
+    // sized by the FFT length, and one size per launch keeps the occupancy of the shorter ones
+    std::map<std::tuple<int, int, int>, std::vector<int>> cg;
     for (int s = 0; s < b->n_sb; s++) {
         const int log_n = 31 - __builtin_clz(b->sb[s].n_fft);
         const int lm = channelize_log_m(log_n, b->sb[s].n_chan);
-        cg[{lm, (log_n - lm) >= 1 ? 2 : 1}].push_back(s);
+        cg[std::make_tuple(lm, channelize_group(log_n, lm), log_n)].push_back(s);
     }
     for (auto &kv : cg) {
         std::vector<ChanJob> jobs;
@@ -181,12 +198,12 @@ int build_launches(nbsi_batch *b) {
                       x.n_chan, tasks};
             jobs.push_back(j);
             tasks += b->n_in * x.n_spec;
-            max_dyn = std::max(max_dyn, channelize_dyn_elems(log_n, kv.first.first));
+            max_dyn = std::max(max_dyn, channelize_dyn_elems(log_n, std::get<0>(kv.first)));
         }
         nbsi_batch::Launch L;
         L.kind = 0;
-        L.a = kv.first.first;
-        L.b = kv.first.second;
+        L.a = std::get<0>(kv.first);
+        L.b = std::get<1>(kv.first);
         L.n_jobs = (int)jobs.size();
         L.n_tasks = tasks;
         L.max_dyn = max_dyn;
@@ -258,7 +275,7 @@ int build_launches(nbsi_batch *b) {
         j.nb = p->d_nb;
         j.corr = p->d_corr;
         j.cvis = b->cvis[s];
-        j.inter = b->inter[s];
+        j.inter = b->inter;
         j.img = b->sb[s].img;
         j.n_pairs = p->n_pairs;
         j.n_ant = p->n_ant;
@@ -285,52 +302,81 @@ int build_launches(nbsi_batch *b) {
         if (rc) return rc;
         b->launches.push_back(L);
     }
+    // rows and columns: channel chunks of every sub-band of one (transform size, tile height),
+    // each chunk's intermediate within IMAGE_CHUNK_BYTES; a chunk's rows launch is followed by
+    // its columns launch, which finds the intermediate still in the last-level cache
     std::map<std::pair<int, int>, std::vector<int>> rg;
-    std::map<int, std::vector<int>> og;
-    for (int s = 0; s < b->n_sb; s++) {
-        rg[{base[s].log_m, b->grid_ge[s]}].push_back(s);
-        og[b->grid_ge[s]].push_back(s);
-    }
+    for (int s = 0; s < b->n_sb; s++) rg[{base[s].log_m, b->grid_ge[s]}].push_back(s);
     for (auto &kv : rg) {
-        std::vector<ImgJob> jobs;
-        int tasks = 0;
+        const int ge = kv.first.second;
+        std::vector<ImgJob> chunk;
+        size_t used = 0;
+        auto flush = [&]() -> int {
+            if (chunk.empty()) return NBSI_OK;
+            std::vector<ImgJob> rows = chunk, cols = chunk;
+            int rt = 0, ct = 0;
+            for (size_t q = 0; q < chunk.size(); q++) {
+                rows[q].rows_task0 = rt;
+                rt += chunk[q].n_chan * chunk[q].n_bands;
+                cols[q].cols_task0 = ct;
+                const int band_cols = 256 * ge / (2 * chunk[q].n_pix);
+                ct += chunk[q].n_chan * (chunk[q].n_pix / band_cols);
+            }
+            nbsi_batch::Launch R;
+            R.kind = 4;
+            R.a = kv.first.first;
+            R.b = ge;
+            R.n_jobs = (int)rows.size();
+            R.n_tasks = rt;
+            R.n_groups = std::min(rt, cus * (ge == 32 ? 2 : 4));
+            int rc = upload(b, rows, (ImgJob **)&R.d_jobs);
+            if (rc) return rc;
+            b->launches.push_back(R);
+            nbsi_batch::Launch C;
+            C.kind = 5;
+            C.b = ge;
+            C.n_jobs = (int)cols.size();
+            C.n_tasks = ct;
+            C.n_groups = std::min(ct, cus * (ge == 32 ? 2 : 4));
+            rc = upload(b, cols, (ImgJob **)&C.d_jobs);
+            if (rc) return rc;
+            b->launches.push_back(C);
+            chunk.clear();
+            used = 0;
+            return NBSI_OK;
+        };
         for (int s : kv.second) {
-            ImgJob j = base[s];
-            j.rows_task0 = tasks;
-            tasks += j.n_chan * j.n_bands;
-            jobs.push_back(j);
+            const ImgJob &j = base[s];
+            const size_t per_chan = (size_t)j.n_pix * 2 * j.n_pix * sizeof(float2);
+            const size_t nb = (size_t)j.n_pix * j.n_pix;
+            for (int c0 = 0; c0 < j.n_chan;) {
+                if (used + per_chan > IMAGE_CHUNK_BYTES && !chunk.empty()) {
+                    const int rc = flush();
+                    if (rc) return rc;
+                }
+                const int fit = (int)std::max<size_t>(1, (IMAGE_CHUNK_BYTES - std::min(used, IMAGE_CHUNK_BYTES)) / per_chan);
+                const int n = std::min(j.n_chan - c0, fit);
+                ImgJob q = j;  // channels [c0, c0 + n) of this sub-band, pointers moved to them
+                q.freq = j.freq + c0;
+                q.nb = j.nb + c0;
+                q.cvis = j.cvis + (size_t)c0 * std::max(1, j.n_pairs);
+                q.inter = b->inter + used / sizeof(float2);
+                q.img = j.img + (size_t)c0 * nb;
+                q.n_chan = n;
+                chunk.push_back(q);
+                used += per_chan * n;
+                c0 += n;
+            }
         }
-        nbsi_batch::Launch L;
-        L.kind = 4;
-        L.a = kv.first.first;
-        L.b = kv.first.second;
-        L.n_jobs = (int)jobs.size();
-        L.n_tasks = tasks;
-        L.n_groups = std::min(tasks, cus * (kv.first.second == 32 ? 2 : 4));
-        int rc = upload(b, jobs, (ImgJob **)&L.d_jobs);
+        const int rc = flush();
         if (rc) return rc;
-        b->launches.push_back(L);
     }
-    for (auto &kv : og) {
-        std::vector<ImgJob> jobs;
-        int tasks = 0;
-        for (int s : kv.second) {
-            ImgJob j = base[s];
-            j.cols_task0 = tasks;
-            const int band_cols = 256 * kv.first / (2 * j.n_pix);
-            tasks += j.n_chan * (j.n_pix / band_cols);
-            jobs.push_back(j);
-        }
-        nbsi_batch::Launch L;
-        L.kind = 5;
-        L.b = kv.first;
-        L.n_jobs = (int)jobs.size();
-        L.n_tasks = tasks;
-        L.n_groups = std::min(tasks, cus * (kv.first == 32 ? 2 : 4));
-        int rc = upload(b, jobs, (ImgJob **)&L.d_jobs);
-        if (rc) return rc;
-        b->launches.push_back(L);
-    }
+    for (size_t q = 0; q < b->launches.size(); q++) b->launches[q].counter = (int)q;
+    int *ctr = nullptr;
+    std::vector<int> zeros(b->launches.size(), 0);
+    const int rc = upload(b, zeros, &ctr);
+    if (rc) return rc;
+    b->d_counters = ctr;
     return NBSI_OK;
 }
 
@@ -491,11 +537,16 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
                                    INFINITY, ge, &p)))
             return fail(rc, "plan failed");
         b->plans.push_back(p);
-        void *cv = nullptr, *in = nullptr;
+        void *cv = nullptr;
         if ((rc = alloc(b, sizeof(float2) * (size_t)x.n_chan * std::max(1, p->n_pairs), &cv))) return fail(rc, "oom");
-        if ((rc = alloc(b, (size_t)x.n_pix * 2 * x.n_pix * sizeof(float2) * x.n_chan, &in))) return fail(rc, "oom");
         b->cvis.push_back((float2 *)cv);
-        b->inter.push_back((float2 *)in);
+    }
+    {
+        size_t need = IMAGE_CHUNK_BYTES;
+        for (int s = 0; s < n_sb; s++) need = std::max(need, (size_t)b->sb[s].n_pix * 2 * b->sb[s].n_pix * sizeof(float2));
+        void *in = nullptr;
+        if ((rc = alloc(b, need, &in))) return fail(rc, "oom");
+        b->inter = (float2 *)in;
     }
     if (cache_dirty) write_cache(tune_cache_path, cache);
     if ((rc = build_launches(b))) return fail(rc, "launch tables failed");

@@ -16,6 +16,8 @@
 #include "internal.h"
 #include "fft_dev.h"
 
+#include <algorithm>
+
 
 namespace {
 
@@ -103,6 +105,8 @@ __device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, in
                                                     const TwiddleTable &tw) {
     using PL = Plan<LOGM>;
     constexpr int M = PL::M, NT = PL::NT, R0 = PL::R0;
+    constexpr int DW = G >= 4 ? G / 2 : 1;  // dwords of raw samples per element
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8, "load grouping");
     const int t = threadIdx.x;
     const int log_n = jb.log_n, n_spec = jb.n_spec, klo = jb.klo, n_chan = jb.n_chan;
     const int N = 1 << log_n;
@@ -131,15 +135,32 @@ __device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, in
     for (int r = 0; r < E; r++) acc[r] = make_float2(0.f, 0.f);
 
     for (int p0 = 0; p0 < P; p0 += G) {
-        // raw samples of G consecutive sub-transforms: element m = t + NT b + (M/R0) r
-        int raw[E];
+        // raw samples of G consecutive sub-transforms (one 2G-byte load per element: the G
+        // samples x[p0 .. p0 + G - 1 + P m] are adjacent), element m = t + NT b + (M/R0) r.
+        // Loading G sub-transforms' samples at once means each 32-byte segment of the spectrum
+        // is fetched P/G times rather than P/2 times when the workgroups' spectra overflow L2.
+        unsigned raw[E][DW];
 #pragma unroll
         for (int b = 0; b < E / R0; b++)
 #pragma unroll
             for (int r = 0; r < R0; r++) {
                 const int soff = 2 * (p0 + ((NT * b + r * (M / R0)) << log_p));
-                if constexpr (G == 2) raw[b * R0 + r] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0);
-                else raw[b * R0 + r] = (int)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(rsrc, voff, soff, 0);
+                unsigned *w = raw[b * R0 + r];
+                if constexpr (G == 8) {
+                    const auto x = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, soff, 0);
+                    w[0] = x[0];
+                    w[1] = x[1];
+                    w[2] = x[2];
+                    w[3] = x[3];
+                } else if constexpr (G == 4) {
+                    const auto x = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff, soff, 0);
+                    w[0] = x[0];
+                    w[1] = x[1];
+                } else if constexpr (G == 2) {
+                    w[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, voff, soff, 0);
+                } else {
+                    w[0] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, voff, soff, 0);
+                }
             }
 #pragma unroll 1
         for (int g = 0; g < G; g++) {
@@ -155,10 +176,19 @@ __device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, in
                     const float2 wc = w16(b + (16 / R0) * r);
                     const float cs = wb.x * wc.x - wb.y * wc.y;
                     const float w = 0.5f - 0.5f * cs;
-                    const int sample = (G == 2) ? (raw[b * R0 + r] >> (16 * g)) : raw[b * R0 + r];
+                    const int sample = (int)raw[b * R0 + r][0];  // low 16 bits: sub-transform p
                     const float re = (float)(int8_t)(sample & 0xff), im = (float)(int8_t)((sample >> 8) & 0xff);
                     v[b * R0 + r] = make_float2(w * re, w * im);
                 }
+            // move the next sub-transform's samples into the low 16 bits
+            if constexpr (G >= 2) {
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+#pragma unroll
+                    for (int w = 0; w + 1 < DW; w++) raw[e][w] = __builtin_amdgcn_alignbit(raw[e][w + 1], raw[e][w], 16);
+                    raw[e][DW - 1] >>= 16;
+                }
+            }
             // first pass (radix R0, no twiddles)
 #pragma unroll
             for (int b = 0; b < E / R0; b++) dft_r<R0>(v + b * R0);
@@ -225,12 +255,14 @@ __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(ChanJob jb
 // into another sub-band.
 template <int LOGM, int G>
 __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_batch_kernel(const ChanJob *__restrict__ jobs,
-                                                                            int n_jobs, int n_tasks) {
+                                                                            int n_jobs, int n_tasks,
+                                                                            int *__restrict__ counter) {
     __shared__ float2 buf[padded_size(1 << LOGM)];
     extern __shared__ float2 dyn[];
     int cur = -1;
     TwiddleTable tw{};
-    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    __shared__ int s_task;
+    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
         int j = 0;
         while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
         const ChanJob jb = jobs[j];
@@ -279,9 +311,11 @@ __global__ __launch_bounds__(256) void corner_turn_q_kernel(const int16_t *__res
 
 __global__ __launch_bounds__(256) void corner_turn_q_batch_kernel(const ChanJob *__restrict__ jobs, int n_jobs,
                                                                   const int *__restrict__ task0, int n_tasks,
-                                                                  int8_t *const *__restrict__ outs, int n_in) {
+                                                                  int8_t *const *__restrict__ outs, int n_in,
+                                                                  int *__restrict__ counter) {
     __shared__ int16_t tile[64][65];
-    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    __shared__ int s_task;
+    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
         int j = 0;
         while (j + 1 < n_jobs && task0[j + 1] <= task) j++;
         const ChanJob jb = jobs[j];
@@ -325,18 +359,32 @@ hipError_t launch_logm(const ChanJob &jb, int n_in, hipStream_t st) {
     dim3 grid((unsigned)n_in * (unsigned)jb.n_spec);
     const int P = 1 << (jb.log_n - LOGM);
     const size_t lds = sizeof(float2) * chan_dyn_elems(jb.log_n, LOGM);
-    if (P >= 2)
-        hipLaunchKernelGGL((channelize_kernel<LOGM, 2>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
-    else
+    if constexpr (LOGM >= 14) {  // 1024 threads leave 128 VGPRs: wider loads would spill
+        if (P >= 2)
+            hipLaunchKernelGGL((channelize_kernel<LOGM, 2>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+        else
+            hipLaunchKernelGGL((channelize_kernel<LOGM, 1>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+    } else if constexpr (LOGM >= 12) {
+        if (P >= 8)
+            hipLaunchKernelGGL((channelize_kernel<LOGM, 8>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+        else if (P == 4)
+            hipLaunchKernelGGL((channelize_kernel<LOGM, 4>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+        else if (P == 2)
+            hipLaunchKernelGGL((channelize_kernel<LOGM, 2>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+        else
+            hipLaunchKernelGGL((channelize_kernel<LOGM, 1>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+    } else {
+        if (P != 1) return hipErrorInvalidValue;  // a transform shorter than 4096 is never split
         hipLaunchKernelGGL((channelize_kernel<LOGM, 1>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+    }
     return hipGetLastError();
 }
 
 template <int LOGM, int G>
-hipError_t launch_batch_logm(const ChanJob *d_jobs, int n_jobs, int n_tasks, size_t lds, int n_groups,
+hipError_t launch_batch_logm(const ChanJob *d_jobs, int n_jobs, int n_tasks, int *counter, size_t lds, int n_groups,
                              hipStream_t st) {
     hipLaunchKernelGGL((channelize_batch_kernel<LOGM, G>), dim3(n_groups), dim3((1 << LOGM) / 16), lds, st, d_jobs,
-                       n_jobs, n_tasks);
+                       n_jobs, n_tasks, counter);
     return hipGetLastError();
 }
 
@@ -369,28 +417,43 @@ hipError_t launch_channelize(const int8_t *volt, int n_in, int log_n, int n_spec
 
 // Jobs that share one sub-transform size and load grouping (log_m, g) run in one persistent
 // launch; d_jobs holds them with consecutive task ranges.
-hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_tasks, int log_m, int g,
+hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_tasks, int *counter, int log_m, int g,
                                    int max_dyn_elems, int n_groups, hipStream_t st) {
     const size_t lds = sizeof(float2) * (size_t)max_dyn_elems;
-#define NBSI_CB(LM)                                                                      \
-    case LM:                                                                             \
-        return g == 2 ? launch_batch_logm<LM, 2>(d_jobs, n_jobs, n_tasks, lds, n_groups, st) \
-                      : launch_batch_logm<LM, 1>(d_jobs, n_jobs, n_tasks, lds, n_groups, st);
+#define NBSI_CB1(LM) \
+    case LM: return g == 1 ? launch_batch_logm<LM, 1>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st) : hipErrorInvalidValue;
+#define NBSI_CBG(LM)                                                                                  \
+    case LM:                                                                                          \
+        switch (g) {                                                                                  \
+            case 1: return launch_batch_logm<LM, 1>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st); \
+            case 2: return launch_batch_logm<LM, 2>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st); \
+            case 4: return launch_batch_logm<LM, 4>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st); \
+            case 8: return launch_batch_logm<LM, 8>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st); \
+            default: return hipErrorInvalidValue;                                                     \
+        }
     switch (log_m) {
-        NBSI_CB(8) NBSI_CB(9) NBSI_CB(10) NBSI_CB(11) NBSI_CB(12) NBSI_CB(13) NBSI_CB(14)
+        NBSI_CB1(8) NBSI_CB1(9) NBSI_CB1(10) NBSI_CB1(11) NBSI_CBG(12) NBSI_CBG(13)
+        case 14:
+            return g == 2   ? launch_batch_logm<14, 2>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st)
+                   : g == 1 ? launch_batch_logm<14, 1>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st)
+                            : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
-#undef NBSI_CB
+#undef NBSI_CB1
+#undef NBSI_CBG
 }
 
 int channelize_dyn_elems(int log_n, int log_m) { return chan_dyn_elems(log_n, log_m); }
 
+// Sub-transforms whose samples one load covers: min(8, P) (min(2, P) for 16384-point sub-transforms).
+int channelize_group(int log_n, int log_m) { return std::min(log_m >= 14 ? 2 : 8, 1 << (log_n - log_m)); }
+
 int corner_turn_tasks(int n_in, int n_spec, int n_chan) { return n_in * ((n_chan + 63) / 64) * ((n_spec + 63) / 64); }
 
-hipError_t launch_corner_turn_q_batch(const ChanJob *d_jobs, int n_jobs, const int *d_task0, int n_tasks,
+hipError_t launch_corner_turn_q_batch(const ChanJob *d_jobs, int n_jobs, const int *d_task0, int n_tasks, int *counter,
                                       int8_t *const *d_outs, int n_in, int n_groups, hipStream_t st) {
     hipLaunchKernelGGL(corner_turn_q_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, d_task0, n_tasks,
-                       d_outs, n_in);
+                       d_outs, n_in, counter);
     return hipGetLastError();
 }
 

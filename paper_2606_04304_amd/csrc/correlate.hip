@@ -158,10 +158,11 @@ __global__ __launch_bounds__(256) void correlate_i8_kernel(const int8_t *__restr
 // Persistent form over several sub-bands: task -> (job, channel group of 8, tile pair, XCD lane)
 // in the same XCD-preserving order as the single-band launch.
 __global__ __launch_bounds__(256) void correlate_i8_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
-                                                                 int n_tasks) {
+                                                                 int n_tasks, int *__restrict__ counter) {
     __shared__ __attribute__((aligned(16))) int8_t sA[TILE * LDS_STRIDE];
     __shared__ __attribute__((aligned(16))) int8_t sB[TILE * LDS_STRIDE];
-    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    __shared__ int s_task;
+    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
         int j = 0;
         while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
         const CorrJob jb = jobs[j];
@@ -240,9 +241,10 @@ __global__ __launch_bounds__(256) void correlate_i8_chan_kernel(const int8_t *__
 
 template <int KP>
 __global__ __launch_bounds__(256) void correlate_i8_chan_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
-                                                                      int n_tasks) {
+                                                                      int n_tasks, int *__restrict__ counter) {
     extern __shared__ __attribute__((aligned(16))) int8_t sY[];
-    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    __shared__ int s_task;
+    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
         int j = 0;
         while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
         const CorrJob jb = jobs[j];
@@ -393,19 +395,19 @@ hipError_t correlate_batch_prepare(int variant, int n_in) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in,
+hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int *counter, int variant, int n_in,
                                   int n_groups, hipStream_t st) {
     if (variant == CORR_VARIANT_TILED) {
-        hipLaunchKernelGGL(correlate_i8_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+        hipLaunchKernelGGL(correlate_i8_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks, counter);
         return hipGetLastError();
     }
     const size_t lds = correlate_chan_lds(n_in, variant);
     if (variant == CORR_VARIANT_CHAN32)
         hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<32>, dim3(n_groups), dim3(256), lds, st, d_jobs, n_jobs,
-                           n_tasks);
+                           n_tasks, counter);
     else
         hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<64>, dim3(n_groups), dim3(256), lds, st, d_jobs, n_jobs,
-                           n_tasks);
+                           n_tasks, counter);
     return hipGetLastError();
 }
 

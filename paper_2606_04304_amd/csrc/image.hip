@@ -268,14 +268,30 @@ __global__ __launch_bounds__(256) void stokes_gather_kernel(const VT *__restrict
                       blockIdx.x * 256 + threadIdx.x);
 }
 
-// Gridding without atomics: every thread owns a fixed rectangle of GE grid cells of the band
-// (CPT consecutive columns x RPT rows) and sums the contributions of the baselines whose
-// 8 x 8 kernel footprint covers it.  The band's baselines are sorted by x separation, hence
-// by grid column for every channel (u is proportional to dx), and are staged in LDS (cell
-// index and fractional offset per axis, value), so a thread finds its few baselines by binary
-// search and evaluates the kernel weights of its own cells in registers, without branches.
-// The sum order is fixed, so the result is deterministic.
-constexpr int STAGE_CAP = 1024;  // baselines staged per round (reuses the grid's LDS)
+// Gridding without atomics.  A workgroup grids one band of R rows of the 2n x 2n grid; every
+// thread owns a fixed rectangle of GE cells of it (CPT consecutive columns x RPT rows) in
+// registers and sums the baselines whose 8 x 8 kernel footprint covers it.  The band's baselines
+// are sorted by x separation, hence by grid column for every channel (u is proportional to dx).
+// Each staging round puts a run of them in LDS with their 8 + 8 separable kernel weights
+// (evaluated once per baseline) and a table of the first staged baseline at or right of every
+// grid column, so a thread's baselines are the contiguous range of those starting within 7
+// columns left of its first column, and it applies them as val * wu (once per column) times wv
+// (once per cell).  Each cell sums its baselines in list order, so the result is deterministic.
+template <int LOGM, int GE>
+struct GridShape {
+    static constexpr int M = 1 << LOGM;
+    static constexpr int CELLS = Tile<GE>::CELLS;
+    static constexpr int R = CELLS / M;              // rows of a band
+    static constexpr int CPT = M >= 256 ? M / 256 : 1;  // owned columns per thread
+    static constexpr int COLT = M / CPT;             // threads across the columns
+    static constexpr int RPT = R / (256 / COLT);     // owned rows per thread
+    static constexpr int XMIN = -16, XMAX = M + 16;  // first-index table range
+    static constexpr int NFIRST = XMAX - XMIN + 1;
+    // staged per baseline: first footprint cell (int2), value (float2), 16 weights
+    static constexpr int CAP = (CELLS * (int)sizeof(float2) - NFIRST * 4) / (8 + 8 + 16 * 4);
+    static_assert(CPT * RPT == GE, "GE cells per thread");
+    static_assert(CAP >= 64, "staging room");
+};
 
 template <int LOGM, int PREC, int GE>
 __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const double2 *__restrict__ dxy,
@@ -283,20 +299,13 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
                                           const int *__restrict__ band_items, int n_pairs, int n_pix,
                                           float2 *__restrict__ inter, int band, int c, float2 *grid,
                                           float2 *tw_lo, float2 *tw_hi, float &vscale) {
-    constexpr int M = 1 << LOGM;
-    constexpr int GRID_CELLS = Tile<GE>::CELLS;
-    constexpr int R = GRID_CELLS / M;               // band rows
-    constexpr int CPT = (M >= 256) ? M / 256 : 1;   // owned columns per thread
-    constexpr int COLT = M / CPT;                   // threads across the columns
-    constexpr int RPT = R / (256 / COLT);           // owned rows per thread
-    static_assert(CPT * RPT == GE, "GE cells per thread");
-    static_assert(STAGE_CAP * 24 <= (int)sizeof(float2) * padded_size(GRID_CELLS), "staging fits");
-    // staging view of the grid's LDS: cell gu0, gv0 (int), fraction ou, ov (float), value (float2)
-    int *s_gu = reinterpret_cast<int *>(grid);
-    int *s_gv = s_gu + STAGE_CAP;
-    float *s_ou = reinterpret_cast<float *>(s_gv + STAGE_CAP);
-    float *s_ov = s_ou + STAGE_CAP;
-    float2 *s_val = reinterpret_cast<float2 *>(s_ov + STAGE_CAP);
+    using GS = GridShape<LOGM, GE>;
+    constexpr int M = GS::M, R = GS::R, CPT = GS::CPT, COLT = GS::COLT, RPT = GS::RPT, CAP = GS::CAP;
+    // staging view of the grid's LDS
+    int2 *s_g = reinterpret_cast<int2 *>(grid);                   // gu0, gv0: first footprint cell
+    float2 *s_val = reinterpret_cast<float2 *>(s_g + CAP);         // Stokes I value
+    float *s_w = reinterpret_cast<float *>(s_val + CAP);           // wu[0..7], wv[0..7]
+    int *s_first = reinterpret_cast<int *>(s_w + 16 * CAP);       // [x - XMIN]: first i with gu0 >= x
 
     const int t = threadIdx.x;
     const int row0 = band * R;
@@ -337,8 +346,8 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
     // grid position u / du + M/2 with du = 1/4 wavelength (the membership of B was decided by
     // the gather kernel; baselines outside B carry a zero value)
     const double sc = freq[c] / C_LIGHT * 4.0;
-    for (int k0 = k_begin; k0 < k_end; k0 += STAGE_CAP) {
-        const int nk = min(STAGE_CAP, k_end - k0);
+    for (int k0 = k_begin; k0 < k_end; k0 += CAP) {
+        const int nk = min(CAP, k_end - k0);
         __syncthreads();
         for (int i = t; i < nk; i += 256) {
             const int k = band_items[k0 + i];
@@ -347,38 +356,54 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
             const double2 d = dxy[k];
             const double cu = d.x * sc + (double)(M / 2), cvv = d.y * sc + (double)(M / 2);
             const double fu = floor(cu), fv = floor(cvv);
-            s_gu[i] = (int)fu - 3;
-            s_gv[i] = (int)fv - 3;
-            s_ou[i] = (float)(cu - fu);  // in [0, 1)
-            s_ov[i] = (float)(cvv - fv);
+            s_g[i] = make_int2((int)fu - 3, (int)fv - 3);
             s_val[i] = val;
+            const float ou = (float)(cu - fu), ov = (float)(cvv - fv);  // in [0, 1)
+            // cell offsets from the baseline's grid position, in cells: (j - 3) - o
+#pragma unroll
+            for (int q = 0; q < 8; q++) s_w[i * 16 + q] = es_kernel_fast(((float)(q - 3) - ou) * 0.25f);
+#pragma unroll
+            for (int q = 0; q < 8; q++) s_w[i * 16 + 8 + q] = es_kernel_fast(((float)(q - 3) - ov) * 0.25f);
+        }
+        for (int x = t; x < GS::NFIRST; x += 256) s_first[x] = nk;
+        __syncthreads();
+        // s_first[x - XMIN] = first staged i with gu0 >= x: baseline i owns the x in (gu0[i-1], gu0[i]]
+        for (int i = t; i < nk; i += 256) {
+            const int a = i == 0 ? GS::XMIN - 1 : min(max(s_g[i - 1].x, GS::XMIN - 1), GS::XMAX);
+            const int b = min(max(s_g[i].x, GS::XMIN - 1), GS::XMAX);
+            for (int x = a + 1; x <= b; x++) s_first[x - GS::XMIN] = i;
         }
         __syncthreads();
-        // first staged baseline whose footprint can reach column col0: gu0 >= col0 - 7
-        int lo = 0, hi = nk;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_gu[mid] < col0 - 7) lo = mid + 1;
-            else hi = mid;
-        }
-        for (int i = lo; i < nk; i++) {
-            const int gu0 = s_gu[i];
-            if (gu0 > col0 + CPT - 1) break;
-            const int gv0 = s_gv[i];
-            const int dr0 = row0 + rown - gv0;  // footprint row of owned row 0
+        // this thread's baselines: gu0 in [col0 - 7, col0 + CPT - 1]
+        const int lo = s_first[col0 - 7 - GS::XMIN], hi = s_first[col0 + CPT - GS::XMIN];
+        for (int i = lo; i < hi; i++) {
+            const int2 g = s_g[i];
+            const int dr0 = row0 + rown - g.y;  // footprint row of owned row 0
             if (dr0 + RPT <= 0 || dr0 >= 8) continue;
-            const float ou = s_ou[i], ov = s_ov[i];
             const float2 val = s_val[i];
-            // cell offsets from the baseline's grid position, in cells: (j - 3) - o
+            const float *w = s_w + i * 16;
+            const int dc0 = col0 - g.x;  // footprint column of owned column 0
             float wu[CPT], wv[RPT];
 #pragma unroll
-            for (int q = 0; q < CPT; q++) wu[q] = es_kernel_fast(((float)(col0 + q - gu0 - 3) - ou) * 0.25f);
+            for (int q = 0; q < CPT; q++) wu[q] = (unsigned)(dc0 + q) < 8u ? w[dc0 + q] : 0.f;
 #pragma unroll
-            for (int r = 0; r < RPT; r++) wv[r] = es_kernel_fast(((float)(dr0 + r - 3) - ov) * 0.25f);
+            for (int r = 0; r < RPT; r++) wv[r] = (unsigned)(dr0 + r) < 8u ? w[8 + dr0 + r] : 0.f;
+            if constexpr (PREC == NBSI_PREC_FP32) {
 #pragma unroll
-            for (int q = 0; q < CPT; q++)
+                for (int q = 0; q < CPT; q++) {
+                    const float2 vu = make_float2(val.x * wu[q], val.y * wu[q]);
 #pragma unroll
-                for (int r = 0; r < RPT; r++) acc[q][r] = cadd(acc[q][r], grid_product<PREC>(val, wu[q], wv[r]));
+                    for (int r = 0; r < RPT; r++) {
+                        acc[q][r].x = fmaf(vu.x, wv[r], acc[q][r].x);
+                        acc[q][r].y = fmaf(vu.y, wv[r], acc[q][r].y);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < CPT; q++)
+#pragma unroll
+                    for (int r = 0; r < RPT; r++) acc[q][r] = cadd(acc[q][r], grid_product<PREC>(val, wu[q], wv[r]));
+            }
         }
     }
     __syncthreads();
@@ -417,11 +442,12 @@ __global__ __launch_bounds__(256) void grid_rows_kernel(
 // Persistent gridding over the sub-bands of one image size: task -> (job, channel, band).
 template <int LOGM, int PREC, int GE>
 __global__ __launch_bounds__(256) void grid_rows_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
-                                                              int n_tasks) {
+                                                              int n_tasks, int *__restrict__ counter) {
     __shared__ float2 grid[padded_size(Tile<GE>::CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
     __shared__ float vscale;
-    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    __shared__ int s_task;
+    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
         int j = 0;
         while (j + 1 < n_jobs && jobs[j + 1].rows_task0 <= task) j++;
         const ImgJob &jb = jobs[j];
@@ -477,10 +503,11 @@ __global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict
 
 template <int GE>
 __global__ __launch_bounds__(256) void grid_cols_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
-                                                              int n_tasks) {
+                                                              int n_tasks, int *__restrict__ counter) {
     __shared__ float2 buf[padded_size(Tile<GE>::CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
-    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+    __shared__ int s_task;
+    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
         int j = 0;
         while (j + 1 < n_jobs && jobs[j + 1].cols_task0 <= task) j++;
         const ImgJob &jb = jobs[j];
@@ -493,8 +520,9 @@ __global__ __launch_bounds__(256) void grid_cols_batch_kernel(const ImgJob *__re
 }
 
 __global__ __launch_bounds__(256) void stokes_gather_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
-                                                                  int n_tasks) {
-    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+                                                                  int n_tasks, int *__restrict__ counter) {
+    __shared__ int s_task;
+    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
         int j = 0;
         while (j + 1 < n_jobs && jobs[j + 1].gather_task0 <= task) j++;
         const ImgJob &jb = jobs[j];
@@ -573,17 +601,18 @@ hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_
                        : launch_grid_ge<16>(p, precision, cvis, inter, img, log_m, st);
 }
 
-hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, int n_groups, hipStream_t st) {
-    hipLaunchKernelGGL(stokes_gather_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int n_groups,
+                                     hipStream_t st) {
+    hipLaunchKernelGGL(stokes_gather_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks, counter);
     return hipGetLastError();
 }
 
 template <int GE>
-static hipError_t launch_batch_rows_ge(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision,
+static hipError_t launch_batch_rows_ge(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int log_m, int precision,
                                        int n_groups, hipStream_t st) {
 #define NBSI_BR(LM, PR)                                                                                        \
     hipLaunchKernelGGL((grid_rows_batch_kernel<LM, PR, GE>), dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, \
-                       n_tasks)
+                       n_tasks, counter)
 #define NBSI_BR_P(LM)                                                    \
     if (precision == NBSI_PREC_FP16) NBSI_BR(LM, NBSI_PREC_FP16);         \
     else if (precision == NBSI_PREC_BF16) NBSI_BR(LM, NBSI_PREC_BF16);    \
@@ -601,17 +630,17 @@ static hipError_t launch_batch_rows_ge(const ImgJob *d_jobs, int n_jobs, int n_t
     return hipGetLastError();
 }
 
-hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision, int ge,
-                                   int n_groups, hipStream_t st) {
-    return ge == 32 ? launch_batch_rows_ge<32>(d_jobs, n_jobs, n_tasks, log_m, precision, n_groups, st)
-                    : launch_batch_rows_ge<16>(d_jobs, n_jobs, n_tasks, log_m, precision, n_groups, st);
+hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int log_m, int precision,
+                                   int ge, int n_groups, hipStream_t st) {
+    return ge == 32 ? launch_batch_rows_ge<32>(d_jobs, n_jobs, n_tasks, counter, log_m, precision, n_groups, st)
+                    : launch_batch_rows_ge<16>(d_jobs, n_jobs, n_tasks, counter, log_m, precision, n_groups, st);
 }
 
-hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int ge, int n_groups,
+hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int ge, int n_groups,
                                    hipStream_t st) {
     if (ge == 32)
-        hipLaunchKernelGGL(grid_cols_batch_kernel<32>, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+        hipLaunchKernelGGL(grid_cols_batch_kernel<32>, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks, counter);
     else
-        hipLaunchKernelGGL(grid_cols_batch_kernel<16>, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+        hipLaunchKernelGGL(grid_cols_batch_kernel<16>, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks, counter);
     return hipGetLastError();
 }
