@@ -158,6 +158,10 @@ def batched_leg(args, nb, torch, ctx, dev, synth):
     k = max(2, args.steps // 2)
     ms_per = timed(per_subband, k)
     log(f"[bench] per-sub-band launches: {ms_per:.2f} ms")
+    eager = nb.Batch(xyz, subs, graph=False, ctx=ctx)
+    ms_eager = timed(eager.run, k)
+    log(f"[bench] batched launches without a graph (default tiles): {ms_eager:.2f} ms")
+    eager.close()
     batch = nb.Batch(xyz, subs, graph=True, ctx=ctx)
     ms_batch = timed(batch.run, k)
     log(f"[bench] batched graph (default tiles): {ms_batch:.2f} ms")
@@ -175,7 +179,8 @@ def batched_leg(args, nb, torch, ctx, dev, synth):
     return {
         "workload": "12 sub-bands x 1024 channels, 352 ant x 2 pol, FFT 2^14..2^18, T 128..8, "
                     "GRID 128^2..512^2 (channelize + correlate + image)",
-        "per_subband_ms": round(ms_per, 3), "batched_graph_ms": round(ms_batch, 3),
+        "per_subband_ms": round(ms_per, 3), "batched_eager_ms": round(ms_eager, 3),
+        "batched_graph_ms": round(ms_batch, 3),
         "batched_graph_autotuned_ms": round(ms_tuned, 3),
         "speedup_batched": round(ms_per / ms_batch, 3), "speedup_autotuned": round(ms_per / ms_tuned, 3),
         "fine_channels_per_s_autotuned": round(n_ch / (ms_tuned * 1e-3), 1),
@@ -363,9 +368,8 @@ def main():
         log("[bench] fp32 path timed")
 
     if not args.no_batch:
-        del volt
-        torch.cuda.empty_cache()
         comp["batched_subbands"] = batched_leg(args, nb, torch, ctx, dev, synth)
+        torch.cuda.empty_cache()
 
     out = {
         "metric": "correlated fine-channel TOPS + imaged channels/s @256^2 vs plain FP32 path",

@@ -189,7 +189,7 @@ int nbsi_detect(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode
  * Batched sub-bands (Sec. 2.1: the band is processed as independent batches of fine channels;
  * Sec. 2.6: re-processing with other FFT lengths and integrations).  Each sub-band is one coarse
  * channel's voltages with its own FFT length, integration count, kept channels and image size;
- * nbsi_batch_run channelizes, correlates and images all of them (each stage one persistent launch
+ * nbsi_batch_run channelizes, correlates and images all of them (each stage one launch
  * over a task table spanning the sub-bands, grouped only where kernel shapes differ), with the
  * same results as the per-sub-band calls above (bit-identical spectra, visibilities and images).
  */

@@ -1,8 +1,11 @@
 // Batched execution of uneven sub-bands (the paper's batch-by-batch processing of the band,
 // Sec. 2.1, with variable FFT lengths and integrations as in its follow-up, Sec. 2.6):
-// channelize -> corner turn -> correlate -> image for every sub-band, each stage one
-// persistent launch over a task table spanning the sub-bands (grouped only where kernel
-// shapes differ), the whole sequence captured once into a hipGraph and replayed.
+// channelize -> corner turn -> correlate -> image for every sub-band, each stage one launch
+// over a task table spanning the sub-bands (grouped only where kernel shapes differ; the
+// imager per cache-sized chunk of channels), one workgroup per task, the whole sequence
+// captured once into a hipGraph and replayed.  A persistent form with a device work queue was
+// measured slower here: the tasks are small and uneven, and the hardware dispatcher spreads
+// them better than an atomic counter per task.
 // An autotuner times the correlator variants (128 x 128 tiles vs whole-channel panels) and the
 // gridding tile height (16 or 32 cells per thread) on each sub-band's real shape and caches
 // the choices in a text file.
@@ -30,15 +33,13 @@ struct nbsi_batch {
     std::vector<int> corr_variant, grid_ge;
     std::vector<void *> owned;  // device allocations of the batch
     std::vector<int8_t *> stage;
-    std::vector<float2 *> cvis;
+    float2 *cvis = nullptr;        // one imaging chunk's Stokes-I gather
     float2 *inter = nullptr;       // one imaging chunk's row-pass intermediate
-    int *d_counters = nullptr;     // one work-queue counter per launch
 
-    struct Launch {  // one persistent launch: kind, shape key, job array on the device
+    struct Launch {  // one batched launch: kind, shape key, job array on the device
         int kind;    // 0 channelize, 1 corner turn, 2 correlate, 3 gather, 4 rows, 5 cols
         int a = 0, b = 0;  // kind-specific shape (log_m/g, variant, log_m/ge)
-        int counter = 0;   // index into d_counters
-        int n_jobs = 0, n_tasks = 0, n_groups = 0, max_dyn = 0;
+        int n_jobs = 0, n_tasks = 0, max_dyn = 0;
         void *d_jobs = nullptr;
         int *d_task0 = nullptr;
         int8_t **d_outs = nullptr;
@@ -54,17 +55,6 @@ struct nbsi_batch {
 };
 
 namespace {
-
-__global__ void zero_counters_kernel(int *c, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) c[i] = 0;
-}
-
-int n_cu(int device) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 256;
-    return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-}
 
 template <typename T>
 int upload(nbsi_batch *b, const std::vector<T> &v, T **out) {
@@ -140,38 +130,26 @@ hipError_t enqueue_channelize_one(nbsi_batch *b, int s, hipStream_t st) {
     return launch_corner_turn_q(b->stage[s], b->n_in, x.n_spec, x.n_chan, x.spec_q, st);
 }
 
-// Every stage of every sub-band, as the grouped persistent launches (the work-queue counters are
-// zeroed by a kernel first, so a captured graph resets them on every replay).
+// Every stage of every sub-band, as the grouped launches.
 hipError_t enqueue_all(nbsi_batch *b, hipStream_t st) {
-    const int n_l = (int)b->launches.size();
-    hipLaunchKernelGGL(zero_counters_kernel, dim3((n_l + 255) / 256), dim3(256), 0, st, b->d_counters, n_l);
-    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     for (const auto &L : b->launches) {
         hipError_t e = hipSuccess;
-        int *ctr = b->d_counters + L.counter;
         switch (L.kind) {
             case 0:
-                e = launch_channelize_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.a, L.b, L.max_dyn,
-                                            L.n_groups, st);
+                e = launch_channelize_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, L.b, L.max_dyn, st);
                 break;
             case 1:
-                e = launch_corner_turn_q_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.d_task0, L.n_tasks, ctr, L.d_outs,
-                                               b->n_in, L.n_groups, st);
+                e = launch_corner_turn_q_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.d_task0, L.n_tasks, L.d_outs,
+                                               b->n_in, st);
                 break;
             case 2:
-                e = launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.a, b->n_in,
-                                           L.n_groups, st);
+                e = launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->n_in, st);
                 break;
-            case 3:
-                e = launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.n_groups, st);
-                break;
+            case 3: e = launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, st); break;
             case 4:
-                e = launch_image_batch_rows((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.a, b->precision, L.b,
-                                            L.n_groups, st);
+                e = launch_image_batch_rows((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->precision, L.b, st);
                 break;
-            case 5:
-                e = launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, ctr, L.b, L.n_groups, st);
-                break;
+            case 5: e = launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.b, st); break;
         }
         if (e != hipSuccess) return e;
     }
@@ -179,7 +157,6 @@ hipError_t enqueue_all(nbsi_batch *b, hipStream_t st) {
 }
 
 int build_launches(nbsi_batch *b) {
-    const int cus = n_cu(b->device);
     // channelize: one launch per (sub-transform size, load grouping, FFT length): the table LDS is
     // sized by the FFT length, and one size per launch keeps the occupancy of the shorter ones
     std::map<std::tuple<int, int, int>, std::vector<int>> cg;
@@ -207,7 +184,6 @@ int build_launches(nbsi_batch *b) {
         L.n_jobs = (int)jobs.size();
         L.n_tasks = tasks;
         L.max_dyn = max_dyn;
-        L.n_groups = std::min(tasks, cus * 4);
         int rc = upload(b, jobs, (ChanJob **)&L.d_jobs);
         if (rc) return rc;
         b->launches.push_back(L);
@@ -229,7 +205,6 @@ int build_launches(nbsi_batch *b) {
         L.kind = 1;
         L.n_jobs = b->n_sb;
         L.n_tasks = tasks;
-        L.n_groups = std::min(tasks, cus * 8);
         int rc = upload(b, jobs, (ChanJob **)&L.d_jobs);
         if (!rc) rc = upload(b, t0, &L.d_task0);
         if (!rc) rc = upload(b, outs, &L.d_outs);
@@ -255,12 +230,11 @@ int build_launches(nbsi_batch *b) {
         L.a = kv.first;
         L.n_jobs = (int)jobs.size();
         L.n_tasks = tasks;
-        L.n_groups = std::min(tasks, cus * (kv.first == CORR_VARIANT_TILED ? 6 : 3));
         int rc = upload(b, jobs, (CorrJob **)&L.d_jobs);
         if (rc) return rc;
         b->launches.push_back(L);
     }
-    // imager: gather over all; rows grouped by (log_m, ge); columns grouped by ge
+    // imager: per channel chunk a gather, a rows and a columns launch (below)
     std::vector<ImgJob> base(b->n_sb);
     for (int s = 0; s < b->n_sb; s++) {
         const nbsi_image_plan *p = b->plans[s];
@@ -274,7 +248,7 @@ int build_launches(nbsi_batch *b) {
         j.band_items = p->d_band_items;
         j.nb = p->d_nb;
         j.corr = p->d_corr;
-        j.cvis = b->cvis[s];
+        j.cvis = b->cvis;
         j.inter = b->inter;
         j.img = b->sb[s].img;
         j.n_pairs = p->n_pairs;
@@ -286,49 +260,41 @@ int build_launches(nbsi_batch *b) {
         j.uv_min = p->uv_min;
         j.uv_max = p->uv_max;
     }
-    {
-        std::vector<ImgJob> jobs = base;
-        int tasks = 0;
-        for (auto &j : jobs) {
-            j.gather_task0 = tasks;
-            tasks += j.n_chan * ((j.n_pairs + 255) / 256);
-        }
-        nbsi_batch::Launch L;
-        L.kind = 3;
-        L.n_jobs = (int)jobs.size();
-        L.n_tasks = tasks;
-        L.n_groups = std::min(tasks, cus * 8);
-        int rc = upload(b, jobs, (ImgJob **)&L.d_jobs);
-        if (rc) return rc;
-        b->launches.push_back(L);
-    }
-    // rows and columns: channel chunks of every sub-band of one (transform size, tile height),
-    // each chunk's intermediate within IMAGE_CHUNK_BYTES; a chunk's rows launch is followed by
-    // its columns launch, which finds the intermediate still in the last-level cache
+    // channel chunks of every sub-band of one (transform size, tile height), each chunk's row
+    // intermediate within IMAGE_CHUNK_BYTES: per chunk a gather, a rows and a columns launch, so
+    // the Stokes-I gather and the intermediate are read back while still in the last-level cache
     std::map<std::pair<int, int>, std::vector<int>> rg;
     for (int s = 0; s < b->n_sb; s++) rg[{base[s].log_m, b->grid_ge[s]}].push_back(s);
     for (auto &kv : rg) {
         const int ge = kv.first.second;
         std::vector<ImgJob> chunk;
-        size_t used = 0;
+        size_t used = 0, cv_used = 0;  // bytes of the chunk's intermediate and Stokes-I gather
         auto flush = [&]() -> int {
             if (chunk.empty()) return NBSI_OK;
-            std::vector<ImgJob> rows = chunk, cols = chunk;
-            int rt = 0, ct = 0;
+            std::vector<ImgJob> gath = chunk, rows = chunk, cols = chunk;
+            int gt = 0, rt = 0, ct = 0;
             for (size_t q = 0; q < chunk.size(); q++) {
+                gath[q].gather_task0 = gt;
+                gt += chunk[q].n_chan * ((chunk[q].n_pairs + 255) / 256);
                 rows[q].rows_task0 = rt;
                 rt += chunk[q].n_chan * chunk[q].n_bands;
                 cols[q].cols_task0 = ct;
                 const int band_cols = 256 * ge / (2 * chunk[q].n_pix);
                 ct += chunk[q].n_chan * (chunk[q].n_pix / band_cols);
             }
+            nbsi_batch::Launch G;
+            G.kind = 3;
+            G.n_jobs = (int)gath.size();
+            G.n_tasks = gt;
+            int rc0 = upload(b, gath, (ImgJob **)&G.d_jobs);
+            if (rc0) return rc0;
+            b->launches.push_back(G);
             nbsi_batch::Launch R;
             R.kind = 4;
             R.a = kv.first.first;
             R.b = ge;
             R.n_jobs = (int)rows.size();
             R.n_tasks = rt;
-            R.n_groups = std::min(rt, cus * (ge == 32 ? 2 : 4));
             int rc = upload(b, rows, (ImgJob **)&R.d_jobs);
             if (rc) return rc;
             b->launches.push_back(R);
@@ -337,12 +303,12 @@ int build_launches(nbsi_batch *b) {
             C.b = ge;
             C.n_jobs = (int)cols.size();
             C.n_tasks = ct;
-            C.n_groups = std::min(ct, cus * (ge == 32 ? 2 : 4));
             rc = upload(b, cols, (ImgJob **)&C.d_jobs);
             if (rc) return rc;
             b->launches.push_back(C);
             chunk.clear();
             used = 0;
+            cv_used = 0;
             return NBSI_OK;
         };
         for (int s : kv.second) {
@@ -357,26 +323,23 @@ int build_launches(nbsi_batch *b) {
                 const int fit = (int)std::max<size_t>(1, (IMAGE_CHUNK_BYTES - std::min(used, IMAGE_CHUNK_BYTES)) / per_chan);
                 const int n = std::min(j.n_chan - c0, fit);
                 ImgJob q = j;  // channels [c0, c0 + n) of this sub-band, pointers moved to them
+                const size_t nprod = (size_t)(2 * j.n_ant) * (2 * j.n_ant + 1) / 2;
+                q.vis = j.vis + (size_t)c0 * nprod * 2;
                 q.freq = j.freq + c0;
                 q.nb = j.nb + c0;
-                q.cvis = j.cvis + (size_t)c0 * std::max(1, j.n_pairs);
+                q.cvis = b->cvis + cv_used / sizeof(float2);
                 q.inter = b->inter + used / sizeof(float2);
                 q.img = j.img + (size_t)c0 * nb;
                 q.n_chan = n;
                 chunk.push_back(q);
                 used += per_chan * n;
+                cv_used += sizeof(float2) * (size_t)n * std::max(1, j.n_pairs);
                 c0 += n;
             }
         }
         const int rc = flush();
         if (rc) return rc;
     }
-    for (size_t q = 0; q < b->launches.size(); q++) b->launches[q].counter = (int)q;
-    int *ctr = nullptr;
-    std::vector<int> zeros(b->launches.size(), 0);
-    const int rc = upload(b, zeros, &ctr);
-    if (rc) return rc;
-    b->d_counters = ctr;
     return NBSI_OK;
 }
 
@@ -467,18 +430,20 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
         if (it != cache.end() && correlate_variant_valid(n_in, x.n_spec, it->second)) {
             b->corr_variant[s] = it->second;
         } else if (tune) {
-            double best = 1e30;
-            int best_v = b->corr_variant[s];
-            for (int v : {CORR_VARIANT_TILED, CORR_VARIANT_CHAN32, CORR_VARIANT_CHAN64}) {
-                if (!correlate_variant_valid(n_in, x.n_spec, v)) continue;
-                const double ms = time_ms(
-                    b->stream, [&]() { return launch_correlate_variant(x.spec_q, x.n_chan, n_in, x.n_spec, x.vis, v, b->stream); },
-                    2);
-                if (ms < best) {
-                    best = ms;
-                    best_v = v;
+            // two alternating rounds, the faster of each candidate's two timings
+            double best_t[3] = {1e30, 1e30, 1e30};
+            for (int round = 0; round < 2; round++)
+                for (int v : {CORR_VARIANT_TILED, CORR_VARIANT_CHAN32, CORR_VARIANT_CHAN64}) {
+                    if (!correlate_variant_valid(n_in, x.n_spec, v)) continue;
+                    const double ms = time_ms(
+                        b->stream,
+                        [&]() { return launch_correlate_variant(x.spec_q, x.n_chan, n_in, x.n_spec, x.vis, v, b->stream); },
+                        3);
+                    best_t[v] = std::min(best_t[v], ms);
                 }
-            }
+            int best_v = b->corr_variant[s];
+            for (int v = 0; v < 3; v++)
+                if (best_t[v] < best_t[best_v]) best_v = v;
             b->corr_variant[s] = best_v;
             cache[key] = best_v;
             cache_dirty = true;
@@ -499,7 +464,7 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
             ge = it->second;
         } else if (tune) {
             double best = 1e30;
-            for (int g : {16, 32}) {
+            for (int g : {16, 32, 16, 32}) {  // two alternating rounds
                 nbsi_image_plan *p = nullptr;
                 if (image_plan_build(ctx, ant_xyz_host, n_ant, x.freq_hz_host, x.n_chan, x.n_pix, NBSI_IMAGE_GRID, 0.0,
                                      INFINITY, g, &p))
@@ -518,7 +483,7 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
                         return launch_image_grid(p, x.vis, NBSI_VIS_I32, precision, (float2 *)cv, (float2 *)in, x.img,
                                                  b->stream);
                     },
-                    2);
+                    3);
                 (void)hipStreamSynchronize(b->stream);
                 (void)hipFree(cv);
                 (void)hipFree(in);
@@ -537,16 +502,25 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
                                    INFINITY, ge, &p)))
             return fail(rc, "plan failed");
         b->plans.push_back(p);
-        void *cv = nullptr;
-        if ((rc = alloc(b, sizeof(float2) * (size_t)x.n_chan * std::max(1, p->n_pairs), &cv))) return fail(rc, "oom");
-        b->cvis.push_back((float2 *)cv);
     }
     {
-        size_t need = IMAGE_CHUNK_BYTES;
-        for (int s = 0; s < n_sb; s++) need = std::max(need, (size_t)b->sb[s].n_pix * 2 * b->sb[s].n_pix * sizeof(float2));
-        void *in = nullptr;
+        // a chunk holds at most max(1, IMAGE_CHUNK_BYTES / per-channel intermediate) channels of
+        // any sub-band; its gather at most that many channels times the largest pair count
+        size_t need = IMAGE_CHUNK_BYTES, cv_need = 0;
+        for (int s = 0; s < n_sb; s++) {
+            const size_t per_chan = (size_t)b->sb[s].n_pix * 2 * b->sb[s].n_pix * sizeof(float2);
+            need = std::max(need, per_chan);
+            const size_t ch = std::max<size_t>(1, IMAGE_CHUNK_BYTES / per_chan);
+            size_t pairs_max = 1;
+            for (int s2 = 0; s2 < n_sb; s2++)
+                if (b->sb[s2].n_pix == b->sb[s].n_pix) pairs_max = std::max<size_t>(pairs_max, b->plans[s2]->n_pairs);
+            cv_need = std::max(cv_need, sizeof(float2) * ch * pairs_max);
+        }
+        void *in = nullptr, *cv = nullptr;
         if ((rc = alloc(b, need, &in))) return fail(rc, "oom");
+        if ((rc = alloc(b, cv_need, &cv))) return fail(rc, "oom");
         b->inter = (float2 *)in;
+        b->cvis = (float2 *)cv;
     }
     if (cache_dirty) write_cache(tune_cache_path, cache);
     if ((rc = build_launches(b))) return fail(rc, "launch tables failed");

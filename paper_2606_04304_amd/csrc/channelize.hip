@@ -250,30 +250,22 @@ __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(ChanJob jb
     channelize_spectrum<LOGM, G>(jb, blockIdx.x / jb.n_spec, blockIdx.x % jb.n_spec, buf, dyn, tw);
 }
 
-// Persistent form over several sub-bands: jobs[j] owns tasks [task0, task0 + n_in n_spec);
-// each workgroup walks tasks with stride gridDim.x and rebuilds the tables when it crosses
-// into another sub-band.
+// Several sub-bands of one transform size in one launch: jobs[j] owns tasks (spectra)
+// [task0, task0 + n_in n_spec), one workgroup per task, so the kernel keeps the register
+// budget and occupancy of the single-band kernel and the dispatcher balances the workgroups.
 template <int LOGM, int G>
 __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_batch_kernel(const ChanJob *__restrict__ jobs,
-                                                                            int n_jobs, int n_tasks,
-                                                                            int *__restrict__ counter) {
+                                                                            int n_jobs, int n_tasks) {
     __shared__ float2 buf[padded_size(1 << LOGM)];
     extern __shared__ float2 dyn[];
-    int cur = -1;
-    TwiddleTable tw{};
-    __shared__ int s_task;
-    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
-        int j = 0;
-        while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
-        const ChanJob jb = jobs[j];
-        if (j != cur) {
-            __syncthreads();  // every thread is done with the previous tables
-            tw = chan_tables<LOGM>(dyn, jb.log_n, jb.klo, threadIdx.x);
-            cur = j;
-        }
-        const int local = task - jb.task0;
-        channelize_spectrum<LOGM, G>(jb, local / jb.n_spec, local % jb.n_spec, buf, dyn, tw);
-    }
+    const int task = blockIdx.x;
+    if (task >= n_tasks) return;
+    int j = 0;
+    while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
+    const ChanJob jb = jobs[j];
+    const TwiddleTable tw = chan_tables<LOGM>(dyn, jb.log_n, jb.klo, threadIdx.x);
+    const int local = task - jb.task0;
+    channelize_spectrum<LOGM, G>(jb, local / jb.n_spec, local % jb.n_spec, buf, dyn, tw);
 }
 
 // [n_in][n_spec][C] complex int8 -> [C][n_in][2][n_spec] int8, through a 64 x 64 LDS tile:
@@ -309,23 +301,21 @@ __global__ __launch_bounds__(256) void corner_turn_q_kernel(const int16_t *__res
     corner_turn_q_tile(stage, n_in, n_spec, n_chan, out, blockIdx.y, blockIdx.x % n_cb, blockIdx.x / n_cb, tile);
 }
 
+// Corner turn of several sub-bands: one workgroup per (job, input, 64 x 64 tile) task.
 __global__ __launch_bounds__(256) void corner_turn_q_batch_kernel(const ChanJob *__restrict__ jobs, int n_jobs,
                                                                   const int *__restrict__ task0, int n_tasks,
-                                                                  int8_t *const *__restrict__ outs, int n_in,
-                                                                  int *__restrict__ counter) {
+                                                                  int8_t *const *__restrict__ outs, int n_in) {
     __shared__ int16_t tile[64][65];
-    __shared__ int s_task;
-    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
-        int j = 0;
-        while (j + 1 < n_jobs && task0[j + 1] <= task) j++;
-        const ChanJob jb = jobs[j];
-        const int local = task - task0[j];
-        const int n_cb = (jb.n_chan + 63) / 64, n_sb = (jb.n_spec + 63) / 64;
-        const int i = local / (n_cb * n_sb), rem = local % (n_cb * n_sb);
-        __syncthreads();
-        corner_turn_q_tile(reinterpret_cast<const int16_t *>(jb.stage_q), n_in, jb.n_spec, jb.n_chan, outs[j], i,
-                           rem % n_cb, rem / n_cb, tile);
-    }
+    const int task = blockIdx.x;
+    if (task >= n_tasks) return;
+    int j = 0;
+    while (j + 1 < n_jobs && task0[j + 1] <= task) j++;
+    const ChanJob jb = jobs[j];
+    const int local = task - task0[j];
+    const int n_cb = (jb.n_chan + 63) / 64, n_sb = (jb.n_spec + 63) / 64;
+    const int i = local / (n_cb * n_sb), rem = local % (n_cb * n_sb);
+    corner_turn_q_tile(reinterpret_cast<const int16_t *>(jb.stage_q), n_in, jb.n_spec, jb.n_chan, outs[j], i,
+                       rem % n_cb, rem / n_cb, tile);
 }
 
 __global__ __launch_bounds__(256) void corner_turn_f_kernel(const float2 *__restrict__ stage, int n_in,
@@ -381,10 +371,10 @@ hipError_t launch_logm(const ChanJob &jb, int n_in, hipStream_t st) {
 }
 
 template <int LOGM, int G>
-hipError_t launch_batch_logm(const ChanJob *d_jobs, int n_jobs, int n_tasks, int *counter, size_t lds, int n_groups,
+hipError_t launch_batch_logm(const ChanJob *d_jobs, int n_jobs, int n_tasks, size_t lds,
                              hipStream_t st) {
-    hipLaunchKernelGGL((channelize_batch_kernel<LOGM, G>), dim3(n_groups), dim3((1 << LOGM) / 16), lds, st, d_jobs,
-                       n_jobs, n_tasks, counter);
+    hipLaunchKernelGGL((channelize_batch_kernel<LOGM, G>), dim3(n_tasks), dim3((1 << LOGM) / 16), lds, st, d_jobs,
+                       n_jobs, n_tasks);
     return hipGetLastError();
 }
 
@@ -415,27 +405,27 @@ hipError_t launch_channelize(const int8_t *volt, int n_in, int log_n, int n_spec
     }
 }
 
-// Jobs that share one sub-transform size and load grouping (log_m, g) run in one persistent
-// launch; d_jobs holds them with consecutive task ranges.
-hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_tasks, int *counter, int log_m, int g,
-                                   int max_dyn_elems, int n_groups, hipStream_t st) {
+// Jobs that share one sub-transform size and load grouping (log_m, g) run in one launch
+// (one workgroup per spectrum); d_jobs holds them with consecutive task ranges.
+hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_tasks, int log_m, int g,
+                                   int max_dyn_elems, hipStream_t st) {
     const size_t lds = sizeof(float2) * (size_t)max_dyn_elems;
 #define NBSI_CB1(LM) \
-    case LM: return g == 1 ? launch_batch_logm<LM, 1>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st) : hipErrorInvalidValue;
+    case LM: return g == 1 ? launch_batch_logm<LM, 1>(d_jobs, n_jobs, n_tasks, lds, st) : hipErrorInvalidValue;
 #define NBSI_CBG(LM)                                                                                  \
     case LM:                                                                                          \
         switch (g) {                                                                                  \
-            case 1: return launch_batch_logm<LM, 1>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st); \
-            case 2: return launch_batch_logm<LM, 2>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st); \
-            case 4: return launch_batch_logm<LM, 4>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st); \
-            case 8: return launch_batch_logm<LM, 8>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st); \
+            case 1: return launch_batch_logm<LM, 1>(d_jobs, n_jobs, n_tasks, lds, st); \
+            case 2: return launch_batch_logm<LM, 2>(d_jobs, n_jobs, n_tasks, lds, st); \
+            case 4: return launch_batch_logm<LM, 4>(d_jobs, n_jobs, n_tasks, lds, st); \
+            case 8: return launch_batch_logm<LM, 8>(d_jobs, n_jobs, n_tasks, lds, st); \
             default: return hipErrorInvalidValue;                                                     \
         }
     switch (log_m) {
         NBSI_CB1(8) NBSI_CB1(9) NBSI_CB1(10) NBSI_CB1(11) NBSI_CBG(12) NBSI_CBG(13)
         case 14:
-            return g == 2   ? launch_batch_logm<14, 2>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st)
-                   : g == 1 ? launch_batch_logm<14, 1>(d_jobs, n_jobs, n_tasks, counter, lds, n_groups, st)
+            return g == 2   ? launch_batch_logm<14, 2>(d_jobs, n_jobs, n_tasks, lds, st)
+                   : g == 1 ? launch_batch_logm<14, 1>(d_jobs, n_jobs, n_tasks, lds, st)
                             : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
@@ -450,10 +440,10 @@ int channelize_group(int log_n, int log_m) { return std::min(log_m >= 14 ? 2 : 8
 
 int corner_turn_tasks(int n_in, int n_spec, int n_chan) { return n_in * ((n_chan + 63) / 64) * ((n_spec + 63) / 64); }
 
-hipError_t launch_corner_turn_q_batch(const ChanJob *d_jobs, int n_jobs, const int *d_task0, int n_tasks, int *counter,
-                                      int8_t *const *d_outs, int n_in, int n_groups, hipStream_t st) {
-    hipLaunchKernelGGL(corner_turn_q_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, d_task0, n_tasks,
-                       d_outs, n_in, counter);
+hipError_t launch_corner_turn_q_batch(const ChanJob *d_jobs, int n_jobs, const int *d_task0, int n_tasks,
+                                      int8_t *const *d_outs, int n_in, hipStream_t st) {
+    hipLaunchKernelGGL(corner_turn_q_batch_kernel, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, d_task0, n_tasks,
+                       d_outs, n_in);
     return hipGetLastError();
 }
 

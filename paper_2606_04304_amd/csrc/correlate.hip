@@ -15,6 +15,10 @@
 // partial cache lines at tile edges merge in that XCD's L2.
 #include "internal.h"
 
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
@@ -155,26 +159,24 @@ __global__ __launch_bounds__(256) void correlate_i8_kernel(const int8_t *__restr
     correlate_tile(q, n_in, T, c, pair, vis, sA, sB);
 }
 
-// Persistent form over several sub-bands: task -> (job, channel group of 8, tile pair, XCD lane)
-// in the same XCD-preserving order as the single-band launch.
+// Several sub-bands in one launch: task -> (job, channel group of 8, tile pair, XCD lane), one
+// workgroup per task, in the same XCD-preserving order as the single-band launch.
 __global__ __launch_bounds__(256) void correlate_i8_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
-                                                                 int n_tasks, int *__restrict__ counter) {
+                                                                 int n_tasks) {
     __shared__ __attribute__((aligned(16))) int8_t sA[TILE * LDS_STRIDE];
     __shared__ __attribute__((aligned(16))) int8_t sB[TILE * LDS_STRIDE];
-    __shared__ int s_task;
-    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
-        int j = 0;
-        while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
-        const CorrJob jb = jobs[j];
-        const int local = task - jb.task0;
-        const int n_tiles = (2 * jb.n_in + TILE - 1) / TILE;
-        const int n_pairs = n_tiles * (n_tiles + 1) / 2;
-        const int xcd = local & 7, rest = local >> 3;
-        const int pair = rest % n_pairs;
-        const int c = (rest / n_pairs) * 8 + xcd;
-        __syncthreads();  // LDS tiles of the previous task are no longer read
-        if (c < jb.n_chan) correlate_tile(jb.q, jb.n_in, jb.n_spec, c, pair, jb.vis, sA, sB);
-    }
+    const int task = blockIdx.x;
+    if (task >= n_tasks) return;
+    int j = 0;
+    while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
+    const CorrJob jb = jobs[j];
+    const int local = task - jb.task0;
+    const int n_tiles = (2 * jb.n_in + TILE - 1) / TILE;
+    const int n_pairs = n_tiles * (n_tiles + 1) / 2;
+    const int xcd = local & 7, rest = local >> 3;
+    const int pair = rest % n_pairs;
+    const int c = (rest / n_pairs) * 8 + xcd;
+    if (c < jb.n_chan) correlate_tile(jb.q, jb.n_in, jb.n_spec, c, pair, jb.vis, sA, sB);
 }
 
 // Short integrations (n_spec <= 64): one workgroup per channel keeps the channel's whole
@@ -241,16 +243,14 @@ __global__ __launch_bounds__(256) void correlate_i8_chan_kernel(const int8_t *__
 
 template <int KP>
 __global__ __launch_bounds__(256) void correlate_i8_chan_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
-                                                                      int n_tasks, int *__restrict__ counter) {
+                                                                      int n_tasks) {
     extern __shared__ __attribute__((aligned(16))) int8_t sY[];
-    __shared__ int s_task;
-    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
-        int j = 0;
-        while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
-        const CorrJob jb = jobs[j];
-        __syncthreads();  // the previous channel's matrix is no longer read
-        correlate_channel<KP>(jb.q, jb.n_in, jb.n_spec, task - jb.task0, jb.vis, sY);
-    }
+    const int task = blockIdx.x;  // one workgroup per channel of any job
+    if (task >= n_tasks) return;
+    int j = 0;
+    while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
+    const CorrJob jb = jobs[j];
+    correlate_channel<KP>(jb.q, jb.n_in, jb.n_spec, task - jb.task0, jb.vis, sY);
 }
 
 // ---- plain FP32 path: the same Gram formulation on v_mfma_f32_32x32x2_f32 ----
@@ -370,11 +370,14 @@ int correlate_batch_tasks(const CorrJob &jb, int variant) {
     return jb.n_chan;
 }
 
-// The whole-channel kernels hold the channel's matrix in LDS; they serve short integrations.
+// The whole-channel kernels hold the channel's matrix in LDS (at most CHAN_LDS_MAX bytes); they
+// serve short integrations.
+constexpr int CHAN_LDS_MAX = 96 * 1024;
+
 bool correlate_variant_valid(int n_in, int n_spec, int variant) {
     if (variant == CORR_VARIANT_TILED) return true;
-    if (variant == CORR_VARIANT_CHAN32) return n_spec <= 32 && correlate_chan_lds(n_in, variant) <= 96 * 1024;
-    if (variant == CORR_VARIANT_CHAN64) return n_spec <= 64 && correlate_chan_lds(n_in, variant) <= 96 * 1024;
+    if (variant == CORR_VARIANT_CHAN32) return n_spec <= 32 && correlate_chan_lds(n_in, variant) <= (size_t)CHAN_LDS_MAX;
+    if (variant == CORR_VARIANT_CHAN64) return n_spec <= 64 && correlate_chan_lds(n_in, variant) <= (size_t)CHAN_LDS_MAX;
     return false;
 }
 
@@ -384,30 +387,44 @@ int correlate_default_variant(int n_in, int n_spec) {
     return CORR_VARIANT_TILED;
 }
 
-// Raise the dynamic-LDS limit of the whole-channel batched kernels once, outside any graph capture.
-hipError_t correlate_batch_prepare(int variant, int n_in) {
-    if (variant == CORR_VARIANT_TILED) return hipSuccess;
-    const int lds = (int)correlate_chan_lds(n_in, variant);
-    return variant == CORR_VARIANT_CHAN32
-               ? hipFuncSetAttribute((const void *)correlate_i8_chan_batch_kernel<32>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds)
-               : hipFuncSetAttribute((const void *)correlate_i8_chan_batch_kernel<64>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+// The whole-channel kernels can need more than the default 64 KB of dynamic LDS: raise the limit
+// of all four to the largest size a valid shape uses, once per device (outside any capture).
+hipError_t chan_lds_prepare() {
+    static std::mutex mu;
+    static std::vector<int> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (std::find(done.begin(), done.end(), dev) != done.end()) return hipSuccess;
+    const void *fns[] = {(const void *)correlate_i8_chan_kernel<32>, (const void *)correlate_i8_chan_kernel<64>,
+                         (const void *)correlate_i8_chan_batch_kernel<32>,
+                         (const void *)correlate_i8_chan_batch_kernel<64>};
+    for (const void *f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, CHAN_LDS_MAX);
+        if (e != hipSuccess) return e;
+    }
+    done.push_back(dev);
+    return hipSuccess;
 }
 
-hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int *counter, int variant, int n_in,
-                                  int n_groups, hipStream_t st) {
+hipError_t correlate_batch_prepare(int variant, int n_in) {
+    (void)n_in;
+    return variant == CORR_VARIANT_TILED ? hipSuccess : chan_lds_prepare();
+}
+
+hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in,
+                                  hipStream_t st) {
     if (variant == CORR_VARIANT_TILED) {
-        hipLaunchKernelGGL(correlate_i8_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks, counter);
+        hipLaunchKernelGGL(correlate_i8_batch_kernel, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
         return hipGetLastError();
     }
     const size_t lds = correlate_chan_lds(n_in, variant);
     if (variant == CORR_VARIANT_CHAN32)
-        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<32>, dim3(n_groups), dim3(256), lds, st, d_jobs, n_jobs,
-                           n_tasks, counter);
+        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<32>, dim3(n_tasks), dim3(256), lds, st, d_jobs, n_jobs,
+                           n_tasks);
     else
-        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<64>, dim3(n_groups), dim3(256), lds, st, d_jobs, n_jobs,
-                           n_tasks, counter);
+        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<64>, dim3(n_tasks), dim3(256), lds, st, d_jobs, n_jobs,
+                           n_tasks);
     return hipGetLastError();
 }
 
@@ -423,18 +440,12 @@ hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n
         return hipGetLastError();
     }
     const size_t lds = correlate_chan_lds(n_in, variant);
-    hipError_t e;
-    if (variant == CORR_VARIANT_CHAN32) {
-        e = hipFuncSetAttribute((const void *)correlate_i8_chan_kernel<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds);
-        if (e != hipSuccess) return e;
+    const hipError_t e = chan_lds_prepare();
+    if (e != hipSuccess) return e;
+    if (variant == CORR_VARIANT_CHAN32)
         hipLaunchKernelGGL(correlate_i8_chan_kernel<32>, dim3(n_chan), dim3(256), lds, st, q, n_chan, n_in, n_spec, vis);
-    } else {
-        e = hipFuncSetAttribute((const void *)correlate_i8_chan_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds);
-        if (e != hipSuccess) return e;
+    else
         hipLaunchKernelGGL(correlate_i8_chan_kernel<64>, dim3(n_chan), dim3(256), lds, st, q, n_chan, n_in, n_spec, vis);
-    }
     return hipGetLastError();
 }
 

@@ -166,10 +166,12 @@ __device__ __forceinline__ float es_kernel(float z) {
     return q > 0.f ? expf(ES_BETA * (sqrtf(q) - 1.f)) : 0.f;
 }
 
-// The same kernel with hardware exp2 and square root (about 2 ulp), used per grid cell.
+// The same kernel with the hardware exp2 and square root instructions (about 2 ulp; the
+// argument of exp2 is <= 0 and the result is only used in [2^-27, 1], so neither needs the
+// library's denormal range handling).
 __device__ __forceinline__ float es_kernel_fast(float z) {
     const float q = 1.f - z * z;
-    return q > 0.f ? __builtin_amdgcn_exp2f(ES_BETA * 1.44269504088896341f * (__builtin_sqrtf(q) - 1.f)) : 0.f;
+    return q > 0.f ? __builtin_amdgcn_exp2f(ES_BETA * 1.44269504088896341f * (__builtin_amdgcn_sqrtf(q) - 1.f)) : 0.f;
 }
 
 template <int PREC>
@@ -287,8 +289,12 @@ struct GridShape {
     static constexpr int RPT = R / (256 / COLT);     // owned rows per thread
     static constexpr int XMIN = -16, XMAX = M + 16;  // first-index table range
     static constexpr int NFIRST = XMAX - XMIN + 1;
-    // staged per baseline: first footprint cell (int2), value (float2), 16 weights
-    static constexpr int CAP = (CELLS * (int)sizeof(float2) - NFIRST * 4) / (8 + 8 + 16 * 4);
+    // staged weights per baseline: wu[0..7] and wv[0..7], each with zeros on both sides so a
+    // thread reads its CPT (RPT) consecutive entries at any footprint offset without a test
+    // (odd stride: the lanes of a wave read different baselines, so they fall in different banks)
+    static constexpr int WU = 8 + 2 * (CPT - 1), WV = 8 + 2 * (RPT - 1), WSTRIDE = (WU + WV) | 1;
+    // staged per baseline: first footprint cell (int2), value (float2), padded weights
+    static constexpr int CAP = (CELLS * (int)sizeof(float2) - NFIRST * 4) / (8 + 8 + WSTRIDE * 4);
     static_assert(CPT * RPT == GE, "GE cells per thread");
     static_assert(CAP >= 64, "staging room");
 };
@@ -304,12 +310,11 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
     // staging view of the grid's LDS
     int2 *s_g = reinterpret_cast<int2 *>(grid);                   // gu0, gv0: first footprint cell
     float2 *s_val = reinterpret_cast<float2 *>(s_g + CAP);         // Stokes I value
-    float *s_w = reinterpret_cast<float *>(s_val + CAP);           // wu[0..7], wv[0..7]
-    int *s_first = reinterpret_cast<int *>(s_w + 16 * CAP);       // [x - XMIN]: first i with gu0 >= x
+    float *s_w = reinterpret_cast<float *>(s_val + CAP);           // padded wu, then padded wv
+    int *s_first = reinterpret_cast<int *>(s_w + GS::WSTRIDE * CAP);  // [x - XMIN]: first i with gu0 >= x
 
     const int t = threadIdx.x;
     const int row0 = band * R;
-    __syncthreads();  // the previous task of a persistent workgroup no longer reads the LDS
     const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, LOGM, t, 256);
     const float2 *cv_c = cvis + (size_t)c * n_pairs;
     const int k_begin = band_off[band], k_end = band_off[band + 1];
@@ -346,11 +351,16 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
     // grid position u / du + M/2 with du = 1/4 wavelength (the membership of B was decided by
     // the gather kernel; baselines outside B carry a zero value)
     const double sc = freq[c] / C_LIGHT * 4.0;
-    for (int k0 = k_begin; k0 < k_end; k0 += CAP) {
-        const int nk = min(CAP, k_end - k0);
+    // when the band holds more baselines than one round stages, round rr takes list entries
+    // rr, rr + n_rounds, ...: still sorted by column, and spread over the whole band, so every
+    // wave has work in every round
+    const int n_items = k_end - k_begin;
+    const int n_rounds = (n_items + CAP - 1) / CAP;
+    for (int rr = 0; rr < n_rounds; rr++) {
+        const int nk = (n_items - rr + n_rounds - 1) / n_rounds;
         __syncthreads();
         for (int i = t; i < nk; i += 256) {
-            const int k = band_items[k0 + i];
+            const int k = band_items[k_begin + rr + i * n_rounds];
             float2 val = cv_c[k];
             if constexpr (PREC == NBSI_PREC_FP16) val = make_float2(val.x * vscale, val.y * vscale);
             const double2 d = dxy[k];
@@ -360,10 +370,17 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
             s_val[i] = val;
             const float ou = (float)(cu - fu), ov = (float)(cvv - fv);  // in [0, 1)
             // cell offsets from the baseline's grid position, in cells: (j - 3) - o
+            float *w = s_w + i * GS::WSTRIDE;
 #pragma unroll
-            for (int q = 0; q < 8; q++) s_w[i * 16 + q] = es_kernel_fast(((float)(q - 3) - ou) * 0.25f);
+            for (int q = 0; q < GS::WU; q++) {
+                const int j = q - (CPT - 1);
+                w[q] = (unsigned)j < 8u ? es_kernel_fast(((float)(j - 3) - ou) * 0.25f) : 0.f;
+            }
 #pragma unroll
-            for (int q = 0; q < 8; q++) s_w[i * 16 + 8 + q] = es_kernel_fast(((float)(q - 3) - ov) * 0.25f);
+            for (int q = 0; q < GS::WV; q++) {
+                const int j = q - (RPT - 1);
+                w[GS::WU + q] = (unsigned)j < 8u ? es_kernel_fast(((float)(j - 3) - ov) * 0.25f) : 0.f;
+            }
         }
         for (int x = t; x < GS::NFIRST; x += 256) s_first[x] = nk;
         __syncthreads();
@@ -381,13 +398,15 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
             const int dr0 = row0 + rown - g.y;  // footprint row of owned row 0
             if (dr0 + RPT <= 0 || dr0 >= 8) continue;
             const float2 val = s_val[i];
-            const float *w = s_w + i * 16;
-            const int dc0 = col0 - g.x;  // footprint column of owned column 0
+            // footprint column of owned column 0 is col0 - gu0 in [-(CPT-1), 7]; footprint row of
+            // owned row 0 is dr0 in [-(RPT-1), 7]: both index the padded rows in range
+            const float *wup = s_w + i * GS::WSTRIDE + (CPT - 1) + (col0 - g.x);
+            const float *wvp = s_w + i * GS::WSTRIDE + GS::WU + (RPT - 1) + dr0;
             float wu[CPT], wv[RPT];
 #pragma unroll
-            for (int q = 0; q < CPT; q++) wu[q] = (unsigned)(dc0 + q) < 8u ? w[dc0 + q] : 0.f;
+            for (int q = 0; q < CPT; q++) wu[q] = wup[q];
 #pragma unroll
-            for (int r = 0; r < RPT; r++) wv[r] = (unsigned)(dr0 + r) < 8u ? w[8 + dr0 + r] : 0.f;
+            for (int r = 0; r < RPT; r++) wv[r] = wvp[r];
             if constexpr (PREC == NBSI_PREC_FP32) {
 #pragma unroll
                 for (int q = 0; q < CPT; q++) {
@@ -439,22 +458,22 @@ __global__ __launch_bounds__(256) void grid_rows_kernel(
                           tw_lo, tw_hi, vscale);
 }
 
-// Persistent gridding over the sub-bands of one image size: task -> (job, channel, band).
+// Gridding of channel ranges of several sub-bands of one image size: task -> (job, channel,
+// band), one workgroup per task.
 template <int LOGM, int PREC, int GE>
 __global__ __launch_bounds__(256) void grid_rows_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
-                                                              int n_tasks, int *__restrict__ counter) {
+                                                              int n_tasks) {
     __shared__ float2 grid[padded_size(Tile<GE>::CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
     __shared__ float vscale;
-    __shared__ int s_task;
-    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
-        int j = 0;
-        while (j + 1 < n_jobs && jobs[j + 1].rows_task0 <= task) j++;
-        const ImgJob &jb = jobs[j];
-        const int local = task - jb.rows_task0;
-        grid_rows<LOGM, PREC, GE>(jb.cvis, jb.dxy, jb.freq, jb.band_off, jb.band_items, jb.n_pairs, jb.n_pix, jb.inter,
+    const int task = blockIdx.x;
+    if (task >= n_tasks) return;
+    int j = 0;
+    while (j + 1 < n_jobs && jobs[j + 1].rows_task0 <= task) j++;
+    const ImgJob &jb = jobs[j];
+    const int local = task - jb.rows_task0;
+    grid_rows<LOGM, PREC, GE>(jb.cvis, jb.dxy, jb.freq, jb.band_off, jb.band_items, jb.n_pairs, jb.n_pix, jb.inter,
                               local % jb.n_bands, local / jb.n_bands, grid, tw_lo, tw_hi, vscale);
-    }
 }
 
 template <int GE>
@@ -463,7 +482,6 @@ __device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, int 
                                           float *__restrict__ img, int xb, int c, float2 *buf, float2 *tw_lo,
                                           float2 *tw_hi) {
     const int t = threadIdx.x;
-    __syncthreads();  // the previous task of a persistent workgroup no longer reads the LDS
     const int M = 1 << log_m;
     const int x0 = xb * band_cols;
     const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_m, t, 256);
@@ -503,34 +521,33 @@ __global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict
 
 template <int GE>
 __global__ __launch_bounds__(256) void grid_cols_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
-                                                              int n_tasks, int *__restrict__ counter) {
+                                                              int n_tasks) {
     __shared__ float2 buf[padded_size(Tile<GE>::CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
-    __shared__ int s_task;
-    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
-        int j = 0;
-        while (j + 1 < n_jobs && jobs[j + 1].cols_task0 <= task) j++;
-        const ImgJob &jb = jobs[j];
-        const int band_cols = Tile<GE>::CELLS / (1 << jb.log_m);
-        const int n_xb = jb.n_pix / band_cols;
-        const int local = task - jb.cols_task0;
-        grid_cols<GE>(jb.inter, jb.n_pix, jb.log_m, band_cols, jb.corr, jb.nb, jb.img, local % n_xb, local / n_xb, buf,
+    const int task = blockIdx.x;  // one workgroup per (job, channel, column band)
+    if (task >= n_tasks) return;
+    int j = 0;
+    while (j + 1 < n_jobs && jobs[j + 1].cols_task0 <= task) j++;
+    const ImgJob &jb = jobs[j];
+    const int band_cols = Tile<GE>::CELLS / (1 << jb.log_m);
+    const int n_xb = jb.n_pix / band_cols;
+    const int local = task - jb.cols_task0;
+    grid_cols<GE>(jb.inter, jb.n_pix, jb.log_m, band_cols, jb.corr, jb.nb, jb.img, local % n_xb, local / n_xb, buf,
                   tw_lo, tw_hi);
-    }
 }
 
+// Gather over channel ranges of several sub-bands: one workgroup per (job, channel, 256 pairs).
 __global__ __launch_bounds__(256) void stokes_gather_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
-                                                                  int n_tasks, int *__restrict__ counter) {
-    __shared__ int s_task;
-    for (int task = batch_next_task(counter, s_task); task < n_tasks; task = batch_next_task(counter, s_task)) {
-        int j = 0;
-        while (j + 1 < n_jobs && jobs[j + 1].gather_task0 <= task) j++;
-        const ImgJob &jb = jobs[j];
-        const int local = task - jb.gather_task0;
-        const int nblk = (jb.n_pairs + 255) / 256;
-        stokes_gather<int2>(reinterpret_cast<const int2 *>(jb.vis), jb.xyz, jb.freq, jb.pairs, jb.n_pairs, jb.n_ant,
-                            jb.n_pix, jb.uv_min, jb.uv_max, jb.cvis, local / nblk, (local % nblk) * 256 + threadIdx.x);
-    }
+                                                                  int n_tasks) {
+    const int task = blockIdx.x;
+    if (task >= n_tasks) return;
+    int j = 0;
+    while (j + 1 < n_jobs && jobs[j + 1].gather_task0 <= task) j++;
+    const ImgJob &jb = jobs[j];
+    const int local = task - jb.gather_task0;
+    const int nblk = (jb.n_pairs + 255) / 256;
+    stokes_gather<int2>(reinterpret_cast<const int2 *>(jb.vis), jb.xyz, jb.freq, jb.pairs, jb.n_pairs, jb.n_ant,
+                        jb.n_pix, jb.uv_min, jb.uv_max, jb.cvis, local / nblk, (local % nblk) * 256 + threadIdx.x);
 }
 
 }  // namespace
@@ -601,18 +618,17 @@ hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_
                        : launch_grid_ge<16>(p, precision, cvis, inter, img, log_m, st);
 }
 
-hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int n_groups,
-                                     hipStream_t st) {
-    hipLaunchKernelGGL(stokes_gather_batch_kernel, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks, counter);
+hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, hipStream_t st) {
+    hipLaunchKernelGGL(stokes_gather_batch_kernel, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
     return hipGetLastError();
 }
 
 template <int GE>
-static hipError_t launch_batch_rows_ge(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int log_m, int precision,
-                                       int n_groups, hipStream_t st) {
+static hipError_t launch_batch_rows_ge(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision,
+                                       hipStream_t st) {
 #define NBSI_BR(LM, PR)                                                                                        \
-    hipLaunchKernelGGL((grid_rows_batch_kernel<LM, PR, GE>), dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, \
-                       n_tasks, counter)
+    hipLaunchKernelGGL((grid_rows_batch_kernel<LM, PR, GE>), dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, \
+                       n_tasks)
 #define NBSI_BR_P(LM)                                                    \
     if (precision == NBSI_PREC_FP16) NBSI_BR(LM, NBSI_PREC_FP16);         \
     else if (precision == NBSI_PREC_BF16) NBSI_BR(LM, NBSI_PREC_BF16);    \
@@ -630,17 +646,16 @@ static hipError_t launch_batch_rows_ge(const ImgJob *d_jobs, int n_jobs, int n_t
     return hipGetLastError();
 }
 
-hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int log_m, int precision,
-                                   int ge, int n_groups, hipStream_t st) {
-    return ge == 32 ? launch_batch_rows_ge<32>(d_jobs, n_jobs, n_tasks, counter, log_m, precision, n_groups, st)
-                    : launch_batch_rows_ge<16>(d_jobs, n_jobs, n_tasks, counter, log_m, precision, n_groups, st);
+hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision, int ge,
+                                   hipStream_t st) {
+    return ge == 32 ? launch_batch_rows_ge<32>(d_jobs, n_jobs, n_tasks, log_m, precision, st)
+                    : launch_batch_rows_ge<16>(d_jobs, n_jobs, n_tasks, log_m, precision, st);
 }
 
-hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int ge, int n_groups,
-                                   hipStream_t st) {
+hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int ge, hipStream_t st) {
     if (ge == 32)
-        hipLaunchKernelGGL(grid_cols_batch_kernel<32>, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks, counter);
+        hipLaunchKernelGGL(grid_cols_batch_kernel<32>, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
     else
-        hipLaunchKernelGGL(grid_cols_batch_kernel<16>, dim3(n_groups), dim3(256), 0, st, d_jobs, n_jobs, n_tasks, counter);
+        hipLaunchKernelGGL(grid_cols_batch_kernel<16>, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
     return hipGetLastError();
 }

@@ -70,20 +70,11 @@ int image_plan_build(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const
                      int n_pix, int method, double uv_min, double uv_max, int ge, nbsi_image_plan **out);
 int nbsi_fail(nbsi_ctx *ctx, int code, const std::string &msg);
 
-// Work queue of the persistent batched kernels: each workgroup draws the next task index from a
-// device counter (zeroed before the launch) until the index passes the task count, so heavy and
-// light tasks spread over the workgroups as they free up.  Every thread of the workgroup gets
-// the same index; the leading barrier keeps the previous task's LDS and index alive until all
-// threads are done with them.
-__device__ __forceinline__ int batch_next_task(int *counter, int &s_task) {
-    __syncthreads();
-    if (threadIdx.x == 0) s_task = atomicAdd(counter, 1);
-    __syncthreads();
-    return s_task;
-}
+// Batched launches: every stage of several sub-bands runs as one launch over a task table,
+// one workgroup per task; each job (sub-band, or channel range of one) records the first task
+// it owns, and a workgroup finds its job by a scan of the (few) jobs.
 
-// One sub-band's channelizer parameters (device-visible; also the task descriptor of the
-// persistent batched launch).
+// One sub-band's channelizer parameters (device-visible; also the job of a batched launch).
 struct ChanJob {
     const int8_t *volt;
     const float *gain;
@@ -93,7 +84,7 @@ struct ChanJob {
     int task0;  // first task of this sub-band in a batched launch
 };
 
-// One sub-band's correlator parameters (task descriptor of the persistent batched launch).
+// One sub-band's correlator parameters (the job of a batched launch).
 struct CorrJob {
     const int8_t *q;
     int32_t *vis;
@@ -106,10 +97,10 @@ int correlate_default_variant(int n_in, int n_spec);
 bool correlate_variant_valid(int n_in, int n_spec, int variant);
 hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
                                     hipStream_t st);
-hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int *counter, int variant, int n_in,
-                                  int n_groups, hipStream_t st);
+hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in,
+                                  hipStream_t st);
 
-// One sub-band's gridding imager parameters (task descriptor of the persistent launches).
+// One sub-band's (or channel range's) gridding imager parameters (the job of batched launches).
 struct ImgJob {
     const int32_t *vis;
     const double *xyz, *freq;
@@ -123,26 +114,24 @@ struct ImgJob {
     double uv_min, uv_max;
     int gather_task0, rows_task0, cols_task0;
 };
-hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int n_groups,
-                                     hipStream_t st);
-hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int log_m, int precision,
-                                   int ge, int n_groups, hipStream_t st);
-hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int *counter, int ge, int n_groups,
+hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, hipStream_t st);
+hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision, int ge,
                                    hipStream_t st);
+hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int ge, hipStream_t st);
 
 int channelize_log_m(int log_n, int n_chan);
 int channelize_dyn_elems(int log_n, int log_m);
 int channelize_group(int log_n, int log_m);
 int corner_turn_tasks(int n_in, int n_spec, int n_chan);
-hipError_t launch_corner_turn_q_batch(const ChanJob *d_jobs, int n_jobs, const int *d_task0, int n_tasks, int *counter,
-                                      int8_t *const *d_outs, int n_in, int n_groups, hipStream_t st);
+hipError_t launch_corner_turn_q_batch(const ChanJob *d_jobs, int n_jobs, const int *d_task0, int n_tasks,
+                                      int8_t *const *d_outs, int n_in, hipStream_t st);
 
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_channelize(const int8_t *volt, int n_in, int log_n, int n_spec, int klo,
                              int n_chan, const float *gain, int8_t *stage_q, float *stage_f,
                              hipStream_t st);
-hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_tasks, int *counter, int log_m, int g,
-                                   int max_dyn_elems, int n_groups, hipStream_t st);
+hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_tasks, int log_m, int g,
+                                   int max_dyn_elems, hipStream_t st);
 hipError_t launch_corner_turn_q(const int8_t *stage, int n_in, int n_spec, int n_chan,
                                 int8_t *out, hipStream_t st);
 hipError_t launch_corner_turn_f(const float *stage, int n_in, int n_spec, int n_chan, float *out,
