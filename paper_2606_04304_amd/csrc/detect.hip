@@ -2,14 +2,14 @@
 // width-1 matched filter), gfx950.
 //
 // Per-pixel kernel: a workgroup stages the spectra of PPW neighbouring pixels in LDS (one
-// read of the cube), and one wave per pixel computes the exact median and MAD by selection
-// (value-range histograms in LDS refined until a few candidates remain, then ranked), scores
-// every channel and keeps threshold crossings that survive +-1 channel non-maximum
-// suppression (ties keep the lower channel).  Candidates are appended
-// with a global atomic counter and sorted afterwards by (y, x, c) with a bitonic network.
+// read of the cube), and one wave per pixel computes the exact median and MAD by a wave-local
+// selection (sampled brackets checked by exact counts, no atomics and no barriers; see
+// wave_select), scores every channel and keeps threshold crossings that survive +-1 channel
+// non-maximum suppression (ties keep the lower channel).  Candidates are appended with a
+// global atomic counter and sorted afterwards by (y, x, c) with a bitonic network.
 //
 // Per-image mode first computes each channel image's median and MAD over the visible
-// hemisphere (the same selection over the image in global memory, one wave per channel),
+// hemisphere (a histogram selection over the image in global memory, one wave per channel),
 // then runs the per-pixel kernel on the standardised values with only the spectral median
 // removed.
 #include "internal.h"
@@ -210,6 +210,361 @@ __device__ float wave_median(ValFn val, int n, int n_valid, unsigned *hist, floa
     return 0.5f * (vlo + vhi);
 }
 
+// The next float above / below a finite x (the bracket bounds around a dropped pivot value).
+__device__ __forceinline__ float float_up(float x) {
+    if (x == 0.f) return __int_as_float(1);  // smallest positive denormal
+    const int b = __float_as_int(x);
+    return __int_as_float(x > 0.f ? b + 1 : b - 1);
+}
+__device__ __forceinline__ float float_down(float x) { return -float_up(-x); }
+
+// Ascending bitonic sort of one value per lane across the wave (64 values).
+__device__ __forceinline__ float wave_sort64(float v, int lane) {
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const float o = __shfl_xor(v, stride, 64);
+            const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
+            v = keep_min ? fminf(v, o) : fmaxf(v, o);
+        }
+    return v;
+}
+
+// Pseudo-random 32-bit hash of (i, round), for reservoir sampling.
+__device__ __forceinline__ unsigned mix_hash(unsigned i, unsigned round) {
+    unsigned h = i * 0x9E3779B1u + round * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return h;
+}
+
+// The rank-th smallest (0-based) of val(i), i < n (finite values), for one wave, without
+// atomics or barriers.  The wave keeps a bracket [lo, hi] of values known to hold the answer,
+// with c_lt values below it and c_le values at or below its top (c_lt <= rank < c_le).  Each
+// round sorts a sample of in-bracket values (one per lane, drawn from the entries l, l + 64, ...),
+// takes the sample values D places either side of the rank's expected place as a candidate
+// [a, b] (a single pivot value when the bracket did not shrink last round), and counts the data
+// below a and at or below b: the rank then lies below a, in [a, b] or above b, and the bracket
+// becomes that part.  The counting pass also keeps the first value of the lane's entries in
+// [a, b], the next sample when the rank is there (the usual case); otherwise, and from round
+// RESAMPLE_FROM on, a separate pass draws a uniform in-bracket sample by reservoir sampling,
+// which keeps sorted or trending data from skewing the sample.  A pivot round always removes
+// the pivot, so the loop ends; noise-like spectra need 3-4 rounds.  At most 64 values are left in
+// the bracket then; they are gathered into `pool` (64 floats) and ranked exactly.
+template <typename ValFn>
+__device__ float wave_select(ValFn val, int n, int rank, float *pool, int lane) {
+    constexpr int D = 8, RESAMPLE_FROM = 4;
+    float lo = -INFINITY, hi = INFINITY;
+    int c_lt = 0, c_le = n;
+    float smp = lane < n ? val(lane) : INFINITY;  // this lane's sample of the bracket (+inf: none)
+    bool pivot = false, resample = false;
+    for (int round = 0; round < 2 * n + 2; round++) {
+        const int m = c_le - c_lt;
+        if (m <= 64 || lo == hi) break;
+        if (resample || round >= RESAMPLE_FROM) {
+            // uniform in-bracket value of this lane's entries (reservoir sampling)
+            smp = INFINITY;
+            int k = 0;
+            for (int i = lane; i < n; i += 64) {
+                const float x = val(i);
+                if (x >= lo && x <= hi) {
+                    k++;
+                    if ((mix_hash((unsigned)i, (unsigned)round) >> 20) * (unsigned)k < 4096u) smp = x;
+                }
+            }
+        }
+        const float srt = wave_sort64(smp, lane);
+        const int s_n = wave_sum(smp < INFINITY ? 1 : 0);  // >= 1: m > 64 values over 64 lanes
+        const int p = min(s_n - 1, (int)(((long long)(rank - c_lt) * s_n) / m));
+        float a, b;
+        if (pivot) {
+            a = b = __shfl(srt, p, 64);
+        } else {
+            a = p - D >= 0 ? __shfl(srt, p - D, 64) : lo;
+            b = p + D < s_n ? __shfl(srt, p + D, 64) : hi;
+            if (a == lo && b == hi) a = b = __shfl(srt, p, 64);
+        }
+        int n_lt = 0, n_le = 0;
+        float s_in = INFINITY;
+        for (int i = lane; i < n; i += 64) {
+            const float x = val(i);
+            n_lt += x < a;
+            n_le += x <= b;
+            s_in = (s_in == INFINITY && x >= a && x <= b) ? x : s_in;
+        }
+        n_lt = wave_sum(n_lt);
+        n_le = wave_sum(n_le);
+        resample = true;
+        if (rank < n_lt) {  // below a
+            hi = float_down(a);
+            c_le = n_lt;
+        } else if (rank >= n_le) {  // above b
+            lo = float_up(b);
+            c_lt = n_le;
+        } else {  // in [a, b]
+            if (a == b) return a;
+            lo = a;
+            hi = b;
+            c_lt = n_lt;
+            c_le = n_le;
+            smp = s_in;
+            resample = false;
+        }
+        pivot = c_le - c_lt == m;  // nothing left the bracket: split at a pivot next round
+    }
+    if (lo == hi) return lo;
+    // at most 64 values in [lo, hi]: gather them and rank exactly
+    int base = 0;
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int i = i0 + lane;
+        float x = 0.f;
+        bool in = false;
+        if (i < n) {
+            x = val(i);
+            in = x >= lo && x <= hi;
+        }
+        const unsigned long long bm = __ballot(in);
+        if (in) pool[base + __popcll(bm & ((1ull << lane) - 1ull))] = x;
+        base += __popcll(bm);
+    }
+    const int m = base;
+    const int k = rank - c_lt;
+    float mine = 0.f;
+    bool hit = false;
+    if (lane < m) {
+        mine = pool[lane];
+        int less = 0, eq = 0;
+        for (int j = 0; j < m; j++) {
+            const float y = pool[j];
+            less += y < mine;
+            eq += y == mine;
+        }
+        hit = less <= k && k < less + eq;
+    }
+    const unsigned long long hb = __ballot(hit);
+    return __shfl(mine, hb ? (int)(__ffsll((long long)hb) - 1) : 0, 64);
+}
+
+// Median of val(i), i < n (finite values; mean of the central pair for even n), wave-local.
+template <typename ValFn>
+__device__ float wave_median_fast(ValFn val, int n, float *pool, int lane) {
+    const float vlo = wave_select(val, n, (n - 1) / 2, pool, lane);
+    if (n & 1) return vlo;
+    int le = 0;
+    float nxt = INFINITY;
+    for (int i = lane; i < n; i += 64) {
+        const float x = val(i);
+        le += x <= vlo;
+        if (x > vlo) nxt = fminf(nxt, x);
+    }
+    le = wave_sum(le);
+    nxt = wave_min_f(nxt);
+    const float vhi = (le >= n / 2 + 1) ? vlo : nxt;
+    return 0.5f * (vlo + vhi);
+}
+
+// ---- spectra held in registers (n_chan <= 64 NR) ----
+// Lane l of a wave holds channels l + 64 j, j < NR, of its pixel in v[j] (NaN past n_chan, which
+// every comparison below treats as false); tf maps a held value to the value being ranked.  The
+// same algorithm as wave_select, with every pass over registers instead of LDS.
+template <int NR, typename TF>
+__device__ float reg_select(const float (&v)[NR], TF tf, int n, int rank, float *pool, int lane) {
+    constexpr int D = 8, RESAMPLE_FROM = 4;
+    float lo = -INFINITY, hi = INFINITY;
+    int c_lt = 0, c_le = n;
+    float smp = lane < n ? tf(v[0]) : INFINITY;
+    bool pivot = false, resample = false;
+    for (int round = 0; round < 2 * n + 2; round++) {
+        const int m = c_le - c_lt;
+        if (m <= 64 || lo == hi) break;
+        if (resample || round >= RESAMPLE_FROM) {
+            smp = INFINITY;
+            int k = 0;
+#pragma unroll
+            for (int j = 0; j < NR; j++) {
+                const float x = tf(v[j]);
+                if (x >= lo && x <= hi) {
+                    k++;
+                    if ((mix_hash((unsigned)(lane + 64 * j), (unsigned)round) >> 20) * (unsigned)k < 4096u) smp = x;
+                }
+            }
+        }
+        const float srt = wave_sort64(smp, lane);
+        const int s_n = wave_sum(smp < INFINITY ? 1 : 0);
+        const int p = min(s_n - 1, (int)(((long long)(rank - c_lt) * s_n) / m));
+        float a, b;
+        if (pivot) {
+            a = b = __shfl(srt, p, 64);
+        } else {
+            a = p - D >= 0 ? __shfl(srt, p - D, 64) : lo;
+            b = p + D < s_n ? __shfl(srt, p + D, 64) : hi;
+            if (a == lo && b == hi) a = b = __shfl(srt, p, 64);
+        }
+        int n_lt = 0, n_le = 0;
+        float s_in = INFINITY;
+#pragma unroll
+        for (int j = 0; j < NR; j++) {
+            const float x = tf(v[j]);
+            n_lt += x < a;
+            n_le += x <= b;
+            s_in = (s_in == INFINITY && x >= a && x <= b) ? x : s_in;
+        }
+        n_lt = wave_sum(n_lt);
+        n_le = wave_sum(n_le);
+        resample = true;
+        if (rank < n_lt) {
+            hi = float_down(a);
+            c_le = n_lt;
+        } else if (rank >= n_le) {
+            lo = float_up(b);
+            c_lt = n_le;
+        } else {
+            if (a == b) return a;
+            lo = a;
+            hi = b;
+            c_lt = n_lt;
+            c_le = n_le;
+            smp = s_in;
+            resample = false;
+        }
+        pivot = c_le - c_lt == m;
+    }
+    if (lo == hi) return lo;
+    int base = 0;
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        const float x = tf(v[j]);
+        const bool in = x >= lo && x <= hi;
+        const unsigned long long bm = __ballot(in);
+        if (in) pool[base + __popcll(bm & ((1ull << lane) - 1ull))] = x;
+        base += __popcll(bm);
+    }
+    const int m = base;
+    const int k = rank - c_lt;
+    float mine = 0.f;
+    bool hit = false;
+    if (lane < m) {
+        mine = pool[lane];
+        int less = 0, eq = 0;
+        for (int j = 0; j < m; j++) {
+            const float y = pool[j];
+            less += y < mine;
+            eq += y == mine;
+        }
+        hit = less <= k && k < less + eq;
+    }
+    const unsigned long long hb = __ballot(hit);
+    return __shfl(mine, hb ? (int)(__ffsll((long long)hb) - 1) : 0, 64);
+}
+
+template <int NR, typename TF>
+__device__ float reg_median(const float (&v)[NR], TF tf, int n, float *pool, int lane) {
+    const float vlo = reg_select<NR>(v, tf, n, (n - 1) / 2, pool, lane);
+    if (n & 1) return vlo;
+    int le = 0;
+    float nxt = INFINITY;
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        const float x = tf(v[j]);
+        le += x <= vlo;
+        if (x > vlo) nxt = fminf(nxt, x);
+    }
+    le = wave_sum(le);
+    nxt = wave_min_f(nxt);
+    const float vhi = (le >= n / 2 + 1) ? vlo : nxt;
+    return 0.5f * (vlo + vhi);
+}
+
+// Per-pixel detection for spectra of up to 64 NR channels: a workgroup of 16 waves takes 16
+// adjacent pixels of one row; each staging round loads 512 channels x 16 pixels (64 contiguous
+// bytes per channel row) through an LDS tile, and every wave keeps its pixel's spectrum in
+// registers, so the selections and the scoring run without LDS or barriers.
+constexpr int REG_PX = 16;
+template <int NR>
+__global__ __launch_bounds__(1024) void detect_pixel_reg_kernel(const float *__restrict__ img, int n_chan, int n_pix,
+                                                                int mode, const float2 *__restrict__ stats,
+                                                                float thresh, float *__restrict__ snr_out,
+                                                                nbsi_cand *__restrict__ cand, int cap,
+                                                                int *__restrict__ counter) {
+    constexpr int CH = 512;  // channels per staging round (8 registers)
+    static_assert(NR % 8 == 0, "staging rounds");
+    __shared__ float tile[CH][REG_PX + 1];
+    __shared__ float pool_all[REG_PX][64];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int groups_per_row = (n_pix + REG_PX - 1) / REG_PX;
+    const int gy = blockIdx.x / groups_per_row, gx0 = (blockIdx.x % groups_per_row) * REG_PX;
+    const size_t npix2 = (size_t)n_pix * n_pix;
+    const int sp = t % REG_PX, sc = t / REG_PX;  // staging: pixel, channel offset (0..63)
+    float v[NR];
+#pragma unroll
+    for (int k = 0; k < NR / 8; k++) {
+        float r[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int c = k * CH + sc + 64 * q;
+            float x = NAN;
+            if (c < n_chan && gx0 + sp < n_pix) {
+                x = img[(size_t)c * npix2 + (size_t)gy * n_pix + gx0 + sp];
+                if (mode == NBSI_DETECT_PER_IMAGE) {
+                    const float2 st = stats[c];
+                    x = st.y > 0.f ? (x - st.x) / st.y : 0.f;
+                }
+            }
+            r[q] = x;
+        }
+        __syncthreads();  // the previous round's tile has been read
+#pragma unroll
+        for (int q = 0; q < 8; q++) tile[sc + 64 * q][sp] = r[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[8 * k + q] = tile[lane + 64 * q][wave];
+    }
+    const int x = gx0 + wave, y = gy;
+    if (x >= n_pix) return;  // no barriers below
+    const bool active = in_horizon(x, y, n_pix);
+    float *pool = pool_all[wave];
+    float med = 0.f, scale = 1.f;
+    bool ok = active;
+    if (active) {
+        med = reg_median<NR>(v, [](float a) { return a; }, n_chan, pool, lane);
+        if (mode == NBSI_DETECT_PER_PIXEL) {
+            const float mad = reg_median<NR>(v, [med](float a) { return fabsf(a - med); }, n_chan, pool, lane);
+            scale = MAD_K * mad;
+            ok = mad > 0.f;
+        }
+    }
+    // SNR = (x - med) / scale as a product with the float32 reciprocal; neighbours along
+    // frequency come from the adjacent lane (channel c +- 1), across register rows at lanes 0/63
+    const float inv = ok ? 1.f / scale : 0.f;
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        const int c = lane + 64 * j;
+        const float xv = v[j];
+        const float up = __shfl_up(xv, 1, 64), dn = __shfl_down(xv, 1, 64);
+        const float prev_row = j > 0 ? __shfl(v[j > 0 ? j - 1 : 0], 63, 64) : 0.f;
+        const float next_row = j + 1 < NR ? __shfl(v[j + 1 < NR ? j + 1 : j], 0, 64) : 0.f;
+        if (c >= n_chan) continue;
+        const float z = (xv - med) * inv;
+        if (snr_out) snr_out[(size_t)c * npix2 + (size_t)y * n_pix + x] = z;
+        if (!ok || z < thresh) continue;
+        const float xl = lane > 0 ? up : prev_row, xr = lane < 63 ? dn : next_row;
+        if (c > 0 && !(z > (xl - med) * inv)) continue;
+        if (c + 1 < n_chan && !(z >= (xr - med) * inv)) continue;
+        const int idx = atomicAdd(counter, 1);
+        if (idx < cap) {
+            nbsi_cand r;
+            r.x = x;
+            r.y = y;
+            r.c = c;
+            r.width = 1;
+            r.snr = z;
+            cand[idx] = r;
+        }
+    }
+}
+
 // stats: per-channel (median, k * MAD) for PER_IMAGE mode, else unused.
 template <int PPW>
 __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
@@ -217,7 +572,6 @@ __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
     float thresh, float *__restrict__ snr_out, nbsi_cand *__restrict__ cand, int cap, int *__restrict__ counter,
     int n_groups) {
     extern __shared__ float spec[];  // [PPW][n_chan]
-    __shared__ unsigned hist_all[PPW][256];
     __shared__ float pool_all[PPW][64];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     // XCD-aware order: consecutive pixel groups of one XCD share cache lines of the cube rows
@@ -246,28 +600,26 @@ __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
     const int x = gx0 + wave, y = gy;
     const bool active = grp_ok && in_horizon(x, y, n_pix);
     float *s = spec + wave * n_chan;
-    unsigned *hist = hist_all[wave];
     float *pool = pool_all[wave];
     auto val_x = [&](int i) { return s[i]; };
-    const float med = wave_median(val_x, n_chan, n_chan, hist, pool, lane);
+    const float med = wave_median_fast(val_x, n_chan, pool, lane);
     float scale = 1.f;  // SNR = (x - med) / scale
     bool ok = active;
     if (mode == NBSI_DETECT_PER_PIXEL) {
         auto val_d = [&](int i) { return fabsf(s[i] - med); };
-        const float mad = wave_median(val_d, n_chan, n_chan, hist, pool, lane);
+        const float mad = wave_median_fast(val_d, n_chan, pool, lane);
         scale = MAD_K * mad;
         ok = ok && mad > 0.f;
     }
-    if (snr_out && grp_ok) {
-        for (int c = lane; c < n_chan; c += 64)
-            snr_out[(size_t)c * npix2 + (size_t)y * n_pix + x] = ok ? (s[c] - med) / scale : 0.f;
-    }
-    if (!ok) return;
+    // SNR = (x - med) / scale, applied as a product with the float32 reciprocal (within an ulp of
+    // the quotient; the same form scores neighbours for the suppression test)
+    const float inv = ok ? 1.f / scale : 0.f;
     for (int c = lane; c < n_chan; c += 64) {
-        const float z = (s[c] - med) / scale;
-        if (z < thresh) continue;
-        if (c > 0 && !(z > (s[c - 1] - med) / scale)) continue;
-        if (c + 1 < n_chan && !(z >= (s[c + 1] - med) / scale)) continue;
+        const float z = (s[c] - med) * inv;
+        if (snr_out && grp_ok) snr_out[(size_t)c * npix2 + (size_t)y * n_pix + x] = z;
+        if (!ok || z < thresh) continue;
+        if (c > 0 && !(z > (s[c - 1] - med) * inv)) continue;
+        if (c + 1 < n_chan && !(z >= (s[c + 1] - med) * inv)) continue;
         const int idx = atomicAdd(counter, 1);
         if (idx < cap) {
             nbsi_cand r;
@@ -356,12 +708,18 @@ hipError_t launch_detect_stats(const float *img, int n_chan, int n_pix, int mode
 hipError_t launch_detect_scan(const float *img, int n_chan, int n_pix, int mode, const float *stats,
                               float thresh, float *snr, nbsi_cand *cand, int cap, int *counter,
                               hipStream_t st) {
+    const float2 *s2 = reinterpret_cast<const float2 *>(stats);
+    if (n_chan <= 64 * 64) {
+        const int n_blocks = n_pix * ((n_pix + REG_PX - 1) / REG_PX);
+        hipLaunchKernelGGL(detect_pixel_reg_kernel<64>, dim3(n_blocks), dim3(64 * REG_PX), 0, st, img, n_chan, n_pix,
+                           mode, s2, thresh, snr, cand, cap, counter);
+        return hipGetLastError();
+    }
     const int ppw = detect_ppw(n_chan);
     const int n_groups = n_pix * n_pix / ppw;
     // grid covers every group id produced by the XCD-aware mapping (blocks of 64 groups)
     const int n_blocks = ((n_groups + 63) / 64) * 64;
     const size_t lds = (size_t)ppw * n_chan * sizeof(float);
-    const float2 *s2 = reinterpret_cast<const float2 *>(stats);
     // the staged spectra may exceed the default 64 KiB of dynamic LDS (gfx950 has 160 KiB)
     hipError_t ea = hipSuccess;
     if (ppw == 4) ea = hipFuncSetAttribute((const void *)detect_pixel_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

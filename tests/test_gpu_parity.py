@@ -274,3 +274,41 @@ def test_detect_truncation_reports_true_count():
     rec, _, n = nb.nbsi_detect(torch.from_numpy(cube).to(DEV), max_out=3)
     assert n >= 15 and len(rec) == 3
     assert [(int(r["y"]), int(r["x"]), int(r["c"])) for r in rec] == [(1, 8, 2), (1, 8, 6), (1, 8, 10)]
+
+
+@pytest.mark.parametrize("n_chan", [777, 4096])
+def test_detect_adversarial_spectra(n_chan):
+    """Spectra the exact median and MAD must survive: sorted and reversed ramps, slopes with
+    noise, a few repeated values, constant pixels (MAD 0: no detections), huge outliers, and
+    spectra with exactly two values; every pixel's SNR spectrum must match the oracle's."""
+    print(f"detect adversarial n_chan={n_chan}", flush=True)
+    n_pix = 16
+    rng = np.random.default_rng(n_chan)
+    cube = rng.standard_normal((n_chan, n_pix, n_pix)).astype(np.float32)
+    ramp = np.linspace(-5, 5, n_chan, dtype=np.float32)
+    for k, (y, x) in enumerate([(y, x) for y in range(4, 12) for x in range(4, 12)]):
+        kind = k % 8
+        if kind == 0:
+            cube[:, y, x] = ramp
+        elif kind == 1:
+            cube[:, y, x] = ramp[::-1]
+        elif kind == 2:
+            cube[:, y, x] = ramp * 3 + rng.standard_normal(n_chan)
+        elif kind == 3:
+            cube[:, y, x] = rng.integers(0, 4, n_chan).astype(np.float32)
+        elif kind == 4:
+            cube[:, y, x] = 2.5
+        elif kind == 5:
+            cube[:, y, x] = rng.standard_normal(n_chan) * np.where(rng.random(n_chan) < 0.05, 1e6, 1.0)
+        elif kind == 6:
+            cube[:, y, x] = np.where(np.arange(n_chan) < n_chan // 2, 1.0, 7.0)
+        else:
+            cube[:, y, x] = np.sort(rng.standard_normal(n_chan))
+    cube[n_chan // 3, 9, 6] += 40.0
+    rec, snr, n = nb.nbsi_detect(torch.from_numpy(cube).to(DEV), thresh=5.0, want_snr=True)
+    ref, snr_ref, valid = oracle.detect.detect(cube, tau=5.0, mode="per_pixel")
+    snr_got = snr.cpu().numpy()
+    scale = np.maximum(1.0, np.abs(snr_ref[:, valid]))
+    assert (np.abs(snr_got - snr_ref)[:, valid] / scale).max() <= 1e-4
+    assert np.all(snr_got[:, 4:12, 4:12][:, 0, 4] == 0)  # constant pixel (y=4, x=8): MAD 0
+    _compare_candidates(rec, ref, snr_ref, 5.0)
