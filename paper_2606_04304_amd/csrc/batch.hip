@@ -6,9 +6,9 @@
 // captured once into a hipGraph and replayed.  A persistent form with a device work queue was
 // measured slower here: the tasks are small and uneven, and the hardware dispatcher spreads
 // them better than an atomic counter per task.
-// An autotuner times the correlator variants (128 x 128 tiles vs whole-channel panels) and the
-// gridding tile height (16 or 32 cells per thread) on each sub-band's real shape and caches
-// the choices in a text file.
+// An autotuner chooses the correlator variant (128 x 128 tiles or whole-channel panels) per
+// integration length and the gridding tile height (16 or 32 cells per thread) per image shape by
+// timing replays of the whole batch, and caches the choices in a text file.
 #include "internal.h"
 
 #include <stdio.h>
@@ -35,6 +35,7 @@ struct nbsi_batch {
     std::vector<int8_t *> stage;
     float2 *cvis = nullptr;        // one imaging chunk's Stokes-I gather
     float2 *inter = nullptr;       // one imaging chunk's row-pass intermediate
+    size_t cvis_bytes = 0, inter_bytes = 0;
 
     struct Launch {  // one batched launch: kind, shape key, job array on the device
         int kind;    // 0 channelize, 1 corner turn, 2 correlate, 3 gather, 4 rows, 5 cols
@@ -119,15 +120,6 @@ double time_ms(hipStream_t st, const std::function<hipError_t()> &fn, int reps) 
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return ms / reps;
-}
-
-hipError_t enqueue_channelize_one(nbsi_batch *b, int s, hipStream_t st) {
-    const nbsi_subband &x = b->sb[s];
-    const int log_n = 31 - __builtin_clz(x.n_fft);
-    const int klo = (x.chan0 + x.n_fft / 2) & (x.n_fft - 1);
-    hipError_t e = launch_channelize(x.volt, b->n_in, log_n, x.n_spec, klo, x.n_chan, x.gain, b->stage[s], nullptr, st);
-    if (e != hipSuccess) return e;
-    return launch_corner_turn_q(b->stage[s], b->n_in, x.n_spec, x.n_chan, x.spec_q, st);
 }
 
 // Every stage of every sub-band, as the grouped launches.
@@ -327,13 +319,16 @@ int build_launches(nbsi_batch *b) {
                 q.vis = j.vis + (size_t)c0 * nprod * 2;
                 q.freq = j.freq + c0;
                 q.nb = j.nb + c0;
+                const size_t cv_n = sizeof(float2) * (size_t)n * std::max(1, j.n_pairs);
+                if (!b->cvis || !b->inter || used + per_chan * n > b->inter_bytes || cv_used + cv_n > b->cvis_bytes)
+                    return NBSI_EINVAL;  // the chunk buffers were sized for fewer pairs or channels
                 q.cvis = b->cvis + cv_used / sizeof(float2);
                 q.inter = b->inter + used / sizeof(float2);
                 q.img = j.img + (size_t)c0 * nb;
                 q.n_chan = n;
                 chunk.push_back(q);
                 used += per_chan * n;
-                cv_used += sizeof(float2) * (size_t)n * std::max(1, j.n_pairs);
+                cv_used += cv_n;
                 c0 += n;
             }
         }
@@ -417,95 +412,30 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
         b->grid_ge.push_back(16);
     }
     const bool tune = (flags & NBSI_BATCH_AUTOTUNE) != 0;
-    // channelize every sub-band once (the tuner needs real spectra and visibilities)
-    if (tune) {
-        for (int s = 0; s < n_sb; s++)
-            if (enqueue_channelize_one(b, s, b->stream) != hipSuccess) return fail(NBSI_EHIP, "channelize failed");
-    }
-    // correlator variant per shape
+    // choices from the cache (else the defaults: correlator variant by shape, 16-cell tiles)
     for (int s = 0; s < n_sb; s++) {
         const nbsi_subband &x = b->sb[s];
-        const std::string key = corr_key(n_in, x.n_spec);
-        auto it = cache.find(key);
-        if (it != cache.end() && correlate_variant_valid(n_in, x.n_spec, it->second)) {
-            b->corr_variant[s] = it->second;
-        } else if (tune) {
-            // two alternating rounds, the faster of each candidate's two timings
-            double best_t[3] = {1e30, 1e30, 1e30};
-            for (int round = 0; round < 2; round++)
-                for (int v : {CORR_VARIANT_TILED, CORR_VARIANT_CHAN32, CORR_VARIANT_CHAN64}) {
-                    if (!correlate_variant_valid(n_in, x.n_spec, v)) continue;
-                    const double ms = time_ms(
-                        b->stream,
-                        [&]() { return launch_correlate_variant(x.spec_q, x.n_chan, n_in, x.n_spec, x.vis, v, b->stream); },
-                        3);
-                    best_t[v] = std::min(best_t[v], ms);
-                }
-            int best_v = b->corr_variant[s];
-            for (int v = 0; v < 3; v++)
-                if (best_t[v] < best_t[best_v]) best_v = v;
-            b->corr_variant[s] = best_v;
-            cache[key] = best_v;
-            cache_dirty = true;
-        }
-        if (tune && launch_correlate_variant(x.spec_q, x.n_chan, n_in, x.n_spec, x.vis, b->corr_variant[s],
-                                             b->stream) != hipSuccess)
-            return fail(NBSI_EHIP, "correlate failed");
+        auto ic = cache.find(corr_key(n_in, x.n_spec));
+        if (ic != cache.end() && correlate_variant_valid(n_in, x.n_spec, ic->second)) b->corr_variant[s] = ic->second;
+        auto ig = cache.find(grid_key(n_ant, x.n_pix, x.n_chan));
+        if (flags & NBSI_BATCH_GRID_TALL) b->grid_ge[s] = 32;
+        else if (ig != cache.end() && (ig->second == 16 || ig->second == 32)) b->grid_ge[s] = ig->second;
     }
-    // imaging plans and the gridding tile height per sub-band
-    for (int s = 0; s < n_sb; s++) {
+    auto build_plan = [&](int s, int ge, nbsi_image_plan **p) {
         const nbsi_subband &x = b->sb[s];
-        const std::string key = grid_key(n_ant, x.n_pix, x.n_chan);
-        auto it = cache.find(key);
-        int ge = 16;
-        if (flags & NBSI_BATCH_GRID_TALL) {
-            ge = 32;
-        } else if (it != cache.end() && (it->second == 16 || it->second == 32)) {
-            ge = it->second;
-        } else if (tune) {
-            double best = 1e30;
-            for (int g : {16, 32, 16, 32}) {  // two alternating rounds
-                nbsi_image_plan *p = nullptr;
-                if (image_plan_build(ctx, ant_xyz_host, n_ant, x.freq_hz_host, x.n_chan, x.n_pix, NBSI_IMAGE_GRID, 0.0,
-                                     INFINITY, g, &p))
-                    return fail(NBSI_EHIP, "plan failed");
-                const size_t per_chan = (size_t)x.n_pix * 2 * x.n_pix * sizeof(float2);
-                void *cv = nullptr, *in = nullptr;
-                if (hipMalloc(&cv, sizeof(float2) * (size_t)x.n_chan * std::max(1, p->n_pairs)) != hipSuccess ||
-                    hipMalloc(&in, per_chan * x.n_chan) != hipSuccess) {
-                    if (cv) (void)hipFree(cv);
-                    nbsi_image_plan_destroy(p);
-                    return fail(NBSI_ENOMEM, "out of memory while tuning");
-                }
-                const double ms = time_ms(
-                    b->stream,
-                    [&]() {
-                        return launch_image_grid(p, x.vis, NBSI_VIS_I32, precision, (float2 *)cv, (float2 *)in, x.img,
-                                                 b->stream);
-                    },
-                    3);
-                (void)hipStreamSynchronize(b->stream);
-                (void)hipFree(cv);
-                (void)hipFree(in);
-                nbsi_image_plan_destroy(p);
-                if (ms < best) {
-                    best = ms;
-                    ge = g;
-                }
-            }
-            cache[key] = ge;
-            cache_dirty = true;
-        }
-        b->grid_ge[s] = ge;
+        return image_plan_build(ctx, ant_xyz_host, n_ant, x.freq_hz_host, x.n_chan, x.n_pix, NBSI_IMAGE_GRID, 0.0,
+                                INFINITY, ge, p);
+    };
+    for (int s = 0; s < n_sb; s++) {
         nbsi_image_plan *p = nullptr;
-        if ((rc = image_plan_build(ctx, ant_xyz_host, n_ant, x.freq_hz_host, x.n_chan, x.n_pix, NBSI_IMAGE_GRID, 0.0,
-                                   INFINITY, ge, &p)))
-            return fail(rc, "plan failed");
+        if ((rc = build_plan(s, b->grid_ge[s], &p))) return fail(rc, "plan failed");
         b->plans.push_back(p);
     }
     {
-        // a chunk holds at most max(1, IMAGE_CHUNK_BYTES / per-channel intermediate) channels of
-        // any sub-band; its gather at most that many channels times the largest pair count
+        // A chunk holds sub-bands of one transform size, so at most max(1, IMAGE_CHUNK_BYTES /
+        // per-channel intermediate) channels; its gather at most that many channels times the
+        // largest pair count among sub-bands of that size (pair counts do not depend on the tile
+        // height, so the tuner's alternative plans fit too).
         size_t need = IMAGE_CHUNK_BYTES, cv_need = 0;
         for (int s = 0; s < n_sb; s++) {
             const size_t per_chan = (size_t)b->sb[s].n_pix * 2 * b->sb[s].n_pix * sizeof(float2);
@@ -517,13 +447,83 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
             cv_need = std::max(cv_need, sizeof(float2) * ch * pairs_max);
         }
         void *in = nullptr, *cv = nullptr;
-        if ((rc = alloc(b, need, &in))) return fail(rc, "oom");
-        if ((rc = alloc(b, cv_need, &cv))) return fail(rc, "oom");
+        if ((rc = alloc(b, need, &in))) return fail(rc, "out of memory");
+        if ((rc = alloc(b, cv_need, &cv))) return fail(rc, "out of memory");
         b->inter = (float2 *)in;
         b->cvis = (float2 *)cv;
+        b->inter_bytes = need;
+        b->cvis_bytes = cv_need;
+    }
+    if ((rc = build_launches(b))) return fail(rc, "launch tables failed");
+    if (tune) {
+        // Coordinate descent over shape classes, each candidate timed as a replay of the whole
+        // batch (a kernel timed alone can mislead: e.g. 1,024 whole-channel correlator groups
+        // leave a tail on 256 CUs that the batched launch, mixing sub-bands, does not have).
+        // Shapes already in the cache keep their choice; a change is kept when the batch gets
+        // more than 1% faster, so the tuned batch is never slower than the default one.
+        auto relaunch = [&]() {
+            b->launches.clear();
+            return build_launches(b);
+        };
+        auto time_batch = [&]() { return time_ms(b->stream, [&]() { return enqueue_all(b, b->stream); }, 3); };
+        double best = time_batch();
+        std::map<int, std::vector<int>> corr_cls;  // n_spec -> sub-bands
+        std::map<std::pair<int, int>, std::vector<int>> grid_cls;  // (n_pix, n_chan) -> sub-bands
+        for (int s = 0; s < n_sb; s++) {
+            if (!cache.count(corr_key(n_in, b->sb[s].n_spec))) corr_cls[b->sb[s].n_spec].push_back(s);
+            if (!(flags & NBSI_BATCH_GRID_TALL) && !cache.count(grid_key(n_ant, b->sb[s].n_pix, b->sb[s].n_chan)))
+                grid_cls[{b->sb[s].n_pix, b->sb[s].n_chan}].push_back(s);
+        }
+        for (auto &kv : corr_cls) {
+            const int cur = b->corr_variant[kv.second[0]];
+            int keep = cur;
+            for (int v : {CORR_VARIANT_TILED, CORR_VARIANT_CHAN32, CORR_VARIANT_CHAN64}) {
+                if (v == cur || !correlate_variant_valid(n_in, kv.first, v)) continue;
+                for (int s : kv.second) b->corr_variant[s] = v;
+                if ((rc = relaunch())) return fail(rc, "launch tables failed");
+                const double t = time_batch();
+                if (t < 0.99 * best) {
+                    best = t;
+                    keep = v;
+                }
+            }
+            for (int s : kv.second) b->corr_variant[s] = keep;
+            cache[corr_key(n_in, kv.first)] = keep;
+            cache_dirty = true;
+        }
+        for (auto &kv : grid_cls) {
+            const int cur = b->grid_ge[kv.second[0]], alt = cur == 16 ? 32 : 16;
+            std::vector<nbsi_image_plan *> old;
+            for (int s : kv.second) {
+                nbsi_image_plan *p = nullptr;
+                if ((rc = build_plan(s, alt, &p))) {
+                    for (size_t q = 0; q < old.size(); q++) std::swap(b->plans[kv.second[q]], old[q]);
+                    for (auto *o : old) nbsi_image_plan_destroy(o);
+                    return fail(rc, "plan failed");
+                }
+                old.push_back(b->plans[s]);
+                b->plans[s] = p;
+                b->grid_ge[s] = alt;
+            }
+            if ((rc = relaunch())) return fail(rc, "launch tables failed");
+            const double t = time_batch();
+            int keep = alt;
+            if (t < 0.99 * best) {
+                best = t;
+            } else {  // revert to the previous plans
+                keep = cur;
+                for (size_t q = 0; q < old.size(); q++) {
+                    std::swap(b->plans[kv.second[q]], old[q]);
+                    b->grid_ge[kv.second[q]] = cur;
+                }
+            }
+            for (auto *o : old) nbsi_image_plan_destroy(o);
+            cache[grid_key(n_ant, kv.first.first, kv.first.second)] = keep;
+            cache_dirty = true;
+        }
+        if ((rc = relaunch())) return fail(rc, "launch tables failed");
     }
     if (cache_dirty) write_cache(tune_cache_path, cache);
-    if ((rc = build_launches(b))) return fail(rc, "launch tables failed");
     if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(NBSI_EHIP, "stream sync failed");
     // description of the choices (JSON)
     std::string d = "{\"subbands\": [";

@@ -210,6 +210,12 @@ __device__ float wave_median(ValFn val, int n, int n_valid, unsigned *hist, floa
     return 0.5f * (vlo + vhi);
 }
 
+// A wave-uniform value moved to a scalar register (frees vector registers in the selection loops).
+__device__ __forceinline__ float uniform_f(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ int uniform_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 // The next float above / below a finite x (the bracket bounds around a dropped pivot value).
 __device__ __forceinline__ float float_up(float x) {
     if (x == 0.f) return __int_as_float(1);  // smallest positive denormal
@@ -392,7 +398,7 @@ __device__ float reg_select(const float (&v)[NR], TF tf, int n, int rank, float 
             }
         }
         const float srt = wave_sort64(smp, lane);
-        const int s_n = wave_sum(smp < INFINITY ? 1 : 0);
+        const int s_n = uniform_i(wave_sum(smp < INFINITY ? 1 : 0));
         const int p = min(s_n - 1, (int)(((long long)(rank - c_lt) * s_n) / m));
         float a, b;
         if (pivot) {
@@ -402,6 +408,8 @@ __device__ float reg_select(const float (&v)[NR], TF tf, int n, int rank, float 
             b = p + D < s_n ? __shfl(srt, p + D, 64) : hi;
             if (a == lo && b == hi) a = b = __shfl(srt, p, 64);
         }
+        a = uniform_f(a);
+        b = uniform_f(b);
         int n_lt = 0, n_le = 0;
         float s_in = INFINITY;
 #pragma unroll
@@ -411,8 +419,8 @@ __device__ float reg_select(const float (&v)[NR], TF tf, int n, int rank, float 
             n_le += x <= b;
             s_in = (s_in == INFINITY && x >= a && x <= b) ? x : s_in;
         }
-        n_lt = wave_sum(n_lt);
-        n_le = wave_sum(n_le);
+        n_lt = uniform_i(wave_sum(n_lt));
+        n_le = uniform_i(wave_sum(n_le));
         resample = true;
         if (rank < n_lt) {
             hi = float_down(a);
