@@ -302,17 +302,28 @@ int image_plan_build(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const
     std::vector<int> band_off, band_items;
     std::vector<float> corr;
     if (method == NBSI_IMAGE_GRID) {
+        // The image is the real part of the grid's transform, i.e. half the transform of the
+        // Hermitian grid h(u, v) = g(u, v) + conj g(-u, -v): every pair is gridded at +(u, v)
+        // with V and at -(u, v) with conj V, and only the rows v >= 0 (array rows M/2 .. M-1)
+        // are gridded and row-transformed; the column pass recovers v < 0 by symmetry.  Items
+        // are 2 k + mirrored.
         p->band_rows = 256 * ge / M;
-        p->n_bands = M / p->band_rows;
+        p->n_bands = (M / 2) / p->band_rows;
         std::vector<std::vector<int>> bins(p->n_bands);
         for (int k = 0; k < p->n_pairs; k++)
-            for (int bnd = lo_row[k] / p->band_rows; bnd <= hi_row[k] / p->band_rows; bnd++) bins[bnd].push_back(k);
+            for (int mir = 0; mir < 2; mir++) {
+                const int lo = mir ? M - hi_row[k] : lo_row[k], hi = mir ? M - lo_row[k] : hi_row[k];
+                if (hi < M / 2) continue;
+                const int b0 = (std::max(lo, M / 2) - M / 2) / p->band_rows;
+                const int b1 = (std::min(hi, M - 1) - M / 2) / p->band_rows;
+                for (int bnd = b0; bnd <= b1; bnd++) bins[bnd].push_back(2 * k + mir);
+            }
         band_off.push_back(0);
         for (int bnd = 0; bnd < p->n_bands; bnd++) {
-            // sorted by x separation: the grid column u / du + M/2 = dx nu / (c du) + M/2 is then
-            // non-decreasing along the list for every channel frequency
-            std::stable_sort(bins[bnd].begin(), bins[bnd].end(),
-                             [&](int a, int b) { return dxy[a].x < dxy[b].x; });
+            // sorted by signed x separation (negated for mirrored items): the grid column
+            // +-dx nu / (c du) + M/2 is then non-decreasing along the list for every channel
+            auto key = [&](int it) { return (it & 1) ? -dxy[it >> 1].x : dxy[it >> 1].x; };
+            std::stable_sort(bins[bnd].begin(), bins[bnd].end(), [&](int a, int b) { return key(a) < key(b); });
             band_items.insert(band_items.end(), bins[bnd].begin(), bins[bnd].end());
             band_off.push_back((int)band_items.size());
         }
@@ -404,9 +415,9 @@ int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int 
         return NBSI_OK;
     }
     // Gridding runs over chunks of channels small enough for the row-transformed intermediate
-    // (n_pix x 2 n_pix complex per channel) to stay in the 256 MB last-level cache between the
+    // (n_pix x n_pix complex per channel) to stay in the 256 MB last-level cache between the
     // row and column passes.
-    const size_t per_chan = (size_t)plan->n_pix * 2 * plan->n_pix * sizeof(float2);
+    const size_t per_chan = (size_t)plan->n_pix * plan->n_pix * sizeof(float2);
     const int chunk = (int)std::max<size_t>(1, std::min<size_t>(plan->n_chan, IMAGE_CHUNK_BYTES / per_chan));
     void *inter = nullptr, *cvis = nullptr;
     int rc = nbsi_scratch(ctx, SLOT_IMG_INTER, per_chan * chunk, &inter);

@@ -271,8 +271,7 @@ int build_launches(nbsi_batch *b) {
                 rows[q].rows_task0 = rt;
                 rt += chunk[q].n_chan * chunk[q].n_bands;
                 cols[q].cols_task0 = ct;
-                const int band_cols = 256 * ge / (2 * chunk[q].n_pix);
-                ct += chunk[q].n_chan * (chunk[q].n_pix / band_cols);
+                ct += chunk[q].n_chan * (chunk[q].n_pix / cols_per_band(ge, chunk[q].n_pix));
             }
             nbsi_batch::Launch G;
             G.kind = 3;
@@ -305,7 +304,7 @@ int build_launches(nbsi_batch *b) {
         };
         for (int s : kv.second) {
             const ImgJob &j = base[s];
-            const size_t per_chan = (size_t)j.n_pix * 2 * j.n_pix * sizeof(float2);
+            const size_t per_chan = (size_t)j.n_pix * j.n_pix * sizeof(float2);
             const size_t nb = (size_t)j.n_pix * j.n_pix;
             for (int c0 = 0; c0 < j.n_chan;) {
                 if (used + per_chan > IMAGE_CHUNK_BYTES && !chunk.empty()) {
@@ -438,7 +437,7 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
         // height, so the tuner's alternative plans fit too).
         size_t need = IMAGE_CHUNK_BYTES, cv_need = 0;
         for (int s = 0; s < n_sb; s++) {
-            const size_t per_chan = (size_t)b->sb[s].n_pix * 2 * b->sb[s].n_pix * sizeof(float2);
+            const size_t per_chan = (size_t)b->sb[s].n_pix * b->sb[s].n_pix * sizeof(float2);
             need = std::max(need, per_chan);
             const size_t ch = std::max<size_t>(1, IMAGE_CHUNK_BYTES / per_chan);
             size_t pairs_max = 1;

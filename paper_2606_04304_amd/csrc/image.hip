@@ -270,10 +270,13 @@ __global__ __launch_bounds__(256) void stokes_gather_kernel(const VT *__restrict
                       blockIdx.x * 256 + threadIdx.x);
 }
 
-// Gridding without atomics.  A workgroup grids one band of R rows of the 2n x 2n grid; every
-// thread owns a fixed rectangle of GE cells of it (CPT consecutive columns x RPT rows) in
-// registers and sums the baselines whose 8 x 8 kernel footprint covers it.  The band's baselines
-// are sorted by x separation, hence by grid column for every channel (u is proportional to dx).
+// Gridding without atomics.  A workgroup grids one band of R rows of the upper half (v >= 0) of
+// the 2n x 2n Hermitian grid, each pair entering at +(u, v) with V and at -(u, v) with conj V
+// where its footprint reaches those rows; every thread owns a fixed rectangle of GE cells of it
+// (CPT consecutive columns x RPT rows) in registers and sums the baselines whose 8 x 8 kernel
+// footprint covers it, then the band is transformed along u and the n kept columns are written
+// (n x n complex per channel).  The band's items are sorted by signed x separation, hence by grid
+// column for every channel (u is proportional to dx).
 // Each staging round puts a run of them in LDS with their 8 + 8 separable kernel weights
 // (evaluated once per baseline) and a table of the first staged baseline at or right of every
 // grid column, so a thread's baselines are the contiguous range of those starting within 7
@@ -314,7 +317,7 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
     int *s_first = reinterpret_cast<int *>(s_w + GS::WSTRIDE * CAP);  // [x - XMIN]: first i with gu0 >= x
 
     const int t = threadIdx.x;
-    const int row0 = band * R;
+    const int row0 = M / 2 + band * R;  // bands cover the rows v >= 0 of the Hermitian grid
     const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, LOGM, t, 256);
     const float2 *cv_c = cvis + (size_t)c * n_pairs;
     const int k_begin = band_off[band], k_end = band_off[band + 1];
@@ -324,7 +327,7 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
         float *red = reinterpret_cast<float *>(grid);
         float mx = 0.f;
         for (int i = k_begin + t; i < k_end; i += 256) {
-            const float2 val = cv_c[band_items[i]];
+            const float2 val = cv_c[band_items[i] >> 1];
             mx = fmaxf(mx, fmaxf(fabsf(val.x), fabsf(val.y)));
         }
         red[t] = mx;
@@ -360,11 +363,15 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
         const int nk = (n_items - rr + n_rounds - 1) / n_rounds;
         __syncthreads();
         for (int i = t; i < nk; i += 256) {
-            const int k = band_items[k_begin + rr + i * n_rounds];
+            const int item = band_items[k_begin + rr + i * n_rounds];
+            const int k = item >> 1;
             float2 val = cv_c[k];
+            // mirrored item: conj V at -(u, v)
+            const double sgn = (item & 1) ? -sc : sc;
+            if (item & 1) val.y = -val.y;
             if constexpr (PREC == NBSI_PREC_FP16) val = make_float2(val.x * vscale, val.y * vscale);
             const double2 d = dxy[k];
-            const double cu = d.x * sc + (double)(M / 2), cvv = d.y * sc + (double)(M / 2);
+            const double cu = d.x * sgn + (double)(M / 2), cvv = d.y * sgn + (double)(M / 2);
             const double fu = floor(cu), fv = floor(cvv);
             s_g[i] = make_int2((int)fu - 3, (int)fv - 3);
             s_val[i] = val;
@@ -442,7 +449,7 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
         const float sgn = (xp & 1) ? -unscale : unscale;
         const float2 f0 = grid[pidx(lr * M + col)], f1 = grid[pidx((lr + 1) * M + col)];
         float4 o = make_float4(f0.x * sgn, f0.y * sgn, f1.x * sgn, f1.y * sgn);
-        *reinterpret_cast<float4 *>(inter + ((size_t)c * n_pix + x) * M + row0 + lr) = o;
+        *reinterpret_cast<float4 *>(inter + ((size_t)c * n_pix + x) * n_pix + band * R + lr) = o;
     }
 }
 
@@ -476,47 +483,82 @@ __global__ __launch_bounds__(256) void grid_rows_batch_kernel(const ImgJob *__re
                               local % jb.n_bands, local / jb.n_bands, grid, tw_lo, tw_hi, vscale);
 }
 
+// Column pass.  After the row pass, column x of the Hermitian grid holds s[i] = H(x, i) for the
+// stored rows i = n .. 2n - 1 (n = n_pix), and s[2n - i] = conj s[i], s[0] = 0 (that row is
+// outside every footprint).  Its transform S[k] = sum_i s[i] w^(ik) (w = exp(-2 pi i / 2n)) is
+// real, and one n-point transform gives it: with a[i] = s[i] + s[i + n] and
+// b[i] = (s[i] - s[i + n]) w^i, i < n, the transform Z of z = a + i b has Z[m] = S[2m] + i S[2m+1].
+// The image is S / 2 (the real part of the transform of the half-plane grid), times the kernel
+// correction and 1 / |B|.  A workgroup takes cols_per_band(ge, n) consecutive columns.
+
 template <int GE>
-__device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, int n_pix, int log_m, int band_cols,
+__device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, int n_pix, int log_m,
                                           const float *__restrict__ corr, const int *__restrict__ nb,
                                           float *__restrict__ img, int xb, int c, float2 *buf, float2 *tw_lo,
                                           float2 *tw_hi) {
     const int t = threadIdx.x;
-    const int M = 1 << log_m;
-    const int x0 = xb * band_cols;
+    const int n = n_pix, log_n = log_m - 1, M = 1 << log_m;
+    constexpr int CELLS = Tile<GE>::CELLS;
+    const int nx = cols_per_band(GE, n_pix);
+    const int x0 = xb * nx;
     const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_m, t, 256);
-    // the band's columns are contiguous in the intermediate: 16 float4 loads per thread in flight
-    const float4 *src = reinterpret_cast<const float4 *>(inter + ((size_t)c * n_pix + x0) * M);
-    constexpr int GRID_CELLS = Tile<GE>::CELLS;
-    float4 r[GRID_CELLS / 2 / 256];
+    // the band's columns are contiguous in the intermediate; a band narrower than the tile
+    // (n = 64, ge = 32) leaves zero columns that are transformed and dropped
+    const float4 *src = reinterpret_cast<const float4 *>(inter + ((size_t)c * n + x0) * n);
+    const int n4 = nx * n / 2;
+    float4 r[CELLS / 2 / 256];
 #pragma unroll
-    for (int q = 0; q < GRID_CELLS / 2 / 256; q++) r[q] = src[t + 256 * q];
+    for (int q = 0; q < CELLS / 2 / 256; q++) {
+        const int e4 = t + 256 * q;
+        r[q] = e4 < n4 ? src[e4] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
 #pragma unroll
-    for (int q = 0; q < GRID_CELLS / 2 / 256; q++) {
+    for (int q = 0; q < CELLS / 2 / 256; q++) {
         const int e = 2 * (t + 256 * q);  // two consecutive elements never straddle a pad
         buf[pidx(e)] = make_float2(r[q].x, r[q].y);
         buf[pidx(e + 1)] = make_float2(r[q].z, r[q].w);
     }
     __syncthreads();
-    batched_fft<GE>(buf, t, log_m, tw, log_m);
-    const int n = nb[c];
-    const float inv = n > 0 ? (float)(1.0 / (double)n) : 0.f;
-    for (int e = t; e < n_pix * band_cols; e += 256) {
-        const int xl = e % band_cols, y = e / band_cols;
-        const int yp = y - n_pix / 2;
-        const float2 f = buf[pidx(xl * M + (yp & (M - 1)))];
+    float2 z[GE];
+#pragma unroll
+    for (int q = 0; q < GE; q++) {
+        const int e = t + 256 * q;
+        const int i = e & (n - 1);
+        const float2 hi = buf[pidx(e)];  // s[i + n]
+        float2 lo = make_float2(0.f, 0.f);
+        if (i) {
+            const float2 m = buf[pidx(e - i + n - i)];  // s[i] = conj s[2n - i], stored at row n - i
+            lo = make_float2(m.x, -m.y);
+        }
+        const float2 a = cadd(lo, hi);
+        const float2 b = cmul(make_float2(lo.x - hi.x, lo.y - hi.y), tw(i));
+        z[q] = make_float2(a.x - b.y, a.y + b.x);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < GE; q++) buf[pidx(t + 256 * q)] = z[q];
+    __syncthreads();
+    batched_fft<GE>(buf, t, log_n, tw, log_m);
+    const int cnt = nb[c];
+    const float inv = cnt > 0 ? (float)(0.5 / (double)cnt) : 0.f;
+    for (int e = t; e < n * nx; e += 256) {
+        const int xl = e % nx, y = e / nx;
+        const int yp = y - n / 2;
+        const int k = yp & (M - 1);
+        const float2 f = buf[pidx(xl * n + (k >> 1))];
+        const float v = (k & 1) ? f.y : f.x;
         const float sgn = (yp & 1) ? -1.f : 1.f;
-        img[((size_t)c * n_pix + y) * n_pix + x0 + xl] = f.x * sgn * corr[x0 + xl] * corr[y] * inv;
+        img[((size_t)c * n + y) * n + x0 + xl] = v * sgn * corr[x0 + xl] * corr[y] * inv;
     }
 }
 
 template <int GE>
 __global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict__ inter, int n_pix, int log_m,
-                                                        int band_cols, const float *__restrict__ corr,
-                                                        const int *__restrict__ nb, float *__restrict__ img) {
+                                                        const float *__restrict__ corr, const int *__restrict__ nb,
+                                                        float *__restrict__ img) {
     __shared__ float2 buf[padded_size(Tile<GE>::CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
-    grid_cols<GE>(inter, n_pix, log_m, band_cols, corr, nb, img, blockIdx.x, blockIdx.y, buf, tw_lo, tw_hi);
+    grid_cols<GE>(inter, n_pix, log_m, corr, nb, img, blockIdx.x, blockIdx.y, buf, tw_lo, tw_hi);
 }
 
 template <int GE>
@@ -529,11 +571,10 @@ __global__ __launch_bounds__(256) void grid_cols_batch_kernel(const ImgJob *__re
     int j = 0;
     while (j + 1 < n_jobs && jobs[j + 1].cols_task0 <= task) j++;
     const ImgJob &jb = jobs[j];
-    const int band_cols = Tile<GE>::CELLS / (1 << jb.log_m);
-    const int n_xb = jb.n_pix / band_cols;
+    const int n_xb = jb.n_pix / cols_per_band(GE, jb.n_pix);
     const int local = task - jb.cols_task0;
-    grid_cols<GE>(jb.inter, jb.n_pix, jb.log_m, band_cols, jb.corr, jb.nb, jb.img, local % n_xb, local / n_xb, buf,
-                  tw_lo, tw_hi);
+    grid_cols<GE>(jb.inter, jb.n_pix, jb.log_m, jb.corr, jb.nb, jb.img, local % n_xb, local / n_xb, buf, tw_lo,
+                  tw_hi);
 }
 
 // Gather over channel ranges of several sub-bands: one workgroup per (job, channel, 256 pairs).
@@ -595,9 +636,8 @@ static hipError_t launch_grid_ge(const nbsi_image_plan *p, int precision, float2
 #undef NBSI_ROWS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int band_cols = Tile<GE>::CELLS / (1 << log_m);
-    hipLaunchKernelGGL(grid_cols_kernel<GE>, dim3(p->n_pix / band_cols, p->n_chan), dim3(256), 0, st, inter,
-                       p->n_pix, log_m, band_cols, p->d_corr, p->d_nb, img);
+    hipLaunchKernelGGL(grid_cols_kernel<GE>, dim3(p->n_pix / cols_per_band(GE, p->n_pix), p->n_chan), dim3(256), 0,
+                       st, inter, p->n_pix, log_m, p->d_corr, p->d_nb, img);
     return hipGetLastError();
 }
 

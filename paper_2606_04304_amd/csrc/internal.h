@@ -42,11 +42,12 @@ struct nbsi_image_plan {
     int2 *d_pairs = nullptr;      // candidate pairs (a, b), a > b
     double2 *d_dxy = nullptr;     // (x_a - x_b, y_a - y_b) metres of each candidate pair
     int n_pairs = 0;
-    // gridding: candidate pairs binned by bands of grid rows (CSR over bands); a workgroup
-    // holds 256 * ge grid cells (ge = 16 or 32), i.e. band_rows = 256 ge / (2 n_pix) rows
+    // gridding: candidate pairs binned by bands of the grid rows v >= 0 (array rows n_pix ..
+    // 2 n_pix - 1; CSR over bands); a workgroup holds 256 * ge grid cells (ge = 16 or 32), i.e.
+    // band_rows = 256 ge / (2 n_pix) rows, and n_bands = n_pix / band_rows
     int ge = 16, band_rows = 0, n_bands = 0;
     int *d_band_off = nullptr;    // [n_bands + 1]
-    int *d_band_items = nullptr;  // indices into d_pairs
+    int *d_band_items = nullptr;  // 2 * (index into d_pairs) + 1 if gridded at -(u, v) with conj V
     int n_band_items = 0;
     float *d_corr = nullptr;      // [n_pix] 1 / (kernel Fourier transform) per image column
 };
@@ -62,7 +63,7 @@ struct nbsi_image_plan {
 
 int nbsi_scratch(nbsi_ctx *ctx, int slot, size_t bytes, void **ptr);
 
-// Channels of a gridded image are processed in chunks whose row-pass intermediate (2 n_pix x n_pix
+// Channels of a gridded image are processed in chunks whose row-pass intermediate (n_pix x n_pix
 // complex float per channel) stays within this many bytes, so the column pass reads it from the
 // 256 MB last-level cache rather than from HBM.
 constexpr size_t IMAGE_CHUNK_BYTES = (size_t)128 << 20;
@@ -114,6 +115,12 @@ struct ImgJob {
     double uv_min, uv_max;
     int gather_task0, rows_task0, cols_task0;
 };
+// Image columns per workgroup of the gridding imager's column pass: a tile of 256 ge cells
+// holds 256 ge / n_pix columns of n_pix complex values, at most the n_pix columns there are.
+__host__ __device__ constexpr int cols_per_band(int ge, int n_pix) {
+    return 256 * ge / n_pix < n_pix ? 256 * ge / n_pix : n_pix;
+}
+
 hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, hipStream_t st);
 hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision, int ge,
                                    hipStream_t st);
