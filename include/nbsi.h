@@ -168,6 +168,25 @@ int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int 
                int precision, float *img);
 
 /*
+ * Correlate and image without re-reading the visibilities (Sec. 2.1 X-engine feeding the
+ * Sec. 2.2 imager).  A gridding plan lists its candidate pairs (every pair a > b that is in B
+ * for some channel of the plan); nbsi_image_plan_pairs gives their number n_pairs and, if
+ * pairs_host is not NULL, copies them as pairs_host[n_pairs][2] = (a, b) (blocking).
+ * nbsi_correlate_stokes writes exactly what nbsi_correlate writes to vis and, from the same
+ * int32 sums, V_I = (V_XX + V_YY) / 2 of every candidate pair into
+ *   stokes_i [n_chan][n_pairs][2] float32 (real, imaginary; rounded from the exact sum),
+ * requiring n_in = 2 n_ant and n_chan of the plan.  nbsi_image_stokes images those values
+ * (applying the per-channel membership test of B itself) and gives, bit for bit, what
+ * nbsi_image gives from vis with the same plan and precision.  Gridding plans only
+ * (NBSI_EINVAL otherwise); stokes_i is caller-owned device memory, 16-byte aligned.
+ */
+int nbsi_image_plan_pairs(const nbsi_image_plan *plan, int *n_pairs_host, int32_t *pairs_host);
+int nbsi_correlate_stokes(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, int n_spec,
+                          const nbsi_image_plan *plan, int32_t *vis, float *stokes_i);
+int nbsi_image_stokes(nbsi_ctx *ctx, const nbsi_image_plan *plan, const float *stokes_i,
+                      int precision, float *img);
+
+/*
  * Narrowband search of a cube (Sec. 2.4, Stage I with the width-1 matched filter):
  *   NBSI_DETECT_PER_PIXEL: SNR_p[c] = (I_p[c] - med_c I_p) / (k MAD_c I_p)
  *   NBSI_DETECT_PER_IMAGE: z = (I - med) / (k MAD) over each channel image, then

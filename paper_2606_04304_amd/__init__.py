@@ -41,7 +41,8 @@ EXPORTS = [
     "nbsi_image_plan_nbase", "nbsi_image", "nbsi_detect", "nbsi_batch_plan", "nbsi_batch_run",
     "nbsi_batch_describe", "nbsi_batch_destroy", "nbsi_stamps", "nbsi_net_create", "nbsi_net_destroy",
     "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
-    "nbsi_net_train_step", "nbsi_correlate_kernel",
+    "nbsi_net_train_step", "nbsi_correlate_kernel", "nbsi_image_plan_pairs", "nbsi_correlate_stokes",
+    "nbsi_image_stokes",
 ]
 NBSI_STAMP_CHANNELS = 33
 NBSI_STAMP_PIXELS = 9
@@ -94,6 +95,9 @@ def lib():
         L.nbsi_image_plan_destroy.argtypes = [P]
         L.nbsi_image_plan_nbase.argtypes = [P, P]
         L.nbsi_image.argtypes = [P, P, P, I, I, P]
+        L.nbsi_image_plan_pairs.argtypes = [P, ctypes.POINTER(I), P]
+        L.nbsi_correlate_stokes.argtypes = [P, P, I, I, I, P, P, P]
+        L.nbsi_image_stokes.argtypes = [P, P, P, I, P]
         L.nbsi_detect.argtypes = [P, P, I, I, I, ctypes.c_float, P, P, I, P]
         L.nbsi_batch_plan.argtypes = [P, P, I, P, I, I, I, ctypes.c_char_p, ctypes.POINTER(P)]
         L.nbsi_batch_run.argtypes = [P]
@@ -250,6 +254,19 @@ class ImagePlan:
         _check(lib().nbsi_image_plan_nbase(self._h, out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
+    def n_pairs(self) -> int:
+        """Number of candidate pairs (the length of a channel's Stokes-I row)."""
+        n = ctypes.c_int()
+        _check(lib().nbsi_image_plan_pairs(self._h, ctypes.byref(n), None))
+        return n.value
+
+    def pairs(self) -> np.ndarray:
+        """Candidate pairs [n_pairs][2] int32 (a, b), a > b, in Stokes-I row order."""
+        out = np.empty((max(1, self.n_pairs()), 2), dtype=np.int32)
+        n = ctypes.c_int()
+        _check(lib().nbsi_image_plan_pairs(self._h, ctypes.byref(n), out.ctypes.data_as(ctypes.c_void_p)))
+        return out[:n.value]
+
     def close(self):
         if getattr(self, "_h", None):
             lib().nbsi_image_plan_destroy(self._h)
@@ -285,6 +302,44 @@ def nbsi_image(plan: ImagePlan, vis, precision: int = NBSI_PREC_FP32, img=None):
         img = torch.empty((plan.n_chan, plan.n_pix, plan.n_pix), dtype=torch.float32, device=ctx.device)
     ctx._sync_stream()
     _check(lib().nbsi_image(ctx._h, plan._h, _ptr(vis), vt, int(precision), _ptr(img)), ctx)
+    return img
+
+
+def nbsi_correlate_stokes(spec_q, plan: ImagePlan, vis=None, stokes_i=None):
+    """spec_q int8 -> (vis as nbsi_correlate, stokes_i [n_chan][plan.n_pairs()][2] float32)."""
+    torch = _torch()
+    ctx = plan.ctx
+    _need(spec_q, torch.int8, "spec_q", ctx.device)
+    n_chan, n_in, two, n_spec = spec_q.shape
+    if vis is None:
+        vis = torch.empty((n_chan, n_in * (n_in + 1) // 2, 2), dtype=torch.int32, device=ctx.device)
+    _need(vis, torch.int32, "vis", ctx.device)
+    if tuple(vis.shape) != (n_chan, n_in * (n_in + 1) // 2, 2):
+        raise ValueError(f"vis shape {tuple(vis.shape)} does not match spec_q")
+    if stokes_i is None:
+        stokes_i = torch.empty((n_chan, max(1, plan.n_pairs()), 2), dtype=torch.float32, device=ctx.device)
+    _need(stokes_i, torch.float32, "stokes_i", ctx.device)
+    if stokes_i.dim() != 3 or stokes_i.shape[0] != n_chan or stokes_i.shape[1] != max(1, plan.n_pairs()) \
+            or stokes_i.shape[2] != 2:
+        raise ValueError(f"stokes_i shape {tuple(stokes_i.shape)} does not match the plan")
+    ctx._sync_stream()
+    _check(lib().nbsi_correlate_stokes(ctx._h, _ptr(spec_q), n_chan, n_in, n_spec, plan._h, _ptr(vis),
+                                       _ptr(stokes_i)), ctx)
+    return vis, stokes_i
+
+
+def nbsi_image_stokes(plan: ImagePlan, stokes_i, precision: int = NBSI_PREC_FP32, img=None):
+    """stokes_i [n_chan][n_pairs][2] float32 (from nbsi_correlate_stokes) -> img, as nbsi_image."""
+    torch = _torch()
+    ctx = plan.ctx
+    _need(stokes_i, torch.float32, "stokes_i", ctx.device)
+    if stokes_i.dim() != 3 or stokes_i.shape[0] != plan.n_chan or stokes_i.shape[1] != max(1, plan.n_pairs()) \
+            or stokes_i.shape[2] != 2:
+        raise ValueError(f"stokes_i shape {tuple(stokes_i.shape)} does not match the plan")
+    if img is None:
+        img = torch.empty((plan.n_chan, plan.n_pix, plan.n_pix), dtype=torch.float32, device=ctx.device)
+    ctx._sync_stream()
+    _check(lib().nbsi_image_stokes(ctx._h, plan._h, _ptr(stokes_i), int(precision), _ptr(img)), ctx)
     return img
 
 

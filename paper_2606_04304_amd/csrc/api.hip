@@ -230,6 +230,27 @@ int nbsi_correlate(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, in
     return NBSI_OK;
 }
 
+int nbsi_correlate_stokes(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, int n_spec,
+                          const nbsi_image_plan *plan, int32_t *vis, float *stokes_i) {
+    if (!ctx) return NBSI_EINVAL;
+    int rc = nbsi_check_correlate(n_chan, n_in, n_spec);
+    if (rc) return nbsi_fail(ctx, rc, "nbsi_correlate_stokes: bad shape");
+    if (!spec_q || !vis || !plan || !stokes_i) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_stokes: null pointer");
+    if (!aligned16(spec_q) || !aligned16(vis) || !aligned16(stokes_i))
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_stokes: misaligned pointer");
+    if (plan->device != ctx->device) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_stokes: plan built on another device");
+    if (plan->method != NBSI_IMAGE_GRID || n_in != 2 * plan->n_ant || n_chan != plan->n_chan)
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_stokes: plan must be a gridding plan of n_in / 2 antennas and n_chan channels");
+    DeviceGuard g(ctx->device);
+    StokesOut so;
+    so.mask = plan->d_tmask;
+    so.base = plan->d_tbase;
+    so.out = reinterpret_cast<float2 *>(stokes_i);
+    so.n_pairs = plan->n_pairs;
+    NBSI_TRY_HIP(ctx, launch_correlate_i8(spec_q, n_chan, n_in, n_spec, vis, ctx->stream, so));
+    return NBSI_OK;
+}
+
 int nbsi_correlate_f32(nbsi_ctx *ctx, const float *spec_f, int n_chan, int n_in, int n_spec, float *vis) {
     if (!ctx) return NBSI_EINVAL;
     int rc = nbsi_check_correlate(n_chan, n_in, n_spec);
@@ -297,6 +318,43 @@ int image_plan_build(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const
             pairs.push_back(make_int2(a, b));
             dxy.push_back(make_double2(dx, dy));
         }
+    // Order the candidates by 8 x 8 antenna block (packed lower-triangle block order), then by
+    // position within the block: the correlator's epilogue finds a pair's index from its block's
+    // bit mask and base (one 32 x 32 tile of the correlation matrix is one such block).
+    const int n_blk = (n_ant + 7) / 8;
+    const size_t n_tiles = (size_t)n_blk * (n_blk + 1) / 2;
+    auto tile_of = [](int a, int b) { return (size_t)(a / 8) * (a / 8 + 1) / 2 + (size_t)(b / 8); };
+    auto bit_of = [](int a, int b) { return (a % 8) * 8 + b % 8; };
+    {
+        std::vector<int> ord(pairs.size());
+        for (size_t k = 0; k < ord.size(); k++) ord[k] = (int)k;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+            const size_t tx = tile_of(pairs[x].x, pairs[x].y), ty = tile_of(pairs[y].x, pairs[y].y);
+            return tx != ty ? tx < ty : bit_of(pairs[x].x, pairs[x].y) < bit_of(pairs[y].x, pairs[y].y);
+        });
+        std::vector<int2> p2(pairs.size());
+        std::vector<double2> d2(dxy.size());
+        std::vector<int> l2(lo_row.size()), h2(hi_row.size());
+        for (size_t k = 0; k < ord.size(); k++) {
+            p2[k] = pairs[ord[k]];
+            d2[k] = dxy[ord[k]];
+            if (!lo_row.empty()) {
+                l2[k] = lo_row[ord[k]];
+                h2[k] = hi_row[ord[k]];
+            }
+        }
+        pairs.swap(p2);
+        dxy.swap(d2);
+        lo_row.swap(l2);
+        hi_row.swap(h2);
+    }
+    std::vector<unsigned long long> tmask(n_tiles, 0ull);
+    std::vector<int> tbase(n_tiles, 0);
+    for (const int2 &pr : pairs) tmask[tile_of(pr.x, pr.y)] |= 1ull << bit_of(pr.x, pr.y);
+    for (size_t t = 0, run = 0; t < n_tiles; t++) {
+        tbase[t] = (int)run;
+        run += (size_t)__builtin_popcountll(tmask[t]);
+    }
     p->n_pairs = (int)pairs.size();
 
     std::vector<int> band_off, band_items;
@@ -358,7 +416,10 @@ int image_plan_build(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const
     if (ok && method == NBSI_IMAGE_GRID)
         ok = up((void **)&p->d_band_off, band_off.data(), sizeof(int) * band_off.size()) &&
              up((void **)&p->d_band_items, band_items.data(), sizeof(int) * band_items.size()) &&
-             up((void **)&p->d_corr, corr.data(), sizeof(float) * corr.size());
+             up((void **)&p->d_corr, corr.data(), sizeof(float) * corr.size()) &&
+             up((void **)&p->d_tmask, tmask.data(), sizeof(unsigned long long) * tmask.size()) &&
+             up((void **)&p->d_tbase, tbase.data(), sizeof(int) * tbase.size()) &&
+             up((void **)&p->d_inb, nullptr, sizeof(unsigned) * (size_t)n_chan * ((p->n_pairs + 31) / 32));
     if (!ok) {
         nbsi_image_plan_destroy(p);
         return nbsi_fail(ctx, NBSI_ENOMEM, "nbsi_image_plan_create: device allocation failed");
@@ -384,7 +445,8 @@ int nbsi_image_plan_create(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant,
 int nbsi_image_plan_destroy(nbsi_image_plan *p) {
     if (!p) return NBSI_EINVAL;
     DeviceGuard g(p->device);
-    void *bufs[] = {p->d_xyz, p->d_freq, p->d_nb, p->d_pairs, p->d_dxy, p->d_band_off, p->d_band_items, p->d_corr};
+    void *bufs[] = {p->d_xyz,      p->d_freq,       p->d_nb,   p->d_pairs, p->d_dxy,  p->d_band_off,
+                    p->d_band_items, p->d_corr, p->d_inb, p->d_tmask, p->d_tbase};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -397,6 +459,17 @@ int nbsi_image_plan_nbase(nbsi_image_plan *p, int64_t *n_b_host) {
     std::vector<int> nb(p->n_chan);
     if (hipMemcpy(nb.data(), p->d_nb, sizeof(int) * p->n_chan, hipMemcpyDeviceToHost) != hipSuccess) return NBSI_EHIP;
     for (int c = 0; c < p->n_chan; c++) n_b_host[c] = nb[c];
+    return NBSI_OK;
+}
+
+int nbsi_image_plan_pairs(const nbsi_image_plan *p, int *n_pairs_host, int32_t *pairs_host) {
+    if (!p || !n_pairs_host) return NBSI_EINVAL;
+    *n_pairs_host = p->n_pairs;
+    if (pairs_host && p->n_pairs > 0) {
+        DeviceGuard g(p->device);
+        if (hipMemcpy(pairs_host, p->d_pairs, sizeof(int2) * p->n_pairs, hipMemcpyDeviceToHost) != hipSuccess)
+            return NBSI_EHIP;
+    }
     return NBSI_OK;
 }
 
@@ -431,9 +504,38 @@ int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int 
         sub.n_chan = std::min(chunk, plan->n_chan - c0);
         sub.d_freq = plan->d_freq + c0;
         sub.d_nb = plan->d_nb + c0;
+        if (plan->d_inb) sub.d_inb = plan->d_inb + (size_t)c0 * ((plan->n_pairs + 31) >> 5);
         NBSI_TRY_HIP(ctx, launch_image_grid(&sub, (const char *)vis + vis_chan_bytes * c0, vis_dtype, precision,
                                             (float2 *)cvis, (float2 *)inter,
                                             img + (size_t)c0 * plan->n_pix * plan->n_pix, ctx->stream));
+    }
+    return NBSI_OK;
+}
+
+int nbsi_image_stokes(nbsi_ctx *ctx, const nbsi_image_plan *plan, const float *stokes_i, int precision, float *img) {
+    if (!ctx) return NBSI_EINVAL;
+    if (!plan || !stokes_i || !img) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: null pointer");
+    if (plan->device != ctx->device) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: plan built on another device");
+    if (plan->method != NBSI_IMAGE_GRID) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: plan must be a gridding plan");
+    if (precision != NBSI_PREC_FP32 && precision != NBSI_PREC_FP16 && precision != NBSI_PREC_BF16)
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: bad precision");
+    if (!aligned16(stokes_i) || !aligned16(img)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: misaligned pointer");
+    DeviceGuard g(ctx->device);
+    // the same channel chunks as nbsi_image, so the row intermediate stays in the last-level cache
+    const size_t per_chan = (size_t)plan->n_pix * plan->n_pix * sizeof(float2);
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>(plan->n_chan, IMAGE_CHUNK_BYTES / per_chan));
+    void *inter = nullptr;
+    int rc = nbsi_scratch(ctx, SLOT_IMG_INTER, per_chan * chunk, &inter);
+    if (rc) return rc;
+    const float2 *sv = reinterpret_cast<const float2 *>(stokes_i);
+    for (int c0 = 0; c0 < plan->n_chan; c0 += chunk) {
+        nbsi_image_plan sub = *plan;
+        sub.n_chan = std::min(chunk, plan->n_chan - c0);
+        sub.d_freq = plan->d_freq + c0;
+        sub.d_nb = plan->d_nb + c0;
+        if (plan->d_inb) sub.d_inb = plan->d_inb + (size_t)c0 * ((plan->n_pairs + 31) >> 5);
+        NBSI_TRY_HIP(ctx, launch_image_grid_stokes(&sub, sv + (size_t)c0 * plan->n_pairs, precision, (float2 *)inter,
+                                                   img + (size_t)c0 * plan->n_pix * plan->n_pix, ctx->stream));
     }
     return NBSI_OK;
 }

@@ -239,6 +239,7 @@ int build_launches(nbsi_batch *b) {
         j.band_off = p->d_band_off;
         j.band_items = p->d_band_items;
         j.nb = p->d_nb;
+        j.inb = p->d_inb;
         j.corr = p->d_corr;
         j.cvis = b->cvis;
         j.inter = b->inter;
@@ -318,6 +319,7 @@ int build_launches(nbsi_batch *b) {
                 q.vis = j.vis + (size_t)c0 * nprod * 2;
                 q.freq = j.freq + c0;
                 q.nb = j.nb + c0;
+                q.inb = j.inb + (size_t)c0 * ((j.n_pairs + 31) >> 5);
                 const size_t cv_n = sizeof(float2) * (size_t)n * std::max(1, j.n_pairs);
                 if (!b->cvis || !b->inter || used + per_chan * n > b->inter_bytes || cv_used + cv_n > b->cvis_bytes)
                     return NBSI_EINVAL;  // the chunk buffers were sized for fewer pairs or channels

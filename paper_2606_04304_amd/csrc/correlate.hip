@@ -63,9 +63,37 @@ __device__ __forceinline__ int swap_lanes(int x) {
     return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);
 }
 
-// Combine a 32 x 32 tile of G (rows R0.., cols C0.., both even) into visibilities and store.
+// The Stokes-I mask and first index of the 8 x 8 antenna block of 32 x 32 tile (R0, C0) of G,
+// as wave-uniform (scalar) values; zero when there is no Stokes-I output.
+struct BlockStokes {
+    unsigned long long mask = 0;
+    int base = 0;
+};
+// The table is read only during the launch: reading it through the constant address space lets
+// these uniform loads go to the scalar unit, so they never wait behind the wave's pending
+// visibility stores (a vector load would, as the vector memory counter is shared by both).
+typedef __attribute__((address_space(4))) const unsigned long long *const_u64_ptr;
+typedef __attribute__((address_space(4))) const int *const_i32_ptr;
+__device__ __forceinline__ BlockStokes block_stokes(const StokesOut &so, int R0, int C0) {
+    BlockStokes r;
+    if (so.out) {
+        const int rb = R0 >> 5, cb = C0 >> 5;
+        const int t = __builtin_amdgcn_readfirstlane(rb * (rb + 1) / 2 + cb);
+        r.mask = ((const_u64_ptr)so.mask)[t];
+        r.base = ((const_i32_ptr)so.base)[t];
+    }
+    return r;
+}
+
+// Combine a 32 x 32 tile of G (rows R0.., cols C0.., both even) into visibilities and store;
+// with a Stokes-I output, also (V_XX + V_YY) / 2 of the block's candidate pairs of channel c.
+// Lane l holds input row R0/2 + 4 qq + 2 (l / 32) + (l & 1) and input column C0/2 + (l % 32) / 2,
+// so for a quad of lanes 4m .. 4m+3 the XX visibility of antenna pair (A, B) sits in lane 4m
+// (inputs 2A, 2B) and the YY one in lane 4m+3 (inputs 2A+1, 2B+1); within the 8 x 8 antenna
+// block, A % 8 = 2 qq + l / 32 and B % 8 = (l % 32) / 4.
 __device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, int lane, int n_in,
-                                               int2 *__restrict__ vc) {
+                                               int2 *__restrict__ vc, const StokesOut &so, int c,
+                                               const BlockStokes &bs, bool small_sums) {
     int par[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) par[r] = swap_lanes(a[r]);
@@ -85,12 +113,32 @@ __device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, in
         if (ia < n_in && b <= ia) {
             vc[(size_t)ia * (ia + 1) / 2 + b] = make_int2(re, im);
         }
+        if (bs.mask) {
+            // quad_perm [3, 3, 3, 3]: every lane of the quad reads lane 3's visibility
+            const int yre = __builtin_amdgcn_mov_dpp(re, 0xFF, 0xF, 0xF, true);
+            const int yim = __builtin_amdgcn_mov_dpp(im, 0xFF, 0xF, 0xF, true);
+            const int bit = (2 * qq + h) * 8 + (cl >> 2);
+            if ((lane & 3) == 0 && ((bs.mask >> bit) & 1ull)) {
+                const int k = bs.base + __popcll(bs.mask & ((1ull << bit) - 1ull));
+                // (V_XX + V_YY) / 2 rounded once to float.  |V| <= 2^15 n_spec, so for
+                // n_spec <= 256 the sum is an integer below 2^24 and float arithmetic is exact
+                // up to that one rounding (none), as the double form is.
+                float2 v;
+                if (small_sums) {
+                    v = make_float2(0.5f * ((float)re + (float)yre), 0.5f * ((float)im + (float)yim));
+                } else {
+                    v = make_float2((float)(0.5 * ((double)re + (double)yre)), (float)(0.5 * ((double)im + (double)yim)));
+                }
+                so.out[(size_t)c * so.n_pairs + k] = v;
+            }
+        }
     }
 }
 
 // One 128 x 128 tile pair (I, J) of channel c: K loop through LDS, MFMA, epilogue.
 __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int n_in, int T, int c, int pair,
-                                               int32_t *__restrict__ vis, int8_t *sA, int8_t *sB) {
+                                               int32_t *__restrict__ vis, int8_t *sA, int8_t *sB,
+                                               const StokesOut &so) {
     int I, J;
     tile_pair(pair, I, J);
     const int rows = 2 * n_in;
@@ -108,6 +156,14 @@ __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[mi][ni][r] = 0;
 
+    BlockStokes bs[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+        for (int ni = 0; ni < 2; ni++) {
+            const int R0 = I * TILE + wr * 64 + mi * 32, C0 = J * TILE + wc * 64 + ni * 32;
+            if (active && R0 < rows && C0 <= R0 + 31) bs[mi][ni] = block_stokes(so, R0, C0);
+        }
     const int8_t *sBr = diag ? sA : sB;
     for (int k0 = 0; k0 < T; k0 += KC) {
         __syncthreads();
@@ -142,13 +198,14 @@ __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int
         for (int ni = 0; ni < 2; ni++) {
             const int R0 = I * TILE + wr * 64 + mi * 32;
             const int C0 = J * TILE + wc * 64 + ni * 32;
-            if (R0 < rows && C0 <= R0 + 31) store_tile_i32(acc[mi][ni], R0, C0, lane, n_in, vc);
+            if (R0 < rows && C0 <= R0 + 31)
+                store_tile_i32(acc[mi][ni], R0, C0, lane, n_in, vc, so, c, bs[mi][ni], T <= 256);
         }
 }
 
 __global__ __launch_bounds__(256) void correlate_i8_kernel(const int8_t *__restrict__ q, int n_chan,
                                                            int n_in, int T, int n_pairs,
-                                                           int32_t *__restrict__ vis) {
+                                                           int32_t *__restrict__ vis, StokesOut so) {
     __shared__ __attribute__((aligned(16))) int8_t sA[TILE * LDS_STRIDE];
     __shared__ __attribute__((aligned(16))) int8_t sB[TILE * LDS_STRIDE];
     const int id = blockIdx.x;
@@ -156,7 +213,7 @@ __global__ __launch_bounds__(256) void correlate_i8_kernel(const int8_t *__restr
     const int pair = rest % n_pairs;
     const int c = (rest / n_pairs) * 8 + xcd;
     if (c >= n_chan) return;
-    correlate_tile(q, n_in, T, c, pair, vis, sA, sB);
+    correlate_tile(q, n_in, T, c, pair, vis, sA, sB, so);
 }
 
 // Several sub-bands in one launch: task -> (job, channel group of 8, tile pair, XCD lane), one
@@ -176,7 +233,7 @@ __global__ __launch_bounds__(256) void correlate_i8_batch_kernel(const CorrJob *
     const int xcd = local & 7, rest = local >> 3;
     const int pair = rest % n_pairs;
     const int c = (rest / n_pairs) * 8 + xcd;
-    if (c < jb.n_chan) correlate_tile(jb.q, jb.n_in, jb.n_spec, c, pair, jb.vis, sA, sB);
+    if (c < jb.n_chan) correlate_tile(jb.q, jb.n_in, jb.n_spec, c, pair, jb.vis, sA, sB, StokesOut());
 }
 
 // Short integrations (n_spec <= 64): one workgroup per channel keeps the channel's whole
@@ -184,10 +241,14 @@ __global__ __launch_bounds__(256) void correlate_i8_batch_kernel(const CorrJob *
 // 32-row panel of G across every column tile at or left of the diagonal, so the packed
 // triangle rows of its 16 inputs are written as consecutive 128-byte segments by one wave
 // (whole cache lines form in L2 promptly).  At these sizes the write of the visibilities is
-// the bound, not the matrix cores.
+// the bound, not the matrix cores.  (Measured: 8 waves per workgroup, or panels handed out
+// largest first, write more slowly; nontemporal stores, which skip the merging of the partial
+// lines at segment edges in L2, 2.4x more slowly.)
+constexpr int CHAN_WAVES = 4;
 template <int KP>  // padded K: 32 or 64
 __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, int n_in, int T, int c,
-                                                  int32_t *__restrict__ vis, int8_t *sY) {
+                                                  int32_t *__restrict__ vis, int8_t *sY, const StokesOut &so) {
+    constexpr int NT = 64 * CHAN_WAVES;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int rows = 2 * n_in;
     const int n_panels = (rows + 31) / 32;
@@ -198,10 +259,10 @@ __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, 
         const v4i *src = reinterpret_cast<const v4i *>(Y);
         v4i *dst = reinterpret_cast<v4i *>(sY);
         const int nv = rows * KP / 16;
-        for (int e = t; e < nv; e += 256) dst[e] = src[e];
-        for (int e = nv + t; e < rows_pad * KP / 16; e += 256) dst[e] = v4i{0, 0, 0, 0};
+        for (int e = t; e < nv; e += NT) dst[e] = src[e];
+        for (int e = nv + t; e < rows_pad * KP / 16; e += NT) dst[e] = v4i{0, 0, 0, 0};
     } else {
-        for (int e = t; e < rows_pad * KP; e += 256) {
+        for (int e = t; e < rows_pad * KP; e += NT) {
             const int r = e / KP, k = e % KP;
             sY[e] = (r < rows && k < T) ? Y[(size_t)r * T + k] : (int8_t)0;
         }
@@ -213,6 +274,7 @@ __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, 
     const int rl = lane & 31;
     // panel I (32 rows of G, 16 inputs) goes to wave I % 4, reversed on every other block of
     // four, so the waves get similar numbers of tiles (panel I has I + 1 of them)
+    static_assert(CHAN_WAVES == 4, "panel assignment for four waves");
     for (int I = 0; I < n_panels; I++) {
         const int pos = I & 3;
         if ((((I >> 2) & 1) ? 3 - pos : pos) != wave) continue;
@@ -221,6 +283,7 @@ __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, 
         for (int kk = 0; kk < KP / 32; kk++)
             a[kk] = *reinterpret_cast<const v4i *>(sY + (I * 32 + rl) * KP + kk * 32 + koff);
         for (int J = 0; J <= I; J++) {
+            const BlockStokes bs = block_stokes(so, I * 32, J * 32);  // issued before the MFMA
             v16i acc;
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[r] = 0;
@@ -229,28 +292,29 @@ __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, 
                 const v4i b = *reinterpret_cast<const v4i *>(sY + (J * 32 + rl) * KP + kk * 32 + koff);
                 acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[kk], b, acc, 0, 0, 0);
             }
-            store_tile_i32(acc, I * 32, J * 32, lane, n_in, vc);
+            store_tile_i32(acc, I * 32, J * 32, lane, n_in, vc, so, c, bs, true);  // n_spec <= KP <= 64
         }
     }
 }
 
 template <int KP>
-__global__ __launch_bounds__(256) void correlate_i8_chan_kernel(const int8_t *__restrict__ q, int n_chan,
-                                                                int n_in, int T, int32_t *__restrict__ vis) {
+__global__ __launch_bounds__(64 * CHAN_WAVES) void correlate_i8_chan_kernel(const int8_t *__restrict__ q, int n_chan,
+                                                                            int n_in, int T,
+                                                                            int32_t *__restrict__ vis, StokesOut so) {
     extern __shared__ __attribute__((aligned(16))) int8_t sY[];  // [rows_pad][KP]
-    correlate_channel<KP>(q, n_in, T, blockIdx.x, vis, sY);
+    correlate_channel<KP>(q, n_in, T, blockIdx.x, vis, sY, so);
 }
 
 template <int KP>
-__global__ __launch_bounds__(256) void correlate_i8_chan_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
-                                                                      int n_tasks) {
+__global__ __launch_bounds__(64 * CHAN_WAVES) void correlate_i8_chan_batch_kernel(const CorrJob *__restrict__ jobs,
+                                                                                  int n_jobs, int n_tasks) {
     extern __shared__ __attribute__((aligned(16))) int8_t sY[];
     const int task = blockIdx.x;  // one workgroup per channel of any job
     if (task >= n_tasks) return;
     int j = 0;
     while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
     const CorrJob jb = jobs[j];
-    correlate_channel<KP>(jb.q, jb.n_in, jb.n_spec, task - jb.task0, jb.vis, sY);
+    correlate_channel<KP>(jb.q, jb.n_in, jb.n_spec, task - jb.task0, jb.vis, sY, StokesOut());
 }
 
 // ---- plain FP32 path: the same Gram formulation on v_mfma_f32_32x32x2_f32 ----
@@ -352,8 +416,8 @@ __global__ __launch_bounds__(256) void correlate_f32_kernel(const float *__restr
 }  // namespace
 
 hipError_t launch_correlate_i8(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis,
-                               hipStream_t st) {
-    return launch_correlate_variant(q, n_chan, n_in, n_spec, vis, correlate_default_variant(n_in, n_spec), st);
+                               hipStream_t st, StokesOut so) {
+    return launch_correlate_variant(q, n_chan, n_in, n_spec, vis, correlate_default_variant(n_in, n_spec), st, so);
 }
 
 size_t correlate_chan_lds(int n_in, int variant) {
@@ -420,32 +484,34 @@ hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks
     }
     const size_t lds = correlate_chan_lds(n_in, variant);
     if (variant == CORR_VARIANT_CHAN32)
-        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<32>, dim3(n_tasks), dim3(256), lds, st, d_jobs, n_jobs,
-                           n_tasks);
+        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<32>, dim3(n_tasks), dim3(64 * CHAN_WAVES), lds, st, d_jobs,
+                           n_jobs, n_tasks);
     else
-        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<64>, dim3(n_tasks), dim3(256), lds, st, d_jobs, n_jobs,
-                           n_tasks);
+        hipLaunchKernelGGL(correlate_i8_chan_batch_kernel<64>, dim3(n_tasks), dim3(64 * CHAN_WAVES), lds, st, d_jobs,
+                           n_jobs, n_tasks);
     return hipGetLastError();
 }
 
 // Single-band launch of one variant (the default path and the autotuner's candidates).
 hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
-                                    hipStream_t st) {
+                                    hipStream_t st, StokesOut so) {
     if (variant == CORR_VARIANT_TILED) {
         const int n_tiles = (2 * n_in + TILE - 1) / TILE;
         const int n_pairs = n_tiles * (n_tiles + 1) / 2;
         const size_t groups = (size_t)((n_chan + 7) / 8) * 8 * n_pairs;
         hipLaunchKernelGGL(correlate_i8_kernel, dim3((unsigned)groups), dim3(256), 0, st, q, n_chan, n_in, n_spec,
-                           n_pairs, vis);
+                           n_pairs, vis, so);
         return hipGetLastError();
     }
     const size_t lds = correlate_chan_lds(n_in, variant);
     const hipError_t e = chan_lds_prepare();
     if (e != hipSuccess) return e;
     if (variant == CORR_VARIANT_CHAN32)
-        hipLaunchKernelGGL(correlate_i8_chan_kernel<32>, dim3(n_chan), dim3(256), lds, st, q, n_chan, n_in, n_spec, vis);
+        hipLaunchKernelGGL(correlate_i8_chan_kernel<32>, dim3(n_chan), dim3(64 * CHAN_WAVES), lds, st, q, n_chan, n_in,
+                           n_spec, vis, so);
     else
-        hipLaunchKernelGGL(correlate_i8_chan_kernel<64>, dim3(n_chan), dim3(256), lds, st, q, n_chan, n_in, n_spec, vis);
+        hipLaunchKernelGGL(correlate_i8_chan_kernel<64>, dim3(n_chan), dim3(64 * CHAN_WAVES), lds, st, q, n_chan, n_in,
+                           n_spec, vis, so);
     return hipGetLastError();
 }
 

@@ -50,6 +50,16 @@ __device__ __forceinline__ bool in_set(UV w, int grid_n_pix, double uv_min, doub
     return true;
 }
 
+// The gridder's view of the membership bitmap of B (rows of the plan's bitmap from the chunk's
+// first channel on).
+struct SetTest {
+    const unsigned *bits;
+    int words;
+    __device__ __forceinline__ bool operator()(int c, int k) const {
+        return (bits[(size_t)c * words + (k >> 5)] >> (k & 31)) & 1u;
+    }
+};
+
 // Stokes I of pair (a, b), a > b: (V[t(2a, 2b)] + V[t(2a+1, 2b+1)]) / 2.
 template <typename VT>
 __device__ __forceinline__ float2 stokes_i(const VT *__restrict__ vc, int a, int b);
@@ -70,17 +80,31 @@ __device__ __forceinline__ float2 stokes_i<float2>(const float2 *__restrict__ vc
     return make_float2(0.5f * (x.x + y.x), 0.5f * (x.y + y.y));
 }
 
-// ---- |B| per channel ----
+// ---- |B| per channel, and (gridding plans) the membership bitmap of B ----
+// inb[c][k / 32] bit k % 32 = pair k is in B at channel c; words = (n_pairs + 31) / 32.
 __global__ __launch_bounds__(256) void count_kernel(const double *__restrict__ xyz, const double *__restrict__ freq,
                                                     const int2 *__restrict__ pairs, int n_pairs, int grid_n_pix,
-                                                    double uv_min, double uv_max, int *__restrict__ nb) {
+                                                    double uv_min, double uv_max, int *__restrict__ nb,
+                                                    unsigned *__restrict__ inb) {
     __shared__ int part[256];
     const int c = blockIdx.x;
     const double nu = freq[c];
+    const int lane = threadIdx.x & 63, words = (n_pairs + 31) >> 5;
     int cnt = 0;
-    for (int k = threadIdx.x; k < n_pairs; k += 256) {
-        const int2 p = pairs[k];
-        cnt += in_set(baseline_uv(xyz, p.x, p.y, nu), grid_n_pix, uv_min, uv_max) ? 1 : 0;
+    for (int k0 = 0; k0 < n_pairs; k0 += 256) {  // every lane takes part in the ballot
+        const int k = k0 + (int)threadIdx.x;
+        bool ok = false;
+        if (k < n_pairs) {
+            const int2 p = pairs[k];
+            ok = in_set(baseline_uv(xyz, p.x, p.y, nu), grid_n_pix, uv_min, uv_max);
+        }
+        cnt += ok ? 1 : 0;
+        if (inb) {
+            const unsigned long long m = __ballot(ok);
+            const int w = (k - lane) >> 5;  // this wave's first word (k - lane is a multiple of 64)
+            if (lane == 0 && w < words) inb[(size_t)c * words + w] = (unsigned)m;
+            if (lane == 32 && w + 1 < words) inb[(size_t)c * words + w + 1] = (unsigned)(m >> 32);
+        }
     }
     part[threadIdx.x] = cnt;
     __syncthreads();
@@ -247,27 +271,22 @@ __device__ __forceinline__ void batched_fft(float2 *buf, int t, int log_l, const
     }
 }
 
-// Stokes I of every candidate pair of every channel of a chunk, 0 outside the imaged set B:
-// the scattered visibility reads happen here, with one thread per (channel, pair).
+// Stokes I of every candidate pair of every channel of a chunk (the gridder applies the
+// membership test of B): the scattered visibility reads happen here, with one thread per
+// (channel, pair).  The correlator can write the same values from its epilogue instead.
 template <typename VT>
-__device__ __forceinline__ void stokes_gather(const VT *__restrict__ vis, const double *__restrict__ xyz,
-                                              const double *__restrict__ freq, const int2 *__restrict__ pairs,
-                                              int n_pairs, int n_ant, int grid_n_pix, double uv_min, double uv_max,
-                                              float2 *__restrict__ cvis, int c, int k) {
+__device__ __forceinline__ void stokes_gather(const VT *__restrict__ vis, const int2 *__restrict__ pairs,
+                                              int n_pairs, int n_ant, float2 *__restrict__ cvis, int c, int k) {
     if (k >= n_pairs) return;
     const int2 p = pairs[k];
     const size_t nprod = (size_t)(2 * n_ant) * (2 * n_ant + 1) / 2;
-    const bool ok = in_set(baseline_uv(xyz, p.x, p.y, freq[c]), grid_n_pix, uv_min, uv_max);
-    cvis[(size_t)c * n_pairs + k] = ok ? stokes_i<VT>(vis + (size_t)c * nprod, p.x, p.y) : make_float2(0.f, 0.f);
+    cvis[(size_t)c * n_pairs + k] = stokes_i<VT>(vis + (size_t)c * nprod, p.x, p.y);
 }
 
 template <typename VT>
-__global__ __launch_bounds__(256) void stokes_gather_kernel(const VT *__restrict__ vis, const double *__restrict__ xyz,
-                                                            const double *__restrict__ freq, const int2 *__restrict__ pairs,
-                                                            int n_pairs, int n_ant, int grid_n_pix, double uv_min,
-                                                            double uv_max, float2 *__restrict__ cvis) {
-    stokes_gather<VT>(vis, xyz, freq, pairs, n_pairs, n_ant, grid_n_pix, uv_min, uv_max, cvis, blockIdx.y,
-                      blockIdx.x * 256 + threadIdx.x);
+__global__ __launch_bounds__(256) void stokes_gather_kernel(const VT *__restrict__ vis, const int2 *__restrict__ pairs,
+                                                            int n_pairs, int n_ant, float2 *__restrict__ cvis) {
+    stokes_gather<VT>(vis, pairs, n_pairs, n_ant, cvis, blockIdx.y, blockIdx.x * 256 + threadIdx.x);
 }
 
 // Gridding without atomics.  A workgroup grids one band of R rows of the upper half (v >= 0) of
@@ -306,8 +325,8 @@ template <int LOGM, int PREC, int GE>
 __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const double2 *__restrict__ dxy,
                                           const double *__restrict__ freq, const int *__restrict__ band_off,
                                           const int *__restrict__ band_items, int n_pairs, int n_pix,
-                                          float2 *__restrict__ inter, int band, int c, float2 *grid,
-                                          float2 *tw_lo, float2 *tw_hi, float &vscale) {
+                                          const SetTest &bset, float2 *__restrict__ inter, int band, int c,
+                                          float2 *grid, float2 *tw_lo, float2 *tw_hi, float &vscale) {
     using GS = GridShape<LOGM, GE>;
     constexpr int M = GS::M, R = GS::R, CPT = GS::CPT, COLT = GS::COLT, RPT = GS::RPT, CAP = GS::CAP;
     // staging view of the grid's LDS
@@ -327,7 +346,9 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
         float *red = reinterpret_cast<float *>(grid);
         float mx = 0.f;
         for (int i = k_begin + t; i < k_end; i += 256) {
-            const float2 val = cv_c[band_items[i] >> 1];
+            const int k = band_items[i] >> 1;
+            if (!bset(c, k)) continue;
+            const float2 val = cv_c[k];
             mx = fmaxf(mx, fmaxf(fabsf(val.x), fabsf(val.y)));
         }
         red[t] = mx;
@@ -351,8 +372,8 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
 #pragma unroll
         for (int r = 0; r < RPT; r++) acc[q][r] = make_float2(0.f, 0.f);
 
-    // grid position u / du + M/2 with du = 1/4 wavelength (the membership of B was decided by
-    // the gather kernel; baselines outside B carry a zero value)
+    // grid position u / du + M/2 with du = 1/4 wavelength; candidate pairs outside B at this
+    // channel's frequency are staged with a zero value
     const double sc = freq[c] / C_LIGHT * 4.0;
     // when the band holds more baselines than one round stages, round rr takes list entries
     // rr, rr + n_rounds, ...: still sorted by column, and spread over the whole band, so every
@@ -365,7 +386,7 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
         for (int i = t; i < nk; i += 256) {
             const int item = band_items[k_begin + rr + i * n_rounds];
             const int k = item >> 1;
-            float2 val = cv_c[k];
+            float2 val = bset(c, k) ? cv_c[k] : make_float2(0.f, 0.f);
             // mirrored item: conj V at -(u, v)
             const double sgn = (item & 1) ? -sc : sc;
             if (item & 1) val.y = -val.y;
@@ -456,13 +477,13 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
 template <int LOGM, int PREC, int GE>
 __global__ __launch_bounds__(256) void grid_rows_kernel(
     const float2 *__restrict__ cvis, const double2 *__restrict__ dxy, const double *__restrict__ freq,
-    const int *__restrict__ band_off, const int *__restrict__ band_items, int n_pairs, int n_pix,
+    const int *__restrict__ band_off, const int *__restrict__ band_items, int n_pairs, int n_pix, SetTest bset,
     float2 *__restrict__ inter) {
     __shared__ float2 grid[padded_size(Tile<GE>::CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
     __shared__ float vscale;
-    grid_rows<LOGM, PREC, GE>(cvis, dxy, freq, band_off, band_items, n_pairs, n_pix, inter, blockIdx.x, blockIdx.y, grid,
-                          tw_lo, tw_hi, vscale);
+    grid_rows<LOGM, PREC, GE>(cvis, dxy, freq, band_off, band_items, n_pairs, n_pix, bset, inter, blockIdx.x,
+                              blockIdx.y, grid, tw_lo, tw_hi, vscale);
 }
 
 // Gridding of channel ranges of several sub-bands of one image size: task -> (job, channel,
@@ -479,8 +500,9 @@ __global__ __launch_bounds__(256) void grid_rows_batch_kernel(const ImgJob *__re
     while (j + 1 < n_jobs && jobs[j + 1].rows_task0 <= task) j++;
     const ImgJob &jb = jobs[j];
     const int local = task - jb.rows_task0;
-    grid_rows<LOGM, PREC, GE>(jb.cvis, jb.dxy, jb.freq, jb.band_off, jb.band_items, jb.n_pairs, jb.n_pix, jb.inter,
-                              local % jb.n_bands, local / jb.n_bands, grid, tw_lo, tw_hi, vscale);
+    const SetTest bset{jb.inb, (jb.n_pairs + 31) >> 5};
+    grid_rows<LOGM, PREC, GE>(jb.cvis, jb.dxy, jb.freq, jb.band_off, jb.band_items, jb.n_pairs, jb.n_pix, bset,
+                              jb.inter, local % jb.n_bands, local / jb.n_bands, grid, tw_lo, tw_hi, vscale);
 }
 
 // Column pass.  After the row pass, column x of the Hermitian grid holds s[i] = H(x, i) for the
@@ -587,8 +609,8 @@ __global__ __launch_bounds__(256) void stokes_gather_batch_kernel(const ImgJob *
     const ImgJob &jb = jobs[j];
     const int local = task - jb.gather_task0;
     const int nblk = (jb.n_pairs + 255) / 256;
-    stokes_gather<int2>(reinterpret_cast<const int2 *>(jb.vis), jb.xyz, jb.freq, jb.pairs, jb.n_pairs, jb.n_ant,
-                        jb.n_pix, jb.uv_min, jb.uv_max, jb.cvis, local / nblk, (local % nblk) * 256 + threadIdx.x);
+    stokes_gather<int2>(reinterpret_cast<const int2 *>(jb.vis), jb.pairs, jb.n_pairs, jb.n_ant, jb.cvis, local / nblk,
+                        (local % nblk) * 256 + threadIdx.x);
 }
 
 }  // namespace
@@ -596,7 +618,7 @@ __global__ __launch_bounds__(256) void stokes_gather_batch_kernel(const ImgJob *
 hipError_t launch_image_count(const nbsi_image_plan *p, hipStream_t st) {
     hipLaunchKernelGGL(count_kernel, dim3(p->n_chan), dim3(256), 0, st, p->d_xyz, p->d_freq, p->d_pairs,
                        p->n_pairs, p->method == NBSI_IMAGE_GRID ? p->n_pix : 0, p->uv_min, p->uv_max,
-                       p->d_nb);
+                       p->d_nb, p->d_inb);
     return hipGetLastError();
 }
 
@@ -614,12 +636,13 @@ hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_d
 }
 
 template <int GE>
-static hipError_t launch_grid_ge(const nbsi_image_plan *p, int precision, float2 *cvis, float2 *inter, float *img,
+static hipError_t launch_grid_ge(const nbsi_image_plan *p, int precision, const float2 *cvis, float2 *inter, float *img,
                                  int log_m, hipStream_t st) {
     dim3 gr(p->n_bands, p->n_chan);
+    const SetTest bset{p->d_inb, (p->n_pairs + 31) >> 5};
 #define NBSI_ROWS(LM, PR)                                                                                   \
     hipLaunchKernelGGL((grid_rows_kernel<LM, PR, GE>), gr, dim3(256), 0, st, cvis, p->d_dxy, p->d_freq,     \
-                       p->d_band_off, p->d_band_items, p->n_pairs, p->n_pix, inter)
+                       p->d_band_off, p->d_band_items, p->n_pairs, p->n_pix, bset, inter)
 #define NBSI_ROWS_P(LM)                                                        \
     if (precision == NBSI_PREC_FP16) NBSI_ROWS(LM, NBSI_PREC_FP16);             \
     else if (precision == NBSI_PREC_BF16) NBSI_ROWS(LM, NBSI_PREC_BF16);        \
@@ -641,21 +664,25 @@ static hipError_t launch_grid_ge(const nbsi_image_plan *p, int precision, float2
     return hipGetLastError();
 }
 
-hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype, int precision,
-                             float2 *cvis, float2 *inter, float *img, hipStream_t st) {
-    const int M = 2 * p->n_pix;
-    const int log_m = 31 - __builtin_clz(M);
-    dim3 gg((p->n_pairs + 255) / 256, p->n_chan);
-    if (vis_dtype == NBSI_VIS_I32)
-        hipLaunchKernelGGL(stokes_gather_kernel<int2>, gg, dim3(256), 0, st, (const int2 *)vis, p->d_xyz, p->d_freq,
-                           p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, cvis);
-    else
-        hipLaunchKernelGGL(stokes_gather_kernel<float2>, gg, dim3(256), 0, st, (const float2 *)vis, p->d_xyz,
-                           p->d_freq, p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, cvis);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_image_grid_stokes(const nbsi_image_plan *p, const float2 *cvis, int precision, float2 *inter,
+                                    float *img, hipStream_t st) {
+    const int log_m = 31 - __builtin_clz(2 * p->n_pix);
     return p->ge == 32 ? launch_grid_ge<32>(p, precision, cvis, inter, img, log_m, st)
                        : launch_grid_ge<16>(p, precision, cvis, inter, img, log_m, st);
+}
+
+hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype, int precision,
+                             float2 *cvis, float2 *inter, float *img, hipStream_t st) {
+    dim3 gg((p->n_pairs + 255) / 256, p->n_chan);
+    if (vis_dtype == NBSI_VIS_I32)
+        hipLaunchKernelGGL(stokes_gather_kernel<int2>, gg, dim3(256), 0, st, (const int2 *)vis, p->d_pairs,
+                           p->n_pairs, p->n_ant, cvis);
+    else
+        hipLaunchKernelGGL(stokes_gather_kernel<float2>, gg, dim3(256), 0, st, (const float2 *)vis, p->d_pairs,
+                           p->n_pairs, p->n_ant, cvis);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_image_grid_stokes(p, cvis, precision, inter, img, st);
 }
 
 hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, hipStream_t st) {

@@ -50,6 +50,14 @@ struct nbsi_image_plan {
     int *d_band_items = nullptr;  // 2 * (index into d_pairs) + 1 if gridded at -(u, v) with conj V
     int n_band_items = 0;
     float *d_corr = nullptr;      // [n_pix] 1 / (kernel Fourier transform) per image column
+    // gridding plans: membership bitmap of B, [n_chan][(n_pairs + 31) / 32] words (bit k % 32 of
+    // word k / 32 = pair k imaged at that channel), written by the count kernel
+    unsigned *d_inb = nullptr;
+    // Candidates are ordered by 8 x 8 antenna block (a / 8, b / 8), blocks in packed lower-triangle
+    // order, then by (a % 8) * 8 + b % 8 within a block: block t holds the pairs whose bits are set
+    // in d_tmask[t], numbered from d_tbase[t] (gridding plans)
+    unsigned long long *d_tmask = nullptr;
+    int *d_tbase = nullptr;
 };
 
 #define NBSI_TRY_HIP(ctx, call)                                                        \
@@ -96,8 +104,18 @@ enum { CORR_VARIANT_TILED = 0, CORR_VARIANT_CHAN32 = 1, CORR_VARIANT_CHAN64 = 2 
 int correlate_batch_tasks(const CorrJob &jb, int variant);
 int correlate_default_variant(int n_in, int n_spec);
 bool correlate_variant_valid(int n_in, int n_spec, int variant);
+// Optional Stokes-I output of the correlator's epilogue: for the candidate pair (A, B) of an
+// imaging plan with index k (see nbsi_image_plan::d_tmask), out[c * n_pairs + k] =
+// (V_XX + V_YY) / 2 of channel c, computed exactly as the imager's gather computes it (inputs
+// 2A, 2A + 1 are antenna A's two polarisations).
+struct StokesOut {
+    const unsigned long long *mask = nullptr;
+    const int *base = nullptr;
+    float2 *out = nullptr;
+    int n_pairs = 0;
+};
 hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
-                                    hipStream_t st);
+                                    hipStream_t st, StokesOut so = StokesOut());
 hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in,
                                   hipStream_t st);
 
@@ -108,6 +126,7 @@ struct ImgJob {
     const int2 *pairs;
     const double2 *dxy;
     const int *band_off, *band_items, *nb;
+    const unsigned *inb;  // membership bitmap rows from the job's first channel
     const float *corr;
     float2 *cvis, *inter;
     float *img;
@@ -144,7 +163,7 @@ hipError_t launch_corner_turn_q(const int8_t *stage, int n_in, int n_spec, int n
 hipError_t launch_corner_turn_f(const float *stage, int n_in, int n_spec, int n_chan, float *out,
                                 hipStream_t st);
 hipError_t launch_correlate_i8(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis,
-                               hipStream_t st);
+                               hipStream_t st, StokesOut so = StokesOut());
 hipError_t launch_correlate_f32(const float *q, int n_chan, int n_in, int n_spec, float *vis,
                                 hipStream_t st);
 hipError_t launch_image_count(const nbsi_image_plan *p, hipStream_t st);
@@ -152,6 +171,8 @@ hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_d
                             hipStream_t st);
 hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype,
                              int precision, float2 *cvis, float2 *inter, float *img, hipStream_t st);
+hipError_t launch_image_grid_stokes(const nbsi_image_plan *p, const float2 *cvis, int precision, float2 *inter,
+                                    float *img, hipStream_t st);
 hipError_t launch_detect_stats(const float *img, int n_chan, int n_pix, int mode, float *stats,
                                hipStream_t st);
 hipError_t launch_detect_scan(const float *img, int n_chan, int n_pix, int mode,

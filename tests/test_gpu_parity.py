@@ -312,3 +312,64 @@ def test_detect_adversarial_spectra(n_chan):
     assert (np.abs(snr_got - snr_ref)[:, valid] / scale).max() <= 1e-4
     assert np.all(snr_got[:, 4:12, 4:12][:, 0, 4] == 0)  # constant pixel (y=4, x=8): MAD 0
     _compare_candidates(rec, ref, snr_ref, 5.0)
+
+
+# ---------------- correlator with the Stokes-I epilogue, imager from Stokes I ----------------
+STOKES_CASES = [
+    # n_ant, n_spec, n_chan, n_pix, radius: whole-channel 32 and 64 kernels, 128 x 128 tiles,
+    # antenna counts that leave ragged tiles, and the instrument's 352 antennas
+    (24, 16, 3, 64, 60.0),
+    (21, 40, 2, 64, 60.0),
+    (37, 100, 2, 128, 150.0),
+    (16, 300, 2, 64, 40.0),     # tiles, sums beyond 2^24: the double-rounded form
+    (352, 32, 2, 256, 750.0),
+]
+
+
+@pytest.mark.parametrize("n_ant,n_spec,n_chan,n_pix,radius", STOKES_CASES)
+def test_correlate_stokes_matches_separate_calls(n_ant, n_spec, n_chan, n_pix, radius):
+    """The fused correlator writes the same visibilities plus V_I = (V_XX + V_YY) / 2 of the
+    plan's candidate pairs; imaging those gives nbsi_image's image bit for bit.  Channels span
+    40-80 MHz so that the imaged set B differs between channels."""
+    print(f"correlate_stokes n_ant={n_ant} n_spec={n_spec} n_chan={n_chan} n_pix={n_pix}", flush=True)
+    xyz = synth.antenna_layout(n_ant, radius, 400 + n_ant)
+    freq = np.linspace(40e6, 80e6, n_chan)
+    plan = nb.nbsi_image_plan_create(xyz, freq, n_pix, nb.NBSI_IMAGE_GRID)
+    nbase = plan.n_baselines()
+    assert nbase.min() > 10 and len(set(nbase.tolist())) == n_chan  # B differs per channel
+    q = synth.random_spectra(n_chan, 2 * n_ant, n_spec, seed=n_ant * 31 + n_spec, full_range=True).to(DEV)
+    vis = nb.nbsi_correlate(q)
+    vis2, st = nb.nbsi_correlate_stokes(q, plan)
+    torch.cuda.synchronize()
+    assert torch.equal(vis, vis2)
+    pairs = plan.pairs()
+    assert len(pairs) == plan.n_pairs() and (pairs[:, 0] > pairs[:, 1]).all()
+    v = vis.cpu().numpy().astype(np.float64)
+    a, b = pairs[:, 0].astype(np.int64), pairs[:, 1].astype(np.int64)
+    txx = (2 * a) * (2 * a + 1) // 2 + 2 * b
+    tyy = (2 * a + 1) * (2 * a + 2) // 2 + 2 * b + 1
+    want = (0.5 * (v[:, txx] + v[:, tyy])).astype(np.float32)
+    np.testing.assert_array_equal(st.cpu().numpy(), want)
+    for prec in (nb.NBSI_PREC_FP32, nb.NBSI_PREC_FP16):
+        img = nb.nbsi_image(plan, vis, precision=prec)
+        img2 = nb.nbsi_image_stokes(plan, st, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(img, img2), prec
+    if n_ant <= 40:
+        ref = oracle.image_dft(v.astype(np.int32), xyz, freq, n_pix, grid_n_pix=n_pix)
+        emax, erms = _rel(nb.nbsi_image_stokes(plan, st).cpu().numpy(), ref)
+        print(f"  vs direct Fourier oracle: max {emax:.2e} rms {erms:.2e}", flush=True)
+        assert emax < 1e-5 and erms < 2e-6
+
+
+def test_correlate_stokes_rejects_mismatched_plan():
+    xyz = synth.antenna_layout(24, 60.0, 3)
+    freq = synth.channel_freqs(65536, 32768, 2)
+    plan = nb.nbsi_image_plan_create(xyz, freq, 64, nb.NBSI_IMAGE_GRID)
+    q = synth.random_spectra(2, 2 * 23, 16, seed=1).to(DEV)  # 23 antennas' worth of inputs
+    with pytest.raises(nb.NbsiError):
+        nb.nbsi_correlate_stokes(q, plan, stokes_i=torch.empty((2, plan.n_pairs(), 2), device=DEV))
+    dft = nb.nbsi_image_plan_create(xyz, freq, 64, nb.NBSI_IMAGE_DFT)
+    q2 = synth.random_spectra(2, 48, 16, seed=2).to(DEV)
+    with pytest.raises(nb.NbsiError):
+        nb.nbsi_correlate_stokes(q2, dft)
