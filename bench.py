@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 INT8_PEAK_TOPS = 5000.0
+FP16_PEAK_TFLOPS = 2500.0
 
 
 def log(msg):
@@ -47,6 +48,10 @@ def parse():
                     help="skip the uneven-sub-band leg (batched graph vs per-sub-band launches)")
     ap.add_argument("--batch-only", action="store_true",
                     help="profiling aid: run only the uneven-sub-band leg and print its figures")
+    ap.add_argument("--no-deep", action="store_true", help="skip the long-integration correlator leg")
+    ap.add_argument("--no-classifier", action="store_true", help="skip the classifier leg")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="profiling aid: run only the long-integration correlator and classifier legs")
     ap.add_argument("--stages", default="all", help="profiling aid: all | correlate")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -146,16 +151,7 @@ def batched_leg(args, nb, torch, ctx, dev, synth):
             nb.nbsi_image(p, vis, img=img)
 
     def timed(fn, k):
-        fn()
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(k):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / k
+        return _timed(torch, fn, k)
 
     k = max(2, args.steps // 2)
     ms_per = timed(per_subband, k)
@@ -194,6 +190,87 @@ def batched_leg(args, nb, torch, ctx, dev, synth):
     }
 
 
+def _timed(torch, fn, k):
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(k):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / k
+
+
+def deep_correlator_leg(args, nb, torch, ctx, dev, synth):
+    """The correlator alone at 704 inputs and 1,024 channels for integrations T = 32 (the
+    instrument configuration), 298 (the paper's 30 s at ~10 Hz) and 1,024 / 2,048: where the
+    output write stops dominating, the int8 matrix cores become the bound."""
+    n_in, C = 704, 1024
+    nprod = n_in * (n_in + 1) // 2
+    vis = torch.empty((C, nprod, 2), dtype=torch.int32, device=dev)
+    rows = []
+    for T in (32, 298, 1024, 2048):
+        q = synth.random_spectra(C, n_in, T, seed=5000 + T, full_range=True, device="cuda")
+        ms = _timed(torch, lambda: nb.nbsi_correlate(q, vis=vis, ctx=ctx), max(3, args.steps // 2))
+        useful = 8.0 * nprod * T * C
+        hbm = C * 2 * n_in * T + C * nprod * 8
+        rows.append({"n_spec": T, "kernel": nb.nbsi_correlate_kernel(n_in, T), "ms": round(ms, 4),
+                     "useful_tops": round(useful / (ms * 1e-3) / 1e12, 2),
+                     "frac_of_int8_mfma_peak": round(useful / (ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+                     "hbm_gbs": round(hbm / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_hbm": round(hbm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+        log(f"[bench] deep correlator T={T}: {ms:.3f} ms, {rows[-1]['useful_tops']} TOPS")
+        del q
+    del vis
+    torch.cuda.empty_cache()
+    return {"workload": "correlator only, 704 inputs x 1024 channels, random int8 spectra", "rows": rows}
+
+
+def classifier_leg(args, nb, torch, ctx, dev, synth):
+    """The candidate classifier on 100,000 stamps (33 channels x 9 x 9, FP16): one training epoch
+    in mini-batches of 512 (forward, backward, Adam per step) and inference over all stamps.
+    FLOP per stamp: forward 7.52 M; training 21.0 M (forward, weight gradients of the three
+    convolutions and data gradients of the upper two)."""
+    n, B = 100_000, 512
+    g = torch.Generator(device=dev)
+    g.manual_seed(6001)
+    stamps = torch.randn((n, nb.NBSI_STAMP_CHANNELS, nb.NBSI_STAMP_PIXELS, nb.NBSI_STAMP_PIXELS),
+                         generator=g, device=dev).to(torch.float16)
+    labels = (torch.rand(n, generator=g, device=dev) < 0.4).to(torch.float32)
+    idx = torch.randperm(n, generator=g, device=dev).to(torch.int32)
+    net = nb.Net(synth.net_init(6002), max_batch=4096, ctx=ctx)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    n_steps = n // B
+
+    def epoch():
+        for s0 in range(0, n_steps * B, B):
+            net.train_step(stamps, labels, index=idx[s0:s0 + B], lr=1e-3, loss=loss)
+
+    logits = torch.empty(n, dtype=torch.float32, device=dev)
+
+    def infer():
+        for s0 in range(0, n, 4096):
+            m = min(4096, n - s0)
+            net.forward(stamps[s0:s0 + m], logits=logits[s0:s0 + m])
+
+    ms_train = _timed(torch, epoch, 2)
+    ms_inf = _timed(torch, infer, 3)
+    net.close()
+    fwd, train = 7.52e6, 21.0e6
+    tr_rate = n_steps * B / (ms_train * 1e-3)
+    inf_rate = n / (ms_inf * 1e-3)
+    log(f"[bench] classifier: train {tr_rate:.0f} stamps/s, infer {inf_rate:.0f} stamps/s")
+    return {"workload": "100,000 FP16 stamps 33x9x9, batch 512 training, batch 4096 inference",
+            "train_epoch_ms": round(ms_train, 3), "train_stamps_per_s": round(tr_rate, 1),
+            "train_tflops": round(train * tr_rate / 1e12, 2),
+            "train_frac_of_fp16_mfma_peak": round(train * tr_rate / 1e12 / FP16_PEAK_TFLOPS, 4),
+            "infer_ms": round(ms_inf, 3), "infer_stamps_per_s": round(inf_rate, 1),
+            "infer_tflops": round(fwd * inf_rate / 1e12, 2),
+            "infer_frac_of_fp16_mfma_peak": round(fwd * inf_rate / 1e12 / FP16_PEAK_TFLOPS, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -208,6 +285,11 @@ def main():
     torch.cuda.set_device(dev)
     if args.batch_only:
         print(json.dumps(batched_leg(args, nb, torch, nb.nbsi_create(0), dev, synth)))
+        return
+    if args.legs_only:
+        c0 = nb.nbsi_create(0)
+        print(json.dumps({"deep_correlator": deep_correlator_leg(args, nb, torch, c0, dev, synth),
+                          "classifier": classifier_leg(args, nb, torch, c0, dev, synth)}))
         return
     cfg = synth.make_config(2)
     log(f"[bench] generating inputs: {cfg.name}")
@@ -377,6 +459,11 @@ def main():
 
     if not args.no_batch:
         comp["batched_subbands"] = batched_leg(args, nb, torch, ctx, dev, synth)
+        torch.cuda.empty_cache()
+    if not args.no_deep:
+        comp["deep_correlator"] = deep_correlator_leg(args, nb, torch, ctx, dev, synth)
+    if not args.no_classifier:
+        comp["classifier"] = classifier_leg(args, nb, torch, ctx, dev, synth)
         torch.cuda.empty_cache()
 
     out = {

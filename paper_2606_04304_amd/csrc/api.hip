@@ -226,7 +226,10 @@ int nbsi_correlate(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, in
     if (!spec_q || !vis) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate: null pointer");
     if (!aligned16(spec_q) || !aligned16(vis)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate: misaligned pointer");
     DeviceGuard g(ctx->device);
-    NBSI_TRY_HIP(ctx, launch_correlate_i8(spec_q, n_chan, n_in, n_spec, vis, ctx->stream));
+    void *pad = nullptr;
+    if (const size_t pb = correlate_pad_bytes(n_chan, n_in, n_spec))
+        if ((rc = nbsi_scratch(ctx, SLOT_CORR_PAD, pb, &pad))) return rc;
+    NBSI_TRY_HIP(ctx, launch_correlate_i8(spec_q, n_chan, n_in, n_spec, vis, ctx->stream, StokesOut(), (int8_t *)pad));
     return NBSI_OK;
 }
 
@@ -247,7 +250,10 @@ int nbsi_correlate_stokes(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n
     so.base = plan->d_tbase;
     so.out = reinterpret_cast<float2 *>(stokes_i);
     so.n_pairs = plan->n_pairs;
-    NBSI_TRY_HIP(ctx, launch_correlate_i8(spec_q, n_chan, n_in, n_spec, vis, ctx->stream, so));
+    void *pad = nullptr;
+    if (const size_t pb = correlate_pad_bytes(n_chan, n_in, n_spec))
+        if ((rc = nbsi_scratch(ctx, SLOT_CORR_PAD, pb, &pad))) return rc;
+    NBSI_TRY_HIP(ctx, launch_correlate_i8(spec_q, n_chan, n_in, n_spec, vis, ctx->stream, so, (int8_t *)pad));
     return NBSI_OK;
 }
 

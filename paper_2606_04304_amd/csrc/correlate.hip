@@ -24,9 +24,10 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int TILE = 128;        // G rows / cols per workgroup tile
+constexpr int TILE = 128;        // G rows / cols per workgroup tile (FP32 path)
+constexpr int TILE_I8 = 128;     // G rows / cols per workgroup tile of the int8 tiled kernel
 constexpr int KC = 64;           // K bytes per LDS stage
-constexpr int LDS_STRIDE = KC + 16;  // padded row stride (bytes) against bank conflicts
+constexpr int LDS_STRIDE = KC + 16;  // padded row stride (bytes): 16 rows of a b128 read hit 64 distinct banks
 
 __device__ __forceinline__ void tile_pair(int pair, int &I, int &J) {
     int a = (int)((sqrtf(8.f * (float)pair + 1.f) - 1.f) * 0.5f);
@@ -36,17 +37,25 @@ __device__ __forceinline__ void tile_pair(int pair, int &I, int &J) {
     J = pair - a * (a + 1) / 2;
 }
 
-// Stage rows [r0, r0 + TILE) x bytes [k0, k0 + KC) of Y (row stride T bytes) into LDS, zero-padded.
-__device__ __forceinline__ void stage_rows(int8_t *s, const int8_t *__restrict__ Y, int rows, int T,
-                                           int r0, int k0, int t) {
-    for (int e = t; e < TILE * (KC / 16); e += 256) {
+// One K stage of rows [r0, r0 + TILE_I8) x bytes [k0, k0 + KC) of Y (row stride ldy bytes), zero past
+// T and past the last row, as STAGE_VECS 16-byte vectors per thread: loaded into registers one
+// stage ahead, then stored to LDS.  Rows whose stride is a multiple of 16 bytes (the library
+// repacks the others before a single-band launch) take whole-vector loads; other strides fall back
+// to byte loads.
+constexpr int STAGE_VECS = TILE_I8 * (KC / 16) / 256;
+template <bool VEC>  // the row stride is a multiple of 16 bytes
+__device__ __forceinline__ void load_stage(v4i (&v)[STAGE_VECS], const int8_t *__restrict__ Y, int rows, int T,
+                                           int ldy, int r0, int k0, int t) {
+#pragma unroll
+    for (int i = 0; i < STAGE_VECS; i++) {
+        const int e = t + 256 * i;
         const int rl = e / (KC / 16), vq = e % (KC / 16);
         const int r = r0 + rl, k = k0 + vq * 16;
         v4i val = {0, 0, 0, 0};
-        if (r < rows) {
-            const int8_t *src = Y + (size_t)r * T + k;
-            if ((T & 15) == 0) {
-                if (k < T) val = *reinterpret_cast<const v4i *>(src);
+        if (r < rows && k < T) {
+            const int8_t *src = Y + (size_t)r * ldy + k;
+            if constexpr (VEC) {  // k + 16 <= ldy: bytes T .. ldy - 1 are the repacked zeros
+                val = *reinterpret_cast<const v4i *>(src);
             } else {
                 int8_t tmp[16];
 #pragma unroll
@@ -54,7 +63,16 @@ __device__ __forceinline__ void stage_rows(int8_t *s, const int8_t *__restrict__
                 val = *reinterpret_cast<v4i *>(tmp);
             }
         }
-        *reinterpret_cast<v4i *>(s + rl * LDS_STRIDE + vq * 16) = val;
+        v[i] = val;
+    }
+}
+
+__device__ __forceinline__ void store_stage(int8_t *s, const v4i (&v)[STAGE_VECS], int t) {
+#pragma unroll
+    for (int i = 0; i < STAGE_VECS; i++) {
+        const int e = t + 256 * i;
+        const int rl = e / (KC / 16), vq = e % (KC / 16);
+        *reinterpret_cast<v4i *>(s + rl * LDS_STRIDE + vq * 16) = v[i];
     }
 }
 
@@ -136,104 +154,141 @@ __device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, in
 }
 
 // One 128 x 128 tile pair (I, J) of channel c: K loop through LDS, MFMA, epilogue.
-__device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int n_in, int T, int c, int pair,
-                                               int32_t *__restrict__ vis, int8_t *sA, int8_t *sB,
+// One TILE_I8 x TILE_I8 tile pair (I, J) of channel c; each of the four waves owns a WT x WT
+// quarter (MI x MI MFMA tiles).  The K loop runs over KC-byte stages double buffered in LDS: the
+// next stage's global loads are issued into registers before the current stage's MFMAs and
+// stored to the other buffer after them, so one barrier per stage separates a buffer's last reads
+// from its next writes.  LDS per workgroup: 2 stages x 2 operands x TILE_I8 x LDS_STRIDE bytes
+// (40 KB), registers for four workgroups per CU.  Measured alternatives, slower on 704 inputs:
+// 256 x 256 tiles with 128 x 128 per wave (one wave per SIMD: its LDS-to-MFMA and barrier waits
+// are exposed), and register prefetch two stages ahead.
+constexpr int TILE_LDS = TILE_I8 * LDS_STRIDE;
+constexpr int WT = TILE_I8 / 2;  // a wave's share of the tile
+constexpr int MI = WT / 32;      // MFMA tiles per wave per dimension
+template <bool VEC, bool STOKES>
+__device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int n_in, int T, int ldy, int c,
+                                               int pair, int32_t *__restrict__ vis, int8_t *lds,
                                                const StokesOut &so) {
     int I, J;
     tile_pair(pair, I, J);
     const int rows = 2 * n_in;
-    const int8_t *Y = q + (size_t)c * rows * T;
+    const int8_t *Y = q + (size_t)c * rows * ldy;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int wr = wave >> 1, wc = wave & 1;
     const bool diag = (I == J);
     const bool active = !(diag && wr < wc);
+    int8_t *sA[2] = {lds, lds + 2 * TILE_LDS};
+    int8_t *sB[2] = {lds + TILE_LDS, lds + 3 * TILE_LDS};
 
-    v16i acc[2][2];
+    v16i acc[MI][MI];
 #pragma unroll
-    for (int mi = 0; mi < 2; mi++)
+    for (int mi = 0; mi < MI; mi++)
 #pragma unroll
-        for (int ni = 0; ni < 2; ni++)
+        for (int ni = 0; ni < MI; ni++)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[mi][ni][r] = 0;
 
-    BlockStokes bs[2][2];
-#pragma unroll
-    for (int mi = 0; mi < 2; mi++)
-#pragma unroll
-        for (int ni = 0; ni < 2; ni++) {
-            const int R0 = I * TILE + wr * 64 + mi * 32, C0 = J * TILE + wc * 64 + ni * 32;
-            if (active && R0 < rows && C0 <= R0 + 31) bs[mi][ni] = block_stokes(so, R0, C0);
+    const int n_st = (T + KC - 1) / KC;
+    v4i ra[STAGE_VECS], rb[STAGE_VECS];
+    load_stage<VEC>(ra, Y, rows, T, ldy, I * TILE_I8, 0, t);
+    if (!diag) load_stage<VEC>(rb, Y, rows, T, ldy, J * TILE_I8, 0, t);
+    store_stage(sA[0], ra, t);
+    if (!diag) store_stage(sB[0], rb, t);
+    __syncthreads();
+    for (int st = 0; st < n_st; st++) {
+        const int cur = st & 1;
+        const bool more = st + 1 < n_st;
+        if (more) {
+            load_stage<VEC>(ra, Y, rows, T, ldy, I * TILE_I8, (st + 1) * KC, t);
+            if (!diag) load_stage<VEC>(rb, Y, rows, T, ldy, J * TILE_I8, (st + 1) * KC, t);
         }
-    const int8_t *sBr = diag ? sA : sB;
-    for (int k0 = 0; k0 < T; k0 += KC) {
-        __syncthreads();
-        stage_rows(sA, Y, rows, T, I * TILE, k0, t);
-        if (!diag) stage_rows(sB, Y, rows, T, J * TILE, k0, t);
-        __syncthreads();
         if (active) {
+            const int8_t *a_s = sA[cur] + (wr * WT + (lane & 31)) * LDS_STRIDE;
+            const int8_t *b_s = (diag ? sA[cur] : sB[cur]) + (wc * WT + (lane & 31)) * LDS_STRIDE;
 #pragma unroll
             for (int kk = 0; kk < KC; kk += 32) {
                 const int koff = kk + (lane >> 5) * 16;
-                v4i a[2], b[2];
+                v4i a[MI], b[MI];
 #pragma unroll
-                for (int mi = 0; mi < 2; mi++)
-                    a[mi] = *reinterpret_cast<const v4i *>(sA + (wr * 64 + mi * 32 + (lane & 31)) * LDS_STRIDE + koff);
+                for (int mi = 0; mi < MI; mi++) a[mi] = *reinterpret_cast<const v4i *>(a_s + mi * 32 * LDS_STRIDE + koff);
 #pragma unroll
-                for (int ni = 0; ni < 2; ni++)
-                    b[ni] = *reinterpret_cast<const v4i *>(sBr + (wc * 64 + ni * 32 + (lane & 31)) * LDS_STRIDE + koff);
+                for (int ni = 0; ni < MI; ni++) b[ni] = *reinterpret_cast<const v4i *>(b_s + ni * 32 * LDS_STRIDE + koff);
 #pragma unroll
-                for (int mi = 0; mi < 2; mi++)
+                for (int mi = 0; mi < MI; mi++)
 #pragma unroll
-                    for (int ni = 0; ni < 2; ni++)
+                    for (int ni = 0; ni < MI; ni++)
                         acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
             }
         }
+        if (more) {
+            store_stage(sA[cur ^ 1], ra, t);
+            if (!diag) store_stage(sB[cur ^ 1], rb, t);
+        }
+        __syncthreads();
     }
     if (!active) return;
     const size_t nprod = (size_t)n_in * (n_in + 1) / 2;
     int2 *vc = reinterpret_cast<int2 *>(vis) + (size_t)c * nprod;
 #pragma unroll
-    for (int mi = 0; mi < 2; mi++)
+    for (int mi = 0; mi < MI; mi++)
 #pragma unroll
-        for (int ni = 0; ni < 2; ni++) {
-            const int R0 = I * TILE + wr * 64 + mi * 32;
-            const int C0 = J * TILE + wc * 64 + ni * 32;
-            if (R0 < rows && C0 <= R0 + 31)
-                store_tile_i32(acc[mi][ni], R0, C0, lane, n_in, vc, so, c, bs[mi][ni], T <= 256);
+        for (int ni = 0; ni < MI; ni++) {
+            const int R0 = I * TILE_I8 + wr * WT + mi * 32;
+            const int C0 = J * TILE_I8 + wc * WT + ni * 32;
+            if (R0 < rows && C0 <= R0 + 31) {
+                const BlockStokes bs = STOKES ? block_stokes(so, R0, C0) : BlockStokes();
+                store_tile_i32(acc[mi][ni], R0, C0, lane, n_in, vc, STOKES ? so : StokesOut(), c, bs, T <= 256);
+            }
         }
 }
 
-__global__ __launch_bounds__(256) void correlate_i8_kernel(const int8_t *__restrict__ q, int n_chan,
-                                                           int n_in, int T, int n_pairs,
-                                                           int32_t *__restrict__ vis, StokesOut so) {
-    __shared__ __attribute__((aligned(16))) int8_t sA[TILE * LDS_STRIDE];
-    __shared__ __attribute__((aligned(16))) int8_t sB[TILE * LDS_STRIDE];
+template <bool VEC, bool STOKES>
+__global__ __launch_bounds__(256, 3) void correlate_i8_kernel(const int8_t *__restrict__ q, int n_chan,
+                                                              int n_in, int T, int ldy, int n_pairs,
+                                                              int32_t *__restrict__ vis, StokesOut so) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[4 * TILE_LDS];
     const int id = blockIdx.x;
     const int xcd = id & 7, rest = id >> 3;
     const int pair = rest % n_pairs;
     const int c = (rest / n_pairs) * 8 + xcd;
     if (c >= n_chan) return;
-    correlate_tile(q, n_in, T, c, pair, vis, sA, sB, so);
+    correlate_tile<VEC, STOKES>(q, n_in, T, ldy, c, pair, vis, lds, so);
 }
 
 // Several sub-bands in one launch: task -> (job, channel group of 8, tile pair, XCD lane), one
 // workgroup per task, in the same XCD-preserving order as the single-band launch.
-__global__ __launch_bounds__(256) void correlate_i8_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
-                                                                 int n_tasks) {
-    __shared__ __attribute__((aligned(16))) int8_t sA[TILE * LDS_STRIDE];
-    __shared__ __attribute__((aligned(16))) int8_t sB[TILE * LDS_STRIDE];
+__global__ __launch_bounds__(256, 3) void correlate_i8_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
+                                                                    int n_tasks) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[4 * TILE_LDS];
     const int task = blockIdx.x;
     if (task >= n_tasks) return;
     int j = 0;
     while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
     const CorrJob jb = jobs[j];
     const int local = task - jb.task0;
-    const int n_tiles = (2 * jb.n_in + TILE - 1) / TILE;
+    const int n_tiles = (2 * jb.n_in + TILE_I8 - 1) / TILE_I8;
     const int n_pairs = n_tiles * (n_tiles + 1) / 2;
     const int xcd = local & 7, rest = local >> 3;
     const int pair = rest % n_pairs;
     const int c = (rest / n_pairs) * 8 + xcd;
-    if (c < jb.n_chan) correlate_tile(jb.q, jb.n_in, jb.n_spec, c, pair, jb.vis, sA, sB, StokesOut());
+    if (c < jb.n_chan)
+        correlate_tile<false, false>(jb.q, jb.n_in, jb.n_spec, jb.n_spec, c, pair, jb.vis, lds, StokesOut());
+}
+
+// Repack int8 rows of T bytes to a stride of ldy bytes (ldy >= T, a multiple of 16), zero-filled,
+// so the tiled correlator stages whole 16-byte vectors.  One thread per 16-byte output vector.
+__global__ __launch_bounds__(256) void pad_rows_kernel(const int8_t *__restrict__ src, size_t n_rows, int T,
+                                                       int ldy, int8_t *__restrict__ dst) {
+    const size_t vpr = (size_t)(ldy / 16);
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n_rows * vpr) return;
+    const size_t r = e / vpr;
+    const int k = (int)(e % vpr) * 16;
+    const int8_t *s = src + r * (size_t)T + k;
+    int8_t tmp[16];
+#pragma unroll
+    for (int b = 0; b < 16; b++) tmp[b] = (k + b < T) ? s[b] : (int8_t)0;
+    *reinterpret_cast<v4i *>(dst + r * (size_t)ldy + k) = *reinterpret_cast<v4i *>(tmp);
 }
 
 // Short integrations (n_spec <= 64): one workgroup per channel keeps the channel's whole
@@ -416,8 +471,14 @@ __global__ __launch_bounds__(256) void correlate_f32_kernel(const float *__restr
 }  // namespace
 
 hipError_t launch_correlate_i8(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis,
-                               hipStream_t st, StokesOut so) {
-    return launch_correlate_variant(q, n_chan, n_in, n_spec, vis, correlate_default_variant(n_in, n_spec), st, so);
+                               hipStream_t st, StokesOut so, int8_t *pad_scratch) {
+    return launch_correlate_variant(q, n_chan, n_in, n_spec, vis, correlate_default_variant(n_in, n_spec), st, so,
+                                    pad_scratch);
+}
+
+size_t correlate_pad_bytes(int n_chan, int n_in, int n_spec) {
+    if (correlate_default_variant(n_in, n_spec) != CORR_VARIANT_TILED || (n_spec & 15) == 0) return 0;
+    return (size_t)n_chan * 2 * n_in * (size_t)((n_spec + 15) & ~15);
 }
 
 size_t correlate_chan_lds(int n_in, int variant) {
@@ -428,7 +489,7 @@ size_t correlate_chan_lds(int n_in, int variant) {
 // Tasks of a batched correlator launch for one job and variant.
 int correlate_batch_tasks(const CorrJob &jb, int variant) {
     if (variant == CORR_VARIANT_TILED) {
-        const int n_tiles = (2 * jb.n_in + TILE - 1) / TILE;
+        const int n_tiles = (2 * jb.n_in + TILE_I8 - 1) / TILE_I8;
         return ((jb.n_chan + 7) / 8) * 8 * (n_tiles * (n_tiles + 1) / 2);
     }
     return jb.n_chan;
@@ -494,13 +555,33 @@ hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks
 
 // Single-band launch of one variant (the default path and the autotuner's candidates).
 hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
-                                    hipStream_t st, StokesOut so) {
+                                    hipStream_t st, StokesOut so, int8_t *pad_scratch) {
     if (variant == CORR_VARIANT_TILED) {
-        const int n_tiles = (2 * n_in + TILE - 1) / TILE;
+        int ldy = n_spec;
+        if ((n_spec & 15) && pad_scratch) {
+            ldy = (n_spec + 15) & ~15;
+            const size_t n_rows = (size_t)n_chan * 2 * n_in;
+            const size_t n_vec = n_rows * (size_t)(ldy / 16);
+            hipLaunchKernelGGL(pad_rows_kernel, dim3((unsigned)((n_vec + 255) / 256)), dim3(256), 0, st, q, n_rows,
+                               n_spec, ldy, pad_scratch);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            q = pad_scratch;
+        }
+        const int n_tiles = (2 * n_in + TILE_I8 - 1) / TILE_I8;
         const int n_pairs = n_tiles * (n_tiles + 1) / 2;
         const size_t groups = (size_t)((n_chan + 7) / 8) * 8 * n_pairs;
-        hipLaunchKernelGGL(correlate_i8_kernel, dim3((unsigned)groups), dim3(256), 0, st, q, n_chan, n_in, n_spec,
-                           n_pairs, vis, so);
+#define NBSI_TILED(V, S)                                                                                    \
+    hipLaunchKernelGGL((correlate_i8_kernel<V, S>), dim3((unsigned)groups), dim3(256), 0, st, q, n_chan, n_in, \
+                       n_spec, ldy, n_pairs, vis, so)
+        if (ldy & 15) {
+            if (so.out) NBSI_TILED(false, true);
+            else NBSI_TILED(false, false);
+        } else {
+            if (so.out) NBSI_TILED(true, true);
+            else NBSI_TILED(true, false);
+        }
+#undef NBSI_TILED
         return hipGetLastError();
     }
     const size_t lds = correlate_chan_lds(n_in, variant);

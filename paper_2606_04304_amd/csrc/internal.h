@@ -28,6 +28,7 @@ enum ScratchSlot {
     SLOT_DET_KEYS = 4,      // detector: sort keys
     SLOT_DET_STATS = 5,     // detector: per-channel / per-pixel statistics
     SLOT_IMG_BL = 6,        // imager: per-channel baseline values
+    SLOT_CORR_PAD = 7,      // correlator: spectra repacked to a 16-byte row stride
 };
 
 
@@ -114,8 +115,11 @@ struct StokesOut {
     float2 *out = nullptr;
     int n_pairs = 0;
 };
+// pad_scratch (correlate_pad_bytes bytes, or null for the byte-load fallback) receives the
+// spectra repacked to a 16-byte row stride when the tiled variant gets n_spec % 16 != 0.
 hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
-                                    hipStream_t st, StokesOut so = StokesOut());
+                                    hipStream_t st, StokesOut so = StokesOut(), int8_t *pad_scratch = nullptr);
+size_t correlate_pad_bytes(int n_chan, int n_in, int n_spec);
 hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in,
                                   hipStream_t st);
 
@@ -163,7 +167,7 @@ hipError_t launch_corner_turn_q(const int8_t *stage, int n_in, int n_spec, int n
 hipError_t launch_corner_turn_f(const float *stage, int n_in, int n_spec, int n_chan, float *out,
                                 hipStream_t st);
 hipError_t launch_correlate_i8(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis,
-                               hipStream_t st, StokesOut so = StokesOut());
+                               hipStream_t st, StokesOut so = StokesOut(), int8_t *pad_scratch = nullptr);
 hipError_t launch_correlate_f32(const float *q, int n_chan, int n_in, int n_spec, float *vis,
                                 hipStream_t st);
 hipError_t launch_image_count(const nbsi_image_plan *p, hipStream_t st);
