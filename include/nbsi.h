@@ -205,6 +205,35 @@ int nbsi_detect(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode
                 float *snr, nbsi_cand *out, int max_out, int *n_out);
 
 /*
+ * Full Stage I search (Sec. 2.4: matched filtering over line widths, FDR control, suppression of
+ * repeated triggers along frequency, local re-evaluation) on a standardised residual cube
+ * snr [n_chan][n_pix][n_pix] (e.g. nbsi_detect's PER_PIXEL or PER_IMAGE SNR output):
+ *   1. S_w[c] = (1/sqrt(w)) sum_{j<w} snr[c - floor(w/2) + j] for every width w of the bank whose
+ *      window lies inside the band; per voxel the largest S and its width (the narrower on ties).
+ *      widths_host NULL selects 1..10, 12..48 step 4, 50..100 step 10 (26 widths); otherwise
+ *      n_widths in [1, NBSI_SEARCH_MAX_WIDTHS] widths in [1, NBSI_SEARCH_MAX_WIDTH].
+ *   2. p = erfc(S / sqrt 2) / 2; Benjamini-Hochberg at level fdr_q in (0, 1) over the
+ *      m = (in-horizon pixels) x n_chan voxels: the k* largest S are provisional detections,
+ *      k* = max{k : p_(k) <= k fdr_q / m}.  The threshold is found among S >= 3: when BH would
+ *      accept every voxel at or above 3 the call returns NBSI_EUNSUPPORTED.
+ *   3. A provisional detection survives when no other one at its pixel within max(floor(w/2), 1)
+ *      channels is higher (a lower channel wins ties), and
+ *   4. when its SNR recomputed against the median and 1.4826 MAD of its flanks (guard w,
+ *      max(16, 2w) channels each side, at least 8 in all) is >= the BH threshold S* (the k*-th
+ *      largest S).
+ * out (device, sorted by (y, x, c)) receives {x, y, c, width, snr = S}; *n_out the survivor count
+ * (NBSI_ETRUNC if above max_out); thresh_host (optional) S*, +inf when nothing is accepted;
+ * n_provisional_host (optional) k*.  best_snr [n_chan][n_pix][n_pix] float32 and best_width
+ * (same shape, uint8) are optional device outputs of step 1 (context scratch when NULL).
+ * Blocks until the result is on the host.
+ */
+#define NBSI_SEARCH_MAX_WIDTHS 32
+#define NBSI_SEARCH_MAX_WIDTH 128
+int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pix, const int32_t *widths_host,
+                int n_widths, double fdr_q, float *best_snr, uint8_t *best_width, nbsi_cand *out,
+                int max_out, int *n_out, float *thresh_host, int64_t *n_provisional_host);
+
+/*
  * Batched sub-bands (Sec. 2.1: the band is processed as independent batches of fine channels;
  * Sec. 2.6: re-processing with other FFT lengths and integrations).  Each sub-band is one coarse
  * channel's voltages with its own FFT length, integration count, kept channels and image size;

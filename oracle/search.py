@@ -16,7 +16,9 @@ width-1 detector: unit-variance noise, spectral median removed):
    p = Q(S) = erfc(S / sqrt 2) / 2.  Benjamini-Hochberg at level q over all m searched voxels
    (in-horizon pixels x channels): k* = max{k : p_(k) <= k q / m}; the voxels with the k*
    smallest p-values (equivalently the k* largest S) are provisional detections; none if no k.
-   The BH decision threshold in SNR units is S* = the k*-th largest S.
+   The BH decision threshold in SNR units is S* = the k*-th largest S.  The step-up search is
+   made among S >= 3 (FLOOR): if BH would accept every voxel at or above the floor the search
+   is reported as unresolved (ValueError), as the GPU library does.
 4. Non-maximum suppression along frequency at each pixel: a provisional detection survives if no
    other provisional detection at that pixel within its exclusion region, of half-width
    max(floor(w/2), 1) channels around its channel, has a higher SNR (on ties the lower channel
@@ -41,6 +43,7 @@ from .detect import MAD_K, horizon_mask, median_even_mean
 
 WIDTHS = tuple(list(range(1, 11)) + list(range(12, 49, 4)) + list(range(50, 101, 10)))
 REEVAL_MIN_FLANK = 8
+FLOOR = 3.0
 
 
 def boxcar_bank(r: np.ndarray, widths=WIDTHS) -> tuple[np.ndarray, np.ndarray]:
@@ -131,7 +134,10 @@ def search(r: np.ndarray, q: float = 0.01, widths=WIDTHS, valid: np.ndarray | No
     S, W = boxcar_bank(r, widths)
     Sv = S[:, valid]
     m = int(valid.sum()) * n_chan
-    kstar, sstar = bh_threshold(Sv.ravel(), m, q)
+    top = Sv[Sv >= FLOOR]
+    kstar, sstar = bh_threshold(top, m, q)
+    if kstar > 0 and kstar == top.size:
+        raise ValueError("the Benjamini-Hochberg threshold reaches the floor")
     flatS, flatW = S.reshape(n_chan, -1), W.reshape(n_chan, -1)
     acc = (flatS >= sstar) & valid.ravel()[None, :]
     surv = nms(flatS, flatW, acc)

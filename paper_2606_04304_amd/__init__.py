@@ -42,8 +42,10 @@ EXPORTS = [
     "nbsi_batch_describe", "nbsi_batch_destroy", "nbsi_stamps", "nbsi_net_create", "nbsi_net_destroy",
     "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
     "nbsi_net_train_step", "nbsi_correlate_kernel", "nbsi_image_plan_pairs", "nbsi_correlate_stokes",
-    "nbsi_image_stokes",
+    "nbsi_image_stokes", "nbsi_search",
 ]
+NBSI_SEARCH_MAX_WIDTHS = 32
+NBSI_SEARCH_MAX_WIDTH = 128
 NBSI_STAMP_CHANNELS = 33
 NBSI_STAMP_PIXELS = 9
 NBSI_NET_NPARAM = 46529
@@ -98,6 +100,8 @@ def lib():
         L.nbsi_image_plan_pairs.argtypes = [P, ctypes.POINTER(I), P]
         L.nbsi_correlate_stokes.argtypes = [P, P, I, I, I, P, P, P]
         L.nbsi_image_stokes.argtypes = [P, P, P, I, P]
+        L.nbsi_search.argtypes = [P, P, I, I, P, I, D, P, P, P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_float),
+                                  ctypes.POINTER(ctypes.c_int64)]
         L.nbsi_detect.argtypes = [P, P, I, I, I, ctypes.c_float, P, P, I, P]
         L.nbsi_batch_plan.argtypes = [P, P, I, P, I, I, I, ctypes.c_char_p, ctypes.POINTER(P)]
         L.nbsi_batch_run.argtypes = [P]
@@ -341,6 +345,37 @@ def nbsi_image_stokes(plan: ImagePlan, stokes_i, precision: int = NBSI_PREC_FP32
     ctx._sync_stream()
     _check(lib().nbsi_image_stokes(ctx._h, plan._h, _ptr(stokes_i), int(precision), _ptr(img)), ctx)
     return img
+
+
+def nbsi_search(snr, fdr_q: float = 0.01, widths=None, max_out: int = 1 << 20, want_cubes: bool = False,
+                ctx: Context | None = None):
+    """Full Stage I search of a standardised residual cube snr [n_chan][n_pix][n_pix] float32:
+    (candidate records sorted by (y, x, c), BH threshold S* (inf if none), provisional count k*,
+    best-SNR cube or None, best-width cube (uint8) or None).  Blocks until done."""
+    torch = _torch()
+    ctx = ctx or nbsi_create(snr.device.index or 0)
+    _need(snr, torch.float32, "snr", ctx.device)
+    n_chan, n_pix, _ = snr.shape
+    S = torch.empty_like(snr) if want_cubes else None
+    W = torch.empty(snr.shape, dtype=torch.uint8, device=ctx.device) if want_cubes else None
+    out = torch.empty((max(1, max_out), 5), dtype=torch.int32, device=ctx.device)
+    wl = None
+    n_w = 0
+    if widths is not None:
+        wl = np.ascontiguousarray(widths, dtype=np.int32)
+        n_w = int(wl.size)
+    n_out = ctypes.c_int()
+    thr = ctypes.c_float()
+    kprov = ctypes.c_int64()
+    ctx._sync_stream()
+    st = lib().nbsi_search(ctx._h, _ptr(snr), n_chan, n_pix, wl.ctypes.data_as(ctypes.c_void_p) if wl is not None else None,
+                           n_w, float(fdr_q), _ptr(S), _ptr(W), _ptr(out), max_out, ctypes.byref(n_out),
+                           ctypes.byref(thr), ctypes.byref(kprov))
+    if st not in (0, NBSI_ETRUNC):
+        _check(st, ctx)
+    n = min(n_out.value, max_out)
+    rec = out[:n].cpu().numpy().copy().view(CAND_DTYPE).reshape(-1)
+    return rec, float(thr.value), int(kprov.value), S, W
 
 
 def nbsi_detect(img, mode: int = NBSI_DETECT_PER_PIXEL, thresh: float = 5.0, want_snr: bool = False,

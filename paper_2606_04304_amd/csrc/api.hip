@@ -15,20 +15,6 @@ namespace {
 
 constexpr double C_LIGHT = 299792458.0;
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 bool is_pow2(long n) { return n > 0 && (n & (n - 1)) == 0; }
 int ilog2(long n) {
     int l = 0;

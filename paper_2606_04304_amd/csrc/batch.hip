@@ -135,7 +135,7 @@ hipError_t enqueue_all(nbsi_batch *b, hipStream_t st) {
                                                b->n_in, st);
                 break;
             case 2:
-                e = launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->n_in, st);
+                e = launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->n_in, L.b != 0, st);
                 break;
             case 3: e = launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, st); break;
             case 4:
@@ -203,9 +203,13 @@ int build_launches(nbsi_batch *b) {
         if (rc) return rc;
         b->launches.push_back(L);
     }
-    // correlate: group by variant
-    std::map<int, std::vector<int>> kg;
-    for (int s = 0; s < b->n_sb; s++) kg[b->corr_variant[s]].push_back(s);
+    // correlate: group by variant (and, for the tiled variant, by whether the spectra rows are
+    // whole 16-byte vectors, which selects the vector-load form of its staging)
+    std::map<std::pair<int, int>, std::vector<int>> kg;
+    for (int s = 0; s < b->n_sb; s++) {
+        const int v = b->corr_variant[s];
+        kg[{v, v == CORR_VARIANT_TILED && (b->sb[s].n_spec & 15) == 0 ? 1 : 0}].push_back(s);
+    }
     for (auto &kv : kg) {
         std::vector<CorrJob> jobs;
         int tasks = 0;
@@ -213,13 +217,14 @@ int build_launches(nbsi_batch *b) {
             const nbsi_subband &x = b->sb[s];
             CorrJob j{x.spec_q, x.vis, b->n_in, x.n_spec, x.n_chan, tasks};
             jobs.push_back(j);
-            tasks += correlate_batch_tasks(j, kv.first);
+            tasks += correlate_batch_tasks(j, kv.first.first);
         }
-        hipError_t e = correlate_batch_prepare(kv.first, b->n_in);
+        hipError_t e = correlate_batch_prepare(kv.first.first, b->n_in);
         if (e != hipSuccess) return NBSI_EHIP;
         nbsi_batch::Launch L;
         L.kind = 2;
-        L.a = kv.first;
+        L.a = kv.first.first;
+        L.b = kv.first.second;
         L.n_jobs = (int)jobs.size();
         L.n_tasks = tasks;
         int rc = upload(b, jobs, (CorrJob **)&L.d_jobs);

@@ -257,6 +257,7 @@ __global__ __launch_bounds__(256, 3) void correlate_i8_kernel(const int8_t *__re
 
 // Several sub-bands in one launch: task -> (job, channel group of 8, tile pair, XCD lane), one
 // workgroup per task, in the same XCD-preserving order as the single-band launch.
+template <bool VEC>
 __global__ __launch_bounds__(256, 3) void correlate_i8_batch_kernel(const CorrJob *__restrict__ jobs, int n_jobs,
                                                                     int n_tasks) {
     __shared__ __attribute__((aligned(16))) int8_t lds[4 * TILE_LDS];
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(256, 3) void correlate_i8_batch_kernel(const CorrJo
     const int pair = rest % n_pairs;
     const int c = (rest / n_pairs) * 8 + xcd;
     if (c < jb.n_chan)
-        correlate_tile<false, false>(jb.q, jb.n_in, jb.n_spec, jb.n_spec, c, pair, jb.vis, lds, StokesOut());
+        correlate_tile<VEC, false>(jb.q, jb.n_in, jb.n_spec, jb.n_spec, c, pair, jb.vis, lds, StokesOut());
 }
 
 // Repack int8 rows of T bytes to a stride of ldy bytes (ldy >= T, a multiple of 16), zero-filled,
@@ -537,10 +538,11 @@ hipError_t correlate_batch_prepare(int variant, int n_in) {
     return variant == CORR_VARIANT_TILED ? hipSuccess : chan_lds_prepare();
 }
 
-hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in,
+hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in, bool vec,
                                   hipStream_t st) {
     if (variant == CORR_VARIANT_TILED) {
-        hipLaunchKernelGGL(correlate_i8_batch_kernel, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+        if (vec) hipLaunchKernelGGL(correlate_i8_batch_kernel<true>, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+        else hipLaunchKernelGGL(correlate_i8_batch_kernel<false>, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
         return hipGetLastError();
     }
     const size_t lds = correlate_chan_lds(n_in, variant);

@@ -15,8 +15,8 @@ struct nbsi_ctx {
     hipStream_t stream = nullptr;
     std::string last_error;
     // grow-only scratch slots, each owned by one stage
-    void *scratch[8] = {nullptr};
-    size_t scratch_size[8] = {0};
+    void *scratch[16] = {nullptr};
+    size_t scratch_size[16] = {0};
     int *d_counter = nullptr;  // small device counters (detector)
 };
 
@@ -29,6 +29,13 @@ enum ScratchSlot {
     SLOT_DET_STATS = 5,     // detector: per-channel / per-pixel statistics
     SLOT_IMG_BL = 6,        // imager: per-channel baseline values
     SLOT_CORR_PAD = 7,      // correlator: spectra repacked to a 16-byte row stride
+    SLOT_SEARCH_S = 8,      // search: best matched-filter SNR per voxel
+    SLOT_SEARCH_W = 9,      // search: its width per voxel
+    SLOT_SEARCH_HIST = 10,  // search: SNR histogram
+    SLOT_SEARCH_VALS = 11,  // search: exact SNRs of one histogram bin
+    SLOT_SEARCH_CAND = 12,  // search: provisional detections
+    SLOT_SEARCH_KEEP = 13,  // search: their keep flags
+    SLOT_SEARCH_SURV = 14,  // search: survivors of the suppression
 };
 
 
@@ -60,6 +67,22 @@ struct nbsi_image_plan {
     unsigned long long *d_tmask = nullptr;
     int *d_tbase = nullptr;
 };
+
+// Makes dev current for the scope (restoring the caller's device on exit).
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 #define NBSI_TRY_HIP(ctx, call)                                                        \
     do {                                                                               \
@@ -120,7 +143,8 @@ struct StokesOut {
 hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
                                     hipStream_t st, StokesOut so = StokesOut(), int8_t *pad_scratch = nullptr);
 size_t correlate_pad_bytes(int n_chan, int n_in, int n_spec);
-hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in,
+// vec: every job's n_spec is a multiple of 16 (the tiled variant then stages whole vectors)
+hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in, bool vec,
                                   hipStream_t st);
 
 // One sub-band's (or channel range's) gridding imager parameters (the job of batched launches).

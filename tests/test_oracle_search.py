@@ -162,3 +162,10 @@ def test_search_finds_injected_line_and_nothing_in_noise():
     others = rec[(rec["x"] != 9) | (rec["y"] != 7)]
     assert len(others) <= max(1, 0.05 * kstar)
     assert (others["snr"] < sstar + 0.5).all()
+
+
+def test_search_reports_threshold_at_the_floor():
+    # every searched voxel far above 3: BH accepts all of them, which the floor cannot resolve
+    r = np.full((64, 8, 8), 4.0)
+    with pytest.raises(ValueError):
+        osr.search(r, q=0.05)
