@@ -451,6 +451,19 @@ def main():
 
     if not args.no_search:
         comp["stage1_search"] = search_leg(args, nb, torch, ctx, dev, C, n_pix)
+    # calibration applied in the correlator epilogue, same spectra, float32 output in place
+    g = torch.Generator(device=dev)
+    g.manual_seed(7003)
+    cal = torch.randn((C, n_in, 2), generator=g, device=dev)
+    vis_f = vis.view(torch.float32)
+    ms_cal = _timed(torch, lambda: nb.nbsi_correlate_cal(spec_q, cal, vis=vis_f, ctx=ctx), max(3, args.steps // 2))
+    ms_plain = _timed(torch, lambda: nb.nbsi_correlate(spec_q, vis=vis, ctx=ctx), max(3, args.steps // 2))
+    cal_bytes = C * (2 * n_in * T) + C * n_in * 8 + C * nprod * 8
+    comp["calibrated_correlator"] = {"ms": round(ms_cal, 4), "plain_ms": round(ms_plain, 4),
+                                     "gbs": round(cal_bytes / (ms_cal * 1e-3) / 1e9, 1),
+                                     "frac_of_hbm": round(cal_bytes / (ms_cal * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"[bench] calibrated correlator {ms_cal:.3f} ms (plain {ms_plain:.3f} ms)")
+    del cal
 
     # ---- plain FP32 path on the same GPU: float spectra, FP32 correlator, float vis ----
     if not args.no_fp32_path:

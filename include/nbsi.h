@@ -129,6 +129,19 @@ int nbsi_correlate(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, in
  * channel) or "correlate_i8_kernel" (128 x 128 tiles). */
 const char *nbsi_correlate_kernel(int n_in, int n_spec);
 
+/*
+ * Correlation with calibration applied in the epilogue (Sec. 2.2: per-antenna complex gains and
+ * bandpass solutions applied before imaging; solving for them is not part of this library):
+ *   vis_cal[c][t(i, j)] = w_i[c] * V_ij[c] * conj(w_j[c]),
+ * with V_ij the exact int32 sum of nbsi_correlate rounded to float32 and the products formed in
+ * float32.  cal [n_chan][n_in][2] float32 (device, 8-byte aligned) holds the complex correction
+ * factors (the inverse of the measured gains, bandpass included) of every input and channel;
+ * vis_cal [n_chan][n_in (n_in + 1) / 2][2] float32, the nbsi_correlate layout, feeds nbsi_image
+ * with NBSI_VIS_F32.  Shapes and errors as nbsi_correlate.
+ */
+int nbsi_correlate_cal(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, int n_spec,
+                       const float *cal, float *vis_cal);
+
 /* The same product from float32 spectra (the plain FP32 path): vis in float32, same layout. */
 int nbsi_correlate_f32(nbsi_ctx *ctx, const float *spec_f, int n_chan, int n_in, int n_spec,
                        float *vis);

@@ -163,6 +163,22 @@ def image_dft_pixels(vis: np.ndarray, ant_xyz, freq, n_pix: int, pix_xy, grid_n_
     return out
 
 
+def calibrate(vis: np.ndarray, cal: np.ndarray) -> np.ndarray:
+    """Apply calibration solutions (Sec. 2.2) to visibilities: vis [n_chan][nprod][2] (packed
+    lower triangle, input i >= j), cal [n_chan][n_in][2] complex correction factors w (the inverse
+    of the measured gains, bandpass included):  V'_ij = w_i V_ij conj(w_j), in float64."""
+    v = np.asarray(vis, dtype=np.float64)
+    w = np.asarray(cal, dtype=np.float64)
+    wc = w[..., 0] + 1j * w[..., 1]                       # [n_chan][n_in]
+    n_in = wc.shape[1]
+    i, j = np.tril_indices(n_in)                          # row-major over i, then j <= i
+    order = np.argsort(tri_index(i, j))
+    i, j = i[order], j[order]
+    vc = v[..., 0] + 1j * v[..., 1]
+    out = wc[:, i] * vc * np.conj(wc[:, j])
+    return np.stack([out.real, out.imag], axis=-1)
+
+
 def tri_index(i, j):
     """Packed lower-triangle index t(i, j) = i(i+1)/2 + j, i >= j."""
     return i * (i + 1) // 2 + j

@@ -42,7 +42,7 @@ EXPORTS = [
     "nbsi_batch_describe", "nbsi_batch_destroy", "nbsi_stamps", "nbsi_net_create", "nbsi_net_destroy",
     "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
     "nbsi_net_train_step", "nbsi_correlate_kernel", "nbsi_image_plan_pairs", "nbsi_correlate_stokes",
-    "nbsi_image_stokes", "nbsi_search",
+    "nbsi_image_stokes", "nbsi_search", "nbsi_correlate_cal",
 ]
 NBSI_SEARCH_MAX_WIDTHS = 32
 NBSI_SEARCH_MAX_WIDTH = 128
@@ -93,6 +93,7 @@ def lib():
         L.nbsi_channelize.argtypes = [P, P, I, I, I, I, I, P, P, P]
         L.nbsi_correlate.argtypes = [P, P, I, I, I, P]
         L.nbsi_correlate_f32.argtypes = [P, P, I, I, I, P]
+        L.nbsi_correlate_cal.argtypes = [P, P, I, I, I, P, P]
         L.nbsi_image_plan_create.argtypes = [P, P, I, P, I, I, I, D, D, ctypes.POINTER(P)]
         L.nbsi_image_plan_destroy.argtypes = [P]
         L.nbsi_image_plan_nbase.argtypes = [P, P]
@@ -213,6 +214,26 @@ def nbsi_correlate(spec_q, vis=None, ctx: Context | None = None):
         vis = torch.empty((n_chan, n_in * (n_in + 1) // 2, 2), dtype=torch.int32, device=ctx.device)
     ctx._sync_stream()
     _check(lib().nbsi_correlate(ctx._h, _ptr(spec_q), n_chan, n_in, n_spec, _ptr(vis)), ctx)
+    return vis
+
+
+def nbsi_correlate_cal(spec_q, cal, vis=None, ctx: Context | None = None):
+    """spec_q int8 + cal [n_chan][n_in][2] float32 correction factors -> calibrated visibilities
+    w_i V_ij conj(w_j) [n_chan][n_in(n_in+1)/2][2] float32."""
+    torch = _torch()
+    ctx = ctx or nbsi_create(spec_q.device.index or 0)
+    _need(spec_q, torch.int8, "spec_q", ctx.device)
+    _need(cal, torch.float32, "cal", ctx.device)
+    n_chan, n_in, two, n_spec = spec_q.shape
+    if tuple(cal.shape) != (n_chan, n_in, 2):
+        raise ValueError(f"cal shape {tuple(cal.shape)} does not match spec_q")
+    if vis is None:
+        vis = torch.empty((n_chan, n_in * (n_in + 1) // 2, 2), dtype=torch.float32, device=ctx.device)
+    _need(vis, torch.float32, "vis", ctx.device)
+    if tuple(vis.shape) != (n_chan, n_in * (n_in + 1) // 2, 2):
+        raise ValueError(f"vis shape {tuple(vis.shape)} does not match spec_q")
+    ctx._sync_stream()
+    _check(lib().nbsi_correlate_cal(ctx._h, _ptr(spec_q), n_chan, n_in, n_spec, _ptr(cal), _ptr(vis)), ctx)
     return vis
 
 

@@ -243,6 +243,24 @@ int nbsi_correlate_stokes(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n
     return NBSI_OK;
 }
 
+int nbsi_correlate_cal(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, int n_spec, const float *cal,
+                       float *vis_cal) {
+    if (!ctx) return NBSI_EINVAL;
+    int rc = nbsi_check_correlate(n_chan, n_in, n_spec);
+    if (rc) return nbsi_fail(ctx, rc, "nbsi_correlate_cal: bad shape");
+    if (!spec_q || !cal || !vis_cal) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_cal: null pointer");
+    if (!aligned16(spec_q) || !aligned16(vis_cal) || ((uintptr_t)cal & 7u))
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_cal: misaligned pointer");
+    DeviceGuard g(ctx->device);
+    void *pad = nullptr;
+    if (const size_t pb = correlate_pad_bytes(n_chan, n_in, n_spec))
+        if ((rc = nbsi_scratch(ctx, SLOT_CORR_PAD, pb, &pad))) return rc;
+    NBSI_TRY_HIP(ctx, launch_correlate_i8(spec_q, n_chan, n_in, n_spec, reinterpret_cast<int32_t *>(vis_cal),
+                                          ctx->stream, StokesOut(), (int8_t *)pad,
+                                          reinterpret_cast<const float2 *>(cal)));
+    return NBSI_OK;
+}
+
 int nbsi_correlate_f32(nbsi_ctx *ctx, const float *spec_f, int n_chan, int n_in, int n_spec, float *vis) {
     if (!ctx) return NBSI_EINVAL;
     int rc = nbsi_check_correlate(n_chan, n_in, n_spec);

@@ -103,6 +103,16 @@ __device__ __forceinline__ BlockStokes block_stokes(const StokesOut &so, int R0,
     return r;
 }
 
+// Calibration applied in the epilogue: w[i - r0] (rows) and w[j - c0] (columns) are LDS copies of
+// channel c's complex correction factors; V'_ij = w_i V_ij conj(w_j) is written as float32 in
+// place of the int32 visibility.  Null: plain int32 output.
+struct CalIn {
+    const float2 *wr = nullptr;
+    int r0 = 0;
+    const float2 *wc = nullptr;
+    int c0 = 0;
+};
+
 // Combine a 32 x 32 tile of G (rows R0.., cols C0.., both even) into visibilities and store;
 // with a Stokes-I output, also (V_XX + V_YY) / 2 of the block's candidate pairs of channel c.
 // Lane l holds input row R0/2 + 4 qq + 2 (l / 32) + (l & 1) and input column C0/2 + (l % 32) / 2,
@@ -111,7 +121,7 @@ __device__ __forceinline__ BlockStokes block_stokes(const StokesOut &so, int R0,
 // block, A % 8 = 2 qq + l / 32 and B % 8 = (l % 32) / 4.
 __device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, int lane, int n_in,
                                                int2 *__restrict__ vc, const StokesOut &so, int c,
-                                               const BlockStokes &bs, bool small_sums) {
+                                               const BlockStokes &bs, bool small_sums, const CalIn &cal) {
     int par[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) par[r] = swap_lanes(a[r]);
@@ -129,7 +139,15 @@ __device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, in
             im = par[4 * qq + 3] - a[4 * qq + 2];
         }
         if (ia < n_in && b <= ia) {
-            vc[(size_t)ia * (ia + 1) / 2 + b] = make_int2(re, im);
+            if (cal.wr) {
+                const float2 wi = cal.wr[ia - cal.r0], wj = cal.wc[b - cal.c0];
+                const float vr = (float)re, vi = (float)im;
+                const float tr = wi.x * vr - wi.y * vi, ti = wi.x * vi + wi.y * vr;  // w_i V
+                const float2 o = make_float2(tr * wj.x + ti * wj.y, ti * wj.x - tr * wj.y);  // * conj(w_j)
+                reinterpret_cast<float2 *>(vc)[(size_t)ia * (ia + 1) / 2 + b] = o;
+            } else {
+                vc[(size_t)ia * (ia + 1) / 2 + b] = make_int2(re, im);
+            }
         }
         if (bs.mask) {
             // quad_perm [3, 3, 3, 3]: every lane of the quad reads lane 3's visibility
@@ -165,10 +183,11 @@ __device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, in
 constexpr int TILE_LDS = TILE_I8 * LDS_STRIDE;
 constexpr int WT = TILE_I8 / 2;  // a wave's share of the tile
 constexpr int MI = WT / 32;      // MFMA tiles per wave per dimension
-template <bool VEC, bool STOKES>
+template <bool VEC, bool STOKES, bool CAL>
 __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int n_in, int T, int ldy, int c,
                                                int pair, int32_t *__restrict__ vis, int8_t *lds,
-                                               const StokesOut &so) {
+                                               const StokesOut &so, const float2 *__restrict__ calw,
+                                               float2 *s_cal) {
     int I, J;
     tile_pair(pair, I, J);
     const int rows = 2 * n_in;
@@ -188,6 +207,14 @@ __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[mi][ni][r] = 0;
 
+    if (CAL) {  // correction factors of the tile's row and column inputs (WT / 2 each)
+        const int in0 = I * (TILE_I8 / 2), jn0 = J * (TILE_I8 / 2);
+        if (t < TILE_I8 / 2) s_cal[t] = in0 + t < n_in ? calw[(size_t)c * n_in + in0 + t] : make_float2(0.f, 0.f);
+        else if (t < TILE_I8) {
+            const int u = t - TILE_I8 / 2;
+            s_cal[t] = jn0 + u < n_in ? calw[(size_t)c * n_in + jn0 + u] : make_float2(0.f, 0.f);
+        }
+    }
     const int n_st = (T + KC - 1) / KC;
     v4i ra[STAGE_VECS], rb[STAGE_VECS];
     load_stage<VEC>(ra, Y, rows, T, ldy, I * TILE_I8, 0, t);
@@ -237,22 +264,26 @@ __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int
             const int C0 = J * TILE_I8 + wc * WT + ni * 32;
             if (R0 < rows && C0 <= R0 + 31) {
                 const BlockStokes bs = STOKES ? block_stokes(so, R0, C0) : BlockStokes();
-                store_tile_i32(acc[mi][ni], R0, C0, lane, n_in, vc, STOKES ? so : StokesOut(), c, bs, T <= 256);
+                CalIn ci;
+                if (CAL) ci = CalIn{s_cal, I * (TILE_I8 / 2), s_cal + TILE_I8 / 2, J * (TILE_I8 / 2)};
+                store_tile_i32(acc[mi][ni], R0, C0, lane, n_in, vc, STOKES ? so : StokesOut(), c, bs, T <= 256, ci);
             }
         }
 }
 
-template <bool VEC, bool STOKES>
+template <bool VEC, bool STOKES, bool CAL>
 __global__ __launch_bounds__(256, 3) void correlate_i8_kernel(const int8_t *__restrict__ q, int n_chan,
                                                               int n_in, int T, int ldy, int n_pairs,
-                                                              int32_t *__restrict__ vis, StokesOut so) {
+                                                              int32_t *__restrict__ vis, StokesOut so,
+                                                              const float2 *__restrict__ calw) {
     __shared__ __attribute__((aligned(16))) int8_t lds[4 * TILE_LDS];
+    __shared__ float2 s_cal[CAL ? TILE_I8 : 1];
     const int id = blockIdx.x;
     const int xcd = id & 7, rest = id >> 3;
     const int pair = rest % n_pairs;
     const int c = (rest / n_pairs) * 8 + xcd;
     if (c >= n_chan) return;
-    correlate_tile<VEC, STOKES>(q, n_in, T, ldy, c, pair, vis, lds, so);
+    correlate_tile<VEC, STOKES, CAL>(q, n_in, T, ldy, c, pair, vis, lds, so, calw, s_cal);
 }
 
 // Several sub-bands in one launch: task -> (job, channel group of 8, tile pair, XCD lane), one
@@ -273,7 +304,8 @@ __global__ __launch_bounds__(256, 3) void correlate_i8_batch_kernel(const CorrJo
     const int pair = rest % n_pairs;
     const int c = (rest / n_pairs) * 8 + xcd;
     if (c < jb.n_chan)
-        correlate_tile<VEC, false>(jb.q, jb.n_in, jb.n_spec, jb.n_spec, c, pair, jb.vis, lds, StokesOut());
+        correlate_tile<VEC, false, false>(jb.q, jb.n_in, jb.n_spec, jb.n_spec, c, pair, jb.vis, lds, StokesOut(),
+                                          nullptr, nullptr);
 }
 
 // Repack int8 rows of T bytes to a stride of ldy bytes (ldy >= T, a multiple of 16), zero-filled,
@@ -303,7 +335,8 @@ __global__ __launch_bounds__(256) void pad_rows_kernel(const int8_t *__restrict_
 constexpr int CHAN_WAVES = 4;
 template <int KP>  // padded K: 32 or 64
 __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, int n_in, int T, int c,
-                                                  int32_t *__restrict__ vis, int8_t *sY, const StokesOut &so) {
+                                                  int32_t *__restrict__ vis, int8_t *sY, const StokesOut &so,
+                                                  const float2 *__restrict__ calw) {
     constexpr int NT = 64 * CHAN_WAVES;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int rows = 2 * n_in;
@@ -322,6 +355,12 @@ __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, 
             const int r = e / KP, k = e % KP;
             sY[e] = (r < rows && k < T) ? Y[(size_t)r * T + k] : (int8_t)0;
         }
+    }
+    CalIn ci;
+    if (calw) {  // channel c's correction factors, after Y in dynamic LDS
+        float2 *sw = reinterpret_cast<float2 *>(sY + rows_pad * KP);
+        for (int e = t; e < n_in; e += NT) sw[e] = calw[(size_t)c * n_in + e];
+        ci = CalIn{sw, 0, sw, 0};
     }
     __syncthreads();
     const size_t nprod = (size_t)n_in * (n_in + 1) / 2;
@@ -348,7 +387,7 @@ __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, 
                 const v4i b = *reinterpret_cast<const v4i *>(sY + (J * 32 + rl) * KP + kk * 32 + koff);
                 acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[kk], b, acc, 0, 0, 0);
             }
-            store_tile_i32(acc, I * 32, J * 32, lane, n_in, vc, so, c, bs, true);  // n_spec <= KP <= 64
+            store_tile_i32(acc, I * 32, J * 32, lane, n_in, vc, so, c, bs, true, ci);  // n_spec <= KP <= 64
         }
     }
 }
@@ -356,9 +395,10 @@ __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, 
 template <int KP>
 __global__ __launch_bounds__(64 * CHAN_WAVES) void correlate_i8_chan_kernel(const int8_t *__restrict__ q, int n_chan,
                                                                             int n_in, int T,
-                                                                            int32_t *__restrict__ vis, StokesOut so) {
-    extern __shared__ __attribute__((aligned(16))) int8_t sY[];  // [rows_pad][KP]
-    correlate_channel<KP>(q, n_in, T, blockIdx.x, vis, sY, so);
+                                                                            int32_t *__restrict__ vis, StokesOut so,
+                                                                            const float2 *__restrict__ calw) {
+    extern __shared__ __attribute__((aligned(16))) int8_t sY[];  // [rows_pad][KP], then [n_in] float2 with calw
+    correlate_channel<KP>(q, n_in, T, blockIdx.x, vis, sY, so, calw);
 }
 
 template <int KP>
@@ -370,7 +410,7 @@ __global__ __launch_bounds__(64 * CHAN_WAVES) void correlate_i8_chan_batch_kerne
     int j = 0;
     while (j + 1 < n_jobs && jobs[j + 1].task0 <= task) j++;
     const CorrJob jb = jobs[j];
-    correlate_channel<KP>(jb.q, jb.n_in, jb.n_spec, task - jb.task0, jb.vis, sY, StokesOut());
+    correlate_channel<KP>(jb.q, jb.n_in, jb.n_spec, task - jb.task0, jb.vis, sY, StokesOut(), nullptr);
 }
 
 // ---- plain FP32 path: the same Gram formulation on v_mfma_f32_32x32x2_f32 ----
@@ -472,9 +512,9 @@ __global__ __launch_bounds__(256) void correlate_f32_kernel(const float *__restr
 }  // namespace
 
 hipError_t launch_correlate_i8(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis,
-                               hipStream_t st, StokesOut so, int8_t *pad_scratch) {
+                               hipStream_t st, StokesOut so, int8_t *pad_scratch, const float2 *calw) {
     return launch_correlate_variant(q, n_chan, n_in, n_spec, vis, correlate_default_variant(n_in, n_spec), st, so,
-                                    pad_scratch);
+                                    pad_scratch, calw);
 }
 
 size_t correlate_pad_bytes(int n_chan, int n_in, int n_spec) {
@@ -557,7 +597,12 @@ hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks
 
 // Single-band launch of one variant (the default path and the autotuner's candidates).
 hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
-                                    hipStream_t st, StokesOut so, int8_t *pad_scratch) {
+                                    hipStream_t st, StokesOut so, int8_t *pad_scratch, const float2 *calw) {
+    // the whole-channel kernels keep the correction factors after Y in LDS; when that does not
+    // fit the tiled kernel (which stages only its tile's factors) takes the channel
+    if (calw && variant != CORR_VARIANT_TILED &&
+        correlate_chan_lds(n_in, variant) + sizeof(float2) * n_in > (size_t)CHAN_LDS_MAX)
+        variant = CORR_VARIANT_TILED;
     if (variant == CORR_VARIANT_TILED) {
         int ldy = n_spec;
         if ((n_spec & 15) && pad_scratch) {
@@ -573,28 +618,30 @@ hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n
         const int n_tiles = (2 * n_in + TILE_I8 - 1) / TILE_I8;
         const int n_pairs = n_tiles * (n_tiles + 1) / 2;
         const size_t groups = (size_t)((n_chan + 7) / 8) * 8 * n_pairs;
-#define NBSI_TILED(V, S)                                                                                    \
-    hipLaunchKernelGGL((correlate_i8_kernel<V, S>), dim3((unsigned)groups), dim3(256), 0, st, q, n_chan, n_in, \
-                       n_spec, ldy, n_pairs, vis, so)
+#define NBSI_TILED(V, S, CL)                                                                                    \
+    hipLaunchKernelGGL((correlate_i8_kernel<V, S, CL>), dim3((unsigned)groups), dim3(256), 0, st, q, n_chan, n_in, \
+                       n_spec, ldy, n_pairs, vis, so, calw)
         if (ldy & 15) {
-            if (so.out) NBSI_TILED(false, true);
-            else NBSI_TILED(false, false);
+            if (calw) NBSI_TILED(false, false, true);
+            else if (so.out) NBSI_TILED(false, true, false);
+            else NBSI_TILED(false, false, false);
         } else {
-            if (so.out) NBSI_TILED(true, true);
-            else NBSI_TILED(true, false);
+            if (calw) NBSI_TILED(true, false, true);
+            else if (so.out) NBSI_TILED(true, true, false);
+            else NBSI_TILED(true, false, false);
         }
 #undef NBSI_TILED
         return hipGetLastError();
     }
-    const size_t lds = correlate_chan_lds(n_in, variant);
+    const size_t lds = correlate_chan_lds(n_in, variant) + (calw ? sizeof(float2) * n_in : 0);
     const hipError_t e = chan_lds_prepare();
     if (e != hipSuccess) return e;
     if (variant == CORR_VARIANT_CHAN32)
         hipLaunchKernelGGL(correlate_i8_chan_kernel<32>, dim3(n_chan), dim3(64 * CHAN_WAVES), lds, st, q, n_chan, n_in,
-                           n_spec, vis, so);
+                           n_spec, vis, so, calw);
     else
         hipLaunchKernelGGL(correlate_i8_chan_kernel<64>, dim3(n_chan), dim3(64 * CHAN_WAVES), lds, st, q, n_chan, n_in,
-                           n_spec, vis, so);
+                           n_spec, vis, so, calw);
     return hipGetLastError();
 }
 

@@ -140,8 +140,11 @@ struct StokesOut {
 };
 // pad_scratch (correlate_pad_bytes bytes, or null for the byte-load fallback) receives the
 // spectra repacked to a 16-byte row stride when the tiled variant gets n_spec % 16 != 0.
+// calw (optional, [n_chan][n_in] complex float): write w_i V_ij conj(w_j) as float32 instead of
+// the int32 visibilities.
 hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
-                                    hipStream_t st, StokesOut so = StokesOut(), int8_t *pad_scratch = nullptr);
+                                    hipStream_t st, StokesOut so = StokesOut(), int8_t *pad_scratch = nullptr,
+                                    const float2 *calw = nullptr);
 size_t correlate_pad_bytes(int n_chan, int n_in, int n_spec);
 // vec: every job's n_spec is a multiple of 16 (the tiled variant then stages whole vectors)
 hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks, int variant, int n_in, bool vec,
@@ -191,7 +194,8 @@ hipError_t launch_corner_turn_q(const int8_t *stage, int n_in, int n_spec, int n
 hipError_t launch_corner_turn_f(const float *stage, int n_in, int n_spec, int n_chan, float *out,
                                 hipStream_t st);
 hipError_t launch_correlate_i8(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis,
-                               hipStream_t st, StokesOut so = StokesOut(), int8_t *pad_scratch = nullptr);
+                               hipStream_t st, StokesOut so = StokesOut(), int8_t *pad_scratch = nullptr,
+                               const float2 *calw = nullptr);
 hipError_t launch_correlate_f32(const float *q, int n_chan, int n_in, int n_spec, float *vis,
                                 hipStream_t st);
 hipError_t launch_image_count(const nbsi_image_plan *p, hipStream_t st);
