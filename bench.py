@@ -311,6 +311,25 @@ def search_leg(args, nb, torch, ctx, dev, C, n_pix):
             "algorithmic_bytes": algo, "gbs": round(algo / (ms * 1e-3) / 1e9, 1)}
 
 
+def dedoppler_leg(args, nb, torch, ctx, dev, C, n_pix):
+    """The drift-rate search at the instrument's cube size: 4 sub-integration residual cubes of
+    4096 x 256^2 (seeded unit white noise), total drifts -16..16 channels."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(7101)
+    sub = torch.randn((4, C, n_pix, n_pix), generator=g, device=dev)
+    best = torch.empty((C, n_pix, n_pix), dtype=torch.float32, device=dev)
+    drift = torch.empty((C, n_pix, n_pix), dtype=torch.int8, device=dev)
+    ms = _timed(torch, lambda: nb.nbsi_dedoppler(sub, 16, best=best, drift=drift, ctx=ctx), max(3, args.steps // 2))
+    vox = C * n_pix * n_pix
+    algo = 4 * vox * 4 + vox * 5  # every sub-integration read once, best SNR and drift written
+    log(f"[bench] de-Doppler (4 sub-integrations, 33 drifts): {ms:.3f} ms")
+    del sub, best, drift
+    torch.cuda.empty_cache()
+    return {"workload": "4 x 4096 x 256^2 sub-integration cubes, drifts -16..16 channels", "ms": round(ms, 3),
+            "track_sums_per_s": round(33 * vox / (ms * 1e-3), 1), "algorithmic_bytes": algo,
+            "gbs": round(algo / (ms * 1e-3) / 1e9, 1), "frac_of_hbm": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -330,7 +349,8 @@ def main():
         c0 = nb.nbsi_create(0)
         print(json.dumps({"deep_correlator": deep_correlator_leg(args, nb, torch, c0, dev, synth),
                           "classifier": classifier_leg(args, nb, torch, c0, dev, synth),
-                          "stage1_search": search_leg(args, nb, torch, c0, dev, 4096, 256)}))
+                          "stage1_search": search_leg(args, nb, torch, c0, dev, 4096, 256),
+                          "dedoppler": dedoppler_leg(args, nb, torch, c0, dev, 4096, 256)}))
         return
     cfg = synth.make_config(2)
     log(f"[bench] generating inputs: {cfg.name}")
@@ -451,6 +471,7 @@ def main():
 
     if not args.no_search:
         comp["stage1_search"] = search_leg(args, nb, torch, ctx, dev, C, n_pix)
+        comp["dedoppler"] = dedoppler_leg(args, nb, torch, ctx, dev, C, n_pix)
     # calibration applied in the correlator epilogue, same spectra, float32 output in place
     g = torch.Generator(device=dev)
     g.manual_seed(7003)

@@ -247,6 +247,24 @@ int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pix, const in
                 int max_out, int *n_out, float *thresh_host, int64_t *n_provisional_host);
 
 /*
+ * Drift-rate search (the paper's Doppler-drift discussion, Sec. 2: a search over drifts of tens
+ * of Hz per dump): snr_sub [n_sub][n_chan][n_pix][n_pix] float32 holds the standardised residual
+ * cubes of n_sub sub-integrations of one dump (each channelised, correlated, imaged and
+ * standardised with this library).  For every total drift d = -max_drift..max_drift channels
+ * over the dump and every start channel c whose track stays in the band (0 <= c + d < n_chan),
+ *   D_d[c] = (1/sqrt(n_sub)) sum_s snr_sub[s][c + shift(d, s)],
+ *   shift(d, s) = round(d s / (n_sub - 1)), halves away from zero (0 when n_sub = 1);
+ * best [n_chan][n_pix][n_pix] float32 receives max_d D_d (-inf where no track fits) and drift
+ * (same shape, int8) its d, trials taken in the order 0, -1, +1, -2, ... (ties keep the first).
+ * 1 <= n_sub <= NBSI_DEDOPPLER_MAX_SUB, 0 <= max_drift <= NBSI_DEDOPPLER_MAX_DRIFT; device
+ * pointers 16-byte aligned.  Asynchronous on the context's stream.
+ */
+#define NBSI_DEDOPPLER_MAX_SUB 8
+#define NBSI_DEDOPPLER_MAX_DRIFT 16
+int nbsi_dedoppler(nbsi_ctx *ctx, const float *snr_sub, int n_sub, int n_chan, int n_pix, int max_drift,
+                   float *best, int8_t *drift);
+
+/*
  * Batched sub-bands (Sec. 2.1: the band is processed as independent batches of fine channels;
  * Sec. 2.6: re-processing with other FFT lengths and integrations).  Each sub-band is one coarse
  * channel's voltages with its own FFT length, integration count, kept channels and image size;

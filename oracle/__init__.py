@@ -187,3 +187,4 @@ def tri_index(i, j):
 from . import detect  # noqa: E402  (numpy detector oracle)
 from . import net  # noqa: E402  (numpy classifier oracle)
 from . import search  # noqa: E402  (numpy full Stage I search oracle)
+from . import drift  # noqa: E402  (numpy drift-rate search oracle)

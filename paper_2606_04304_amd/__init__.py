@@ -42,8 +42,10 @@ EXPORTS = [
     "nbsi_batch_describe", "nbsi_batch_destroy", "nbsi_stamps", "nbsi_net_create", "nbsi_net_destroy",
     "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
     "nbsi_net_train_step", "nbsi_correlate_kernel", "nbsi_image_plan_pairs", "nbsi_correlate_stokes",
-    "nbsi_image_stokes", "nbsi_search", "nbsi_correlate_cal",
+    "nbsi_image_stokes", "nbsi_search", "nbsi_correlate_cal", "nbsi_dedoppler",
 ]
+NBSI_DEDOPPLER_MAX_SUB = 8
+NBSI_DEDOPPLER_MAX_DRIFT = 16
 NBSI_SEARCH_MAX_WIDTHS = 32
 NBSI_SEARCH_MAX_WIDTH = 128
 NBSI_STAMP_CHANNELS = 33
@@ -94,6 +96,7 @@ def lib():
         L.nbsi_correlate.argtypes = [P, P, I, I, I, P]
         L.nbsi_correlate_f32.argtypes = [P, P, I, I, I, P]
         L.nbsi_correlate_cal.argtypes = [P, P, I, I, I, P, P]
+        L.nbsi_dedoppler.argtypes = [P, P, I, I, I, I, P, P]
         L.nbsi_image_plan_create.argtypes = [P, P, I, P, I, I, I, D, D, ctypes.POINTER(P)]
         L.nbsi_image_plan_destroy.argtypes = [P]
         L.nbsi_image_plan_nbase.argtypes = [P, P]
@@ -397,6 +400,27 @@ def nbsi_search(snr, fdr_q: float = 0.01, widths=None, max_out: int = 1 << 20, w
     n = min(n_out.value, max_out)
     rec = out[:n].cpu().numpy().copy().view(CAND_DTYPE).reshape(-1)
     return rec, float(thr.value), int(kprov.value), S, W
+
+
+def nbsi_dedoppler(snr_sub, max_drift: int, best=None, drift=None, ctx: Context | None = None):
+    """snr_sub [n_sub][n_chan][n_pix][n_pix] float32 -> (best de-Dopplered SNR [n_chan][n_pix][n_pix]
+    float32, its total drift in channels int8)."""
+    torch = _torch()
+    ctx = ctx or nbsi_create(snr_sub.device.index or 0)
+    _need(snr_sub, torch.float32, "snr_sub", ctx.device)
+    n_sub, n_chan, n_pix, _ = snr_sub.shape
+    if best is None:
+        best = torch.empty((n_chan, n_pix, n_pix), dtype=torch.float32, device=ctx.device)
+    if drift is None:
+        drift = torch.empty((n_chan, n_pix, n_pix), dtype=torch.int8, device=ctx.device)
+    _need(best, torch.float32, "best", ctx.device)
+    _need(drift, torch.int8, "drift", ctx.device)
+    if tuple(best.shape) != (n_chan, n_pix, n_pix) or tuple(drift.shape) != (n_chan, n_pix, n_pix):
+        raise ValueError("best / drift shape does not match snr_sub")
+    ctx._sync_stream()
+    _check(lib().nbsi_dedoppler(ctx._h, _ptr(snr_sub), n_sub, n_chan, n_pix, int(max_drift), _ptr(best),
+                                _ptr(drift)), ctx)
+    return best, drift
 
 
 def nbsi_detect(img, mode: int = NBSI_DETECT_PER_PIXEL, thresh: float = 5.0, want_snr: bool = False,

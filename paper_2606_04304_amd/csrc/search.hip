@@ -74,10 +74,21 @@ __global__ __launch_bounds__(256) void search_bank_kernel(const float *__restric
     const int base = c0 - SB_HALO_L;  // channel of staged row 0
     for (int i = t; i < HIST_BINS; i += 256) h_lds[i] = 0u;
     // stage rows base .. base + SB_ROWS - 1 (zero outside the band and past the last pixel)
-    for (int e = t; e < SB_ROWS * SB_PX; e += 256) {
-        const int i = e >> 6, l = e & 63;
-        const int ch = base + i, pp = p0 + l;
-        P[(i + 1) * SB_PX + l] = (ch >= 0 && ch < n_chan && pp < npx) ? r[(size_t)ch * npx + pp] : 0.f;
+    // eight independent loads in flight per thread before their LDS stores
+    for (int e0 = t; e0 < SB_ROWS * SB_PX; e0 += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = e0 + 256 * u;
+            const int i = e >> 6, l = e & 63;
+            const int ch = base + i, pp = p0 + l;
+            v[u] = (e < SB_ROWS * SB_PX && ch >= 0 && ch < n_chan && pp < npx) ? r[(size_t)ch * npx + pp] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = e0 + 256 * u;
+            if (e < SB_ROWS * SB_PX) P[((e >> 6) + 1) * SB_PX + (e & 63)] = v[u];
+        }
     }
     if (t < SB_PX) P[t] = 0.f;
     __syncthreads();
