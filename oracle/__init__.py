@@ -188,3 +188,4 @@ from . import detect  # noqa: E402  (numpy detector oracle)
 from . import net  # noqa: E402  (numpy classifier oracle)
 from . import search  # noqa: E402  (numpy full Stage I search oracle)
 from . import drift  # noqa: E402  (numpy drift-rate search oracle)
+from . import stage2  # noqa: E402  (numpy/SciPy Stage II cuts and Gaussian centroid fits)

@@ -404,3 +404,59 @@ def add_sources(vis_f, ant_xyz: np.ndarray, freq: np.ndarray, sources, chunk: in
             for ix in idx:
                 rows = (ch[:, None] * vis_f.shape[1] + ix[None, :]).reshape(-1)
                 flat.index_copy_(0, rows, flat.index_select(0, rows) + upd.reshape(-1, 2))
+
+
+def elliptical_blob(n_pix: int, x0: float, y0: float, amp: float, sigma_maj: float, sigma_min: float,
+                    theta: float) -> np.ndarray:
+    """[n_pix][n_pix] float64 image of an elliptical Gaussian blob: peak amp at (x0, y0) (x =
+    column, y = row), standard deviations sigma_maj along the direction at angle theta from the
+    +x axis (towards +y) and sigma_min across it."""
+    y, x = np.mgrid[0:n_pix, 0:n_pix].astype(np.float64)
+    u = (x - x0) * math.cos(theta) + (y - y0) * math.sin(theta)
+    v = -(x - x0) * math.sin(theta) + (y - y0) * math.cos(theta)
+    return amp * np.exp(-0.5 * (u / sigma_maj) ** 2 - 0.5 * (v / sigma_min) ** 2)
+
+
+@dataclass
+class Blob:
+    c: int
+    x: float
+    y: float
+    amp: float
+    sigma_maj: float
+    sigma_min: float
+    theta: float
+    extended: bool
+
+
+def stage2_scene(rng: np.random.Generator, n_chan: int, n_pix: int, beam_sigma=(1.6, 1.2, 0.5),
+                 n_point: int = 24, n_ext: int = 8, noisy=(), snr=(8.0, 40.0)):
+    """A float32 image cube [n_chan][n_pix][n_pix] of unit white noise (sigma 1; the channels in
+    noisy get sigma 3, or 0.3 for a negative entry -c - 1) with n_point beam-shaped blobs
+    (beam_sigma = (sigma_maj, sigma_min, theta) in pixels and radians) and n_ext blobs 2.5-4
+    times wider, at random sub-pixel positions at least 8 pixels inside the image, peaks
+    snr[0]..snr[1] times the channel noise; blobs keep 12 pixels apart within a channel.
+    Returns (cube, blobs)."""
+    cube = rng.standard_normal((n_chan, n_pix, n_pix))
+    sig = np.ones(n_chan)
+    for c in noisy:
+        if c >= 0:
+            sig[c] = 3.0
+        else:
+            sig[-c - 1] = 0.3
+    cube *= sig[:, None, None]
+    blobs, taken = [], []
+    for k in range(n_point + n_ext):
+        ext = k >= n_point
+        for _ in range(200):
+            c = int(rng.integers(0, n_chan))
+            x, y = rng.uniform(8, n_pix - 9), rng.uniform(8, n_pix - 9)
+            if all(cc != c or math.hypot(x - xx, y - yy) >= 12 for (cc, xx, yy) in taken):
+                break
+        taken.append((c, x, y))
+        f = rng.uniform(2.5, 4.0) if ext else 1.0
+        th = rng.uniform(0, math.pi) if ext else beam_sigma[2]
+        b = Blob(c, x, y, rng.uniform(*snr) * sig[c], beam_sigma[0] * f, beam_sigma[1] * f, th, ext)
+        cube[c] += elliptical_blob(n_pix, b.x, b.y, b.amp, b.sigma_maj, b.sigma_min, b.theta)
+        blobs.append(b)
+    return cube.astype(np.float32), blobs
