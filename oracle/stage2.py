@@ -89,7 +89,7 @@ def fit(cut: np.ndarray, sigma: float):
     xx, yy = _grid(h)
     p0 = initial(cut, sigma)
     res = least_squares(lambda p: (model(p, xx, yy) - cut).ravel(), p0,
-                        jac=lambda p: jacobian(p, xx, yy), method="lm", xtol=1e-13, ftol=1e-13, gtol=1e-13,
+                        jac=lambda p: jacobian(p, xx, yy), method="lm", xtol=1e-15, ftol=1e-15, gtol=1e-15,
                         max_nfev=2000)
     p = res.x
     J = jacobian(p, xx, yy)
