@@ -330,6 +330,42 @@ def dedoppler_leg(args, nb, torch, ctx, dev, C, n_pix):
             "gbs": round(algo / (ms * 1e-3) / 1e9, 1), "frac_of_hbm": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def stage2_leg(args, nb, torch, ctx, dev, C, n_pix, n_cand=4096):
+    """Stage II cuts at the instrument's cube size: 4096 x 256^2 unit white noise with n_cand
+    beam-shaped (sigma 1.6 x 1.2 px) blobs at seeded sub-pixel positions, a quarter of them 3x
+    wider; every blob is a candidate (9 x 9 cutout fits, noise statistics of every channel)."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(7201)
+    cube = torch.randn((C, n_pix, n_pix), generator=g, device=dev)
+    rng = np.random.default_rng(7202)
+    xs = rng.integers(8, n_pix - 8, n_cand)
+    ys = rng.integers(8, n_pix - 8, n_cand)
+    cs = rng.integers(0, C, n_cand)
+    off = rng.uniform(-0.5, 0.5, (n_cand, 2))
+    yy, xx = torch.meshgrid(torch.arange(-5, 6, device=dev, dtype=torch.float64),
+                            torch.arange(-5, 6, device=dev, dtype=torch.float64), indexing="ij")
+    K = 2.0 * math.sqrt(2.0 * math.log(2.0))
+    for i in range(n_cand):
+        f = 3.0 if i % 4 == 3 else 1.0
+        u, v = xx - off[i, 0], yy - off[i, 1]
+        ct, st = math.cos(0.5), math.sin(0.5)
+        a, b = (u * ct + v * st) / (1.6 * f), (-u * st + v * ct) / (1.2 * f)
+        amp = 8.0 + 32.0 * ((i * 0.6180339887) % 1.0)
+        cube[cs[i], ys[i] - 5:ys[i] + 6, xs[i] - 5:xs[i] + 6] += (amp * torch.exp(-0.5 * (a * a + b * b))).float()
+    cands = torch.from_numpy(np.stack([xs, ys, cs, np.ones(n_cand), np.zeros(n_cand)], 1).astype(np.int32)).to(dev)
+    beam = torch.tensor([[K * 1.6, K * 1.2, 0.5]] * C, dtype=torch.float64, device=dev)
+    out = torch.empty((n_cand, 160), dtype=torch.uint8, device=dev)
+    ms = _timed(torch, lambda: nb.nbsi_stage2(cube, cands, beam, out=out, ctx=ctx), max(3, args.steps // 2))
+    rec = nb.fits_host(out, n_cand)
+    kept = int((rec["flags"] == 0).sum())
+    log(f"[bench] Stage II ({n_cand} candidates): {ms:.3f} ms, kept {kept}")
+    del cube
+    torch.cuda.empty_cache()
+    return {"workload": f"{C} x {n_pix}^2 cube, {n_cand} candidates (9 x 9 Gaussian fits, FP64)", "ms": round(ms, 3),
+            "candidates_per_s": round(n_cand / (ms * 1e-3), 1), "kept": kept,
+            "median_iterations": float(np.median(rec["n_iter"])), "max_iterations": int(rec["n_iter"].max())}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -350,7 +386,8 @@ def main():
         print(json.dumps({"deep_correlator": deep_correlator_leg(args, nb, torch, c0, dev, synth),
                           "classifier": classifier_leg(args, nb, torch, c0, dev, synth),
                           "stage1_search": search_leg(args, nb, torch, c0, dev, 4096, 256),
-                          "dedoppler": dedoppler_leg(args, nb, torch, c0, dev, 4096, 256)}))
+                          "dedoppler": dedoppler_leg(args, nb, torch, c0, dev, 4096, 256),
+                          "stage2": stage2_leg(args, nb, torch, c0, dev, 4096, 256)}))
         return
     cfg = synth.make_config(2)
     log(f"[bench] generating inputs: {cfg.name}")
@@ -472,6 +509,7 @@ def main():
     if not args.no_search:
         comp["stage1_search"] = search_leg(args, nb, torch, ctx, dev, C, n_pix)
         comp["dedoppler"] = dedoppler_leg(args, nb, torch, ctx, dev, C, n_pix)
+        comp["stage2"] = stage2_leg(args, nb, torch, ctx, dev, C, n_pix)
     # calibration applied in the correlator epilogue, same spectra, float32 output in place
     g = torch.Generator(device=dev)
     g.manual_seed(7003)

@@ -265,6 +265,52 @@ int nbsi_dedoppler(nbsi_ctx *ctx, const float *snr_sub, int n_sub, int n_chan, i
                    float *best, int8_t *drift);
 
 /*
+ * Stage II automated cuts (Sec. 2.4: candidates consistent with narrowband point sources are
+ * kept; extended morphology is rejected, images with deviant noise are flagged; positions come
+ * from Gaussian centroid fits whose covariance errors are rescaled by sqrt(reduced chi-square)).
+ *
+ * Fit of one cutout: the (2 half + 1)^2 pixels of the candidate's channel image centred on its
+ * pixel, model f = bkg + amp exp(-Q/2), Q = a dx^2 + 2 b dx dy + c dy^2 with dx, dy measured from
+ * the centroid (x0, y0), least squares with unit weights (Levenberg-Marquardt in FP64, started
+ * from amp = centre - bkg, the pixel itself, a = c = 1/sigma^2 with sigma = the beam's major
+ * FWHM / 2 sqrt(2 ln 2), or 1 pixel without a beam, b = 0, bkg = median of the border pixels).
+ * err[i] = sqrt(((J^T J)^-1)_ii RSS / (n - 7)), n the pixel count; chi2_red = RSS / (sigma_c^2
+ * (n - 7)) with sigma_c the channel image's 1.4826 MAD over the visible hemisphere.  FWHM of the
+ * principal axes 2 sqrt(2 ln 2) / sqrt(eigenvalue of [[a, b], [b, c]]) in pixels; pa: angle of
+ * the major axis from +x towards +y, radians in [0, pi).
+ */
+#define NBSI_S2_FIT_FAILED 1 /* amp <= 0, Q not positive definite, or singular normal matrix */
+#define NBSI_S2_EXTENDED 2   /* major or minor FWHM above ext_factor times the beam's */
+#define NBSI_S2_NOISY 4      /* sigma_c outside [m / noise_k, noise_k m], m = median of sigma_c */
+#define NBSI_S2_OUTSIDE 8    /* cutout not inside the image, or channel outside the cube */
+#define NBSI_S2_MAX_HALF 5
+#define NBSI_S2_MAX_CANDS (1 << 22)
+#define NBSI_BEAM_HALF 2
+typedef struct {
+    double amp, x0, y0, a, b, c, bkg; /* x0, y0 in image pixels (x = column, y = row) */
+    double err[7];                    /* 1-sigma errors, same order */
+    double fwhm_maj, fwhm_min, pa;
+    double rss, chi2_red;
+    int32_t flags; /* NBSI_S2_* bits; 0 = kept */
+    int32_t n_iter;
+} nbsi_fit;
+
+/* Synthesized beam of every channel of a plan: the image of unit Stokes-I visibilities on the
+ * plan's baselines (its point-spread function, same imager and uv cuts) fitted as above with
+ * half = NBSI_BEAM_HALF at the image centre.  beam: device double [n_chan][3] (FWHM major,
+ * minor in pixels, pa; NaN if the fit fails), 8-byte aligned.  Asynchronous on the context's
+ * stream; uses context scratch for one imager chunk of the point-spread function. */
+int nbsi_beam(nbsi_ctx *ctx, const nbsi_image_plan *plan, double *beam);
+
+/* Stage II over candidates on an image cube img [n_chan][n_pix][n_pix] float32 (device,
+ * 16-byte aligned; shape limits of nbsi_detect): cands [n_cand] device nbsi_cand (x, y, c used),
+ * beam device double [n_chan][3] (e.g. from nbsi_beam), 2 <= half <= NBSI_S2_MAX_HALF,
+ * ext_factor > 0, noise_k >= 1, 0 <= n_cand <= NBSI_S2_MAX_CANDS; out [n_cand] device nbsi_fit
+ * (fields NaN where no fit was made).  Asynchronous on the context's stream. */
+int nbsi_stage2(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, const nbsi_cand *cands, int n_cand,
+                const double *beam, int half, double ext_factor, double noise_k, nbsi_fit *out);
+
+/*
  * Batched sub-bands (Sec. 2.1: the band is processed as independent batches of fine channels;
  * Sec. 2.6: re-processing with other FFT lengths and integrations).  Each sub-band is one coarse
  * channel's voltages with its own FFT length, integration count, kept channels and image size;

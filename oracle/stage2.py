@@ -21,7 +21,7 @@ errors from the fit covariance rescaled by sqrt(reduced chi-square).  Readings u
 * Cuts (flags): fit failed (no positive-definite Q or A <= 0) 1; extended, either FWHM above
   ext_factor (1.5) times the beam's 2; the channel's image noise (1.4826 MAD over the visible
   hemisphere) outside [median / k, k * median] over channels, k = 1.5, 4; cutout not inside the
-  image 8.  A candidate is kept when no flag is set.
+  image (or channel outside the cube, then alone) 8.  A candidate is kept when no flag is set.
 """
 from __future__ import annotations
 
@@ -139,6 +139,9 @@ def stage2(img: np.ndarray, cands, beam_fwhm, ext_factor: float = EXT_FACTOR, no
     out = []
     for r in cands:
         x, y, c = int(r["x"]), int(r["y"]), int(r["c"])
+        if not 0 <= c < n_chan:                     # no such channel: only the outside flag
+            out.append({"flags": EDGE, "fit": None})
+            continue
         bmaj, bmin = float(bm[c, 0]), float(bm[c, 1])
         sigma0 = bmaj / FWHM_PER_SIGMA if math.isfinite(bmaj) and bmaj > 0 else 1.0
         flags = 0

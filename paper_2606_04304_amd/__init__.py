@@ -42,10 +42,14 @@ EXPORTS = [
     "nbsi_batch_describe", "nbsi_batch_destroy", "nbsi_stamps", "nbsi_net_create", "nbsi_net_destroy",
     "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
     "nbsi_net_train_step", "nbsi_correlate_kernel", "nbsi_image_plan_pairs", "nbsi_correlate_stokes",
-    "nbsi_image_stokes", "nbsi_search", "nbsi_correlate_cal", "nbsi_dedoppler",
+    "nbsi_image_stokes", "nbsi_search", "nbsi_correlate_cal", "nbsi_dedoppler", "nbsi_beam", "nbsi_stage2",
 ]
 NBSI_DEDOPPLER_MAX_SUB = 8
 NBSI_DEDOPPLER_MAX_DRIFT = 16
+NBSI_S2_FIT_FAILED, NBSI_S2_EXTENDED, NBSI_S2_NOISY, NBSI_S2_OUTSIDE = 1, 2, 4, 8
+NBSI_S2_MAX_HALF = 5
+NBSI_S2_MAX_CANDS = 1 << 22
+NBSI_BEAM_HALF = 2
 NBSI_SEARCH_MAX_WIDTHS = 32
 NBSI_SEARCH_MAX_WIDTH = 128
 NBSI_STAMP_CHANNELS = 33
@@ -58,6 +62,12 @@ NBSI_BATCH_GRID_TALL = 4
 
 CAND_DTYPE = np.dtype([("x", np.int32), ("y", np.int32), ("c", np.int32), ("width", np.int32),
                        ("snr", np.float32)])
+# nbsi_fit (160 bytes)
+FIT_DTYPE = np.dtype([("amp", np.float64), ("x0", np.float64), ("y0", np.float64), ("a", np.float64),
+                      ("b", np.float64), ("c", np.float64), ("bkg", np.float64), ("err", np.float64, (7,)),
+                      ("fwhm_maj", np.float64), ("fwhm_min", np.float64), ("pa", np.float64),
+                      ("rss", np.float64), ("chi2_red", np.float64), ("flags", np.int32), ("n_iter", np.int32)])
+assert FIT_DTYPE.itemsize == 160
 
 
 class NbsiError(RuntimeError):
@@ -97,6 +107,8 @@ def lib():
         L.nbsi_correlate_f32.argtypes = [P, P, I, I, I, P]
         L.nbsi_correlate_cal.argtypes = [P, P, I, I, I, P, P]
         L.nbsi_dedoppler.argtypes = [P, P, I, I, I, I, P, P]
+        L.nbsi_beam.argtypes = [P, P, P]
+        L.nbsi_stage2.argtypes = [P, P, I, I, P, I, P, I, D, D, P]
         L.nbsi_image_plan_create.argtypes = [P, P, I, P, I, I, I, D, D, ctypes.POINTER(P)]
         L.nbsi_image_plan_destroy.argtypes = [P]
         L.nbsi_image_plan_nbase.argtypes = [P, P]
@@ -421,6 +433,53 @@ def nbsi_dedoppler(snr_sub, max_drift: int, best=None, drift=None, ctx: Context 
     _check(lib().nbsi_dedoppler(ctx._h, _ptr(snr_sub), n_sub, n_chan, n_pix, int(max_drift), _ptr(best),
                                 _ptr(drift)), ctx)
     return best, drift
+
+
+def nbsi_beam(plan: "ImagePlan", beam=None):
+    """Synthesized beam per channel of a plan: float64 device tensor [n_chan][3] (FWHM major,
+    minor in pixels, position angle in radians)."""
+    torch = _torch()
+    ctx = plan.ctx
+    if beam is None:
+        beam = torch.empty((plan.n_chan, 3), dtype=torch.float64, device=ctx.device)
+    _need(beam, torch.float64, "beam", ctx.device)
+    if tuple(beam.shape) != (plan.n_chan, 3):
+        raise ValueError("beam must be [n_chan][3]")
+    ctx._sync_stream()
+    _check(lib().nbsi_beam(ctx._h, plan._h, _ptr(beam)), ctx)
+    return beam
+
+
+def nbsi_stage2(img, cands, beam, half: int = 4, ext_factor: float = 1.5, noise_k: float = 1.5, out=None,
+                ctx: Context | None = None):
+    """Stage II fits and flags: img [n_chan][n_pix][n_pix] float32, cands int32 device tensor
+    [n][5] (nbsi_cand records), beam float64 [n_chan][3] -> uint8 device tensor [n][160] of
+    nbsi_fit records (view on the host with FIT_DTYPE)."""
+    torch = _torch()
+    ctx = ctx or nbsi_create(img.device.index or 0)
+    _need(img, torch.float32, "img", ctx.device)
+    _need(cands, torch.int32, "cands", ctx.device)
+    _need(beam, torch.float64, "beam", ctx.device)
+    n_chan, n_pix, _ = img.shape
+    if cands.dim() != 2 or cands.shape[1] != 5:
+        raise ValueError("cands must be [n][5] int32 (nbsi_cand records)")
+    if tuple(beam.shape) != (n_chan, 3):
+        raise ValueError("beam must be [n_chan][3]")
+    n = cands.shape[0]
+    if out is None:
+        out = torch.empty((max(1, n), FIT_DTYPE.itemsize), dtype=torch.uint8, device=ctx.device)
+    _need(out, torch.uint8, "out", ctx.device)
+    if out.numel() < n * FIT_DTYPE.itemsize:
+        raise ValueError("out too small")
+    ctx._sync_stream()
+    _check(lib().nbsi_stage2(ctx._h, _ptr(img), n_chan, n_pix, _ptr(cands), n, _ptr(beam), int(half),
+                             float(ext_factor), float(noise_k), _ptr(out)), ctx)
+    return out
+
+
+def fits_host(out, n: int) -> np.ndarray:
+    """nbsi_fit records of a device buffer as a numpy structured array."""
+    return out.reshape(-1)[:n * FIT_DTYPE.itemsize].cpu().numpy().copy().view(FIT_DTYPE).reshape(-1)
 
 
 def nbsi_detect(img, mode: int = NBSI_DETECT_PER_PIXEL, thresh: float = 5.0, want_snr: bool = False,

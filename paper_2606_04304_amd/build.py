@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnbsi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "batch.hip", "channelize.hip", "correlate.hip", "image.hip", "detect.hip", "net.hip", "search.hip", "drift.hip"]
+SOURCES = ["api.hip", "batch.hip", "channelize.hip", "correlate.hip", "image.hip", "detect.hip", "net.hip", "search.hip", "drift.hip", "stage2.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -36,6 +36,7 @@ enum ScratchSlot {
     SLOT_SEARCH_CAND = 12,  // search: provisional detections
     SLOT_SEARCH_KEEP = 13,  // search: their keep flags
     SLOT_SEARCH_SURV = 14,  // search: survivors of the suppression
+    SLOT_S2_PSF = 15,       // Stage II: unit visibilities and point-spread-function images
 };
 
 
