@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-deep", action="store_true", help="skip the long-integration correlator leg")
     ap.add_argument("--no-classifier", action="store_true", help="skip the classifier leg")
     ap.add_argument("--no-search", action="store_true", help="skip the full Stage I search leg")
+    ap.add_argument("--step-only", action="store_true",
+                    help="profiling aid: only the timed step (no legs, no FP32 path, no batch)")
     ap.add_argument("--legs-only", action="store_true",
                     help="profiling aid: run only the long-integration correlator, classifier and search legs")
     ap.add_argument("--stages", default="all", help="profiling aid: all | correlate")
@@ -330,6 +332,22 @@ def dedoppler_leg(args, nb, torch, ctx, dev, C, n_pix):
             "gbs": round(algo / (ms * 1e-3) / 1e9, 1), "frac_of_hbm": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def calibrated_leg(args, nb, torch, ctx, dev, spec_q, vis, C, n_in, T, nprod):
+    """Calibration applied in the correlator epilogue on the step's spectra (complex factors per
+    input and channel, float32 output in place of the int32 visibilities), against the plain call."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(7003)
+    cal = torch.randn((C, n_in, 2), generator=g, device=dev)
+    vis_f = vis.view(torch.float32)
+    ms_cal = _timed(torch, lambda: nb.nbsi_correlate_cal(spec_q, cal, vis=vis_f, ctx=ctx), max(3, args.steps // 2))
+    ms_plain = _timed(torch, lambda: nb.nbsi_correlate(spec_q, vis=vis, ctx=ctx), max(3, args.steps // 2))
+    cal_bytes = C * (2 * n_in * T) + C * n_in * 8 + C * nprod * 8
+    log(f"[bench] calibrated correlator {ms_cal:.3f} ms (plain {ms_plain:.3f} ms)")
+    return {"ms": round(ms_cal, 4), "plain_ms": round(ms_plain, 4),
+            "gbs": round(cal_bytes / (ms_cal * 1e-3) / 1e9, 1),
+            "frac_of_hbm": round(cal_bytes / (ms_cal * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def stage2_leg(args, nb, torch, ctx, dev, C, n_pix, n_cand=4096):
     """Stage II cuts at the instrument's cube size: 4096 x 256^2 unit white noise with n_cand
     beam-shaped (sigma 1.6 x 1.2 px) blobs at seeded sub-pixel positions, a quarter of them 3x
@@ -506,23 +524,14 @@ def main():
         "stage_hbm_roofline": stage_roof,
     }
 
+    if args.step_only:
+        args.no_search = args.no_fp32_path = args.no_batch = args.no_deep = args.no_classifier = True
     if not args.no_search:
         comp["stage1_search"] = search_leg(args, nb, torch, ctx, dev, C, n_pix)
         comp["dedoppler"] = dedoppler_leg(args, nb, torch, ctx, dev, C, n_pix)
         comp["stage2"] = stage2_leg(args, nb, torch, ctx, dev, C, n_pix)
-    # calibration applied in the correlator epilogue, same spectra, float32 output in place
-    g = torch.Generator(device=dev)
-    g.manual_seed(7003)
-    cal = torch.randn((C, n_in, 2), generator=g, device=dev)
-    vis_f = vis.view(torch.float32)
-    ms_cal = _timed(torch, lambda: nb.nbsi_correlate_cal(spec_q, cal, vis=vis_f, ctx=ctx), max(3, args.steps // 2))
-    ms_plain = _timed(torch, lambda: nb.nbsi_correlate(spec_q, vis=vis, ctx=ctx), max(3, args.steps // 2))
-    cal_bytes = C * (2 * n_in * T) + C * n_in * 8 + C * nprod * 8
-    comp["calibrated_correlator"] = {"ms": round(ms_cal, 4), "plain_ms": round(ms_plain, 4),
-                                     "gbs": round(cal_bytes / (ms_cal * 1e-3) / 1e9, 1),
-                                     "frac_of_hbm": round(cal_bytes / (ms_cal * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    log(f"[bench] calibrated correlator {ms_cal:.3f} ms (plain {ms_plain:.3f} ms)")
-    del cal
+    if not args.step_only:
+        comp["calibrated_correlator"] = calibrated_leg(args, nb, torch, ctx, dev, spec_q, vis, C, n_in, T, nprod)
 
     # ---- plain FP32 path on the same GPU: float spectra, FP32 correlator, float vis ----
     if not args.no_fp32_path:
