@@ -9,7 +9,7 @@
 // global atomic counter and sorted afterwards by (y, x, c) with a bitonic network.
 //
 // Per-image mode first computes each channel image's median and MAD over the visible
-// hemisphere (a histogram selection over the image in global memory, one wave per channel),
+// hemisphere (a histogram selection over the image in global memory, one block per channel),
 // then runs the per-pixel kernel on the standardised values with only the spectral median
 // removed.
 #include "internal.h"
@@ -63,149 +63,158 @@ __device__ __forceinline__ int value_bin(float x, float lo, float scale) {
     return t >= 256.f ? 255 : (t > 0.f ? (int)t : 0);
 }
 
-// The rank-th smallest (0-based) of val(i), i < n, for one wave (exact order statistic).
-// NaN values are ignored (they never fall inside a range), so callers can mask entries out.
-// Values are binned by value over the current range [lo, hi] into 256 LDS counters; the bin
-// index is a non-decreasing function of the value, so the bin holding the rank-th value is
-// found from the cumulative counts, and the range shrinks to that bin's own min and max until
-// at most 64 values remain, which are ranked directly.  `hist` is this wave's 256 counters and
-// `pool` its 64 floats of LDS; every wave of the block makes the same calls (uniform barriers).
-template <typename ValFn>
-__device__ float wave_kth(ValFn val, int n, int rank, unsigned *hist, float *pool, int lane) {
-    float lo = INFINITY, hi = -INFINITY;
-    for (int i = lane; i < n; i += 64) {
-        const float x = val(i);
-        lo = fminf(lo, x);
-        hi = fmaxf(hi, x);
-    }
-    lo = wave_min_f(lo);
-    hi = wave_max_f(hi);
-    int k = rank;
-    float result = lo;
-    bool done = false;
-    for (int iter = 0; iter < 40; iter++) {
-        // counts of in-range values (ties at the bounds included)
-        int cnt_in = 0;
-        if (!done) {
-            if (!(hi > lo)) {
-                result = lo;
-                done = true;
-            }
-        }
-        // the loop structure (and its barriers) is identical in every wave
-        const float scale = done ? 0.f : 256.f / (hi - lo);
+// Block-wide sum / min / max over SEL_NT threads through `red` (SEL_NT / 64 slots of LDS); every
+// thread gets the result.  Callers keep the calls uniform across the block.
+constexpr int SEL_NT = 1024;
+constexpr int SEL_NW = SEL_NT / 64;
+constexpr int SEL_POOL = 1024;
+
+__device__ __forceinline__ int block_sum(int v, int *red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    int s = 0;
 #pragma unroll
-        for (int b = 0; b < 4; b++) hist[lane * 4 + b] = 0;
-        __syncthreads();
-        if (!done) {
-            for (int i = lane; i < n; i += 64) {
-                const float x = val(i);
-                if (x >= lo && x <= hi) atomicAdd(&hist[value_bin(x, lo, scale)], 1u);
-            }
-        }
-        __syncthreads();
-        int c4[4], s4 = 0;
+    for (int q = 0; q < SEL_NW; q++) s += red[q];
+    return s;
+}
+__device__ __forceinline__ float block_min_f(float v, float *red) {
+    v = wave_min_f(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    float s = INFINITY;
 #pragma unroll
-        for (int b = 0; b < 4; b++) {
-            c4[b] = (int)hist[lane * 4 + b];
-            s4 += c4[b];
-        }
-        const int incl = wave_inclusive_scan(s4, lane);
-        const int excl = incl - s4;
-        int bsel = 0, below = 0;
-        const bool mine = !done && (excl <= k) && (k < incl);
-        if (mine) {
-            int run = excl;
+    for (int q = 0; q < SEL_NW; q++) s = fminf(s, red[q]);
+    return s;
+}
+__device__ __forceinline__ float block_max_f(float v, float *red) {
+    v = wave_max_f(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    float s = -INFINITY;
 #pragma unroll
-            for (int b = 0; b < 4; b++) {
-                if (k >= run && k < run + c4[b]) {
-                    bsel = lane * 4 + b;
-                    below = run;
-                    cnt_in = c4[b];
-                }
-                run += c4[b];
-            }
-        }
-        const unsigned long long ball = __ballot(mine);
-        const int src = ball ? (int)(__ffsll((long long)ball) - 1) : 0;
-        bsel = __shfl(bsel, src, 64);
-        below = __shfl(below, src, 64);
-        cnt_in = __shfl(cnt_in, src, 64);
-        // min / max of the selected bin, and (when small) its values into the pool
-        float nlo = INFINITY, nhi = -INFINITY;
-        int slot_base = 0;
-        if (!done) {
-            for (int i0 = 0; i0 < n; i0 += 64) {
-                const int i = i0 + lane;
-                bool in = false;
-                float x = 0.f;
-                if (i < n) {
-                    x = val(i);
-                    in = x >= lo && x <= hi && value_bin(x, lo, scale) == bsel;
-                }
-                if (in) {
-                    nlo = fminf(nlo, x);
-                    nhi = fmaxf(nhi, x);
-                }
-                if (cnt_in <= 64) {
-                    const unsigned long long bm = __ballot(in);
-                    if (in) pool[slot_base + __popcll(bm & ((1ull << lane) - 1ull))] = x;
-                    slot_base += __popcll(bm);
-                }
-            }
-            nlo = wave_min_f(nlo);
-            nhi = wave_max_f(nhi);
-        }
-        __syncthreads();
-        if (!done) {
-            k -= below;
-            if (cnt_in <= 64) {
-                // exact rank within the pool
-                float mine_v = 0.f;
-                bool hit = false;
-                if (lane < cnt_in) {
-                    mine_v = pool[lane];
-                    int less = 0, eq = 0;
-                    for (int j = 0; j < cnt_in; j++) {
-                        const float y = pool[j];
-                        less += y < mine_v;
-                        eq += y == mine_v;
-                    }
-                    hit = (less <= k) && (k < less + eq);
-                }
-                const unsigned long long hb = __ballot(hit);
-                const int hsrc = hb ? (int)(__ffsll((long long)hb) - 1) : 0;
-                result = __shfl(mine_v, hsrc, 64);
-                done = true;
-            } else {
-                lo = nlo;
-                hi = nhi;
-            }
-        }
-        __syncthreads();
-        // all waves leave together once every wave is done
-        if (__syncthreads_and(done ? 1 : 0)) break;
-    }
-    return result;
+    for (int q = 0; q < SEL_NW; q++) s = fmaxf(s, red[q]);
+    return s;
 }
 
-// Median of the n_valid non-NaN values among val(i), i < n (mean of the central pair for even
+// LDS of one block selection
+struct SelLds {
+    unsigned hist[4][256];  // four copies (by wave % 4) against atomic contention
+    int cnt[256];           // bin totals
+    float pool[SEL_POOL];
+    int ired[SEL_NW];
+    float fred[SEL_NW];
+    int sel[4];             // selected bin, values below it, values in it, pool fill
+    float res;              // the selected value
+};
+
+// The rank-th smallest (0-based) of the values a block of SEL_NT threads enumerates (each(f)
+// calls f on every value the calling thread owns; exact order statistic).  Values are binned by value over the current range [lo, hi] into 256 LDS
+// counters; the bin index is a non-decreasing function of the value, so the bin holding the
+// rank-th value is found from the cumulative counts, and the range shrinks to that bin's own
+// min and max until at most SEL_POOL values remain, which are ranked directly.
+template <typename Each>
+__device__ __forceinline__ float block_kth(Each each, int rank, SelLds &L) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    float lo = INFINITY, hi = -INFINITY;
+    each([&](float x) __attribute__((always_inline)) {
+        lo = fminf(lo, x);
+        hi = fmaxf(hi, x);
+    });
+    lo = block_min_f(lo, L.fred);
+    hi = block_max_f(hi, L.fred);
+    int k = rank;
+    for (int iter = 0; iter < 40; iter++) {
+        if (!(hi > lo)) return lo;  // uniform: one value left in range
+        const float scale = 256.f / (hi - lo);
+        for (int e = t; e < 4 * 256; e += SEL_NT) (&L.hist[0][0])[e] = 0;
+        __syncthreads();
+        each([&](float x) __attribute__((always_inline)) {
+            if (x >= lo && x <= hi) atomicAdd(&L.hist[w & 3][value_bin(x, lo, scale)], 1u);
+        });
+        __syncthreads();
+        if (t < 256) L.cnt[t] = (int)(L.hist[0][t] + L.hist[1][t] + L.hist[2][t] + L.hist[3][t]);
+        __syncthreads();
+        // the bin holding rank k: threads 0..255 own one bin each (waves 0..3)
+        if (t < 256) {
+            const int cnt = L.cnt[t];
+            const int incl = wave_inclusive_scan(cnt, lane);
+            if (lane == 63) L.ired[w] = incl;
+            L.pool[t] = __int_as_float(cnt);  // park the count until the wave totals are known
+            L.pool[256 + t] = __int_as_float(incl);
+        }
+        __syncthreads();
+        if (t < 256) {
+            int base = 0;
+            for (int q = 0; q < w; q++) base += L.ired[q];
+            const int cnt = __float_as_int(L.pool[t]);
+            const int incl = base + __float_as_int(L.pool[256 + t]);
+            if (incl - cnt <= k && k < incl) {
+                L.sel[0] = t;
+                L.sel[1] = incl - cnt;
+                L.sel[2] = cnt;
+            }
+        }
+        if (t == 0) L.sel[3] = 0;
+        __syncthreads();
+        const int bsel = L.sel[0], below = L.sel[1], cnt_in = L.sel[2];
+        // min / max of the selected bin, and (when small) its values into the pool
+        float nlo = INFINITY, nhi = -INFINITY;
+        each([&](float x) __attribute__((always_inline)) {
+            if (x >= lo && x <= hi && value_bin(x, lo, scale) == bsel) {
+                nlo = fminf(nlo, x);
+                nhi = fmaxf(nhi, x);
+                if (cnt_in <= SEL_POOL) L.pool[atomicAdd(&L.sel[3], 1)] = x;
+            }
+        });
+        nlo = block_min_f(nlo, L.fred);  // (its barriers also order the pool writes)
+        nhi = block_max_f(nhi, L.fred);
+        k -= below;
+        if (cnt_in <= SEL_POOL) {
+            // exact rank within the pool: the pool value with k values below it (ties: any copy)
+            for (int e = t; e < cnt_in; e += SEL_NT) {
+                const float v = L.pool[e];
+                int less = 0, eq = 0;
+                for (int j = 0; j < cnt_in; j++) {
+                    const float y = L.pool[j];
+                    less += y < v;
+                    eq += y == v;
+                }
+                if (less <= k && k < less + eq) L.res = v;  // every writer writes the same value
+            }
+            __syncthreads();
+            const float r = L.res;
+            __syncthreads();
+            return r;
+        }
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
+// Median of the n_valid values the block enumerates (mean of the central pair for even
 // n_valid).
-template <typename ValFn>
-__device__ float wave_median(ValFn val, int n, int n_valid, unsigned *hist, float *pool, int lane) {
-    const float vlo = wave_kth(val, n, (n_valid - 1) / 2, hist, pool, lane);
+template <typename Each>
+__device__ __forceinline__ float block_median(Each each, int n_valid, SelLds &L) {
+    const float vlo = block_kth(each, (n_valid - 1) / 2, L);
     if (n_valid & 1) return vlo;
     // rank n_valid/2: vlo itself when more than n_valid/2 values are <= vlo, else the next
     // larger value
     int le = 0;
     float nxt = INFINITY;
-    for (int i = lane; i < n; i += 64) {
-        const float x = val(i);
+    each([&](float x) __attribute__((always_inline)) {
         le += x <= vlo;
         if (x > vlo) nxt = fminf(nxt, x);
-    }
-    le = wave_sum(le);
-    nxt = wave_min_f(nxt);
+    });
+    le = block_sum(le, L.ired);
+    nxt = block_min_f(nxt, L.fred);
     const float vhi = (le >= n_valid / 2 + 1) ? vlo : nxt;
     return 0.5f * (vlo + vhi);
 }
@@ -641,25 +650,98 @@ __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
     }
 }
 
-// Per-channel median and k*MAD over the visible hemisphere (PER_IMAGE mode); pixels outside
-// the hemisphere read as NaN and are ignored by the selection.
-__global__ __launch_bounds__(64) void image_stats_kernel(const float *__restrict__ img, int n_pix,
-                                                         float2 *__restrict__ stats) {
-    __shared__ unsigned hist[256];
-    __shared__ float pool[64];
-    const int c = blockIdx.x, lane = threadIdx.x;
+// Per-channel median and k*MAD over the visible hemisphere (PER_IMAGE mode), one block of SEL_NT
+// threads per channel image.  Thread t owns column x = t % n_pix and the rows
+// y = y_lo(x) + t / n_pix, + G, ... (G = SEL_NT / n_pix row groups; for n_pix > SEL_NT a thread
+// owns several columns) inside the hemisphere, whose extent in each column is an integer square
+// root: coalesced row reads, no masking.  Up to 256 x 256 pixels a thread owns at most 64
+// values, which are read once and kept on chip (32 in registers, the rest in LDS), so every pass
+// of the selection runs from there; larger images are re-read each pass with eight loads in
+// flight (the passes of many channels at once do not fit the caches).
+__device__ __forceinline__ int isqrt_floor(int q) {  // largest r >= 0 with r * r <= q (q >= 0)
+    int r = (int)sqrtf((float)q);
+    while (r * r > q) r--;
+    while ((r + 1) * (r + 1) <= q) r++;
+    return r;
+}
+
+constexpr int STATS_VR = 32;  // values per thread in registers (n_pix <= 256)
+constexpr int STATS_VL = 32;  // values per thread in LDS, [j][thread] (conflict-free rows)
+
+template <bool ONCHIP>
+__global__ __launch_bounds__(SEL_NT) void image_stats_kernel(const float *__restrict__ img, int n_pix,
+                                                             float2 *__restrict__ stats) {
+    __shared__ SelLds L;
+    __shared__ float s_v[ONCHIP ? STATS_VL * SEL_NT : 1];
+    const int c = blockIdx.x, t = threadIdx.x;
     const float *im = img + (size_t)c * n_pix * n_pix;
-    const int n_all = n_pix * n_pix;
-    int n_in = 0;
-    for (int i = lane; i < n_all; i += 64) n_in += in_horizon(i % n_pix, i / n_pix, n_pix);
-    n_in = wave_sum(n_in);
-    auto val_x = [&](int i) -> float { return in_horizon(i % n_pix, i / n_pix, n_pix) ? im[i] : NAN; };
-    const float med = wave_median(val_x, n_all, n_in, hist, pool, lane);
-    auto val_d = [&](int i) -> float {
-        return in_horizon(i % n_pix, i / n_pix, n_pix) ? fabsf(im[i] - med) : NAN;
+    const int h = n_pix / 2;
+    const int G = n_pix <= SEL_NT ? SEL_NT / n_pix : 1;  // row groups
+    const int g = n_pix <= SEL_NT ? t / n_pix : 0;
+    const bool on = g < G;
+    const int x0 = n_pix <= SEL_NT ? t % n_pix : t;
+    // rows y0 + g, + G, ... <= y1 of column x in the hemisphere:
+    // (x - h)^2 + (y - h)^2 < h^2  <=>  |y - h| <= isqrt(h^2 - (x - h)^2 - 1)
+    auto rows = [&](int x, int &y0, int &y1) __attribute__((always_inline)) {
+        const int q = h * h - (x - h) * (x - h);
+        if (q <= 0) {
+            y0 = 1;
+            y1 = 0;
+            return;
+        }
+        const int r = isqrt_floor(q - 1);
+        y0 = h - r + g;
+        y1 = h + r;
     };
-    const float mad = wave_median(val_d, n_all, n_in, hist, pool, lane);
-    if (lane == 0) stats[c] = make_float2(med, MAD_K * mad);
+    float v[ONCHIP ? STATS_VR : 1];
+    int nv = 0;
+    if constexpr (ONCHIP) {
+        // n_pix <= 256: one column, at most ceil(n_pix / G) <= 64 rows
+        int y0 = 1, y1 = 0;
+        if (on) rows(x0, y0, y1);
+        nv = y1 >= y0 ? (y1 - y0) / G + 1 : 0;
+#pragma unroll
+        for (int j = 0; j < STATS_VR; j++) v[j] = j < nv ? im[(size_t)(y0 + j * G) * n_pix + x0] : 0.f;
+#pragma unroll
+        for (int j = 0; j < STATS_VL; j++) {
+            const int jj = STATS_VR + j;
+            s_v[j * SEL_NT + t] = jj < nv ? im[(size_t)(y0 + jj * G) * n_pix + x0] : 0.f;
+        }
+        // (the selection's first block reduction orders these LDS writes before any read)
+    }
+    auto visit = [&](auto f) __attribute__((always_inline)) {
+        if constexpr (ONCHIP) {
+#pragma unroll
+            for (int j = 0; j < STATS_VR; j++)
+                if (j < nv) f(v[j]);
+            for (int j = 0; j < nv - STATS_VR; j++) f(s_v[j * SEL_NT + t]);
+        } else {
+            if (!on) return;
+            for (int x = x0; x < n_pix; x += SEL_NT) {
+                int y0, y1;
+                rows(x, y0, y1);
+                int y = y0;
+                for (; y + 7 * G <= y1; y += 8 * G) {
+                    float u[8];
+#pragma unroll
+                    for (int k = 0; k < 8; k++) u[k] = im[(size_t)(y + k * G) * n_pix + x];
+#pragma unroll
+                    for (int k = 0; k < 8; k++) f(u[k]);
+                }
+                for (; y <= y1; y += G) f(im[(size_t)y * n_pix + x]);
+            }
+        }
+    };
+    int n_in = 0;
+    visit([&](float) __attribute__((always_inline)) { n_in++; });
+    n_in = block_sum(n_in, L.ired);
+    const float med = block_median([&](auto f) __attribute__((always_inline)) { visit(f); }, n_in, L);
+    const float mad = block_median(
+        [&](auto f) __attribute__((always_inline)) {
+            visit([&](float x) __attribute__((always_inline)) { f(fabsf(x - med)); });
+        },
+        n_in, L);
+    if (t == 0) stats[c] = make_float2(med, MAD_K * mad);
 }
 
 __device__ __forceinline__ unsigned long long cand_key(const nbsi_cand &r, int n_chan, int n_pix) {
@@ -708,8 +790,12 @@ int detect_ppw(int n_chan) {
 hipError_t launch_detect_stats(const float *img, int n_chan, int n_pix, int mode, float *stats,
                                hipStream_t st) {
     if (mode != NBSI_DETECT_PER_IMAGE) return hipSuccess;
-    hipLaunchKernelGGL(image_stats_kernel, dim3(n_chan), dim3(64), 0, st, img, n_pix,
-                       reinterpret_cast<float2 *>(stats));
+    if (n_pix <= 256)
+        hipLaunchKernelGGL(image_stats_kernel<true>, dim3(n_chan), dim3(SEL_NT), 0, st, img, n_pix,
+                           reinterpret_cast<float2 *>(stats));
+    else
+        hipLaunchKernelGGL(image_stats_kernel<false>, dim3(n_chan), dim3(SEL_NT), 0, st, img, n_pix,
+                           reinterpret_cast<float2 *>(stats));
     return hipGetLastError();
 }
 

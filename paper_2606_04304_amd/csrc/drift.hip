@@ -8,7 +8,9 @@
 // dedoppler_kernel: a workgroup takes 32 pixels (one per lane of a half-wave) x 64 channels
 // (8 per thread) and stages every sub-integration's channels [c0 - D_MAX, c0 + 64 + D_MAX) of
 // those pixels in LDS with coalesced 128-byte row loads, so each input value is read from HBM
-// once per workgroup and reused by all 2D + 1 trials from LDS.
+// once per workgroup and reused by all 2D + 1 trials from LDS.  All 33 trials are evaluated
+// (those beyond the requested drift masked), so each distinct (sub-integration, shift) value is
+// read once per channel.
 #include "internal.h"
 
 #include <algorithm>
@@ -21,27 +23,23 @@ constexpr int DD_PX = 32;
 constexpr int DD_CB = 64;
 constexpr int DD_ROWS = DD_CB + 2 * NBSI_DEDOPPLER_MAX_DRIFT;
 
-__device__ __forceinline__ int drift_shift(int d, int s, int n_sub) {
+__host__ __device__ constexpr int drift_shift(int d, int s, int n_sub) {
     if (n_sub <= 1 || d == 0 || s == 0) return 0;
     const int ad = d < 0 ? -d : d;
     const int mag = (2 * ad * s + (n_sub - 1)) / (2 * (n_sub - 1));
     return d > 0 ? mag : -mag;
 }
 
-__global__ __launch_bounds__(256) void dedoppler_kernel(const float *__restrict__ r, int n_sub, int n_chan,
-                                                        int n_pix, int max_drift, float *__restrict__ best,
+// The sub-integration count is a template parameter, so with the trial loop unrolled every
+// track offset (s DD_ROWS + shift(d, s)) DD_PX is an immediate of its LDS read, and reads shared
+// by several trials are issued once.
+template <int NS>
+__global__ __launch_bounds__(256) void dedoppler_kernel(const float *__restrict__ r, int n_chan, int n_pix,
+                                                        int max_drift, float *__restrict__ best,
                                                         int8_t *__restrict__ drift) {
+    constexpr int n_sub = NS;
     extern __shared__ float tile[];  // [n_sub][DD_ROWS][DD_PX]
-    // staged-row offset of every (trial, sub-integration): (s DD_ROWS + shift(d, s)) DD_PX, trial k
-    // being d = 0, -1, +1, -2, +2, ...
-    __shared__ int off[(2 * NBSI_DEDOPPLER_MAX_DRIFT + 1) * NBSI_DEDOPPLER_MAX_SUB];
     const int t = threadIdx.x, lane = t & (DD_PX - 1), grp = t / DD_PX;  // 8 groups of 8 channels
-    const int n_trials = 2 * max_drift + 1;
-    for (int e = t; e < n_trials * n_sub; e += 256) {
-        const int k = e / n_sub, s = e % n_sub;
-        const int d = (k == 0) ? 0 : ((k & 1) ? -((k + 1) >> 1) : (k >> 1));
-        off[e] = (s * DD_ROWS + drift_shift(d, s, n_sub)) * DD_PX;
-    }
     const size_t npx = (size_t)n_pix * n_pix;
     const size_t p0 = (size_t)blockIdx.x * DD_PX;
     const int c0 = blockIdx.y * DD_CB;
@@ -73,13 +71,15 @@ __global__ __launch_bounds__(256) void dedoppler_kernel(const float *__restrict_
         float bv = -INFINITY;
         int bd = 0;
         const float *col = tile + ic * DD_PX + lane;
-        for (int k = 0; k < n_trials; k++) {  // 0, -1, +1, -2, +2, ...
+#pragma unroll
+        for (int k = 0; k < 2 * NBSI_DEDOPPLER_MAX_DRIFT + 1; k++) {  // 0, -1, +1, -2, +2, ...
             const int d = (k == 0) ? 0 : ((k & 1) ? -((k + 1) >> 1) : (k >> 1));
-            if (c + d < 0 || c + d >= n_chan) continue;
             float acc = 0.f;
-            for (int s = 0; s < n_sub; s++) acc += col[off[k * n_sub + s]];
+#pragma unroll
+            for (int s = 0; s < n_sub; s++) acc += col[(s * DD_ROWS + drift_shift(d, s, n_sub)) * DD_PX];
             const float v = acc * inv;
-            if (v > bv) {
+            const bool ok = k < 2 * max_drift + 1 && c + d >= 0 && c + d < n_chan;
+            if (ok && v > bv) {
                 bv = v;
                 bd = d;
             }
@@ -91,17 +91,25 @@ __global__ __launch_bounds__(256) void dedoppler_kernel(const float *__restrict_
 
 // More than 64 KB of dynamic LDS (6 to 8 sub-integrations) needs the kernel's limit raised, once
 // per device.
-hipError_t dedoppler_lds_prepare() {
+template <int NS>
+hipError_t dedoppler_launch(dim3 grid, size_t lds, hipStream_t st, const float *r, int n_chan, int n_pix,
+                            int max_drift, float *best, int8_t *drift) {
     static std::mutex mu;
     static std::vector<int> done;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
-    std::lock_guard<std::mutex> lock(mu);
-    if (std::find(done.begin(), done.end(), dev) != done.end()) return hipSuccess;
-    const hipError_t e = hipFuncSetAttribute((const void *)dedoppler_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)(sizeof(float) * NBSI_DEDOPPLER_MAX_SUB * DD_ROWS * DD_PX));
-    if (e == hipSuccess) done.push_back(dev);
-    return e;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (std::find(done.begin(), done.end(), dev) == done.end()) {
+            const hipError_t e = hipFuncSetAttribute((const void *)dedoppler_kernel<NS>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)(sizeof(float) * NS * DD_ROWS * DD_PX));
+            if (e != hipSuccess) return e;
+            done.push_back(dev);
+        }
+    }
+    hipLaunchKernelGGL(dedoppler_kernel<NS>, grid, dim3(256), lds, st, r, n_chan, n_pix, max_drift, best, drift);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -119,9 +127,18 @@ extern "C" int nbsi_dedoppler(nbsi_ctx *ctx, const float *snr_sub, int n_sub, in
     DeviceGuard g(ctx->device);
     const size_t npx = (size_t)n_pix * n_pix;
     const size_t lds = sizeof(float) * (size_t)n_sub * DD_ROWS * DD_PX;
-    NBSI_TRY_HIP(ctx, dedoppler_lds_prepare());
-    hipLaunchKernelGGL(dedoppler_kernel, dim3((unsigned)((npx + DD_PX - 1) / DD_PX), (unsigned)((n_chan + DD_CB - 1) / DD_CB)),
-                       dim3(256), lds, ctx->stream, snr_sub, n_sub, n_chan, n_pix, max_drift, best, drift);
-    NBSI_TRY_HIP(ctx, hipGetLastError());
+    const dim3 grid((unsigned)((npx + DD_PX - 1) / DD_PX), (unsigned)((n_chan + DD_CB - 1) / DD_CB));
+    hipError_t e = hipErrorInvalidValue;
+    switch (n_sub) {
+        case 1: e = dedoppler_launch<1>(grid, lds, ctx->stream, snr_sub, n_chan, n_pix, max_drift, best, drift); break;
+        case 2: e = dedoppler_launch<2>(grid, lds, ctx->stream, snr_sub, n_chan, n_pix, max_drift, best, drift); break;
+        case 3: e = dedoppler_launch<3>(grid, lds, ctx->stream, snr_sub, n_chan, n_pix, max_drift, best, drift); break;
+        case 4: e = dedoppler_launch<4>(grid, lds, ctx->stream, snr_sub, n_chan, n_pix, max_drift, best, drift); break;
+        case 5: e = dedoppler_launch<5>(grid, lds, ctx->stream, snr_sub, n_chan, n_pix, max_drift, best, drift); break;
+        case 6: e = dedoppler_launch<6>(grid, lds, ctx->stream, snr_sub, n_chan, n_pix, max_drift, best, drift); break;
+        case 7: e = dedoppler_launch<7>(grid, lds, ctx->stream, snr_sub, n_chan, n_pix, max_drift, best, drift); break;
+        case 8: e = dedoppler_launch<8>(grid, lds, ctx->stream, snr_sub, n_chan, n_pix, max_drift, best, drift); break;
+    }
+    NBSI_TRY_HIP(ctx, e);
     return NBSI_OK;
 }

@@ -306,7 +306,9 @@ struct GridShape {
     static constexpr int M = 1 << LOGM;
     static constexpr int CELLS = Tile<GE>::CELLS;
     static constexpr int R = CELLS / M;              // rows of a band
-    static constexpr int CPT = M >= 256 ? M / 256 : 1;  // owned columns per thread
+    // owned columns per thread: 4 x 4 cells at M = 512 (measured 3.5% faster than 2 x 8 there),
+    // else one column per 256 of M
+    static constexpr int CPT = M == 512 ? 4 : (M >= 256 ? M / 256 : 1);
     static constexpr int COLT = M / CPT;             // threads across the columns
     static constexpr int RPT = R / (256 / COLT);     // owned rows per thread
     static constexpr int XMIN = -16, XMAX = M + 16;  // first-index table range

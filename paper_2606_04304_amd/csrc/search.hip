@@ -109,27 +109,49 @@ __global__ __launch_bounds__(256) void search_bank_kernel(const float *__restric
     const int p = p0 + lane;
     const bool pix_ok = p < npx;
     const bool hor = pix_ok && in_horizon(p, n_pix);
-    for (int j = 0; j < SB_CB / 4; j++) {
-        const int c = c0 + wave * (SB_CB / 4) + j;
-        if (c >= n_chan) break;
-        const int ic = c - base;
-        float bs = -INFINITY;
-        int bw = 0;
+    // eight channels at a time: sixteen independent LDS reads per width.  Every index stays
+    // inside the staged block whether or not the window fits the band (h <= 64, w - h <= 64), so
+    // the reads are unconditional and the band test only masks the result.
+    constexpr int CQ = 8;
+    for (int j = 0; j < SB_CB / 4; j += CQ) {
+        const int cb = c0 + wave * (SB_CB / 4) + j;
+        if (cb >= n_chan) break;
+        float bs[CQ];
+        int bw[CQ];
+#pragma unroll
+        for (int q = 0; q < CQ; q++) {
+            bs[q] = -INFINITY;
+            bw[q] = 0;
+        }
         for (int k = 0; k < W.n; k++) {  // widths ascending: the narrower one wins ties
             const int w = W.w[k], h = w >> 1;
-            if (c - h < 0 || c - h + w > n_chan) continue;
-            const int is = ic - h;
-            const float v = (P[(is + w) * SB_PX + lane] - P[is * SB_PX + lane]) * W.inv_sqrt[k];
-            if (v > bs) {
-                bs = v;
-                bw = w;
+            const float inv = W.inv_sqrt[k];
+            float v[CQ];
+#pragma unroll
+            for (int q = 0; q < CQ; q++) {
+                const int is = cb + q - base - h;
+                v[q] = (P[(is + w) * SB_PX + lane] - P[is * SB_PX + lane]) * inv;
+            }
+#pragma unroll
+            for (int q = 0; q < CQ; q++) {
+                const int c = cb + q;
+                const bool fits = c < n_chan && c - h >= 0 && c - h + w <= n_chan;
+                if (fits && v[q] > bs[q]) {
+                    bs[q] = v[q];
+                    bw[q] = w;
+                }
             }
         }
-        if (pix_ok) {
-            best[(size_t)c * npx + p] = bs;
-            wbest[(size_t)c * npx + p] = (uint8_t)bw;
+#pragma unroll
+        for (int q = 0; q < CQ; q++) {
+            const int c = cb + q;
+            if (c >= n_chan) break;
+            if (pix_ok) {
+                best[(size_t)c * npx + p] = bs[q];
+                wbest[(size_t)c * npx + p] = (uint8_t)bw[q];
+            }
+            if (hor && bs[q] >= HIST_LO) atomicAdd(&h_lds[hist_bin(bs[q])], 1u);
         }
-        if (hor && bs >= HIST_LO) atomicAdd(&h_lds[hist_bin(bs)], 1u);
     }
     __syncthreads();
     for (int i = t; i < HIST_BINS; i += 256)

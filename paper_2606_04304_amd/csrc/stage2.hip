@@ -18,13 +18,29 @@
 namespace {
 
 constexpr int NP = 7;          // amp, x0, y0, a, b, c, bkg
-constexpr int S2_WAVES = 4;    // candidates per workgroup
-constexpr int LM_MAX_IT = 1000;
+constexpr int S2_WAVES = 1;    // candidates per workgroup (a slow fit holds back no other)
+constexpr int LM_MAX_IT = 300;
 constexpr double FWHM_PER_SIGMA = 2.3548200450309493;  // 2 sqrt(2 ln 2)
 
+// A lane's double moved across lanes by a DPP pattern (both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Wave sum that leaves the same (bitwise) total in every lane: within rows of 16 lanes by DPP
+// (pair swap, quad half swap, half-row mirror, row mirror: each partner holds the other half's
+// partial sum), then across rows by lane shuffles.
 __device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
     return v;
 }
 

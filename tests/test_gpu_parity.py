@@ -246,7 +246,7 @@ def _compare_candidates(rec, ref, snr_ref, tau, tol=1e-4):
 @pytest.mark.parametrize("n_chan,n_pix,mode", [
     (64, 16, nb.NBSI_DETECT_PER_PIXEL), (257, 32, nb.NBSI_DETECT_PER_PIXEL),
     (4096, 8, nb.NBSI_DETECT_PER_PIXEL), (100, 24, nb.NBSI_DETECT_PER_IMAGE),
-    (5000, 8, nb.NBSI_DETECT_PER_PIXEL),
+    (5000, 8, nb.NBSI_DETECT_PER_PIXEL), (32, 256, nb.NBSI_DETECT_PER_IMAGE), (16, 128, nb.NBSI_DETECT_PER_IMAGE), (12, 512, nb.NBSI_DETECT_PER_IMAGE),
 ])
 def test_detect_matches_oracle(n_chan, n_pix, mode):
     print(f"detect n_chan={n_chan} n_pix={n_pix} mode={mode}", flush=True)
@@ -266,6 +266,25 @@ def test_detect_matches_oracle(n_chan, n_pix, mode):
     assert d.max() <= 1e-4 * max(1.0, np.abs(snr_ref).max())
     _compare_candidates(rec, ref, snr_ref, 5.0)
     assert len(ref) >= 3
+
+
+def test_per_image_statistics_adversarial():
+    """Per-image medians and MADs through images with many ties (integer values), a constant
+    image, a two-valued image, a ramp and huge outliers: every SNR must match the oracle's."""
+    n_chan, n_pix = 12, 128
+    rng = np.random.default_rng(12)
+    cube = rng.standard_normal((n_chan, n_pix, n_pix)).astype(np.float32)
+    cube[1] = rng.integers(-3, 4, (n_pix, n_pix)).astype(np.float32)
+    cube[2] = rng.integers(0, 2, (n_pix, n_pix)).astype(np.float32)
+    cube[3] = 1.25
+    cube[4] = np.linspace(-4, 4, n_pix * n_pix, dtype=np.float32).reshape(n_pix, n_pix)
+    cube[5, ::7, ::5] = 1e6
+    cube[6] = rng.integers(0, 3, (n_pix, n_pix)).astype(np.float32) * 1e-30
+    rec, snr, n = nb.nbsi_detect(torch.from_numpy(cube).to(DEV), mode=nb.NBSI_DETECT_PER_IMAGE, thresh=5.0,
+                                 want_snr=True)
+    _, snr_ref, valid = oracle.detect.detect(cube, tau=5.0, mode="per_image")
+    d = np.abs(snr.cpu().numpy() - snr_ref)[:, valid]
+    assert d.max() <= 1e-4 * max(1.0, np.abs(snr_ref).max())
 
 
 def test_detect_truncation_reports_true_count():
