@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--no-deep", action="store_true", help="skip the long-integration correlator leg")
     ap.add_argument("--no-classifier", action="store_true", help="skip the classifier leg")
     ap.add_argument("--no-search", action="store_true", help="skip the full Stage I search leg")
+    ap.add_argument("--leg", default=None,
+                    choices=["deep_correlator", "classifier", "stage1_search", "dedoppler", "stage2"],
+                    help="with --legs-only: run this leg alone")
     ap.add_argument("--step-only", action="store_true",
                     help="profiling aid: only the timed step (no legs, no FP32 path, no batch)")
     ap.add_argument("--legs-only", action="store_true",
@@ -401,11 +404,13 @@ def main():
         return
     if args.legs_only:
         c0 = nb.nbsi_create(0)
-        print(json.dumps({"deep_correlator": deep_correlator_leg(args, nb, torch, c0, dev, synth),
-                          "classifier": classifier_leg(args, nb, torch, c0, dev, synth),
-                          "stage1_search": search_leg(args, nb, torch, c0, dev, 4096, 256),
-                          "dedoppler": dedoppler_leg(args, nb, torch, c0, dev, 4096, 256),
-                          "stage2": stage2_leg(args, nb, torch, c0, dev, 4096, 256)}))
+        legs = {"deep_correlator": lambda: deep_correlator_leg(args, nb, torch, c0, dev, synth),
+                "classifier": lambda: classifier_leg(args, nb, torch, c0, dev, synth),
+                "stage1_search": lambda: search_leg(args, nb, torch, c0, dev, 4096, 256),
+                "dedoppler": lambda: dedoppler_leg(args, nb, torch, c0, dev, 4096, 256),
+                "stage2": lambda: stage2_leg(args, nb, torch, c0, dev, 4096, 256)}
+        names = [args.leg] if args.leg else list(legs)
+        print(json.dumps({k: legs[k]() for k in names}))
         return
     cfg = synth.make_config(2)
     log(f"[bench] generating inputs: {cfg.name}")
