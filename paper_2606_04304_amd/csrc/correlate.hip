@@ -334,7 +334,9 @@ __global__ __launch_bounds__(256) void pad_rows_kernel(const int8_t *__restrict_
 // lines at segment edges in L2, 2.4x more slowly; staging four or two tiles' rows in LDS so each
 // store writes one row segment of 64 or 32 products, 3% and 5% more slowly.  A store-only probe
 // of this pattern takes as long as the kernel; writing each triangle row whole before the next
-// would take 40% less, but a wave's 16 rows advance together across its panel.)
+// takes 40% less there, but a wave's 16 rows advance together across its panel, and a kernel
+// that stages a whole panel's rows in LDS to write them row by row fits one workgroup per CU
+// and ran 1.4x more slowly.)
 constexpr int CHAN_WAVES = 4;
 template <int KP>  // padded K: 32 or 64
 __device__ __forceinline__ void correlate_channel(const int8_t *__restrict__ q, int n_in, int T, int c,
