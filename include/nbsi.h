@@ -200,6 +200,24 @@ int nbsi_image_stokes(nbsi_ctx *ctx, const nbsi_image_plan *plan, const float *s
                       int precision, float *img);
 
 /*
+ * Both of the above with the two stages overlapped (the X-engine and imager of Sec. 2.1 run as
+ * a pipeline over channel chunks, as the paper's batches stream through its GPU stages):
+ * the channels are cut into n_stages ranges of whole imaging chunks (0 = NBSI_DEFAULT_STAGES,
+ * at most NBSI_MAX_STAGES; fewer when the plan has fewer chunks); range k is correlated on the
+ * context's stream while range k - 1 is imaged on an auxiliary stream of the context (created
+ * on first use, default priority), and the context's stream waits for the last image before
+ * its next work.  vis, stokes_i and img receive, bit for bit, what nbsi_correlate_stokes
+ * followed by nbsi_image_stokes write; same shapes, alignment and ownership.  Two calls on
+ * one context are ordered like any other work of the context; concurrent calls on one
+ * context from several host threads race (as for every entry point).
+ */
+#define NBSI_MAX_STAGES 64
+#define NBSI_DEFAULT_STAGES 16
+int nbsi_correlate_image(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, int n_spec,
+                         const nbsi_image_plan *plan, int precision, int n_stages, int32_t *vis,
+                         float *stokes_i, float *img);
+
+/*
  * Narrowband search of a cube (Sec. 2.4, Stage I with the width-1 matched filter):
  *   NBSI_DETECT_PER_PIXEL: SNR_p[c] = (I_p[c] - med_c I_p) / (k MAD_c I_p)
  *   NBSI_DETECT_PER_IMAGE: z = (I - med) / (k MAD) over each channel image, then

@@ -42,7 +42,7 @@ EXPORTS = [
     "nbsi_batch_describe", "nbsi_batch_destroy", "nbsi_stamps", "nbsi_net_create", "nbsi_net_destroy",
     "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
     "nbsi_net_train_step", "nbsi_correlate_kernel", "nbsi_image_plan_pairs", "nbsi_correlate_stokes",
-    "nbsi_image_stokes", "nbsi_search", "nbsi_correlate_cal", "nbsi_dedoppler", "nbsi_beam", "nbsi_stage2",
+    "nbsi_image_stokes", "nbsi_correlate_image", "nbsi_search", "nbsi_correlate_cal", "nbsi_dedoppler", "nbsi_beam", "nbsi_stage2",
 ]
 NBSI_DEDOPPLER_MAX_SUB = 8
 NBSI_DEDOPPLER_MAX_DRIFT = 16
@@ -116,6 +116,7 @@ def lib():
         L.nbsi_image_plan_pairs.argtypes = [P, ctypes.POINTER(I), P]
         L.nbsi_correlate_stokes.argtypes = [P, P, I, I, I, P, P, P]
         L.nbsi_image_stokes.argtypes = [P, P, P, I, P]
+        L.nbsi_correlate_image.argtypes = [P, P, I, I, I, P, I, I, P, P, P]
         L.nbsi_search.argtypes = [P, P, I, I, P, I, D, P, P, P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_float),
                                   ctypes.POINTER(ctypes.c_int64)]
         L.nbsi_detect.argtypes = [P, P, I, I, I, ctypes.c_float, P, P, I, P]
@@ -345,10 +346,11 @@ def nbsi_image(plan: ImagePlan, vis, precision: int = NBSI_PREC_FP32, img=None):
     return img
 
 
-def nbsi_correlate_stokes(spec_q, plan: ImagePlan, vis=None, stokes_i=None):
-    """spec_q int8 -> (vis as nbsi_correlate, stokes_i [n_chan][plan.n_pairs()][2] float32)."""
+def nbsi_correlate_stokes(spec_q, plan: ImagePlan, vis=None, stokes_i=None, ctx: Context | None = None):
+    """spec_q int8 -> (vis as nbsi_correlate, stokes_i [n_chan][plan.n_pairs()][2] float32).  ctx:
+    the context to run on (default: the plan's), e.g. one with its own scratch for another stream."""
     torch = _torch()
-    ctx = plan.ctx
+    ctx = ctx or plan.ctx
     _need(spec_q, torch.int8, "spec_q", ctx.device)
     n_chan, n_in, two, n_spec = spec_q.shape
     if vis is None:
@@ -368,10 +370,12 @@ def nbsi_correlate_stokes(spec_q, plan: ImagePlan, vis=None, stokes_i=None):
     return vis, stokes_i
 
 
-def nbsi_image_stokes(plan: ImagePlan, stokes_i, precision: int = NBSI_PREC_FP32, img=None):
-    """stokes_i [n_chan][n_pairs][2] float32 (from nbsi_correlate_stokes) -> img, as nbsi_image."""
+def nbsi_image_stokes(plan: ImagePlan, stokes_i, precision: int = NBSI_PREC_FP32, img=None,
+                      ctx: Context | None = None):
+    """stokes_i [n_chan][n_pairs][2] float32 (from nbsi_correlate_stokes) -> img, as nbsi_image
+    (ctx: the context to run on, default the plan's)."""
     torch = _torch()
-    ctx = plan.ctx
+    ctx = ctx or plan.ctx
     _need(stokes_i, torch.float32, "stokes_i", ctx.device)
     if stokes_i.dim() != 3 or stokes_i.shape[0] != plan.n_chan or stokes_i.shape[1] != max(1, plan.n_pairs()) \
             or stokes_i.shape[2] != 2:
@@ -381,6 +385,36 @@ def nbsi_image_stokes(plan: ImagePlan, stokes_i, precision: int = NBSI_PREC_FP32
     ctx._sync_stream()
     _check(lib().nbsi_image_stokes(ctx._h, plan._h, _ptr(stokes_i), int(precision), _ptr(img)), ctx)
     return img
+
+
+def nbsi_correlate_image(spec_q, plan: ImagePlan, precision: int = NBSI_PREC_FP32, n_stages: int = 0,
+                         vis=None, stokes_i=None, img=None, ctx: Context | None = None):
+    """nbsi_correlate_stokes then nbsi_image_stokes, overlapped over n_stages channel ranges
+    (0: the library's default) -> (vis, stokes_i, img), bit for bit those of the two calls."""
+    torch = _torch()
+    ctx = ctx or plan.ctx
+    _need(spec_q, torch.int8, "spec_q", ctx.device)
+    n_chan, n_in, two, n_spec = spec_q.shape
+    nprod = n_in * (n_in + 1) // 2
+    if vis is None:
+        vis = torch.empty((n_chan, nprod, 2), dtype=torch.int32, device=ctx.device)
+    if stokes_i is None:
+        stokes_i = torch.empty((n_chan, max(1, plan.n_pairs()), 2), dtype=torch.float32, device=ctx.device)
+    if img is None:
+        img = torch.empty((plan.n_chan, plan.n_pix, plan.n_pix), dtype=torch.float32, device=ctx.device)
+    _need(vis, torch.int32, "vis", ctx.device)
+    _need(stokes_i, torch.float32, "stokes_i", ctx.device)
+    _need(img, torch.float32, "img", ctx.device)
+    if tuple(vis.shape) != (n_chan, nprod, 2):
+        raise ValueError(f"vis shape {tuple(vis.shape)} does not match spec_q")
+    if tuple(stokes_i.shape) != (n_chan, max(1, plan.n_pairs()), 2):
+        raise ValueError(f"stokes_i shape {tuple(stokes_i.shape)} does not match the plan")
+    if tuple(img.shape) != (plan.n_chan, plan.n_pix, plan.n_pix):
+        raise ValueError(f"img shape {tuple(img.shape)} does not match the plan")
+    ctx._sync_stream()
+    _check(lib().nbsi_correlate_image(ctx._h, _ptr(spec_q), n_chan, n_in, n_spec, plan._h, int(precision),
+                                      int(n_stages), _ptr(vis), _ptr(stokes_i), _ptr(img)), ctx)
+    return vis, stokes_i, img
 
 
 def nbsi_search(snr, fdr_q: float = 0.01, widths=None, max_out: int = 1 << 20, want_cubes: bool = False,

@@ -74,6 +74,60 @@ int nbsi_scratch(nbsi_ctx *ctx, int slot, size_t bytes, void **ptr) {
     return NBSI_OK;
 }
 
+namespace {
+
+// the auxiliary stream (non-blocking, default priority) and the stage events of a context
+int nbsi_aux_stream(nbsi_ctx *ctx) {
+    if (ctx->aux) return NBSI_OK;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        return nbsi_fail(ctx, NBSI_EHIP, "auxiliary stream creation failed");
+    for (int k = 0; k <= NBSI_MAX_STAGES; k++)
+        if (hipEventCreateWithFlags(&ctx->ev_stage[k], hipEventDisableTiming) != hipSuccess) {
+            for (int j = 0; j < k; j++) (void)hipEventDestroy(ctx->ev_stage[j]);
+            for (int j = 0; j <= NBSI_MAX_STAGES; j++) ctx->ev_stage[j] = nullptr;
+            (void)hipStreamDestroy(s);
+            return nbsi_fail(ctx, NBSI_EHIP, "stage event creation failed");
+        }
+    ctx->aux = s;
+    return NBSI_OK;
+}
+
+int check_image_stokes(nbsi_ctx *ctx, const nbsi_image_plan *plan, int precision, const char *who) {
+    if (plan->device != ctx->device) return nbsi_fail(ctx, NBSI_EINVAL, std::string(who) + ": plan built on another device");
+    if (plan->method != NBSI_IMAGE_GRID) return nbsi_fail(ctx, NBSI_EINVAL, std::string(who) + ": plan must be a gridding plan");
+    if (precision != NBSI_PREC_FP32 && precision != NBSI_PREC_FP16 && precision != NBSI_PREC_BF16)
+        return nbsi_fail(ctx, NBSI_EINVAL, std::string(who) + ": bad precision");
+    return NBSI_OK;
+}
+
+// The imager runs over channel chunks whose row-pass intermediate stays in the last-level cache.
+size_t image_stokes_per_chan(const nbsi_image_plan *plan) { return (size_t)plan->n_pix * plan->n_pix * sizeof(float2); }
+
+int image_stokes_chunk(const nbsi_image_plan *plan) {
+    return (int)std::max<size_t>(1, std::min<size_t>(plan->n_chan, IMAGE_CHUNK_BYTES / image_stokes_per_chan(plan)));
+}
+
+// Images of channels [c_begin, c_end) (c_begin a multiple of the chunk) from their Stokes-I rows.
+hipError_t image_stokes_range(const nbsi_image_plan *plan, const float *stokes_i, int precision, float2 *inter,
+                              float *img, int c_begin, int c_end, hipStream_t st) {
+    const int chunk = image_stokes_chunk(plan);
+    const float2 *sv = reinterpret_cast<const float2 *>(stokes_i);
+    for (int c0 = c_begin; c0 < c_end; c0 += chunk) {
+        nbsi_image_plan sub = *plan;
+        sub.n_chan = std::min(chunk, c_end - c0);
+        sub.d_freq = plan->d_freq + c0;
+        sub.d_nb = plan->d_nb + c0;
+        if (plan->d_inb) sub.d_inb = plan->d_inb + (size_t)c0 * ((plan->n_pairs + 31) >> 5);
+        const hipError_t e = launch_image_grid_stokes(&sub, sv + (size_t)c0 * plan->n_pairs, precision, inter,
+                                                      img + (size_t)c0 * plan->n_pix * plan->n_pix, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 extern "C" {
 
 int nbsi_version(void) { return 1; }
@@ -161,7 +215,12 @@ int nbsi_destroy(nbsi_ctx *ctx) {
     if (!ctx) return NBSI_EINVAL;
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    for (int s = 0; s < 8; s++)
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        for (int k = 0; k <= NBSI_MAX_STAGES; k++) (void)hipEventDestroy(ctx->ev_stage[k]);
+        (void)hipStreamDestroy(ctx->aux);
+    }
+    for (int s = 0; s < 16; s++)
         if (ctx->scratch[s]) (void)hipFree(ctx->scratch[s]);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
     delete ctx;
@@ -525,28 +584,69 @@ int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int 
 int nbsi_image_stokes(nbsi_ctx *ctx, const nbsi_image_plan *plan, const float *stokes_i, int precision, float *img) {
     if (!ctx) return NBSI_EINVAL;
     if (!plan || !stokes_i || !img) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: null pointer");
-    if (plan->device != ctx->device) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: plan built on another device");
-    if (plan->method != NBSI_IMAGE_GRID) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: plan must be a gridding plan");
-    if (precision != NBSI_PREC_FP32 && precision != NBSI_PREC_FP16 && precision != NBSI_PREC_BF16)
-        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: bad precision");
+    int rc = check_image_stokes(ctx, plan, precision, "nbsi_image_stokes");
+    if (rc) return rc;
     if (!aligned16(stokes_i) || !aligned16(img)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image_stokes: misaligned pointer");
     DeviceGuard g(ctx->device);
-    // the same channel chunks as nbsi_image, so the row intermediate stays in the last-level cache
-    const size_t per_chan = (size_t)plan->n_pix * plan->n_pix * sizeof(float2);
-    const int chunk = (int)std::max<size_t>(1, std::min<size_t>(plan->n_chan, IMAGE_CHUNK_BYTES / per_chan));
     void *inter = nullptr;
-    int rc = nbsi_scratch(ctx, SLOT_IMG_INTER, per_chan * chunk, &inter);
-    if (rc) return rc;
-    const float2 *sv = reinterpret_cast<const float2 *>(stokes_i);
-    for (int c0 = 0; c0 < plan->n_chan; c0 += chunk) {
-        nbsi_image_plan sub = *plan;
-        sub.n_chan = std::min(chunk, plan->n_chan - c0);
-        sub.d_freq = plan->d_freq + c0;
-        sub.d_nb = plan->d_nb + c0;
-        if (plan->d_inb) sub.d_inb = plan->d_inb + (size_t)c0 * ((plan->n_pairs + 31) >> 5);
-        NBSI_TRY_HIP(ctx, launch_image_grid_stokes(&sub, sv + (size_t)c0 * plan->n_pairs, precision, (float2 *)inter,
-                                                   img + (size_t)c0 * plan->n_pix * plan->n_pix, ctx->stream));
+    if ((rc = nbsi_scratch(ctx, SLOT_IMG_INTER, image_stokes_chunk(plan) * image_stokes_per_chan(plan), &inter)))
+        return rc;
+    NBSI_TRY_HIP(ctx, image_stokes_range(plan, stokes_i, precision, (float2 *)inter, img, 0, plan->n_chan, ctx->stream));
+    return NBSI_OK;
+}
+
+int nbsi_correlate_image(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, int n_spec,
+                         const nbsi_image_plan *plan, int precision, int n_stages, int32_t *vis, float *stokes_i,
+                         float *img) {
+    if (!ctx) return NBSI_EINVAL;
+    int rc = nbsi_check_correlate(n_chan, n_in, n_spec);
+    if (rc) return nbsi_fail(ctx, rc, "nbsi_correlate_image: bad shape");
+    if (!spec_q || !vis || !plan || !stokes_i || !img) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_image: null pointer");
+    if (!aligned16(spec_q) || !aligned16(vis) || !aligned16(stokes_i) || !aligned16(img))
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_image: misaligned pointer");
+    if ((rc = check_image_stokes(ctx, plan, precision, "nbsi_correlate_image"))) return rc;
+    if (n_in != 2 * plan->n_ant || n_chan != plan->n_chan)
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_image: plan must be a gridding plan of n_in / 2 antennas and n_chan channels");
+    if (n_stages < 0 || n_stages > NBSI_MAX_STAGES)
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_correlate_image: n_stages must be 0 .. NBSI_MAX_STAGES");
+    DeviceGuard g(ctx->device);
+    // Stages are whole imaging chunks, so every image is made by exactly the launches of
+    // nbsi_image_stokes and the result is bit-identical to the two calls in sequence.
+    const int chunk = image_stokes_chunk(plan);
+    const int n_chunks = (n_chan + chunk - 1) / chunk;
+    const int want = n_stages ? n_stages : NBSI_DEFAULT_STAGES;
+    const int per_stage = (n_chunks + want - 1) / want * chunk;
+    const int n_st = (n_chan + per_stage - 1) / per_stage;
+    void *inter = nullptr, *pad = nullptr;
+    if ((rc = nbsi_scratch(ctx, SLOT_IMG_INTER, chunk * image_stokes_per_chan(plan), &inter))) return rc;
+    if (const size_t pb = correlate_pad_bytes(std::min(per_stage, n_chan), n_in, n_spec))
+        if ((rc = nbsi_scratch(ctx, SLOT_CORR_PAD, pb, &pad))) return rc;
+    if ((rc = nbsi_aux_stream(ctx))) return rc;
+    const size_t q_row = (size_t)n_in * 2 * n_spec;
+    const size_t v_row = (size_t)n_in * (n_in + 1);  // int32 words of one channel's visibilities
+    const size_t s_row = (size_t)plan->n_pairs * 2;
+    hipError_t e = hipSuccess;
+    // Stage k is correlated on the caller's stream while stage k - 1 is imaged on the auxiliary
+    // stream: the correlator is bound by its writes, the gridder by vector and LDS work.
+    for (int k = 0; k < n_st && e == hipSuccess; k++) {
+        const int c0 = k * per_stage, cn = std::min(per_stage, n_chan - c0);
+        StokesOut so;
+        so.mask = plan->d_tmask;
+        so.base = plan->d_tbase;
+        so.out = reinterpret_cast<float2 *>(stokes_i + (size_t)c0 * s_row);
+        so.n_pairs = plan->n_pairs;
+        e = launch_correlate_i8(spec_q + (size_t)c0 * q_row, cn, n_in, n_spec, vis + (size_t)c0 * v_row, ctx->stream, so,
+                                (int8_t *)pad);
+        if (e == hipSuccess) e = hipEventRecord(ctx->ev_stage[k], ctx->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ctx->aux, ctx->ev_stage[k], 0);
+        if (e == hipSuccess)
+            e = image_stokes_range(plan, stokes_i, precision, (float2 *)inter, img, c0, c0 + cn, ctx->aux);
     }
+    // the caller's stream resumes only after the last image, also after a failed launch
+    const hipError_t e2 = hipEventRecord(ctx->ev_stage[NBSI_MAX_STAGES], ctx->aux);
+    const hipError_t e3 = e2 == hipSuccess ? hipStreamWaitEvent(ctx->stream, ctx->ev_stage[NBSI_MAX_STAGES], 0) : e2;
+    if (e == hipSuccess) e = e3;
+    if (e != hipSuccess) return nbsi_fail(ctx, NBSI_EHIP, std::string("nbsi_correlate_image: ") + hipGetErrorString(e));
     return NBSI_OK;
 }
 

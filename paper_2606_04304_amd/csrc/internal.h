@@ -18,6 +18,9 @@ struct nbsi_ctx {
     void *scratch[16] = {nullptr};
     size_t scratch_size[16] = {0};
     int *d_counter = nullptr;  // small device counters (detector)
+    // auxiliary stream and events of the overlapped correlate + image call (created on first use)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_stage[NBSI_MAX_STAGES + 1] = {};
 };
 
 enum ScratchSlot {

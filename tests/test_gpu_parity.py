@@ -381,6 +381,57 @@ def test_correlate_stokes_matches_separate_calls(n_ant, n_spec, n_chan, n_pix, r
         assert emax < 1e-5 and erms < 2e-6
 
 
+@pytest.mark.parametrize("n_ant,n_spec,n_pix,n_chan", [
+    (24, 16, 1024, 37),   # 16-channel imaging chunks: 3 chunks, the last ragged
+    (40, 48, 512, 70),    # 64-channel chunks, tiled correlator (n_spec > 32)
+    (16, 300, 256, 5),    # one chunk, n_spec padded to the 16-byte row stride
+])
+def test_correlate_image_overlapped_matches_sequential(n_ant, n_spec, n_pix, n_chan):
+    """The overlapped call gives the visibilities, Stokes-I rows and images of
+    nbsi_correlate_stokes followed by nbsi_image_stokes bit for bit, for every stage count
+    (default, one, two, more stages than chunks), twice in a row on one context."""
+    print(f"correlate_image n_ant={n_ant} n_spec={n_spec} n_pix={n_pix} n_chan={n_chan}", flush=True)
+    xyz = synth.antenna_layout(n_ant, 60.0, 700 + n_ant)
+    freq = np.linspace(40e6, 80e6, n_chan)
+    ctx = nb.nbsi_create(0)
+    plan = nb.nbsi_image_plan_create(xyz, freq, n_pix, nb.NBSI_IMAGE_GRID, ctx=ctx)
+    q = synth.random_spectra(n_chan, 2 * n_ant, n_spec, seed=n_ant * 7 + n_chan, full_range=True).to(DEV)
+    vis, st = nb.nbsi_correlate_stokes(q, plan)
+    img = nb.nbsi_image_stokes(plan, st)
+    torch.cuda.synchronize()
+    for n_stages in (0, 1, 2, 64, 0):
+        vis2, st2, img2 = nb.nbsi_correlate_image(q, plan, n_stages=n_stages)
+        # work queued after the call on the same stream sees the finished images
+        s = img2.sum(dim=(1, 2))
+        torch.cuda.synchronize()
+        assert torch.equal(vis, vis2), n_stages
+        assert torch.equal(st, st2), n_stages
+        assert torch.equal(img, img2), n_stages
+        assert torch.equal(s, img.sum(dim=(1, 2))), n_stages
+    img16 = nb.nbsi_image_stokes(plan, st, precision=nb.NBSI_PREC_FP16)
+    _, _, img16b = nb.nbsi_correlate_image(q, plan, precision=nb.NBSI_PREC_FP16, n_stages=3)
+    torch.cuda.synchronize()
+    assert torch.equal(img16, img16b)
+
+
+def test_correlate_image_rejects_bad_arguments():
+    xyz = synth.antenna_layout(24, 60.0, 3)
+    freq = synth.channel_freqs(65536, 32768, 2)
+    plan = nb.nbsi_image_plan_create(xyz, freq, 64, nb.NBSI_IMAGE_GRID)
+    q = synth.random_spectra(2, 48, 16, seed=1).to(DEV)
+    with pytest.raises(nb.NbsiError):
+        nb.nbsi_correlate_image(q, plan, n_stages=65)
+    with pytest.raises(nb.NbsiError):
+        nb.nbsi_correlate_image(q, plan, n_stages=-1)
+    with pytest.raises(nb.NbsiError):
+        nb.nbsi_correlate_image(q, plan, precision=7)
+    with pytest.raises(nb.NbsiError):
+        nb.nbsi_correlate_image(synth.random_spectra(2, 46, 16, seed=2).to(DEV), plan)
+    dft = nb.nbsi_image_plan_create(xyz, freq, 64, nb.NBSI_IMAGE_DFT)
+    with pytest.raises(nb.NbsiError):
+        nb.nbsi_correlate_image(q, dft)
+
+
 def test_correlate_stokes_rejects_mismatched_plan():
     xyz = synth.antenna_layout(24, 60.0, 3)
     freq = synth.channel_freqs(65536, 32768, 2)
