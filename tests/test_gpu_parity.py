@@ -98,6 +98,9 @@ CORR_CASES = [
     # n_chan, n_in, n_spec
     (1, 1, 1), (3, 2, 7), (9, 5, 16), (2, 64, 32), (2, 65, 33), (3, 130, 64),
     (1, 200, 100), (2, 352, 32), (1, 704, 32), (1, 64, 1024),
+    # more channels than the whole-channel kernel's grid of 384 workgroups: each walks several
+    # channels, the last round ragged
+    (1000, 48, 32), (777, 20, 64), (385, 96, 17),
 ]
 
 
