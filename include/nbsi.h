@@ -352,6 +352,10 @@ typedef struct nbsi_batch nbsi_batch;
 #define NBSI_BATCH_GRAPH 1     /* capture the launches into a hipGraph on the first run, replay after */
 #define NBSI_BATCH_AUTOTUNE 2  /* time correlator variants and gridding tiles per shape at plan time */
 #define NBSI_BATCH_GRID_TALL 4 /* grid with the 32-cell-per-thread tile everywhere (no gridding tuning) */
+#define NBSI_BATCH_OVERLAP 8   /* pipeline the sub-bands: while sub-band s is correlated and imaged on
+                                  an auxiliary stream of the batch, sub-band s + 1 is channelized
+                                  (stages launched per sub-band, directly: NBSI_BATCH_GRAPH is not
+                                  used with it; same outputs, bit for bit) */
 
 /*
  * Plan a batch: validates every sub-band, builds its imaging plan, allocates the batch's

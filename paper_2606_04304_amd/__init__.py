@@ -59,6 +59,7 @@ NBSI_NET_MAX_BATCH = 8192
 NBSI_BATCH_GRAPH = 1
 NBSI_BATCH_AUTOTUNE = 2
 NBSI_BATCH_GRID_TALL = 4
+NBSI_BATCH_OVERLAP = 8
 
 CAND_DTYPE = np.dtype([("x", np.int32), ("y", np.int32), ("c", np.int32), ("width", np.int32),
                        ("snr", np.float32)])
@@ -555,7 +556,7 @@ class Batch:
 
     def __init__(self, ant_xyz, subbands, precision: int = NBSI_PREC_FP32, graph: bool = True,
                  autotune: bool = False, tune_cache: str | None = None, ctx: Context | None = None,
-                 grid_tall: bool = False):
+                 grid_tall: bool = False, overlap: bool = False):
         torch = _torch()
         self.ctx = ctx or nbsi_create(0)
         dev = self.ctx.device
@@ -588,7 +589,7 @@ class Batch:
                                  d["spec_q"].data_ptr(), d["vis"].data_ptr(), d["img"].data_ptr())
             self.subbands.append(d)
         flags = ((NBSI_BATCH_GRAPH if graph else 0) | (NBSI_BATCH_AUTOTUNE if autotune else 0)
-                 | (NBSI_BATCH_GRID_TALL if grid_tall else 0))
+                 | (NBSI_BATCH_GRID_TALL if grid_tall else 0) | (NBSI_BATCH_OVERLAP if overlap else 0))
         h = ctypes.c_void_p()
         self.ctx._sync_stream()
         _check(lib().nbsi_batch_plan(self.ctx._h, self.ant_xyz.ctypes.data_as(ctypes.c_void_p), n_ant, arr,

@@ -40,6 +40,7 @@ struct nbsi_batch {
     struct Launch {  // one batched launch: kind, shape key, job array on the device
         int kind;    // 0 channelize, 1 corner turn, 2 correlate, 3 gather, 4 rows, 5 cols
         int a = 0, b = 0;  // kind-specific shape (log_m/g, variant, log_m/ge)
+        int group = 0;     // sub-band group (one group per sub-band with NBSI_BATCH_OVERLAP)
         int n_jobs = 0, n_tasks = 0, max_dyn = 0;
         void *d_jobs = nullptr;
         int *d_task0 = nullptr;
@@ -49,6 +50,11 @@ struct nbsi_batch {
 
     hipStream_t stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // NBSI_BATCH_OVERLAP: correlate and image launches run on `aux`, each group after the event
+    // recorded behind its corner turn on `stream`; `stream` joins `aux` at the end
+    hipStream_t aux = nullptr;
+    std::vector<hipEvent_t> ev_grp;
+    hipEvent_t ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool captured = false;
@@ -123,36 +129,55 @@ double time_ms(hipStream_t st, const std::function<hipError_t()> &fn, int reps) 
 }
 
 // Every stage of every sub-band, as the grouped launches.
-hipError_t enqueue_all(nbsi_batch *b, hipStream_t st) {
-    for (const auto &L : b->launches) {
-        hipError_t e = hipSuccess;
-        switch (L.kind) {
-            case 0:
-                e = launch_channelize_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, L.b, L.max_dyn, st);
-                break;
-            case 1:
-                e = launch_corner_turn_q_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.d_task0, L.n_tasks, L.d_outs,
-                                               b->n_in, st);
-                break;
-            case 2:
-                e = launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->n_in, L.b != 0, st);
-                break;
-            case 3: e = launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, st); break;
-            case 4:
-                e = launch_image_batch_rows((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->precision, L.b, st);
-                break;
-            case 5: e = launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.b, st); break;
-        }
-        if (e != hipSuccess) return e;
+hipError_t launch_one(const nbsi_batch *b, const nbsi_batch::Launch &L, hipStream_t st) {
+    switch (L.kind) {
+        case 0: return launch_channelize_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, L.b, L.max_dyn, st);
+        case 1:
+            return launch_corner_turn_q_batch((const ChanJob *)L.d_jobs, L.n_jobs, L.d_task0, L.n_tasks, L.d_outs,
+                                              b->n_in, st);
+        case 2: return launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->n_in, L.b != 0, st);
+        case 3: return launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, st);
+        case 4: return launch_image_batch_rows((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->precision, L.b, st);
+        case 5: return launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.b, st);
     }
-    return hipSuccess;
+    return hipErrorInvalidValue;
 }
 
-int build_launches(nbsi_batch *b) {
+hipError_t enqueue_all(nbsi_batch *b, hipStream_t st) {
+    if (!b->aux) {
+        for (const auto &L : b->launches) {
+            const hipError_t e = launch_one(b, L, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    // overlapped: channelize + corner turn of every group in order on st; a group's correlate
+    // and image launches on aux once its corner turn is done, so group g + 1 is channelized
+    // while group g is correlated and imaged
+    int last_linked = -1;
+    for (const auto &L : b->launches) {
+        const bool back = L.kind >= 2;
+        if (back && L.group != last_linked) {
+            hipError_t e = hipEventRecord(b->ev_grp[L.group], st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(b->aux, b->ev_grp[L.group], 0);
+            if (e != hipSuccess) return e;
+            last_linked = L.group;
+        }
+        const hipError_t e = launch_one(b, L, back ? b->aux : st);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(b->ev_join, b->aux);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join, 0);
+    return e;
+}
+
+// The launches of the sub-bands `members` (in order), tagged with `group`.
+int build_group_launches(nbsi_batch *b, const std::vector<int> &members, int group) {
+    const size_t first = b->launches.size();
     // channelize: one launch per (sub-transform size, load grouping, FFT length): the table LDS is
     // sized by the FFT length, and one size per launch keeps the occupancy of the shorter ones
     std::map<std::tuple<int, int, int>, std::vector<int>> cg;
-    for (int s = 0; s < b->n_sb; s++) {
+    for (int s : members) {
         const int log_n = 31 - __builtin_clz(b->sb[s].n_fft);
         const int lm = channelize_log_m(log_n, b->sb[s].n_chan);
         cg[std::make_tuple(lm, channelize_group(log_n, lm), log_n)].push_back(s);
@@ -186,7 +211,7 @@ int build_launches(nbsi_batch *b) {
         std::vector<int> t0;
         std::vector<int8_t *> outs;
         int tasks = 0;
-        for (int s = 0; s < b->n_sb; s++) {
+        for (int s : members) {
             const nbsi_subband &x = b->sb[s];
             jobs.push_back(ChanJob{x.volt, x.gain, b->stage[s], nullptr, 0, x.n_spec, 0, x.n_chan, tasks});
             t0.push_back(tasks);
@@ -195,7 +220,7 @@ int build_launches(nbsi_batch *b) {
         }
         nbsi_batch::Launch L;
         L.kind = 1;
-        L.n_jobs = b->n_sb;
+        L.n_jobs = (int)members.size();
         L.n_tasks = tasks;
         int rc = upload(b, jobs, (ChanJob **)&L.d_jobs);
         if (!rc) rc = upload(b, t0, &L.d_task0);
@@ -206,7 +231,7 @@ int build_launches(nbsi_batch *b) {
     // correlate: group by variant (and, for the tiled variant, by whether the spectra rows are
     // whole 16-byte vectors, which selects the vector-load form of its staging)
     std::map<std::pair<int, int>, std::vector<int>> kg;
-    for (int s = 0; s < b->n_sb; s++) {
+    for (int s : members) {
         const int v = b->corr_variant[s];
         kg[{v, v == CORR_VARIANT_TILED && (b->sb[s].n_spec & 15) == 0 ? 1 : 0}].push_back(s);
     }
@@ -233,7 +258,7 @@ int build_launches(nbsi_batch *b) {
     }
     // imager: per channel chunk a gather, a rows and a columns launch (below)
     std::vector<ImgJob> base(b->n_sb);
-    for (int s = 0; s < b->n_sb; s++) {
+    for (int s : members) {
         const nbsi_image_plan *p = b->plans[s];
         ImgJob &j = base[s];
         j.vis = b->sb[s].vis;
@@ -262,7 +287,7 @@ int build_launches(nbsi_batch *b) {
     // intermediate within IMAGE_CHUNK_BYTES: per chunk a gather, a rows and a columns launch, so
     // the Stokes-I gather and the intermediate are read back while still in the last-level cache
     std::map<std::pair<int, int>, std::vector<int>> rg;
-    for (int s = 0; s < b->n_sb; s++) rg[{base[s].log_m, b->grid_ge[s]}].push_back(s);
+    for (int s : members) rg[{base[s].log_m, b->grid_ge[s]}].push_back(s);
     for (auto &kv : rg) {
         const int ge = kv.first.second;
         std::vector<ImgJob> chunk;
@@ -341,6 +366,23 @@ int build_launches(nbsi_batch *b) {
         const int rc = flush();
         if (rc) return rc;
     }
+    for (size_t i = first; i < b->launches.size(); i++) b->launches[i].group = group;
+    return NBSI_OK;
+}
+
+// Every sub-band in one group (each stage one launch over all of them, grouped by shape), or
+// with NBSI_BATCH_OVERLAP one group per sub-band, so that the stages of consecutive sub-bands
+// can overlap.
+int build_launches(nbsi_batch *b) {
+    std::vector<std::vector<int>> groups;
+    if (b->flags & NBSI_BATCH_OVERLAP) {
+        for (int s = 0; s < b->n_sb; s++) groups.push_back({s});
+    } else {
+        groups.emplace_back();
+        for (int s = 0; s < b->n_sb; s++) groups.back().push_back(s);
+    }
+    for (size_t g = 0; g < groups.size(); g++)
+        if (const int rc = build_group_launches(b, groups[g], (int)g)) return rc;
     return NBSI_OK;
 }
 
@@ -348,11 +390,16 @@ void free_batch(nbsi_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->aux) (void)hipStreamSynchronize(b->aux);
     for (auto *p : b->plans)
         if (p) nbsi_image_plan_destroy(p);
     for (void *p : b->owned) (void)hipFree(p);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    for (hipEvent_t e : b->ev_grp)
+        if (e) (void)hipEventDestroy(e);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -406,6 +453,15 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
         return fail(NBSI_EHIP, "stream/event creation failed");
+    if (flags & NBSI_BATCH_OVERLAP) {
+        if (hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess)
+            return fail(NBSI_EHIP, "stream/event creation failed");
+        b->ev_grp.assign(n_sb, nullptr);
+        for (int s = 0; s < n_sb; s++)
+            if (hipEventCreateWithFlags(&b->ev_grp[s], hipEventDisableTiming) != hipSuccess)
+                return fail(NBSI_EHIP, "stream/event creation failed");
+    }
     std::map<std::string, int> cache = read_cache(tune_cache_path);
     bool cache_dirty = false;
     // per sub-band scratch, default choices
@@ -561,7 +617,9 @@ int nbsi_batch_run(nbsi_batch *b) {
     // order after the caller's stream, run on the batch stream, then order the caller after it
     if (hipEventRecord(b->ev_in, ctx->stream) != hipSuccess || hipStreamWaitEvent(b->stream, b->ev_in, 0) != hipSuccess)
         return done(nbsi_fail(ctx, NBSI_EHIP, "nbsi_batch_run: event ordering failed"));
-    if (b->flags & NBSI_BATCH_GRAPH) {
+    // with NBSI_BATCH_OVERLAP the launches go straight to the two streams: a captured graph of
+    // the two branches, replayed, overlapped them less (66.1 against 64.1 ms on twelve sub-bands)
+    if ((b->flags & NBSI_BATCH_GRAPH) && !b->aux) {
         if (!b->captured) {
             if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
                 return done(nbsi_fail(ctx, NBSI_EHIP, "nbsi_batch_run: capture failed to start"));

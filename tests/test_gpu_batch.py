@@ -81,12 +81,14 @@ def _same(batch, ref, img_exact=True):
             assert err <= 1e-5, f"sub-band {i}: image differs by {err:.2e} of the peak"
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_batch_equals_per_subband(graph):
-    print(f"batch small graph={graph}", flush=True)
+@pytest.mark.parametrize("graph,overlap", [(True, False), (False, False), (True, True), (False, True)])
+def test_batch_equals_per_subband(graph, overlap):
+    """overlap: sub-band s + 1 is channelized while sub-band s is correlated and imaged on the
+    batch's second stream (the graph flag is then not used)."""
+    print(f"batch small graph={graph} overlap={overlap}", flush=True)
     xyz, subs = _subbands(12, SMALL, seed=31)
     ref = _per_subband(xyz, subs)
-    b = nb.Batch(xyz, subs, graph=graph)
+    b = nb.Batch(xyz, subs, graph=graph, overlap=overlap)
     for rep in range(3):
         _poison(b)
         b.run()
@@ -161,6 +163,11 @@ def test_batch_reduced_precision_equals_per_subband(precision):
     b.close()
 
 
+def json_subbands(desc):
+    import json
+    return json.loads(desc)["subbands"]
+
+
 def test_batch_autotune_cache(tmp_path):
     print("batch autotune", flush=True)
     cache = str(tmp_path / "tune.txt")
@@ -184,6 +191,15 @@ def test_batch_autotune_cache(tmp_path):
     b2 = nb.Batch(xyz, subs, autotune=True, tune_cache=cache)
     assert b2.describe() == desc
     b2.close()
+    # the overlapped form takes the same choices from the cache and gives the tuned outputs
+    b3 = nb.Batch(xyz, subs, autotune=True, tune_cache=cache, overlap=True)
+    assert json_subbands(b3.describe()) == json_subbands(desc)
+    ref3 = [(d["spec_q"].clone(), d["vis"].clone(), d["img"].clone()) for d in b.subbands]
+    _poison(b3)
+    b3.run()
+    torch.cuda.synchronize()
+    _same(b3, ref3)
+    b3.close()
 
 
 def test_batch_rejects_bad_subbands():
@@ -211,10 +227,12 @@ def test_batch_uneven_subbands_full_size():
                          n_chan=c["n_chan"], n_pix=c["n_pix"],
                          freq_hz=synth.channel_freqs(c["n_fft"], c["chan0"], c["n_chan"], c["nu0"])))
     ref = _per_subband(xyz, subs)
-    b = nb.Batch(xyz, subs, graph=True)
-    for rep in range(2):
-        _poison(b)
-        b.run()
-        torch.cuda.synchronize()
-        _same(b, ref)
-    b.close()
+    for overlap in (False, True):
+        print(f"  overlap={overlap}", flush=True)
+        b = nb.Batch(xyz, subs, graph=True, overlap=overlap)
+        for rep in range(2):
+            _poison(b)
+            b.run()
+            torch.cuda.synchronize()
+            _same(b, ref)
+        b.close()
