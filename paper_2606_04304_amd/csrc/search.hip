@@ -5,11 +5,13 @@
 //
 // Kernels:
 //  * search_bank_kernel: a workgroup takes 64 consecutive pixels (one per lane) and 128
-//    channels (32 per wave).  It stages those channels plus the widest window's halo
-//    (64 below, 63 above) in LDS with coalesced 256-byte row loads, turns them into exclusive
-//    prefix sums along frequency in place (relative to the staged block, so window sums never
-//    carry the rounding of a long running sum), and for every channel takes the maximum of
-//    (P[s + w] - P[s]) / sqrt(w) over the widths whose window fits in the band.  It writes the
+//    channels (32 per wave).  Each wave loads a quarter of those channels plus the widest
+//    window's halo (64 below, 63 above) into registers with coalesced 256-byte row loads, all in
+//    flight at once, scans them there and writes exclusive prefix sums along frequency to LDS
+//    once (relative to the staged block, so window sums never carry the rounding of a long
+//    running sum); for every channel it takes the maximum of (P[s + w] - P[s]) / sqrt(w) over
+//    the widths whose window fits in the band (a test skipped for channels at least 64 from
+//    both band edges, where every window fits).  It writes the
 //    best SNR and width cubes and adds the in-horizon SNRs >= 3 to a histogram (1/32 bins;
 //    LDS first, then one global atomic per non-empty bin).
 //  * The host walks the histogram from the lowest bin up to find the largest k with
@@ -73,38 +75,33 @@ __global__ __launch_bounds__(256) void search_bank_kernel(const float *__restric
     const int p0 = blockIdx.x * SB_PX, c0 = blockIdx.y * SB_CB;
     const int base = c0 - SB_HALO_L;  // channel of staged row 0
     for (int i = t; i < HIST_BINS; i += 256) h_lds[i] = 0u;
-    // stage rows base .. base + SB_ROWS - 1 (zero outside the band and past the last pixel)
-    // eight independent loads in flight per thread before their LDS stores
-    for (int e0 = t; e0 < SB_ROWS * SB_PX; e0 += 8 * 256) {
-        float v[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const int e = e0 + 256 * u;
-            const int i = e >> 6, l = e & 63;
-            const int ch = base + i, pp = p0 + l;
-            v[u] = (e < SB_ROWS * SB_PX && ch >= 0 && ch < n_chan && pp < npx) ? r[(size_t)ch * npx + pp] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const int e = e0 + 256 * u;
-            if (e < SB_ROWS * SB_PX) P[((e >> 6) + 1) * SB_PX + (e & 63)] = v[u];
-        }
-    }
-    if (t < SB_PX) P[t] = 0.f;
-    __syncthreads();
-    // inclusive scan of each wave's segment of rows, then the totals of the segments below
+    // wave w loads its own segment of staged rows (one 256-byte row per load, its lane's pixel)
+    // into registers, all loads in flight at once, scans it there and writes the prefix sums
+    // once, offset by the totals of the segments below (rows outside the band or past the last
+    // pixel are zero)
     constexpr int SEG = (SB_ROWS + 3) / 4;
     const int i0 = wave * SEG, i1 = min(SB_ROWS, i0 + SEG);
+    const int pp = p0 + lane;
+    float v[SEG];
+#pragma unroll
+    for (int k = 0; k < SEG; k++) {
+        const int i = i0 + k, ch = base + i;
+        v[k] = (i < i1 && ch >= 0 && ch < n_chan && pp < npx) ? r[(size_t)ch * npx + pp] : 0.f;
+    }
     float run = 0.f;
-    for (int i = i0; i < i1; i++) {
-        run += P[(i + 1) * SB_PX + lane];
-        P[(i + 1) * SB_PX + lane] = run;
+#pragma unroll
+    for (int k = 0; k < SEG; k++) {
+        run += v[k];
+        v[k] = run;
     }
     seg_tot[wave][lane] = run;
+    if (t < SB_PX) P[t] = 0.f;
     __syncthreads();
     float off = 0.f;
     for (int k = 0; k < wave; k++) off += seg_tot[k][lane];
-    for (int i = i0; i < i1; i++) P[(i + 1) * SB_PX + lane] += off;
+#pragma unroll
+    for (int k = 0; k < SEG; k++)
+        if (i0 + k < i1) P[(i0 + k + 1) * SB_PX + lane] = v[k] + off;
     __syncthreads();
     const int p = p0 + lane;
     const bool pix_ok = p < npx;
@@ -123,22 +120,44 @@ __global__ __launch_bounds__(256) void search_bank_kernel(const float *__restric
             bs[q] = -INFINITY;
             bw[q] = 0;
         }
-        for (int k = 0; k < W.n; k++) {  // widths ascending: the narrower one wins ties
-            const int w = W.w[k], h = w >> 1;
-            const float inv = W.inv_sqrt[k];
-            float v[CQ];
+        // every window of these channels fits the band (h <= 64, w - h <= 64): no band test
+        const bool interior = cb >= SB_HALO_L && cb + CQ + SB_HALO_L <= n_chan;
+        if (interior) {
+            for (int k = 0; k < W.n; k++) {  // widths ascending: the narrower one wins ties
+                const int w = W.w[k], h = w >> 1;
+                const float inv = W.inv_sqrt[k];
+                float v[CQ];
 #pragma unroll
-            for (int q = 0; q < CQ; q++) {
-                const int is = cb + q - base - h;
-                v[q] = (P[(is + w) * SB_PX + lane] - P[is * SB_PX + lane]) * inv;
+                for (int q = 0; q < CQ; q++) {
+                    const int is = cb + q - base - h;
+                    v[q] = (P[(is + w) * SB_PX + lane] - P[is * SB_PX + lane]) * inv;
+                }
+#pragma unroll
+                for (int q = 0; q < CQ; q++) {
+                    if (v[q] > bs[q]) {
+                        bs[q] = v[q];
+                        bw[q] = w;
+                    }
+                }
             }
+        } else {
+            for (int k = 0; k < W.n; k++) {
+                const int w = W.w[k], h = w >> 1;
+                const float inv = W.inv_sqrt[k];
+                float v[CQ];
 #pragma unroll
-            for (int q = 0; q < CQ; q++) {
-                const int c = cb + q;
-                const bool fits = c < n_chan && c - h >= 0 && c - h + w <= n_chan;
-                if (fits && v[q] > bs[q]) {
-                    bs[q] = v[q];
-                    bw[q] = w;
+                for (int q = 0; q < CQ; q++) {
+                    const int is = cb + q - base - h;
+                    v[q] = (P[(is + w) * SB_PX + lane] - P[is * SB_PX + lane]) * inv;
+                }
+#pragma unroll
+                for (int q = 0; q < CQ; q++) {
+                    const int c = cb + q;
+                    const bool fits = c < n_chan && c - h >= 0 && c - h + w <= n_chan;
+                    if (fits && v[q] > bs[q]) {
+                        bs[q] = v[q];
+                        bw[q] = w;
+                    }
                 }
             }
         }
