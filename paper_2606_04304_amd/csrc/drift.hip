@@ -10,7 +10,8 @@
 // those pixels in LDS with coalesced 128-byte row loads, so each input value is read from HBM
 // once per workgroup and reused by all 2D + 1 trials from LDS.  All 33 trials are evaluated
 // (those beyond the requested drift masked), so each distinct (sub-integration, shift) value is
-// read once per channel.
+// read once per channel.  Channels at least D_MAX from both band edges with the full drift range
+// requested skip the per-trial band test (every track fits).
 #include "internal.h"
 
 #include <algorithm>
@@ -44,12 +45,12 @@ __global__ __launch_bounds__(256) void dedoppler_kernel(const float *__restrict_
     const size_t p0 = (size_t)blockIdx.x * DD_PX;
     const int c0 = blockIdx.y * DD_CB;
     const int base = c0 - NBSI_DEDOPPLER_MAX_DRIFT;
-    // eight independent loads in flight per thread before their LDS stores
+    // 24 independent loads in flight per thread before their LDS stores
     const int n_el = n_sub * DD_ROWS * DD_PX;
-    for (int e0 = t; e0 < n_el; e0 += 8 * 256) {
-        float v[8];
+    for (int e0 = t; e0 < n_el; e0 += 24 * 256) {
+        float v[24];
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
+        for (int u = 0; u < 24; u++) {
             const int e = e0 + 256 * u;
             const int l = e % DD_PX, row = (e / DD_PX) % DD_ROWS, s = e / (DD_PX * DD_ROWS);
             const int ch = base + row;
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(256) void dedoppler_kernel(const float *__restrict_
             v[u] = (e < n_el && ch >= 0 && ch < n_chan && p < npx) ? r[((size_t)s * n_chan + ch) * npx + p] : 0.f;
         }
 #pragma unroll
-        for (int u = 0; u < 8; u++)
+        for (int u = 0; u < 24; u++)
             if (e0 + 256 * u < n_el) tile[e0 + 256 * u] = v[u];
     }
     __syncthreads();
@@ -71,17 +72,35 @@ __global__ __launch_bounds__(256) void dedoppler_kernel(const float *__restrict_
         float bv = -INFINITY;
         int bd = 0;
         const float *col = tile + ic * DD_PX + lane;
+        // every trial's track lies in the band and is requested: no per-trial test
+        const bool all_ok = max_drift == NBSI_DEDOPPLER_MAX_DRIFT && c >= NBSI_DEDOPPLER_MAX_DRIFT &&
+                            c + NBSI_DEDOPPLER_MAX_DRIFT < n_chan;
+        if (all_ok) {
 #pragma unroll
-        for (int k = 0; k < 2 * NBSI_DEDOPPLER_MAX_DRIFT + 1; k++) {  // 0, -1, +1, -2, +2, ...
-            const int d = (k == 0) ? 0 : ((k & 1) ? -((k + 1) >> 1) : (k >> 1));
-            float acc = 0.f;
+            for (int k = 0; k < 2 * NBSI_DEDOPPLER_MAX_DRIFT + 1; k++) {  // 0, -1, +1, -2, +2, ...
+                const int d = (k == 0) ? 0 : ((k & 1) ? -((k + 1) >> 1) : (k >> 1));
+                float acc = 0.f;
 #pragma unroll
-            for (int s = 0; s < n_sub; s++) acc += col[(s * DD_ROWS + drift_shift(d, s, n_sub)) * DD_PX];
-            const float v = acc * inv;
-            const bool ok = k < 2 * max_drift + 1 && c + d >= 0 && c + d < n_chan;
-            if (ok && v > bv) {
-                bv = v;
-                bd = d;
+                for (int s = 0; s < n_sub; s++) acc += col[(s * DD_ROWS + drift_shift(d, s, n_sub)) * DD_PX];
+                const float v = acc * inv;
+                if (v > bv) {
+                    bv = v;
+                    bd = d;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 2 * NBSI_DEDOPPLER_MAX_DRIFT + 1; k++) {
+                const int d = (k == 0) ? 0 : ((k & 1) ? -((k + 1) >> 1) : (k >> 1));
+                float acc = 0.f;
+#pragma unroll
+                for (int s = 0; s < n_sub; s++) acc += col[(s * DD_ROWS + drift_shift(d, s, n_sub)) * DD_PX];
+                const float v = acc * inv;
+                const bool ok = k < 2 * max_drift + 1 && c + d >= 0 && c + d < n_chan;
+                if (ok && v > bv) {
+                    bv = v;
+                    bd = d;
+                }
             }
         }
         best[(size_t)c * npx + p] = bv;
