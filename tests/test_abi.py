@@ -94,6 +94,22 @@ def test_null_context_is_rejected():
     assert L.nbsi_detect(None, None, 8, 8, 0, 5.0, None, None, 0, ctypes.byref(n)) == nb.NBSI_EINVAL
     assert L.nbsi_destroy(None) == nb.NBSI_EINVAL
     assert L.nbsi_synchronize(None) == nb.NBSI_EINVAL
+    assert L.nbsi_correlate_stokes(None, None, 1, 2, 1, None, None, None) == nb.NBSI_EINVAL
+    assert L.nbsi_image_stokes(None, None, None, 0, None) == nb.NBSI_EINVAL
+    assert L.nbsi_correlate_image(None, None, 1, 2, 1, None, 0, 0, None, None, None) == nb.NBSI_EINVAL
+
+
+def test_binding_constants_match_the_header():
+    """Every integer #define of include/nbsi.h that the binding also names has the same value."""
+    text = open(os.path.join(ROOT, "include", "nbsi.h")).read()
+    defs = {}
+    for name, val in re.findall(r"^#define\s+(NBSI_\w+)\s+(\(1 << \d+\)|\(-?\d+\)|-?\d+)", text, re.M):
+        defs[name] = eval(val, {"__builtins__": {}})
+    shared = [n for n in defs if hasattr(nb, n)]
+    assert len(shared) >= 20, shared
+    for n in shared:
+        assert getattr(nb, n) == defs[n], (n, getattr(nb, n), defs[n])
+    assert defs["NBSI_BATCH_OVERLAP"] == 8 and defs["NBSI_DEFAULT_STAGES"] >= 1
 
 
 def test_create_without_gfx950_fails_cleanly():
