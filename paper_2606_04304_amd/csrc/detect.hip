@@ -771,6 +771,36 @@ __global__ void bitonic_step_kernel(unsigned long long *__restrict__ keys, int n
     }
 }
 
+// The same bitonic network for at most SORT1_MAX candidates in one workgroup: keys in LDS, a
+// barrier between steps (each pair (i, i ^ j) is handled by the thread of its lower index), and
+// the gather of the sorted records.  One launch instead of one per step.
+constexpr int SORT1_MAX = 4096;
+__global__ __launch_bounds__(1024) void sort_small_kernel(const nbsi_cand *__restrict__ cand, int n, int n_pow2,
+                                                          int n_chan, int n_pix, int n_out,
+                                                          nbsi_cand *__restrict__ out) {
+    __shared__ unsigned long long s[SORT1_MAX];
+    const int t = threadIdx.x;
+    for (int i = t; i < n_pow2; i += 1024)
+        s[i] = (i < n) ? ((cand_key(cand[i], n_chan, n_pix) << 24) | (unsigned long long)i) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= n_pow2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = t; i < n_pow2; i += 1024) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const unsigned long long a = s[i], b = s[p];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        s[i] = b;
+                        s[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = t; i < n_out; i += 1024) out[i] = cand[(int)(s[i] & 0xffffffull)];
+}
+
 __global__ void gather_sorted_kernel(const unsigned long long *__restrict__ keys, const nbsi_cand *__restrict__ cand,
                                      int n_out, nbsi_cand *__restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -841,6 +871,11 @@ hipError_t launch_detect_sort(nbsi_cand *cand, int n, unsigned long long *keys, 
     if (n <= 0 || n_out <= 0) return hipSuccess;
     int n_pow2 = 1;
     while (n_pow2 < n) n_pow2 <<= 1;
+    if (n_pow2 <= SORT1_MAX) {
+        hipLaunchKernelGGL(sort_small_kernel, dim3(1), dim3(1024), 0, st, cand, n, n_pow2, n_chan, n_pix,
+                           n_out <= n ? n_out : n, out);
+        return hipGetLastError();
+    }
     const int blocks = (n_pow2 + 255) / 256;
     hipLaunchKernelGGL(sort_keys_kernel, dim3(blocks), dim3(256), 0, st, cand, n, n_pow2, n_chan, n_pix, keys);
     for (int k = 2; k <= n_pow2; k <<= 1)
