@@ -245,8 +245,9 @@ int nbsi_detect(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode
  *      n_widths in [1, NBSI_SEARCH_MAX_WIDTHS] widths in [1, NBSI_SEARCH_MAX_WIDTH].
  *   2. p = erfc(S / sqrt 2) / 2; Benjamini-Hochberg at level fdr_q in (0, 1) over the
  *      m = (in-horizon pixels) x n_chan voxels: the k* largest S are provisional detections,
- *      k* = max{k : p_(k) <= k fdr_q / m}.  The threshold is found among S >= 3: when BH would
- *      accept every voxel at or above 3 the call returns NBSI_EUNSUPPORTED.
+ *      k* = max{k : p_(k) <= k fdr_q / m}, exactly, for every fdr_q (BH accepts no
+ *      p-value above fdr_q, so only S >= Q^-1(fdr_q) are ranked; values of S are compared in
+ *      float32 as the kernel computed them, p in float64 from libm erfc).
  *   3. A provisional detection survives when no other one at its pixel within max(floor(w/2), 1)
  *      channels is higher (a lower channel wins ties), and
  *   4. when its SNR recomputed against the median and 1.4826 MAD of its flanks (guard w,

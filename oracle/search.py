@@ -16,19 +16,19 @@ width-1 detector: unit-variance noise, spectral median removed):
    p = Q(S) = erfc(S / sqrt 2) / 2.  Benjamini-Hochberg at level q over all m searched voxels
    (in-horizon pixels x channels): k* = max{k : p_(k) <= k q / m}; the voxels with the k*
    smallest p-values (equivalently the k* largest S) are provisional detections; none if no k.
-   The BH decision threshold in SNR units is S* = the k*-th largest S.  The step-up search is
-   made among S >= 3 (FLOOR): if BH would accept every voxel at or above the floor the search
-   is reported as unresolved (ValueError), as the GPU library does.
+   The BH decision threshold in SNR units is S* = the k*-th largest S.  Every one of the m
+   in-horizon voxels takes part in the step-up comparison.
 4. Non-maximum suppression along frequency at each pixel: a provisional detection survives if no
    other provisional detection at that pixel within its exclusion region, of half-width
    max(floor(w/2), 1) channels around its channel, has a higher SNR (on ties the lower channel
    survives).
-5. Local re-evaluation (reading of "re-estimating the small-scale baseline and recomputing the
-   SNR"): with the detection's window [s, s + w), s = c - floor(w/2), guard g = w and flank
-   length L = max(16, 2 w), the flanks [s - g - L, s - g) and [s + w + g, s + w + g + L) inside
-   the band give a baseline b (median) and noise sigma = 1.482602218505602 * MAD; the
-   re-evaluated SNR is sum_{window}(r - b) / (sqrt(w) sigma).  The detection is kept when that
-   is >= S*; with fewer than 8 flank channels or sigma = 0 it is discarded.
+5. Local re-evaluation (reading: the baseline is re-estimated from the flanks next to the
+   detection and the SNR recomputed against it): with the detection's window [s, s + w),
+   s = c - floor(w/2), guard g = w and flank length L = max(16, 2 w), the flanks
+   [s - g - L, s - g) and [s + w + g, s + w + g + L) inside the band give a baseline b (median)
+   and noise sigma = 1.482602218505602 * MAD; the re-evaluated SNR is
+   sum_{window}(r - b) / (sqrt(w) sigma).  The detection is kept when that is >= S*; with
+   fewer than 8 flank channels or sigma = 0 it is discarded.
 
 Medians of even counts are the mean of the two central order statistics.  Output records
 (x, y, c, width, snr = the matched-filter S) sorted by (y, x, c).
@@ -43,7 +43,6 @@ from .detect import MAD_K, horizon_mask, median_even_mean
 
 WIDTHS = tuple(list(range(1, 11)) + list(range(12, 49, 4)) + list(range(50, 101, 10)))
 REEVAL_MIN_FLANK = 8
-FLOOR = 3.0
 
 
 def boxcar_bank(r: np.ndarray, widths=WIDTHS) -> tuple[np.ndarray, np.ndarray]:
@@ -134,10 +133,7 @@ def search(r: np.ndarray, q: float = 0.01, widths=WIDTHS, valid: np.ndarray | No
     S, W = boxcar_bank(r, widths)
     Sv = S[:, valid]
     m = int(valid.sum()) * n_chan
-    top = Sv[Sv >= FLOOR]
-    kstar, sstar = bh_threshold(top, m, q)
-    if kstar > 0 and kstar == top.size:
-        raise ValueError("the Benjamini-Hochberg threshold reaches the floor")
+    kstar, sstar = bh_threshold(Sv.ravel(), m, q)
     flatS, flatW = S.reshape(n_chan, -1), W.reshape(n_chan, -1)
     acc = (flatS >= sstar) & valid.ravel()[None, :]
     surv = nms(flatS, flatW, acc)

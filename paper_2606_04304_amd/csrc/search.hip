@@ -12,8 +12,11 @@
 //    running sum); for every channel it takes the maximum of (P[s + w] - P[s]) / sqrt(w) over
 //    the widths whose window fits in the band (a test skipped for channels at least 64 from
 //    both band edges, where every window fits).  It writes the
-//    best SNR and width cubes and adds the in-horizon SNRs >= 3 to a histogram (1/32 bins;
-//    LDS first, then one global atomic per non-empty bin).
+//    best SNR and width cubes and adds the in-horizon SNRs at or above a floor F to a histogram
+//    (1/32 bins; LDS first, then one global atomic per non-empty bin).  Benjamini-Hochberg never
+//    accepts a p-value above q (k q / m <= q), so no voxel with S < Q^-1(q) is ever accepted; F
+//    lies at least one bin below Q^-1(q), and the step-up search over the histogram is the
+//    search over all m voxels.
 //  * The host walks the histogram from the lowest bin up to find the largest k with
 //    p_(k) <= k q / m; only a bin where that is undecided by its edges is gathered exactly
 //    (search_gather_kernel) and sorted on the host.
@@ -36,9 +39,9 @@ constexpr int SB_CB = 128;                                   // channels per wor
 constexpr int SB_HALO_L = NBSI_SEARCH_MAX_WIDTH / 2;         // floor(w / 2) <= 64
 constexpr int SB_HALO_R = NBSI_SEARCH_MAX_WIDTH / 2 - 1;     // w - floor(w / 2) - 1 <= 63
 constexpr int SB_ROWS = SB_CB + SB_HALO_L + SB_HALO_R;       // staged channels
-constexpr float HIST_LO = 3.0f;                              // histogram floor (SNR)
 constexpr int HIST_PER_UNIT = 32;
-constexpr int HIST_BINS = 61 * HIST_PER_UNIT + 1;            // [3, 64) in 1/32 steps, then >= 64
+constexpr int HIST_SPAN = 64;                                // SNR units of 1/32 bins above F
+constexpr int HIST_BINS = HIST_SPAN * HIST_PER_UNIT + 1;     // [F, F + 64) in 1/32 steps, then >= F + 64
 constexpr int FLANK_MAX = 4 * NBSI_SEARCH_MAX_WIDTH;         // two flanks of at most 2 w_max each
 constexpr int REEVAL_MIN_FLANK = 8;
 constexpr float MAD_TO_SIGMA = 1.482602218505602f;
@@ -59,13 +62,21 @@ __device__ __forceinline__ bool in_horizon(int p, int n_pix) {
     return (x - h) * (x - h) + (y - h) * (y - h) < h * h;
 }
 
-__device__ __forceinline__ int hist_bin(float s) {
-    const float u = (s - HIST_LO) * (float)HIST_PER_UNIT;
-    return u >= (float)(HIST_BINS - 1) ? HIST_BINS - 1 : (int)u;
+// Bin of an SNR s >= F = f32 / 32: bin j holds [(f32 + j) / 32, (f32 + j + 1) / 32).  s * 32 is
+// exact (a power-of-two scale), so the bin edges are exact and no value lands beside its bin.
+__device__ __forceinline__ int hist_bin(float s, int f32) {
+    const float u = s * (float)HIST_PER_UNIT;
+    return u >= (float)(f32 + HIST_BINS - 1) ? HIST_BINS - 1 : (int)floorf(u) - f32;
+}
+
+// Order-preserving map of a float to an unsigned key (negative values below positive ones).
+__device__ __forceinline__ unsigned order_key(float s) {
+    const unsigned b = __float_as_uint(s);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
 __global__ __launch_bounds__(256) void search_bank_kernel(const float *__restrict__ r, int n_chan, int n_pix,
-                                                          Widths W, float *__restrict__ best,
+                                                          Widths W, int f32, float *__restrict__ best,
                                                           uint8_t *__restrict__ wbest, unsigned *__restrict__ hist) {
     __shared__ float P[(SB_ROWS + 1) * SB_PX];  // P[i][lane] = sum of staged rows < i (exclusive)
     __shared__ float seg_tot[4][SB_PX];
@@ -104,6 +115,7 @@ __global__ __launch_bounds__(256) void search_bank_kernel(const float *__restric
         if (i0 + k < i1) P[(i0 + k + 1) * SB_PX + lane] = v[k] + off;
     __syncthreads();
     const int p = p0 + lane;
+    const float hist_lo = (float)f32 / (float)HIST_PER_UNIT;  // exact
     const bool pix_ok = p < npx;
     const bool hor = pix_ok && in_horizon(p, n_pix);
     // eight channels at a time: sixteen independent LDS reads per width.  Every index stays
@@ -169,7 +181,7 @@ __global__ __launch_bounds__(256) void search_bank_kernel(const float *__restric
                 best[(size_t)c * npx + p] = bs[q];
                 wbest[(size_t)c * npx + p] = (uint8_t)bw[q];
             }
-            if (hor && bs[q] >= HIST_LO) atomicAdd(&h_lds[hist_bin(bs[q])], 1u);
+            if (hor && bs[q] >= hist_lo) atomicAdd(&h_lds[hist_bin(bs[q], f32)], 1u);
         }
     }
     __syncthreads();
@@ -192,7 +204,8 @@ __global__ __launch_bounds__(256) void search_gather_kernel(const float *__restr
     }
 }
 
-// In-horizon voxels with SNR >= thr (the provisional detections) and the smallest such SNR.
+// In-horizon voxels with SNR >= thr (the provisional detections) and the order key of the
+// smallest such SNR.
 __global__ __launch_bounds__(256) void search_accept_kernel(const float *__restrict__ best,
                                                             const uint8_t *__restrict__ wbest, int n_chan, int n_pix,
                                                             float thr, Cand *__restrict__ out, int cap,
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(256) void search_accept_kernel(const float *__restr
         if (s >= thr && in_horizon((int)(e % npx), n_pix)) {
             const int i = atomicAdd(counter, 1);
             if (i < cap) out[i] = Cand{(int)(e / npx), (int)(e % npx), (int)wbest[e], s};
-            atomicMin(min_bits, __float_as_uint(s));  // s >= 3 > 0: unsigned order = float order
+            atomicMin(min_bits, order_key(s));
         }
     }
 }
@@ -338,6 +351,11 @@ extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pi
         W.w[k] = ws[k];
         W.inv_sqrt[k] = (float)(1.0 / sqrt((double)ws[k]));
     }
+    // histogram floor F = f32 / 32: a whole bin below Q^-1(q) (q_tail(f32 / 32 + 1 / 32) > q), far
+    // beyond erfc's rounding, so every voxel BH can accept is counted
+    int kq = -32 * HIST_PER_UNIT;
+    while (kq < HIST_SPAN * HIST_PER_UNIT && q_tail((double)(kq + 1) / HIST_PER_UNIT) > fdr_q) kq++;
+    const int f32 = kq - 1;
     DeviceGuard g(ctx->device);
     const size_t npx = (size_t)n_pix * n_pix, nvox = (size_t)n_chan * npx;
     void *S = best_snr, *Wc = best_width, *hist = nullptr;
@@ -346,7 +364,7 @@ extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pi
     if ((rc = nbsi_scratch(ctx, SLOT_SEARCH_HIST, sizeof(unsigned) * HIST_BINS, &hist))) return rc;
     NBSI_TRY_HIP(ctx, hipMemsetAsync(hist, 0, sizeof(unsigned) * HIST_BINS, ctx->stream));
     hipLaunchKernelGGL(search_bank_kernel, dim3((unsigned)((npx + SB_PX - 1) / SB_PX), (unsigned)((n_chan + SB_CB - 1) / SB_CB)),
-                       dim3(256), 0, ctx->stream, snr, n_chan, n_pix, W, (float *)S, (uint8_t *)Wc, (unsigned *)hist);
+                       dim3(256), 0, ctx->stream, snr, n_chan, n_pix, W, f32, (float *)S, (uint8_t *)Wc, (unsigned *)hist);
     NBSI_TRY_HIP(ctx, hipGetLastError());
     std::vector<unsigned> h(HIST_BINS);
     NBSI_TRY_HIP(ctx, hipMemcpyAsync(h.data(), hist, sizeof(unsigned) * HIST_BINS, hipMemcpyDeviceToHost, ctx->stream));
@@ -360,7 +378,7 @@ extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pi
     const double m = (double)n_hor * (double)n_chan;
     std::vector<int64_t> above(HIST_BINS + 1, 0);  // above[j] = #{S >= lower edge of bin j}
     for (int j = HIST_BINS - 1; j >= 0; j--) above[j] = above[j + 1] + h[j];
-    auto lo_of = [](int j) { return (double)HIST_LO + (double)j / HIST_PER_UNIT; };
+    auto lo_of = [f32](int j) { return (double)(f32 + j) / HIST_PER_UNIT; };
 
     // Benjamini-Hochberg: the largest k with p_(k) <= k q / m.  Bins are visited from the lowest
     // SNR (largest k) up; a bin is skipped when even its highest SNR cannot satisfy the rule,
@@ -400,20 +418,18 @@ extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pi
             }
         }
     }
-    if (kstar > 0 && kstar == above[0])
-        return nbsi_fail(ctx, NBSI_EUNSUPPORTED,
-                         "nbsi_search: the Benjamini-Hochberg threshold reaches the 3-sigma histogram floor");
     *n_out = 0;
     if (thresh_host) *thresh_host = INFINITY;
     if (n_provisional_host) *n_provisional_host = kstar;
     if (kstar == 0) return NBSI_OK;
 
     // provisional detections
-    const int cap = (int)above[std::max(0, (int)((thr_acc - HIST_LO) * HIST_PER_UNIT))];
+    const int j_acc = (int)floor((double)thr_acc * HIST_PER_UNIT) - f32;  // the bin holding thr_acc
+    const int cap = (int)above[std::min(HIST_BINS - 1, std::max(0, j_acc))];
     void *cands = nullptr, *keep = nullptr;
     if ((rc = nbsi_scratch(ctx, SLOT_SEARCH_CAND, sizeof(Cand) * (size_t)std::max(cap, 1), &cands))) return rc;
     if ((rc = nbsi_scratch(ctx, SLOT_SEARCH_KEEP, sizeof(int) * (size_t)std::max(cap, 1), &keep))) return rc;
-    const unsigned init[2] = {0u, 0x7f800000u};  // counter, +inf bits
+    const unsigned init[2] = {0u, 0xffffffffu};  // counter, the largest order key
     NBSI_TRY_HIP(ctx, hipMemcpyAsync(ctx->d_counter, init, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
     hipLaunchKernelGGL(search_accept_kernel, dim3(4096), dim3(256), 0, ctx->stream, (const float *)S, (const uint8_t *)Wc,
                        n_chan, n_pix, thr_acc, (Cand *)cands, cap, ctx->d_counter, (unsigned *)(ctx->d_counter + 1));
@@ -423,9 +439,10 @@ extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pi
     NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const int n_acc = (int)got[0];
     if (n_acc > cap) return nbsi_fail(ctx, NBSI_EHIP, "nbsi_search: provisional detections exceed the histogram count");
-    if (!exact) {
+    if (!exact) {  // invert the order key of the smallest accepted SNR
+        const unsigned bits = (got[1] & 0x80000000u) ? (got[1] & 0x7fffffffu) : ~got[1];
         float mn;
-        memcpy(&mn, &got[1], sizeof(float));
+        memcpy(&mn, &bits, sizeof(float));
         sstar = mn;
     }
     if (thresh_host) *thresh_host = sstar;

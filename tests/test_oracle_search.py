@@ -164,8 +164,33 @@ def test_search_finds_injected_line_and_nothing_in_noise():
     assert (others["snr"] < sstar + 0.5).all()
 
 
-def test_search_reports_threshold_at_the_floor():
-    # every searched voxel far above 3: BH accepts all of them, which the floor cannot resolve
+@pytest.mark.parametrize("sigma,q", [(1.4, 0.05), (1.0, 0.2), (1.0, 0.6)])
+def test_search_bh_over_every_searched_voxel(sigma, q):
+    # Benjamini-Hochberg over all m in-horizon voxels (Sec. 2.4), pinned to SciPy's adjusted
+    # p-values over the same voxels.  Noise wider than the unit-normal model (sigma = 1.4, as
+    # Hann-correlated channels give) or a lenient level puts the threshold well below 3 SNR; at
+    # q = 0.6 the step-up reaches voxels with S < 0 (p > 1/2)
+    rng = np.random.default_rng(int(sigma * 100 + q * 1000))
+    n_chan, n = 96, 12
+    r = sigma * rng.standard_normal((n_chan, n, n))
+    r[40:46, 5, 6] += 3.0
+    rec, S, W, kstar, sstar = osr.search(r, q=q)
+    valid = oracle.detect.horizon_mask(n)
+    sv = S[:, valid].ravel()
+    rej = scipy.stats.false_discovery_control(osr.q_value(sv), method="bh") <= q
+    assert kstar == int(rej.sum()) > 0
+    assert sstar == sv[rej].min() and sstar < 3.0
+    if q == 0.6:
+        assert sstar < 0.0
+    # suppression and re-evaluation see exactly the accepted voxels
+    assert all(S[int(a["c"]), int(a["y"]), int(a["x"])] >= sstar for a in rec)
+
+
+def test_search_accepts_every_voxel_when_all_are_significant():
+    # every searched voxel far above any threshold: BH accepts all m of them; constant flanks
+    # (MAD 0) then discard every survivor at the re-evaluation
     r = np.full((64, 8, 8), 4.0)
-    with pytest.raises(ValueError):
-        osr.search(r, q=0.05)
+    rec, S, _, kstar, sstar = osr.search(r, q=0.05)
+    m = int(oracle.detect.horizon_mask(8).sum()) * 64
+    assert kstar == m and sstar == S[:, oracle.detect.horizon_mask(8)].min()
+    assert len(rec) == 0
