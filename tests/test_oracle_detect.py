@@ -94,3 +94,30 @@ def test_records_sorted_by_y_x_c():
     keys = list(zip(rec["y"], rec["x"], rec["c"]))
     assert keys == sorted(keys)
     assert {(3, 4, 7), (3, 9, 5), (3, 9, 40), (9, 3, 10)} <= set(keys)
+
+
+def test_per_image_mode_hand_computed():
+    # A 4 x 4 image has nine pixels in the visible hemisphere, the 3 x 3 block x, y in {1, 2, 3}.
+    # Channel c holds m_c + s_c v there, with v = -4..4 in raster order over the block (channel 2
+    # reversed); so each channel's in-horizon median is m_c and its MAD 2 s_c, and
+    # z = v / (2k) in channels 0 and 1 and -v / (2k) in channel 2.  Per pixel the median of z over
+    # the three channels is v / (2k), so the standardised residual is (0, 0, -v / k).
+    # A huge value at the below-horizon pixel (0, 0) changes nothing; had it entered the
+    # per-image statistics, every median would move.  Had the per-pixel spectral median not
+    # been removed, channels 0 and 1 would keep v / (2k).
+    k = D.MAD_K
+    v = np.arange(-4.0, 5.0).reshape(3, 3)
+    m_c, s_c = (10.0, -5.0, 100.0), (1.0, 3.0, 0.5)
+    cube = np.zeros((3, 4, 4))
+    for c in range(3):
+        vc = v if c < 2 else v[::-1, ::-1]
+        cube[c, 1:4, 1:4] = m_c[c] + s_c[c] * vc
+    cube[:, 0, 0] = 1e6
+    rec, snr, valid = D.detect(cube, tau=2.5, mode="per_image")
+    expect = np.zeros((3, 4, 4))
+    expect[2, 1:4, 1:4] = -v / k
+    np.testing.assert_allclose(snr, expect, atol=1e-12)
+    assert valid.sum() == 9 and not valid[0, 0]
+    # only v = -4 (pixel (1, 1)) reaches 4 / k = 2.698 >= 2.5, in channel 2
+    assert [(int(a["x"]), int(a["y"]), int(a["c"])) for a in rec] == [(1, 1, 2)]
+    assert rec["snr"][0] == pytest.approx(4.0 / k, rel=1e-12)

@@ -113,3 +113,22 @@ def test_uv_range_cut(orc):
     # nu = c: |uv| of (1,0) = 4, (2,0) = 10, (2,1) = sqrt(116)
     n_b = orc.count_baselines(xyz, np.array([C]), 0, 5.0, 10.5)
     assert n_b[0] == 1
+
+
+@pytest.mark.parametrize("grid_n_pix,uv_min,uv_max", [(0, 0.0, np.inf), (32, 0.0, np.inf), (0, 2.0, 9.0)])
+def test_pixel_list_equals_full_image(orc, grid_n_pix, uv_min, uv_max):
+    # the direct Fourier image evaluated at a list of pixels is the full image at those pixels
+    # (the same sum, written a second time for large images), for every baseline-set rule
+    rng = np.random.default_rng(17)
+    n_ant, n_chan, n = 12, 3, 32
+    xyz = np.zeros((n_ant, 3))
+    xyz[:, :2] = rng.uniform(-40.0, 40.0, (n_ant, 2))
+    freq = 70e6 + 1e3 * np.arange(n_chan)
+    n_in = 2 * n_ant
+    vis = rng.standard_normal((n_chan, n_in * (n_in + 1) // 2, 2)) * 100.0
+    full = orc.image_dft(vis, xyz, freq, n, grid_n_pix, uv_min, uv_max)
+    pix = np.array([(0, 0), (31, 31), (16, 16), (3, 29), (29, 3), (7, 11), (16, 0), (0, 16)])
+    got = orc.image_dft_pixels(vis, xyz, freq, n, pix, grid_n_pix, uv_min, uv_max)
+    ref = full[:, pix[:, 1], pix[:, 0]]
+    assert np.abs(ref).max() > 1.0
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(full).max())
