@@ -236,6 +236,22 @@ int nbsi_detect(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode
                 float *snr, nbsi_cand *out, int max_out, int *n_out);
 
 /*
+ * nbsi_detect for callers that cannot allocate device memory (serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and results, with the detector's statistics, candidate
+ * buffer, sort keys and counter in a fixed workspace of NBSI_DETECT_NOALLOC_BYTES per GPU
+ * (a static device array, resolved by nbsi_create and held until the process ends); the call
+ * allocates nothing.  Same arguments, layouts and ownership as nbsi_detect.  More than
+ * NBSI_DETECT_NOALLOC_MAX_CANDS candidates (before truncation to max_out) returns
+ * NBSI_EOVERFLOW with nothing written to out.  Every call on one GPU shares that GPU's
+ * workspace: calls that overlap on one GPU (several contexts or streams at once) race.
+ * Blocks until the result is written.
+ */
+#define NBSI_DETECT_NOALLOC_MAX_CANDS 65536
+#define NBSI_DETECT_NOALLOC_BYTES 2097408
+int nbsi_detect_noalloc(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode,
+                        float thresh, float *snr, nbsi_cand *out, int max_out, int *n_out);
+
+/*
  * Full Stage I search (Sec. 2.4: matched filtering over line widths, FDR control, suppression of
  * repeated triggers along frequency, local re-evaluation) on a standardised residual cube
  * snr [n_chan][n_pix][n_pix] (e.g. nbsi_detect's PER_PIXEL or PER_IMAGE SNR output):

@@ -43,7 +43,10 @@ EXPORTS = [
     "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
     "nbsi_net_train_step", "nbsi_correlate_kernel", "nbsi_image_plan_pairs", "nbsi_correlate_stokes",
     "nbsi_image_stokes", "nbsi_correlate_image", "nbsi_search", "nbsi_correlate_cal", "nbsi_dedoppler", "nbsi_beam", "nbsi_stage2",
+    "nbsi_detect_noalloc",
 ]
+NBSI_DETECT_NOALLOC_MAX_CANDS = 65536
+NBSI_DETECT_NOALLOC_BYTES = 2097408
 NBSI_DEDOPPLER_MAX_SUB = 8
 NBSI_DEDOPPLER_MAX_DRIFT = 16
 NBSI_S2_FIT_FAILED, NBSI_S2_EXTENDED, NBSI_S2_NOISY, NBSI_S2_OUTSIDE = 1, 2, 4, 8
@@ -121,6 +124,7 @@ def lib():
         L.nbsi_search.argtypes = [P, P, I, I, P, I, D, P, P, P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_float),
                                   ctypes.POINTER(ctypes.c_int64)]
         L.nbsi_detect.argtypes = [P, P, I, I, I, ctypes.c_float, P, P, I, P]
+        L.nbsi_detect_noalloc.argtypes = [P, P, I, I, I, ctypes.c_float, P, P, I, P]
         L.nbsi_batch_plan.argtypes = [P, P, I, P, I, I, I, ctypes.c_char_p, ctypes.POINTER(P)]
         L.nbsi_batch_run.argtypes = [P]
         L.nbsi_batch_describe.argtypes = [P, ctypes.c_char_p, I]
@@ -517,25 +521,39 @@ def fits_host(out, n: int) -> np.ndarray:
     return out.reshape(-1)[:n * FIT_DTYPE.itemsize].cpu().numpy().copy().view(FIT_DTYPE).reshape(-1)
 
 
-def nbsi_detect(img, mode: int = NBSI_DETECT_PER_PIXEL, thresh: float = 5.0, want_snr: bool = False,
-                max_out: int = 1 << 20, ctx: Context | None = None):
-    """img [n_chan][n_pix][n_pix] float32 -> (candidates as a numpy structured array sorted by
-    (y, x, c), snr cube or None).  Blocks until the candidate count is known."""
+def _detect_call(fn, img, mode, thresh, want_snr, max_out, ctx, snr=None, out=None):
     torch = _torch()
     ctx = ctx or nbsi_create(img.device.index or 0)
     _need(img, torch.float32, "img", ctx.device)
     n_chan, n_pix, _ = img.shape
-    snr = torch.empty_like(img) if want_snr else None
-    out = torch.empty((max(1, max_out), 5), dtype=torch.int32, device=ctx.device)
+    if want_snr and snr is None:
+        snr = torch.empty_like(img)
+    if out is None:
+        out = torch.empty((max(1, max_out), 5), dtype=torch.int32, device=ctx.device)
     n_out = ctypes.c_int(0)
     ctx._sync_stream()
-    st = lib().nbsi_detect(ctx._h, _ptr(img), n_chan, n_pix, int(mode), float(thresh), _ptr(snr),
-                           _ptr(out), int(max_out), ctypes.byref(n_out))
+    st = fn(ctx._h, _ptr(img), n_chan, n_pix, int(mode), float(thresh), _ptr(snr), _ptr(out), int(max_out),
+            ctypes.byref(n_out))
     if st not in (NBSI_OK, NBSI_ETRUNC):
         _check(st, ctx)
     n = min(n_out.value, max_out)
     rec = out[:n].cpu().numpy().view(CAND_DTYPE).reshape(-1)
     return rec, snr, n_out.value
+
+
+def nbsi_detect(img, mode: int = NBSI_DETECT_PER_PIXEL, thresh: float = 5.0, want_snr: bool = False,
+                max_out: int = 1 << 20, ctx: Context | None = None):
+    """img [n_chan][n_pix][n_pix] float32 -> (candidates as a numpy structured array sorted by
+    (y, x, c), snr cube or None).  Blocks until the candidate count is known."""
+    return _detect_call(lib().nbsi_detect, img, mode, thresh, want_snr, max_out, ctx)
+
+
+def nbsi_detect_noalloc(img, mode: int = NBSI_DETECT_PER_PIXEL, thresh: float = 5.0, snr=None, out=None,
+                        max_out: int = 1 << 16, ctx: Context | None = None):
+    """nbsi_detect with the library's fixed per-GPU workspace: the C call allocates nothing.
+    snr (optional [n_chan][n_pix][n_pix] float32) and out ([max_out][5] int32) are the caller's
+    tensors (out is allocated here when not given).  Returns (candidates, snr, true count)."""
+    return _detect_call(lib().nbsi_detect_noalloc, img, mode, thresh, False, max_out, ctx, snr=snr, out=out)
 
 
 class NbsiSubband(ctypes.Structure):

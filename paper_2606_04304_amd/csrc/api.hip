@@ -5,11 +5,43 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
 int channelize_log_m(int log_n, int n_chan);
 int detect_ppw(int n_chan);
+
+// Fixed workspace of the no-allocation detector entry point: one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself (on the host it names a stand-in, not
+// device memory); it uses the address hipGetSymbolAddress returns on each device, resolved
+// once per device by nbsi_create with that device current.  Layout: candidate counter, the
+// per-channel statistics of up to 32,768 channels, NBSI_DETECT_NOALLOC_MAX_CANDS candidates
+// and as many sort keys.
+constexpr size_t NOALLOC_OFF_COUNTER = 0;
+constexpr size_t NOALLOC_OFF_STATS = 256;
+constexpr size_t NOALLOC_OFF_CAND = NOALLOC_OFF_STATS + sizeof(float2) * 32768;
+constexpr size_t NOALLOC_OFF_KEYS = NOALLOC_OFF_CAND + sizeof(nbsi_cand) * (size_t)NBSI_DETECT_NOALLOC_MAX_CANDS;
+constexpr size_t NOALLOC_END = NOALLOC_OFF_KEYS + sizeof(unsigned long long) * (size_t)NBSI_DETECT_NOALLOC_MAX_CANDS;
+static_assert(NOALLOC_END == NBSI_DETECT_NOALLOC_BYTES, "workspace layout");
+static_assert(NOALLOC_OFF_CAND % 256 == 0 && NOALLOC_OFF_KEYS % 256 == 0, "workspace alignment");
+
+static __device__ __align__(256) unsigned char scratch[NBSI_DETECT_NOALLOC_BYTES];
+
+constexpr int NBSI_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NBSI_MAX_DEVICES] = {};
+
+// Resolve this device's copy of the workspace (the device must be current).
+static int resolve_noalloc_scratch(int device) {
+    if (device < 0 || device >= NBSI_MAX_DEVICES) return NBSI_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return NBSI_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return NBSI_EHIP;
+    g_scratch_ptr[device] = ptr;
+    return NBSI_OK;
+}
 
 namespace {
 
@@ -126,6 +158,65 @@ hipError_t image_stokes_range(const nbsi_image_plan *plan, const float *stokes_i
     return hipSuccess;
 }
 
+// Workspace of the detector when the caller's call may not allocate: stats, the candidate
+// buffer (cap entries), sort keys for cap entries and the candidate counter.
+struct DetectWs {
+    float *stats = nullptr;
+    nbsi_cand *cand = nullptr;
+    unsigned long long *keys = nullptr;
+    int *counter = nullptr;
+    int cap = 0;
+};
+
+// nbsi_detect with context scratch (ws null; grown when the candidates overflow it) or with a
+// fixed workspace (ws set; more candidates than it holds is an error, nothing is allocated).
+int detect_run(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode, float thresh, float *snr,
+               nbsi_cand *out, int max_out, int *n_out, const DetectWs *ws, const char *who) {
+    if (!ctx) return NBSI_EINVAL;
+    const std::string w(who);
+    int rc = nbsi_check_detect(n_chan, n_pix, mode, max_out);
+    if (rc) return nbsi_fail(ctx, rc, w + ": bad shape");
+    if (!img || !n_out || (max_out > 0 && !out)) return nbsi_fail(ctx, NBSI_EINVAL, w + ": null pointer");
+    if (!aligned16(img) || (snr && !aligned16(snr)) || (out && !aligned16(out)))
+        return nbsi_fail(ctx, NBSI_EINVAL, w + ": misaligned pointer");
+    DeviceGuard g(ctx->device);
+    void *stats = ws ? (void *)ws->stats : nullptr;
+    if (!ws && (rc = nbsi_scratch(ctx, SLOT_DET_STATS, sizeof(float2) * n_chan, &stats))) return rc;
+    int *counter = ws ? ws->counter : ctx->d_counter;
+    NBSI_TRY_HIP(ctx, launch_detect_stats(img, n_chan, n_pix, mode, (float *)stats, ctx->stream));
+    int cap = ws ? ws->cap : (int)std::max<size_t>(65536, ctx->scratch_size[SLOT_DET_CAND] / sizeof(nbsi_cand));
+    int count = 0;
+    void *cand = nullptr;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        cand = ws ? (void *)ws->cand : nullptr;
+        if (!ws && (rc = nbsi_scratch(ctx, SLOT_DET_CAND, sizeof(nbsi_cand) * (size_t)cap, &cand))) return rc;
+        NBSI_TRY_HIP(ctx, hipMemsetAsync(counter, 0, sizeof(int), ctx->stream));
+        NBSI_TRY_HIP(ctx, launch_detect_scan(img, n_chan, n_pix, mode, (const float *)stats, thresh, snr,
+                                             (nbsi_cand *)cand, cap, counter, ctx->stream));
+        NBSI_TRY_HIP(ctx, hipMemcpyAsync(&count, counter, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (count <= cap) break;
+        if (ws)
+            return nbsi_fail(ctx, NBSI_EOVERFLOW,
+                             w + ": " + std::to_string(count) + " candidates, more than the fixed workspace's " +
+                                 std::to_string(cap) + " (use nbsi_detect)");
+        if (count > (1 << 24)) return nbsi_fail(ctx, NBSI_EOVERFLOW, w + ": more than 2^24 candidates");
+        cap = count;
+    }
+    *n_out = count;
+    const int n_write = std::min(count, max_out);
+    if (count > 0 && n_write > 0) {
+        int n_pow2 = 1;
+        while (n_pow2 < count) n_pow2 <<= 1;
+        void *keys = ws ? (void *)ws->keys : nullptr;
+        if (!ws && (rc = nbsi_scratch(ctx, SLOT_DET_KEYS, sizeof(unsigned long long) * n_pow2, &keys))) return rc;
+        NBSI_TRY_HIP(ctx, launch_detect_sort((nbsi_cand *)cand, count, (unsigned long long *)keys, n_chan, n_pix, out,
+                                             n_write, ctx->stream));
+        NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return count > max_out ? NBSI_ETRUNC : NBSI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -206,6 +297,11 @@ int nbsi_create(nbsi_ctx **out, int device, void *stream) {
     if (!g.ok || hipMalloc(&ctx->d_counter, 256) != hipSuccess) {
         delete ctx;
         return NBSI_EHIP;
+    }
+    if (const int rs = resolve_noalloc_scratch(device)) {
+        (void)hipFree(ctx->d_counter);
+        delete ctx;
+        return rs;
     }
     *out = ctx;
     return NBSI_OK;
@@ -652,42 +748,25 @@ int nbsi_correlate_image(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_
 
 int nbsi_detect(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode, float thresh, float *snr,
                 nbsi_cand *out, int max_out, int *n_out) {
+    return detect_run(ctx, img, n_chan, n_pix, mode, thresh, snr, out, max_out, n_out, nullptr, "nbsi_detect");
+}
+
+int nbsi_detect_noalloc(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode, float thresh, float *snr,
+                        nbsi_cand *out, int max_out, int *n_out) {
     if (!ctx) return NBSI_EINVAL;
-    int rc = nbsi_check_detect(n_chan, n_pix, mode, max_out);
-    if (rc) return nbsi_fail(ctx, rc, "nbsi_detect: bad shape");
-    if (!img || !n_out || (max_out > 0 && !out)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_detect: null pointer");
-    if (!aligned16(img) || (snr && !aligned16(snr)) || (out && !aligned16(out)))
-        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_detect: misaligned pointer");
-    DeviceGuard g(ctx->device);
-    void *stats = nullptr;
-    if ((rc = nbsi_scratch(ctx, SLOT_DET_STATS, sizeof(float2) * n_chan, &stats))) return rc;
-    NBSI_TRY_HIP(ctx, launch_detect_stats(img, n_chan, n_pix, mode, (float *)stats, ctx->stream));
-    int cap = (int)std::max<size_t>(65536, ctx->scratch_size[SLOT_DET_CAND] / sizeof(nbsi_cand));
-    int count = 0;
-    for (int attempt = 0; attempt < 2; attempt++) {
-        void *cand = nullptr;
-        if ((rc = nbsi_scratch(ctx, SLOT_DET_CAND, sizeof(nbsi_cand) * (size_t)cap, &cand))) return rc;
-        NBSI_TRY_HIP(ctx, hipMemsetAsync(ctx->d_counter, 0, sizeof(int), ctx->stream));
-        NBSI_TRY_HIP(ctx, launch_detect_scan(img, n_chan, n_pix, mode, (const float *)stats, thresh, snr,
-                                             (nbsi_cand *)cand, cap, ctx->d_counter, ctx->stream));
-        NBSI_TRY_HIP(ctx, hipMemcpyAsync(&count, ctx->d_counter, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-        NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        if (count <= cap) break;
-        if (count > (1 << 24)) return nbsi_fail(ctx, NBSI_EOVERFLOW, "nbsi_detect: more than 2^24 candidates");
-        cap = count;
+    char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (ctx->device >= 0 && ctx->device < NBSI_MAX_DEVICES) base = static_cast<char *>(g_scratch_ptr[ctx->device]);
     }
-    *n_out = count;
-    const int n_write = std::min(count, max_out);
-    if (count > 0 && n_write > 0) {
-        int n_pow2 = 1;
-        while (n_pow2 < count) n_pow2 <<= 1;
-        void *keys = nullptr;
-        if ((rc = nbsi_scratch(ctx, SLOT_DET_KEYS, sizeof(unsigned long long) * n_pow2, &keys))) return rc;
-        NBSI_TRY_HIP(ctx, launch_detect_sort((nbsi_cand *)ctx->scratch[SLOT_DET_CAND], count,
-                                             (unsigned long long *)keys, n_chan, n_pix, out, n_write, ctx->stream));
-        NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    }
-    return count > max_out ? NBSI_ETRUNC : NBSI_OK;
+    if (!base) return nbsi_fail(ctx, NBSI_EHIP, "nbsi_detect_noalloc: the device's fixed workspace was not resolved");
+    DetectWs ws;
+    ws.counter = reinterpret_cast<int *>(base + NOALLOC_OFF_COUNTER);
+    ws.stats = reinterpret_cast<float *>(base + NOALLOC_OFF_STATS);
+    ws.cand = reinterpret_cast<nbsi_cand *>(base + NOALLOC_OFF_CAND);
+    ws.keys = reinterpret_cast<unsigned long long *>(base + NOALLOC_OFF_KEYS);
+    ws.cap = NBSI_DETECT_NOALLOC_MAX_CANDS;
+    return detect_run(ctx, img, n_chan, n_pix, mode, thresh, snr, out, max_out, n_out, &ws, "nbsi_detect_noalloc");
 }
 
 }  // extern "C"
