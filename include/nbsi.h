@@ -81,6 +81,31 @@ const char *nbsi_last_error(const nbsi_ctx *ctx);
 int nbsi_synchronize(nbsi_ctx *ctx);
 
 /*
+ * Device-side status of a context: bits that kernels set when they meet non-finite numbers or
+ * saturate (the data conditions a caller cannot see from the return codes, which report only
+ * argument and runtime errors):
+ *   NBSI_FLAG_SPEC_NONFINITE  nbsi_channelize: some g_i X was not finite (a non-finite or
+ *                             overflowing gain); its spec_f value is written as computed and
+ *                             its int8 code is 0.
+ *   NBSI_FLAG_SPEC_CLIPPED    nbsi_channelize: some requantised component saturated at +-127.
+ *   NBSI_FLAG_IMAGE_NONFINITE nbsi_image, nbsi_image_stokes, nbsi_correlate_image, nbsi_batch_run:
+ *                             some output pixel is not finite (a non-finite input visibility
+ *                             in the imaged set, which spreads over the image).
+ *   NBSI_FLAG_CUBE_NONFINITE  nbsi_detect, nbsi_detect_noalloc: some pixel inside the visible
+ *                             hemisphere has a non-finite value in its spectrum; that pixel is
+ *                             not searched (its SNR output is 0, as outside the hemisphere),
+ *                             and PER_IMAGE statistics use each channel's finite pixels only.
+ * nbsi_status waits for the context's work (its stream and auxiliary stream), stores the bits
+ * set since the previous nbsi_status of this context (or its creation) in *flags_host and
+ * clears them.  Kernels of every call on the context set them; contexts do not share them.
+ */
+#define NBSI_FLAG_SPEC_NONFINITE 1
+#define NBSI_FLAG_SPEC_CLIPPED 2
+#define NBSI_FLAG_IMAGE_NONFINITE 4
+#define NBSI_FLAG_CUBE_NONFINITE 8
+int nbsi_status(nbsi_ctx *ctx, uint32_t *flags_host);
+
+/*
  * Host-only argument checks, also run first by each call below.  They need no GPU.
  * nbsi_check_channelize: n_fft a power of two in [2^8, 2^18]; 1 <= n_spec <= NBSI_MAX_SPEC;
  *   n_chan >= 1, 0 <= chan0, chan0 + n_chan <= n_fft, n_chan <= 16384 (the kept band must fit

@@ -21,6 +21,9 @@ Follows the paper's Stage I (Sec. 2.4) reduced to the width-1 matched filter:
 5. Only pixels inside the visible hemisphere, l^2 + m^2 < 1, are searched; with
    l = (x - N/2) 2/N this is the integer test (x - N/2)^2 + (y - N/2)^2 < (N/2)^2.
    Pixels whose MAD is zero give no detections.
+6. Non-finite input (reading; the paper's images are finite): a pixel whose spectrum holds a
+   non-finite value cannot be standardised and is not searched, like a pixel below the
+   horizon; in per_image mode each channel's statistics use its finite in-horizon pixels.
 
 Output: records (x, y, c, snr, width) sorted by (y, x, c).
 """
@@ -62,16 +65,28 @@ def snr_cube(cube: np.ndarray, mode: str = "per_pixel") -> tuple[np.ndarray, np.
     n_chan, n_pix, _ = cube.shape
     mask = horizon_mask(n_pix)
     flat = cube.reshape(n_chan, -1)[:, mask.ravel()]          # [C][P_in]
+    fin = np.isfinite(flat)
+    fin_pix = fin.all(axis=0)                                 # searchable: whole spectrum finite
     if mode == "per_pixel":
-        snr, good = per_pixel_snr(flat)
+        snr = np.zeros_like(flat)
+        snr[:, fin_pix], good = per_pixel_snr(flat[:, fin_pix])
+        good_all = np.zeros(flat.shape[1], dtype=bool)
+        good_all[fin_pix] = good
+        good = good_all
     elif mode == "per_image":
-        med_c = median_even_mean(flat, axis=1)                # per channel image
-        mad_c = median_even_mean(np.abs(flat - med_c[:, None]), axis=1)
-        goodc = mad_c > 0
         z = np.zeros_like(flat)
-        z[goodc] = (flat[goodc] - med_c[goodc, None]) / (MAD_K * mad_c[goodc, None])
-        snr = z - median_even_mean(z, axis=0)[None, :]
-        good = np.ones(flat.shape[1], dtype=bool)
+        for c in range(n_chan):                               # per channel image, finite pixels
+            vals = flat[c, fin[c]]
+            if vals.size == 0:
+                continue
+            med_c = float(median_even_mean(vals, axis=0))
+            mad_c = float(median_even_mean(np.abs(vals - med_c), axis=0))
+            if mad_c > 0:
+                z[c, fin[c]] = (vals - med_c) / (MAD_K * mad_c)
+        snr = np.zeros_like(flat)
+        zf = z[:, fin_pix]
+        snr[:, fin_pix] = zf - median_even_mean(zf, axis=0)[None, :]
+        good = fin_pix
     else:
         raise ValueError(mode)
     out = np.zeros((n_chan, n_pix * n_pix), dtype=np.float64)

@@ -43,8 +43,12 @@ EXPORTS = [
     "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
     "nbsi_net_train_step", "nbsi_correlate_kernel", "nbsi_image_plan_pairs", "nbsi_correlate_stokes",
     "nbsi_image_stokes", "nbsi_correlate_image", "nbsi_search", "nbsi_correlate_cal", "nbsi_dedoppler", "nbsi_beam", "nbsi_stage2",
-    "nbsi_detect_noalloc",
+    "nbsi_detect_noalloc", "nbsi_status",
 ]
+NBSI_FLAG_SPEC_NONFINITE = 0x1
+NBSI_FLAG_SPEC_CLIPPED = 0x2
+NBSI_FLAG_IMAGE_NONFINITE = 0x4
+NBSI_FLAG_CUBE_NONFINITE = 0x8
 NBSI_DETECT_NOALLOC_MAX_CANDS = 65536
 NBSI_DETECT_NOALLOC_BYTES = 2097408
 NBSI_DEDOPPLER_MAX_SUB = 8
@@ -102,6 +106,7 @@ def lib():
         L.nbsi_last_error.argtypes = [P]
         L.nbsi_last_error.restype = ctypes.c_char_p
         L.nbsi_synchronize.argtypes = [P]
+        L.nbsi_status.argtypes = [P, ctypes.POINTER(ctypes.c_uint32)]
         L.nbsi_check_channelize.argtypes = [I, I, I, I, I]
         L.nbsi_check_correlate.argtypes = [I, I, I]
         L.nbsi_check_image.argtypes = [I, I, I, I, I, D, D]
@@ -196,6 +201,15 @@ class Context:
 
 
 _default = {}
+
+
+def nbsi_status(ctx: "Context | None" = None) -> int:
+    """Wait for the context's work and return (and clear) its NBSI_FLAG_* bits."""
+    ctx = ctx or nbsi_create(0)
+    ctx._sync_stream()
+    f = ctypes.c_uint32(0)
+    _check(lib().nbsi_status(ctx._h, ctypes.byref(f)), ctx)
+    return int(f.value)
 
 
 def nbsi_create(device: int = 0) -> Context:

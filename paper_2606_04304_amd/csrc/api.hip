@@ -142,7 +142,7 @@ int image_stokes_chunk(const nbsi_image_plan *plan) {
 
 // Images of channels [c_begin, c_end) (c_begin a multiple of the chunk) from their Stokes-I rows.
 hipError_t image_stokes_range(const nbsi_image_plan *plan, const float *stokes_i, int precision, float2 *inter,
-                              float *img, int c_begin, int c_end, hipStream_t st) {
+                              float *img, int c_begin, int c_end, hipStream_t st, unsigned *flags) {
     const int chunk = image_stokes_chunk(plan);
     const float2 *sv = reinterpret_cast<const float2 *>(stokes_i);
     for (int c0 = c_begin; c0 < c_end; c0 += chunk) {
@@ -152,7 +152,7 @@ hipError_t image_stokes_range(const nbsi_image_plan *plan, const float *stokes_i
         sub.d_nb = plan->d_nb + c0;
         if (plan->d_inb) sub.d_inb = plan->d_inb + (size_t)c0 * ((plan->n_pairs + 31) >> 5);
         const hipError_t e = launch_image_grid_stokes(&sub, sv + (size_t)c0 * plan->n_pairs, precision, inter,
-                                                      img + (size_t)c0 * plan->n_pix * plan->n_pix, st);
+                                                      img + (size_t)c0 * plan->n_pix * plan->n_pix, st, flags);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -192,7 +192,7 @@ int detect_run(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode,
         if (!ws && (rc = nbsi_scratch(ctx, SLOT_DET_CAND, sizeof(nbsi_cand) * (size_t)cap, &cand))) return rc;
         NBSI_TRY_HIP(ctx, hipMemsetAsync(counter, 0, sizeof(int), ctx->stream));
         NBSI_TRY_HIP(ctx, launch_detect_scan(img, n_chan, n_pix, mode, (const float *)stats, thresh, snr,
-                                             (nbsi_cand *)cand, cap, counter, ctx->stream));
+                                             (nbsi_cand *)cand, cap, counter, ctx->stream, ctx->d_flags));
         NBSI_TRY_HIP(ctx, hipMemcpyAsync(&count, counter, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
         if (count <= cap) break;
@@ -298,7 +298,14 @@ int nbsi_create(nbsi_ctx **out, int device, void *stream) {
         delete ctx;
         return NBSI_EHIP;
     }
+    if (hipMalloc(&ctx->d_flags, 256) != hipSuccess || hipMemset(ctx->d_flags, 0, 256) != hipSuccess) {
+        if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+        (void)hipFree(ctx->d_counter);
+        delete ctx;
+        return NBSI_EHIP;
+    }
     if (const int rs = resolve_noalloc_scratch(device)) {
+        (void)hipFree(ctx->d_flags);
         (void)hipFree(ctx->d_counter);
         delete ctx;
         return rs;
@@ -319,6 +326,7 @@ int nbsi_destroy(nbsi_ctx *ctx) {
     for (int s = 0; s < 16; s++)
         if (ctx->scratch[s]) (void)hipFree(ctx->scratch[s]);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
+    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     delete ctx;
     return NBSI_OK;
 }
@@ -338,6 +346,19 @@ int nbsi_synchronize(nbsi_ctx *ctx) {
     return NBSI_OK;
 }
 
+int nbsi_status(nbsi_ctx *ctx, uint32_t *flags_host) {
+    if (!ctx || !flags_host) return NBSI_EINVAL;
+    DeviceGuard g(ctx->device);
+    NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->aux) NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->aux));
+    unsigned f = 0;
+    NBSI_TRY_HIP(ctx, hipMemcpyAsync(&f, ctx->d_flags, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+    NBSI_TRY_HIP(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof(f), ctx->stream));
+    NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *flags_host = f;
+    return NBSI_OK;
+}
+
 int nbsi_channelize(nbsi_ctx *ctx, const int8_t *volt, int n_in, int n_fft, int n_spec, int chan0,
                     int n_chan, const float *gain, int8_t *spec_q, float *spec_f) {
     if (!ctx) return NBSI_EINVAL;
@@ -354,7 +375,7 @@ int nbsi_channelize(nbsi_ctx *ctx, const int8_t *volt, int n_in, int n_fft, int 
     if (spec_q && (rc = nbsi_scratch(ctx, SLOT_CHAN_STAGE_Q, cells * 2, &sq))) return rc;
     if (spec_f && (rc = nbsi_scratch(ctx, SLOT_CHAN_STAGE_F, cells * 8, &sf))) return rc;
     NBSI_TRY_HIP(ctx, launch_channelize(volt, n_in, log_n, n_spec, klo, n_chan, gain, (int8_t *)sq, (float *)sf,
-                                        ctx->stream));
+                                        ctx->stream, ctx->d_flags));
     if (spec_q) NBSI_TRY_HIP(ctx, launch_corner_turn_q((int8_t *)sq, n_in, n_spec, n_chan, spec_q, ctx->stream));
     if (spec_f) NBSI_TRY_HIP(ctx, launch_corner_turn_f((float *)sf, n_in, n_spec, n_chan, spec_f, ctx->stream));
     return NBSI_OK;
@@ -649,7 +670,7 @@ int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int 
     if (!aligned16(vis) || !aligned16(img)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_image: misaligned pointer");
     DeviceGuard g(ctx->device);
     if (plan->method == NBSI_IMAGE_DFT) {
-        NBSI_TRY_HIP(ctx, launch_image_dft(plan, vis, vis_dtype, img, ctx->stream));
+        NBSI_TRY_HIP(ctx, launch_image_dft(plan, vis, vis_dtype, img, ctx->stream, ctx->d_flags));
         return NBSI_OK;
     }
     // Gridding runs over chunks of channels small enough for the row-transformed intermediate
@@ -672,7 +693,7 @@ int nbsi_image(nbsi_ctx *ctx, const nbsi_image_plan *plan, const void *vis, int 
         if (plan->d_inb) sub.d_inb = plan->d_inb + (size_t)c0 * ((plan->n_pairs + 31) >> 5);
         NBSI_TRY_HIP(ctx, launch_image_grid(&sub, (const char *)vis + vis_chan_bytes * c0, vis_dtype, precision,
                                             (float2 *)cvis, (float2 *)inter,
-                                            img + (size_t)c0 * plan->n_pix * plan->n_pix, ctx->stream));
+                                            img + (size_t)c0 * plan->n_pix * plan->n_pix, ctx->stream, ctx->d_flags));
     }
     return NBSI_OK;
 }
@@ -687,7 +708,8 @@ int nbsi_image_stokes(nbsi_ctx *ctx, const nbsi_image_plan *plan, const float *s
     void *inter = nullptr;
     if ((rc = nbsi_scratch(ctx, SLOT_IMG_INTER, image_stokes_chunk(plan) * image_stokes_per_chan(plan), &inter)))
         return rc;
-    NBSI_TRY_HIP(ctx, image_stokes_range(plan, stokes_i, precision, (float2 *)inter, img, 0, plan->n_chan, ctx->stream));
+    NBSI_TRY_HIP(ctx, image_stokes_range(plan, stokes_i, precision, (float2 *)inter, img, 0, plan->n_chan, ctx->stream,
+                                         ctx->d_flags));
     return NBSI_OK;
 }
 
@@ -736,7 +758,7 @@ int nbsi_correlate_image(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_
         if (e == hipSuccess) e = hipEventRecord(ctx->ev_stage[k], ctx->stream);
         if (e == hipSuccess) e = hipStreamWaitEvent(ctx->aux, ctx->ev_stage[k], 0);
         if (e == hipSuccess)
-            e = image_stokes_range(plan, stokes_i, precision, (float2 *)inter, img, c0, c0 + cn, ctx->aux);
+            e = image_stokes_range(plan, stokes_i, precision, (float2 *)inter, img, c0, c0 + cn, ctx->aux, ctx->d_flags);
     }
     // the caller's stream resumes only after the last image, also after a failed launch
     const hipError_t e2 = hipEventRecord(ctx->ev_stage[NBSI_MAX_STAGES], ctx->aux);

@@ -189,7 +189,7 @@ int build_group_launches(nbsi_batch *b, const std::vector<int> &members, int gro
             const nbsi_subband &x = b->sb[s];
             const int log_n = 31 - __builtin_clz(x.n_fft);
             ChanJob j{x.volt, x.gain, b->stage[s], nullptr, log_n, x.n_spec, (x.chan0 + x.n_fft / 2) & (x.n_fft - 1),
-                      x.n_chan, tasks};
+                      x.n_chan, tasks, b->ctx->d_flags};
             jobs.push_back(j);
             tasks += b->n_in * x.n_spec;
             max_dyn = std::max(max_dyn, channelize_dyn_elems(log_n, std::get<0>(kv.first)));
@@ -282,6 +282,7 @@ int build_group_launches(nbsi_batch *b, const std::vector<int> &members, int gro
         j.n_chan = p->n_chan;
         j.uv_min = p->uv_min;
         j.uv_max = p->uv_max;
+        j.flags = b->ctx->d_flags;
     }
     // channel chunks of every sub-band of one (transform size, tile height), each chunk's row
     // intermediate within IMAGE_CHUNK_BYTES: per chunk a gather, a rows and a columns launch, so

@@ -226,20 +226,27 @@ __device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, in
 
     const float g = jb.gain[i];
     const size_t rowo = ((size_t)i * n_spec + s) * (size_t)n_chan;
+    unsigned fl = 0;  // NBSI_FLAG_SPEC_* met by this thread
 #pragma unroll
     for (int r = 0; r < E; r++) {
         if (!(kept & (1u << r))) continue;
         const int k1 = t + r * NT;
         const int d = (k1 - klo) & (M - 1);
         const float2 gx = make_float2(acc[r].x * g, acc[r].y * g);
+        const bool fin = __builtin_isfinite(gx.x) && __builtin_isfinite(gx.y);
+        fl |= fin ? 0u : NBSI_FLAG_SPEC_NONFINITE;
         if (jb.stage_f) jb.stage_f[rowo + d] = gx;
         if (jb.stage_q) {
-            const float qr = fminf(fmaxf(rintf(gx.x), -127.f), 127.f);
-            const float qi = fminf(fmaxf(rintf(gx.y), -127.f), 127.f);
+            // a non-finite value has no code: it is requantised to 0 (and flagged)
+            const float rr = fin ? rintf(gx.x) : 0.f, ri = fin ? rintf(gx.y) : 0.f;
+            fl |= (fabsf(rr) > 127.f || fabsf(ri) > 127.f) ? NBSI_FLAG_SPEC_CLIPPED : 0u;
+            const float qr = fminf(fmaxf(rr, -127.f), 127.f);
+            const float qi = fminf(fmaxf(ri, -127.f), 127.f);
             const int16_t packed = (int16_t)(((int)qi << 8) | ((int)qr & 0xff));
             reinterpret_cast<int16_t *>(jb.stage_q)[rowo + d] = packed;
         }
     }
+    if (fl && jb.flags) atomicOr(jb.flags, fl);
 }
 
 template <int LOGM, int G>
@@ -391,8 +398,8 @@ int channelize_log_m(int log_n, int n_chan) {
 
 hipError_t launch_channelize(const int8_t *volt, int n_in, int log_n, int n_spec, int klo,
                              int n_chan, const float *gain, int8_t *stage_q, float *stage_f,
-                             hipStream_t st) {
-    ChanJob jb{volt, gain, stage_q, reinterpret_cast<float2 *>(stage_f), log_n, n_spec, klo, n_chan, 0};
+                             hipStream_t st, unsigned *flags) {
+    ChanJob jb{volt, gain, stage_q, reinterpret_cast<float2 *>(stage_f), log_n, n_spec, klo, n_chan, 0, flags};
     switch (channelize_log_m(log_n, n_chan)) {
         case 8: return launch_logm<8>(jb, n_in, st);
         case 9: return launch_logm<9>(jb, n_in, st);

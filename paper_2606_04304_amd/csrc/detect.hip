@@ -504,7 +504,7 @@ __global__ __launch_bounds__(1024) void detect_pixel_reg_kernel(const float *__r
                                                                 int mode, const float2 *__restrict__ stats,
                                                                 float thresh, float *__restrict__ snr_out,
                                                                 nbsi_cand *__restrict__ cand, int cap,
-                                                                int *__restrict__ counter) {
+                                                                int *__restrict__ counter, unsigned *__restrict__ flags) {
     constexpr int CH = 512;  // channels per staging round (8 registers)
     static_assert(NR % 8 == 0, "staging rounds");
     __shared__ float tile[CH][REG_PX + 1];
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(1024) void detect_pixel_reg_kernel(const float *__r
                 x = img[(size_t)c * npix2 + (size_t)gy * n_pix + gx0 + sp];
                 if (mode == NBSI_DETECT_PER_IMAGE) {
                     const float2 st = stats[c];
-                    x = st.y > 0.f ? (x - st.x) / st.y : 0.f;
+                    x = st.y > 0.f ? (x - st.x) / st.y : x * 0.f;  // (x * 0: non-finite stays non-finite)
                 }
             }
             r[q] = x;
@@ -540,7 +540,14 @@ __global__ __launch_bounds__(1024) void detect_pixel_reg_kernel(const float *__r
     }
     const int x = gx0 + wave, y = gy;
     if (x >= n_pix) return;  // no barriers below
-    const bool active = in_horizon(x, y, n_pix);
+    // a spectrum holding a non-finite value is not searched (wave-uniform: one pixel per wave)
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < NR; j++) bad |= (lane + 64 * j < n_chan) && !__builtin_isfinite(v[j]);
+    const bool finite = __ballot(bad) == 0ull;
+    const bool in_hor = in_horizon(x, y, n_pix);
+    if (in_hor && !finite && lane == 0 && flags) atomicOr(flags, NBSI_FLAG_CUBE_NONFINITE);
+    const bool active = in_hor && finite;
     float *pool = pool_all[wave];
     float med = 0.f, scale = 1.f;
     bool ok = active;
@@ -563,7 +570,7 @@ __global__ __launch_bounds__(1024) void detect_pixel_reg_kernel(const float *__r
         const float prev_row = j > 0 ? __shfl(v[j > 0 ? j - 1 : 0], 63, 64) : 0.f;
         const float next_row = j + 1 < NR ? __shfl(v[j + 1 < NR ? j + 1 : j], 0, 64) : 0.f;
         if (c >= n_chan) continue;
-        const float z = (xv - med) * inv;
+        const float z = ok ? (xv - med) * inv : 0.f;
         if (snr_out) snr_out[(size_t)c * npix2 + (size_t)y * n_pix + x] = z;
         if (!ok || z < thresh) continue;
         const float xl = lane > 0 ? up : prev_row, xr = lane < 63 ? dn : next_row;
@@ -587,7 +594,7 @@ template <int PPW>
 __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
     const float *__restrict__ img, int n_chan, int n_pix, int mode, const float2 *__restrict__ stats,
     float thresh, float *__restrict__ snr_out, nbsi_cand *__restrict__ cand, int cap, int *__restrict__ counter,
-    int n_groups) {
+    int n_groups, unsigned *__restrict__ flags) {
     extern __shared__ float spec[];  // [PPW][n_chan]
     __shared__ float pool_all[PPW][64];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -608,21 +615,27 @@ __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
             v = img[(size_t)c * npix2 + (size_t)gy * n_pix + gx0 + pl];
             if (mode == NBSI_DETECT_PER_IMAGE) {
                 const float2 st = stats[c];
-                v = st.y > 0.f ? (v - st.x) / st.y : 0.f;
+                v = st.y > 0.f ? (v - st.x) / st.y : v * 0.f;  // (v * 0: non-finite stays non-finite)
             }
         }
         spec[pl * n_chan + c] = v;
     }
     __syncthreads();
     const int x = gx0 + wave, y = gy;
-    const bool active = grp_ok && in_horizon(x, y, n_pix);
     float *s = spec + wave * n_chan;
+    // a spectrum holding a non-finite value is not searched (wave-uniform: one pixel per wave)
+    bool bad = false;
+    for (int c = lane; c < n_chan; c += 64) bad |= !__builtin_isfinite(s[c]);
+    const bool finite = __ballot(bad) == 0ull;
+    const bool in_hor = grp_ok && in_horizon(x, y, n_pix);
+    if (in_hor && !finite && lane == 0 && flags) atomicOr(flags, NBSI_FLAG_CUBE_NONFINITE);
+    const bool active = in_hor && finite;
     float *pool = pool_all[wave];
     auto val_x = [&](int i) { return s[i]; };
-    const float med = wave_median_fast(val_x, n_chan, pool, lane);
+    const float med = finite ? wave_median_fast(val_x, n_chan, pool, lane) : 0.f;
     float scale = 1.f;  // SNR = (x - med) / scale
     bool ok = active;
-    if (mode == NBSI_DETECT_PER_PIXEL) {
+    if (mode == NBSI_DETECT_PER_PIXEL && finite) {
         auto val_d = [&](int i) { return fabsf(s[i] - med); };
         const float mad = wave_median_fast(val_d, n_chan, pool, lane);
         scale = MAD_K * mad;
@@ -632,7 +645,7 @@ __global__ __launch_bounds__(64 * PPW) void detect_pixel_kernel(
     // the quotient; the same form scores neighbours for the suppression test)
     const float inv = ok ? 1.f / scale : 0.f;
     for (int c = lane; c < n_chan; c += 64) {
-        const float z = (s[c] - med) * inv;
+        const float z = ok ? (s[c] - med) * inv : 0.f;
         if (snr_out && grp_ok) snr_out[(size_t)c * npix2 + (size_t)y * n_pix + x] = z;
         if (!ok || z < thresh) continue;
         if (c > 0 && !(z > (s[c - 1] - med) * inv)) continue;
@@ -709,12 +722,16 @@ __global__ __launch_bounds__(SEL_NT) void image_stats_kernel(const float *__rest
         }
         // (the selection's first block reduction orders these LDS writes before any read)
     }
+    // every pass visits the finite values only (non-finite pixels take no part in the statistics)
     auto visit = [&](auto f) __attribute__((always_inline)) {
         if constexpr (ONCHIP) {
 #pragma unroll
             for (int j = 0; j < STATS_VR; j++)
-                if (j < nv) f(v[j]);
-            for (int j = 0; j < nv - STATS_VR; j++) f(s_v[j * SEL_NT + t]);
+                if (j < nv && __builtin_isfinite(v[j])) f(v[j]);
+            for (int j = 0; j < nv - STATS_VR; j++) {
+                const float u = s_v[j * SEL_NT + t];
+                if (__builtin_isfinite(u)) f(u);
+            }
         } else {
             if (!on) return;
             for (int x = x0; x < n_pix; x += SEL_NT) {
@@ -726,15 +743,23 @@ __global__ __launch_bounds__(SEL_NT) void image_stats_kernel(const float *__rest
 #pragma unroll
                     for (int k = 0; k < 8; k++) u[k] = im[(size_t)(y + k * G) * n_pix + x];
 #pragma unroll
-                    for (int k = 0; k < 8; k++) f(u[k]);
+                    for (int k = 0; k < 8; k++)
+                        if (__builtin_isfinite(u[k])) f(u[k]);
                 }
-                for (; y <= y1; y += G) f(im[(size_t)y * n_pix + x]);
+                for (; y <= y1; y += G) {
+                    const float u1 = im[(size_t)y * n_pix + x];
+                    if (__builtin_isfinite(u1)) f(u1);
+                }
             }
         }
     };
     int n_in = 0;
     visit([&](float) __attribute__((always_inline)) { n_in++; });
     n_in = block_sum(n_in, L.ired);
+    if (n_in == 0) {  // no finite pixel in this channel image (uniform)
+        if (t == 0) stats[c] = make_float2(0.f, 0.f);
+        return;
+    }
     const float med = block_median([&](auto f) __attribute__((always_inline)) { visit(f); }, n_in, L);
     const float mad = block_median(
         [&](auto f) __attribute__((always_inline)) {
@@ -831,12 +856,12 @@ hipError_t launch_detect_stats(const float *img, int n_chan, int n_pix, int mode
 
 hipError_t launch_detect_scan(const float *img, int n_chan, int n_pix, int mode, const float *stats,
                               float thresh, float *snr, nbsi_cand *cand, int cap, int *counter,
-                              hipStream_t st) {
+                              hipStream_t st, unsigned *flags) {
     const float2 *s2 = reinterpret_cast<const float2 *>(stats);
     if (n_chan <= 64 * 64) {
         const int n_blocks = n_pix * ((n_pix + REG_PX - 1) / REG_PX);
         hipLaunchKernelGGL(detect_pixel_reg_kernel<64>, dim3(n_blocks), dim3(64 * REG_PX), 0, st, img, n_chan, n_pix,
-                           mode, s2, thresh, snr, cand, cap, counter);
+                           mode, s2, thresh, snr, cand, cap, counter, flags);
         return hipGetLastError();
     }
     const int ppw = detect_ppw(n_chan);
@@ -853,15 +878,15 @@ hipError_t launch_detect_scan(const float *img, int n_chan, int n_pix, int mode,
     switch (ppw) {
         case 4:
             hipLaunchKernelGGL(detect_pixel_kernel<4>, dim3(n_blocks), dim3(256), lds, st, img, n_chan, n_pix, mode,
-                               s2, thresh, snr, cand, cap, counter, n_groups);
+                               s2, thresh, snr, cand, cap, counter, n_groups, flags);
             break;
         case 2:
             hipLaunchKernelGGL(detect_pixel_kernel<2>, dim3(n_blocks), dim3(128), lds, st, img, n_chan, n_pix, mode,
-                               s2, thresh, snr, cand, cap, counter, n_groups);
+                               s2, thresh, snr, cand, cap, counter, n_groups, flags);
             break;
         default:
             hipLaunchKernelGGL(detect_pixel_kernel<1>, dim3(n_blocks), dim3(64), lds, st, img, n_chan, n_pix, mode,
-                               s2, thresh, snr, cand, cap, counter, n_groups);
+                               s2, thresh, snr, cand, cap, counter, n_groups, flags);
     }
     return hipGetLastError();
 }

@@ -115,12 +115,18 @@ __global__ __launch_bounds__(256) void count_kernel(const double *__restrict__ x
     if (threadIdx.x == 0) nb[c] = part[0];
 }
 
+// One atomic per wave that met a non-finite output value.
+__device__ __forceinline__ void flag_nonfinite(bool bad, unsigned *flags) {
+    if (__ballot(bad) && flags && (threadIdx.x & 63) == 0) atomicOr(flags, NBSI_FLAG_IMAGE_NONFINITE);
+}
+
 // ---- direct Fourier imager ----
 template <typename VT>
 __global__ __launch_bounds__(256) void dft_kernel(const VT *__restrict__ vis, const double *__restrict__ xyz,
                                                   const double *__restrict__ freq, const int2 *__restrict__ pairs,
                                                   int n_pairs, int n_ant, int n_pix, double uv_min, double uv_max,
-                                                  const int *__restrict__ nb, float *__restrict__ img) {
+                                                  const int *__restrict__ nb, float *__restrict__ img,
+                                                  unsigned *__restrict__ flags) {
     __shared__ double su[256], sv[256];
     __shared__ float2 sval[256];
     __shared__ int sok[256];
@@ -167,11 +173,17 @@ __global__ __launch_bounds__(256) void dft_kernel(const VT *__restrict__ vis, co
     }
     const int n = nb[c];
     const float inv = n > 0 ? (float)(1.0 / (double)n) : 0.f;
+    bool bad = false;
 #pragma unroll
     for (int xi = 0; xi < 4; xi++) {
         const int x = t + 256 * xi;
-        if (x < n_pix) img[((size_t)c * n_pix + y) * n_pix + x] = acc[xi] * inv;
+        if (x < n_pix) {
+            const float o = acc[xi] * inv;
+            bad |= !__builtin_isfinite(o);
+            img[((size_t)c * n_pix + y) * n_pix + x] = o;
+        }
     }
+    flag_nonfinite(bad, flags);
 }
 
 // ---- gridding ----
@@ -519,7 +531,7 @@ template <int GE>
 __device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, int n_pix, int log_m,
                                           const float *__restrict__ corr, const int *__restrict__ nb,
                                           float *__restrict__ img, int xb, int c, float2 *buf, float2 *tw_lo,
-                                          float2 *tw_hi) {
+                                          float2 *tw_hi, unsigned *__restrict__ flags) {
     const int t = threadIdx.x;
     const int n = n_pix, log_n = log_m - 1, M = 1 << log_m;
     constexpr int CELLS = Tile<GE>::CELLS;
@@ -565,6 +577,7 @@ __device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, int 
     batched_fft<GE>(buf, t, log_n, tw, log_m);
     const int cnt = nb[c];
     const float inv = cnt > 0 ? (float)(0.5 / (double)cnt) : 0.f;
+    bool bad = false;
     for (int e = t; e < n * nx; e += 256) {
         const int xl = e % nx, y = e / nx;
         const int yp = y - n / 2;
@@ -572,17 +585,20 @@ __device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, int 
         const float2 f = buf[pidx(xl * n + (k >> 1))];
         const float v = (k & 1) ? f.y : f.x;
         const float sgn = (yp & 1) ? -1.f : 1.f;
-        img[((size_t)c * n + y) * n + x0 + xl] = v * sgn * corr[x0 + xl] * corr[y] * inv;
+        const float o = v * sgn * corr[x0 + xl] * corr[y] * inv;
+        bad |= !__builtin_isfinite(o);
+        img[((size_t)c * n + y) * n + x0 + xl] = o;
     }
+    flag_nonfinite(bad, flags);
 }
 
 template <int GE>
 __global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict__ inter, int n_pix, int log_m,
                                                         const float *__restrict__ corr, const int *__restrict__ nb,
-                                                        float *__restrict__ img) {
+                                                        float *__restrict__ img, unsigned *__restrict__ flags) {
     __shared__ float2 buf[padded_size(Tile<GE>::CELLS)];
     __shared__ float2 tw_lo[64], tw_hi[64];
-    grid_cols<GE>(inter, n_pix, log_m, corr, nb, img, blockIdx.x, blockIdx.y, buf, tw_lo, tw_hi);
+    grid_cols<GE>(inter, n_pix, log_m, corr, nb, img, blockIdx.x, blockIdx.y, buf, tw_lo, tw_hi, flags);
 }
 
 template <int GE>
@@ -598,7 +614,7 @@ __global__ __launch_bounds__(256) void grid_cols_batch_kernel(const ImgJob *__re
     const int n_xb = jb.n_pix / cols_per_band(GE, jb.n_pix);
     const int local = task - jb.cols_task0;
     grid_cols<GE>(jb.inter, jb.n_pix, jb.log_m, jb.corr, jb.nb, jb.img, local % n_xb, local / n_xb, buf, tw_lo,
-                  tw_hi);
+                  tw_hi, jb.flags);
 }
 
 // Gather over channel ranges of several sub-bands: one workgroup per (job, channel, 256 pairs).
@@ -625,21 +641,21 @@ hipError_t launch_image_count(const nbsi_image_plan *p, hipStream_t st) {
 }
 
 hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_dtype, float *img,
-                            hipStream_t st) {
+                            hipStream_t st, unsigned *flags) {
     dim3 grid(p->n_pix, p->n_chan);
     if (vis_dtype == NBSI_VIS_I32)
         hipLaunchKernelGGL(dft_kernel<int2>, grid, dim3(256), 0, st, (const int2 *)vis, p->d_xyz, p->d_freq,
-                           p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, p->d_nb, img);
+                           p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max, p->d_nb, img, flags);
     else
         hipLaunchKernelGGL(dft_kernel<float2>, grid, dim3(256), 0, st, (const float2 *)vis, p->d_xyz,
                            p->d_freq, p->d_pairs, p->n_pairs, p->n_ant, p->n_pix, p->uv_min, p->uv_max,
-                           p->d_nb, img);
+                           p->d_nb, img, flags);
     return hipGetLastError();
 }
 
 template <int GE>
 static hipError_t launch_grid_ge(const nbsi_image_plan *p, int precision, const float2 *cvis, float2 *inter, float *img,
-                                 int log_m, hipStream_t st) {
+                                 int log_m, hipStream_t st, unsigned *flags) {
     dim3 gr(p->n_bands, p->n_chan);
     const SetTest bset{p->d_inb, (p->n_pairs + 31) >> 5};
 #define NBSI_ROWS(LM, PR)                                                                                   \
@@ -662,19 +678,19 @@ static hipError_t launch_grid_ge(const nbsi_image_plan *p, int precision, const 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(grid_cols_kernel<GE>, dim3(p->n_pix / cols_per_band(GE, p->n_pix), p->n_chan), dim3(256), 0,
-                       st, inter, p->n_pix, log_m, p->d_corr, p->d_nb, img);
+                       st, inter, p->n_pix, log_m, p->d_corr, p->d_nb, img, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_image_grid_stokes(const nbsi_image_plan *p, const float2 *cvis, int precision, float2 *inter,
-                                    float *img, hipStream_t st) {
+                                    float *img, hipStream_t st, unsigned *flags) {
     const int log_m = 31 - __builtin_clz(2 * p->n_pix);
-    return p->ge == 32 ? launch_grid_ge<32>(p, precision, cvis, inter, img, log_m, st)
-                       : launch_grid_ge<16>(p, precision, cvis, inter, img, log_m, st);
+    return p->ge == 32 ? launch_grid_ge<32>(p, precision, cvis, inter, img, log_m, st, flags)
+                       : launch_grid_ge<16>(p, precision, cvis, inter, img, log_m, st, flags);
 }
 
 hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype, int precision,
-                             float2 *cvis, float2 *inter, float *img, hipStream_t st) {
+                             float2 *cvis, float2 *inter, float *img, hipStream_t st, unsigned *flags) {
     dim3 gg((p->n_pairs + 255) / 256, p->n_chan);
     if (vis_dtype == NBSI_VIS_I32)
         hipLaunchKernelGGL(stokes_gather_kernel<int2>, gg, dim3(256), 0, st, (const int2 *)vis, p->d_pairs,
@@ -684,7 +700,7 @@ hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_
                            p->n_pairs, p->n_ant, cvis);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_image_grid_stokes(p, cvis, precision, inter, img, st);
+    return launch_image_grid_stokes(p, cvis, precision, inter, img, st, flags);
 }
 
 hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, hipStream_t st) {

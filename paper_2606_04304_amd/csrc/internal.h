@@ -18,6 +18,7 @@ struct nbsi_ctx {
     void *scratch[16] = {nullptr};
     size_t scratch_size[16] = {0};
     int *d_counter = nullptr;  // small device counters (detector)
+    unsigned *d_flags = nullptr;  // NBSI_FLAG_* bits set by kernels, read and cleared by nbsi_status
     // auxiliary stream and events of the overlapped correlate + image call (created on first use)
     hipStream_t aux = nullptr;
     hipEvent_t ev_stage[NBSI_MAX_STAGES + 1] = {};
@@ -119,6 +120,7 @@ struct ChanJob {
     float2 *stage_f;
     int log_n, n_spec, klo, n_chan;
     int task0;  // first task of this sub-band in a batched launch
+    unsigned *flags;  // NBSI_FLAG_* bits (null: not reported)
 };
 
 // One sub-band's correlator parameters (the job of a batched launch).
@@ -168,6 +170,7 @@ struct ImgJob {
     int n_pairs, n_ant, n_pix, log_m, n_bands, n_chan;
     double uv_min, uv_max;
     int gather_task0, rows_task0, cols_task0;
+    unsigned *flags = nullptr;  // NBSI_FLAG_* bits (null: not reported)
 };
 // Image columns per workgroup of the gridding imager's column pass: a tile of 256 ge cells
 // holds 256 ge / n_pix columns of n_pix complex values, at most the n_pix columns there are.
@@ -190,7 +193,7 @@ hipError_t launch_corner_turn_q_batch(const ChanJob *d_jobs, int n_jobs, const i
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_channelize(const int8_t *volt, int n_in, int log_n, int n_spec, int klo,
                              int n_chan, const float *gain, int8_t *stage_q, float *stage_f,
-                             hipStream_t st);
+                             hipStream_t st, unsigned *flags = nullptr);
 hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_tasks, int log_m, int g,
                                    int max_dyn_elems, hipStream_t st);
 hipError_t launch_corner_turn_q(const int8_t *stage, int n_in, int n_spec, int n_chan,
@@ -204,15 +207,16 @@ hipError_t launch_correlate_f32(const float *q, int n_chan, int n_in, int n_spec
                                 hipStream_t st);
 hipError_t launch_image_count(const nbsi_image_plan *p, hipStream_t st);
 hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_dtype, float *img,
-                            hipStream_t st);
+                            hipStream_t st, unsigned *flags = nullptr);
 hipError_t launch_image_grid(const nbsi_image_plan *p, const void *vis, int vis_dtype,
-                             int precision, float2 *cvis, float2 *inter, float *img, hipStream_t st);
+                             int precision, float2 *cvis, float2 *inter, float *img, hipStream_t st,
+                             unsigned *flags = nullptr);
 hipError_t launch_image_grid_stokes(const nbsi_image_plan *p, const float2 *cvis, int precision, float2 *inter,
-                                    float *img, hipStream_t st);
+                                    float *img, hipStream_t st, unsigned *flags = nullptr);
 hipError_t launch_detect_stats(const float *img, int n_chan, int n_pix, int mode, float *stats,
                                hipStream_t st);
 hipError_t launch_detect_scan(const float *img, int n_chan, int n_pix, int mode,
                               const float *stats, float thresh, float *snr, nbsi_cand *cand,
-                              int cap, int *counter, hipStream_t st);
+                              int cap, int *counter, hipStream_t st, unsigned *flags = nullptr);
 hipError_t launch_detect_sort(nbsi_cand *cand, int n, unsigned long long *keys, int n_chan,
                               int n_pix, nbsi_cand *out, int n_out, hipStream_t st);

@@ -97,6 +97,8 @@ def test_null_context_is_rejected():
     assert L.nbsi_correlate_stokes(None, None, 1, 2, 1, None, None, None) == nb.NBSI_EINVAL
     assert L.nbsi_image_stokes(None, None, None, 0, None) == nb.NBSI_EINVAL
     assert L.nbsi_correlate_image(None, None, 1, 2, 1, None, 0, 0, None, None, None) == nb.NBSI_EINVAL
+    assert L.nbsi_status(None, None) == nb.NBSI_EINVAL
+    assert L.nbsi_detect_noalloc(None, None, 8, 8, 0, 5.0, None, None, 0, ctypes.byref(n)) == nb.NBSI_EINVAL
 
 
 def test_binding_constants_match_the_header():

@@ -121,3 +121,38 @@ def test_per_image_mode_hand_computed():
     # only v = -4 (pixel (1, 1)) reaches 4 / k = 2.698 >= 2.5, in channel 2
     assert [(int(a["x"]), int(a["y"]), int(a["c"])) for a in rec] == [(1, 1, 2)]
     assert rec["snr"][0] == pytest.approx(4.0 / k, rel=1e-12)
+
+
+def test_non_finite_pixels_are_not_searched():
+    # the cube of the per-image hand case with channel 0 of the centre pixel (v = 0) not finite:
+    # that pixel is not searched, and channel 0's statistics come from its 8 finite in-horizon
+    # pixels, v = -4..-1, 1..4: median 0, MAD 2.5, so z = v / (2.5 k) there; channels 1 and 2
+    # keep v / (2k) and -v / (2k).  Per pixel the median over channels is v / (2.5 k), so the
+    # standardised residual is (0, v (1/2 - 1/2.5) / k, -v (1/2 + 1/2.5) / k)
+    k = D.MAD_K
+    v = np.arange(-4.0, 5.0).reshape(3, 3)
+    cube = np.zeros((3, 4, 4))
+    for c, (m_c, s_c) in enumerate([(10.0, 1.0), (-5.0, 3.0), (100.0, 0.5)]):
+        cube[c, 1:4, 1:4] = m_c + s_c * (v if c < 2 else v[::-1, ::-1])
+    for bad in (np.nan, np.inf, -np.inf):
+        cube[0, 2, 2] = bad
+        rec, snr, valid = D.detect(cube, tau=100.0, mode="per_image")
+        expect = np.zeros((3, 4, 4))
+        expect[1, 1:4, 1:4] = v * (0.5 - 0.4) / k
+        expect[2, 1:4, 1:4] = -v * (0.5 + 0.4) / k
+        expect[:, 2, 2] = 0.0
+        np.testing.assert_allclose(snr, expect, atol=1e-12)
+        assert valid.sum() == 8 and not valid[2, 2]
+    # per pixel: every other pixel is scored exactly as in the cube without that value
+    rng = np.random.default_rng(6)
+    noisy = rng.standard_normal((64, 16, 16))
+    noisy[20, 7, 9] += 40.0
+    ref_rec, ref_snr, _ = D.detect(noisy, tau=5.0)
+    hit = noisy.copy()
+    hit[33, 8, 8] = np.nan
+    rec, snr, valid = D.detect(hit, tau=5.0)
+    assert not valid[8, 8] and (snr[:, 8, 8] == 0).all()
+    keep = np.ones((16, 16), bool)
+    keep[8, 8] = False
+    np.testing.assert_array_equal(snr[:, keep], ref_snr[:, keep])
+    assert [tuple(r) for r in rec] == [tuple(r) for r in ref_rec if not (r["x"] == 8 and r["y"] == 8)]
