@@ -74,6 +74,9 @@ const char *nbsi_strerror(int status);
  * the default stream).  Returns NBSI_EHIP if the device cannot be used. */
 int nbsi_create(nbsi_ctx **ctx, int device, void *stream);
 int nbsi_destroy(nbsi_ctx *ctx);
+/* Enqueue later calls on `stream`.  When it differs from the current one, the new stream first
+ * waits for all work the context enqueued before (the context's scratch is shared by its
+ * calls, so calls on different streams of one context never overlap). */
 int nbsi_set_stream(nbsi_ctx *ctx, void *stream);
 /* Human-readable detail of the last failure on this context ("" if none). */
 const char *nbsi_last_error(const nbsi_ctx *ctx);

@@ -323,6 +323,7 @@ int nbsi_destroy(nbsi_ctx *ctx) {
         for (int k = 0; k <= NBSI_MAX_STAGES; k++) (void)hipEventDestroy(ctx->ev_stage[k]);
         (void)hipStreamDestroy(ctx->aux);
     }
+    if (ctx->ev_switch) (void)hipEventDestroy(ctx->ev_switch);
     for (int s = 0; s < 16; s++)
         if (ctx->scratch[s]) (void)hipFree(ctx->scratch[s]);
     if (ctx->d_counter) (void)hipFree(ctx->d_counter);
@@ -333,7 +334,19 @@ int nbsi_destroy(nbsi_ctx *ctx) {
 
 int nbsi_set_stream(nbsi_ctx *ctx, void *stream) {
     if (!ctx) return NBSI_EINVAL;
-    ctx->stream = (hipStream_t)stream;
+    hipStream_t s = (hipStream_t)stream;
+    if (s == ctx->stream) return NBSI_OK;
+    // the context's scratch is shared by all its calls: work enqueued on the new stream waits
+    // for everything the context enqueued before (its old stream and auxiliary stream)
+    DeviceGuard g(ctx->device);
+    if (!ctx->ev_switch) NBSI_TRY_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_switch, hipEventDisableTiming));
+    NBSI_TRY_HIP(ctx, hipEventRecord(ctx->ev_switch, ctx->stream));
+    NBSI_TRY_HIP(ctx, hipStreamWaitEvent(s, ctx->ev_switch, 0));
+    if (ctx->aux) {
+        NBSI_TRY_HIP(ctx, hipEventRecord(ctx->ev_switch, ctx->aux));
+        NBSI_TRY_HIP(ctx, hipStreamWaitEvent(s, ctx->ev_switch, 0));
+    }
+    ctx->stream = s;
     return NBSI_OK;
 }
 

@@ -22,6 +22,9 @@ struct nbsi_ctx {
     // auxiliary stream and events of the overlapped correlate + image call (created on first use)
     hipStream_t aux = nullptr;
     hipEvent_t ev_stage[NBSI_MAX_STAGES + 1] = {};
+    // orders the work of a new stream after the context's earlier work (nbsi_set_stream), so
+    // calls on several streams never overlap on the context's scratch
+    hipEvent_t ev_switch = nullptr;
 };
 
 enum ScratchSlot {

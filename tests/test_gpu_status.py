@@ -123,3 +123,29 @@ def test_imager_flags_non_finite_visibilities(method):
     im = img.cpu().numpy()
     assert np.isfinite(im[[0, 2]]).all() and not np.isfinite(im[1]).all()
     ctx.close()
+
+
+def test_calls_on_alternating_streams_of_one_context():
+    """The default context follows torch's current stream; a call on a new stream waits for the
+    context's earlier work, so calls sharing its scratch on different streams give the results of
+    one stream."""
+    ctx = nb.Context(0)
+    n_ant = 48
+    xyz = synth.antenna_layout(n_ant, 150.0, 5)
+    freq = synth.channel_freqs(65536, 32768 - 150, 300)
+    plan = nb.ImagePlan(xyz, freq, 128, nb.NBSI_IMAGE_GRID, ctx=ctx)
+    n_in = 2 * n_ant
+    rng = np.random.default_rng(8)
+    vis = [torch.from_numpy(rng.integers(-900, 900, (300, n_in * (n_in + 1) // 2, 2)).astype(np.int32)).to(DEV)
+           for _ in range(4)]
+    ref = [nb.nbsi_image(plan, v).clone() for v in vis]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for k in range(8):
+        with torch.cuda.stream(streams[k % 2]):
+            outs.append(nb.nbsi_image(plan, vis[k % 4]))
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        assert torch.equal(o, ref[k % 4]), k
+    ctx.close()
