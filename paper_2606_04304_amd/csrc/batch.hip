@@ -138,7 +138,7 @@ hipError_t launch_one(const nbsi_batch *b, const nbsi_batch::Launch &L, hipStrea
         case 2: return launch_correlate_batch((const CorrJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->n_in, L.b != 0, st);
         case 3: return launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, st);
         case 4: return launch_image_batch_rows((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->precision, L.b, st);
-        case 5: return launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.b, st);
+        case 5: return launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, L.b, st);
     }
     return hipErrorInvalidValue;
 }
@@ -323,6 +323,7 @@ int build_group_launches(nbsi_batch *b, const std::vector<int> &members, int gro
             b->launches.push_back(R);
             nbsi_batch::Launch C;
             C.kind = 5;
+            C.a = kv.first.first;
             C.b = ge;
             C.n_jobs = (int)cols.size();
             C.n_tasks = ct;

@@ -229,58 +229,93 @@ __device__ __forceinline__ float2 grid_product(float2 val, float wu, float wv) {
     }
 }
 
-// Batched Stockham FFT over rows of length 2^log_l stored row-major in LDS (padded layout,
-// see pidx), 256 * GE elements in all.  Radix-16 passes, with one smaller first pass when
-// log_l % 4 != 0.
-template <int R, int E>
-__device__ __forceinline__ void batched_pass(float2 *buf, int t, int log_l, int ns, const TwiddleTable &tw,
-                                             int log_tab) {
-    const int L = 1 << log_l;
-    constexpr int log_r = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
-    const int per_row = L / R;  // butterflies per row
+// LDS layout of the imager's transform buffers: rows of L complex values, one pad slot after
+// every 8 values and 2 more per row.  With it the Stockham passes' loads (consecutive lanes,
+// consecutive values) and strided stores (strides of 1, 2, 4, 8 and 64 values x the radix) fall
+// in distinct banks, and values of one column in consecutive rows do not share a bank.
+__device__ __forceinline__ int p8(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int p8_size(int n) { return n + n / 8; }
+__host__ __device__ constexpr int row_stride(int l) { return p8_size(l) + 2; }
+
+// Radix of pass p of a 2^LOGL-point transform: 8 throughout, after one radix-2 or radix-4 pass
+// when LOGL is not a multiple of 3.
+template <int LOGL>
+struct FftPasses {
+    static constexpr int REM = LOGL % 3;
+    static constexpr int N = LOGL / 3 + (REM ? 1 : 0);
+    static constexpr int log_radix(int p) { return (REM && p == 0) ? REM : 3; }
+    static constexpr int log_ns(int p) { return p == 0 ? 0 : (REM ? REM + 3 * (p - 1) : 3 * p); }
+};
+
+// W_T^m from the half table tab[m] = W_T^m, m < T / 2 (W_T^(m + T/2) = -W_T^m).
+template <int LOGT>
+__device__ __forceinline__ float2 twid(const float2 *tab, int m) {
+    constexpr int H = 1 << (LOGT - 1);
+    const float2 w = tab[m & (H - 1)];
+    return (m & H) ? make_float2(-w.x, -w.y) : w;
+}
+
+// One Stockham pass (radix 2^LOGR, 2^LOGNS points already combined) over NROWS rows of
+// L = 2^LOGL values in LDS, 256 threads, E = NROWS L / 256 values per thread.  Twiddles
+// W_{NS R}^{k r} come from the half table of W_T^m (T = 2^LOGT >= L).  Every twiddled pass has
+// L / R <= 256 butterflies per row, so all of a thread's butterflies sit at the same position k
+// of their rows and share one set of twiddles.
+template <int LOGL, int NROWS, int LOGR, int LOGNS, int LOGT>
+__device__ __forceinline__ void fft_pass(float2 *buf, const float2 *tab, int t) {
+    constexpr int L = 1 << LOGL, R = 1 << LOGR, NS = 1 << LOGNS;
+    constexpr int RS = row_stride(L);
+    constexpr int E = NROWS * L / 256, NB = E / R, PER_ROW = L / R;
+    static_assert(E % R == 0, "whole butterflies per thread");
+    static_assert(NS == 1 || 256 % PER_ROW == 0, "shared twiddles");
     float2 v[E];
 #pragma unroll
-    for (int b = 0; b < E / R; b++) {
-        const int g = t + 256 * b;
-        const int row = g >> (log_l - log_r), j = g & (per_row - 1);
+    for (int b = 0; b < NB; b++) {
+        const int g = t + 256 * b, row = g / PER_ROW, j = g % PER_ROW;
 #pragma unroll
-        for (int r = 0; r < R; r++) v[b * R + r] = buf[pidx(row * L + j + r * per_row)];
+        for (int r = 0; r < R; r++) v[b * R + r] = buf[row * RS + p8(j + r * PER_ROW)];
     }
     __syncthreads();
+    float2 w[R];
+    if constexpr (NS > 1) {
+        const int k = (t % PER_ROW) & (NS - 1);
 #pragma unroll
-    for (int b = 0; b < E / R; b++) {
-        const int g = t + 256 * b;
-        const int row = g >> (log_l - log_r), j = g & (per_row - 1);
-        const int k = j & (ns - 1);
-        if (ns > 1) {
-            const int sh = log_tab - (31 - __clz(ns * R));
-            const float2 w = tw(k << sh);
-            float2 cur = w;
+        for (int r = 1; r < R; r++) w[r] = twid<LOGT>(tab, (k * r) << (LOGT - LOGNS - LOGR));
+    }
 #pragma unroll
-            for (int r = 1; r < R; r++) {
-                v[b * R + r] = cmul(v[b * R + r], cur);
-                cur = cmul(cur, w);
-            }
+    for (int b = 0; b < NB; b++) {
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; r++) v[b * R + r] = cmul(v[b * R + r], w[r]);
         }
         dft_r<R>(v + b * R);
-        const int base = row * L + ((j >> (31 - __clz(ns))) << (31 - __clz(ns * R))) + k;
+        const int g = t + 256 * b, row = g / PER_ROW, j = g % PER_ROW;
+        const int base = ((j >> LOGNS) << (LOGNS + LOGR)) + (j & (NS - 1));
 #pragma unroll
-        for (int r = 0; r < R; r++) buf[pidx(base + r * ns)] = v[b * R + r];
+        for (int r = 0; r < R; r++) buf[row * RS + p8(base + r * NS)] = v[b * R + r];
     }
     __syncthreads();
 }
 
-template <int GE>
-__device__ __forceinline__ void batched_fft(float2 *buf, int t, int log_l, const TwiddleTable &tw, int log_tab) {
-    int ns = 1;
-    const int rem = log_l % 4;
-    if (rem == 1) { batched_pass<2, GE>(buf, t, log_l, ns, tw, log_tab); ns = 2; }
-    else if (rem == 2) { batched_pass<4, GE>(buf, t, log_l, ns, tw, log_tab); ns = 4; }
-    else if (rem == 3) { batched_pass<8, GE>(buf, t, log_l, ns, tw, log_tab); ns = 8; }
-    for (int p = 0; p < log_l / 4; p++) {
-        batched_pass<16, GE>(buf, t, log_l, ns, tw, log_tab);
-        ns *= 16;
+// Forward transforms of NROWS rows of 2^LOGL values in LDS (natural order in and out; the
+// caller synchronises before).
+template <int LOGL, int NROWS, int LOGT, int P = 0>
+__device__ __forceinline__ void fft_rows(float2 *buf, const float2 *tab, int t) {
+    using FP = FftPasses<LOGL>;
+    if constexpr (P < FP::N) {
+        fft_pass<LOGL, NROWS, FP::log_radix(P), FP::log_ns(P), LOGT>(buf, tab, t);
+        fft_rows<LOGL, NROWS, LOGT, P + 1>(buf, tab, t);
     }
+}
+
+// tab[m] = W_T^m = exp(-2 pi i m / T), m < T / 2 (T = 2^LOGT), from the float64-derived
+// two-level table (each entry within ~1.5 ulp), built in `lohi` (128 values of LDS that are
+// free until the call returns); synchronises before returning.
+template <int LOGT>
+__device__ __forceinline__ void fill_twiddles(float2 *tab, float2 *lohi, int t) {
+    const TwiddleTable tw = build_twiddles(lohi, lohi + 64, LOGT, t, 256);
+    __syncthreads();
+    for (int m = t; m < (1 << (LOGT - 1)); m += 256) tab[m] = tw(m);
+    __syncthreads();
 }
 
 // Stokes I of every candidate pair of every channel of a chunk (the gridder applies the
@@ -306,8 +341,9 @@ __global__ __launch_bounds__(256) void stokes_gather_kernel(const VT *__restrict
 // where its footprint reaches those rows; every thread owns a fixed rectangle of GE cells of it
 // (CPT consecutive columns x RPT rows) in registers and sums the baselines whose 8 x 8 kernel
 // footprint covers it, then the band is transformed along u and the n kept columns are written
-// (n x n complex per channel).  The band's items are sorted by signed x separation, hence by grid
-// column for every channel (u is proportional to dx).
+// as the band's tile of the intermediate: [channel][band][image column][R rows], n R complex
+// values, one contiguous block per workgroup.  The band's items are sorted by signed x
+// separation, hence by grid column for every channel (u is proportional to dx).
 // Each staging round puts a run of them in LDS with their 8 + 8 separable kernel weights
 // (evaluated once per baseline) and a table of the first staged baseline at or right of every
 // grid column, so a thread's baselines are the contiguous range of those starting within 7
@@ -318,6 +354,9 @@ struct GridShape {
     static constexpr int M = 1 << LOGM;
     static constexpr int CELLS = Tile<GE>::CELLS;
     static constexpr int R = CELLS / M;              // rows of a band
+    static constexpr int NB = M / 2 / R;             // bands of the half plane
+    static constexpr int RS = row_stride(M);
+    static constexpr int BUF = R * RS;               // LDS complex values of the band
     // owned columns per thread: 4 x 4 cells at M = 512 (measured 3.5% faster than 2 x 8 there),
     // else one column per 256 of M
     static constexpr int CPT = M == 512 ? 4 : (M >= 256 ? M / 256 : 1);
@@ -329,21 +368,44 @@ struct GridShape {
     // thread reads its CPT (RPT) consecutive entries at any footprint offset without a test
     // (odd stride: the lanes of a wave read different baselines, so they fall in different banks)
     static constexpr int WU = 8 + 2 * (CPT - 1), WV = 8 + 2 * (RPT - 1), WSTRIDE = (WU + WV) | 1;
-    // staged per baseline: first footprint cell (int2), value (float2), padded weights
-    static constexpr int CAP = (CELLS * (int)sizeof(float2) - NFIRST * 4) / (8 + 8 + WSTRIDE * 4);
+    // staged per baseline: first footprint cell (int2), value (float2), padded weights; at most
+    // one per thread and round
+    static constexpr int CAP0 = (BUF * (int)sizeof(float2) - NFIRST * 4) / (8 + 8 + WSTRIDE * 4);
+    static constexpr int CAP = CAP0 < 256 ? CAP0 : 256;
     static_assert(CPT * RPT == GE, "GE cells per thread");
     static_assert(CAP >= 64, "staging room");
 };
 
+// What one thread loads for the baseline it stages in a round: its list item, the membership
+// word of B, Stokes I and the antenna separation.
+struct StageIn {
+    int item = 0;
+    unsigned word = 0;
+    float2 val = make_float2(0.f, 0.f);
+    double2 d = make_double2(0.0, 0.0);
+};
+
+__device__ __forceinline__ StageIn stage_load(int item, const float2 *__restrict__ cv_c, const double2 *__restrict__ dxy,
+                                              const SetTest &bset, int c) {
+    StageIn s;
+    const int k = item >> 1;
+    s.item = item;
+    s.word = bset.bits[(size_t)c * bset.words + (k >> 5)];
+    s.val = cv_c[k];
+    s.d = dxy[k];
+    return s;
+}
+
 template <int LOGM, int PREC, int GE>
 __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const double2 *__restrict__ dxy,
                                           const double *__restrict__ freq, const int *__restrict__ band_off,
-                                          const int *__restrict__ band_items, int n_pairs, int n_pix,
-                                          const SetTest &bset, float2 *__restrict__ inter, int band, int c,
-                                          float2 *grid, float2 *tw_lo, float2 *tw_hi, float &vscale) {
+                                          const int *__restrict__ band_items, int n_pairs, const SetTest &bset,
+                                          float2 *__restrict__ inter, int band, int c, float2 *grid, float2 *tab,
+                                          float &vscale) {
     using GS = GridShape<LOGM, GE>;
-    constexpr int M = GS::M, R = GS::R, CPT = GS::CPT, COLT = GS::COLT, RPT = GS::RPT, CAP = GS::CAP;
-    // staging view of the grid's LDS
+    constexpr int M = GS::M, R = GS::R, RS = GS::RS, CPT = GS::CPT, COLT = GS::COLT, RPT = GS::RPT, CAP = GS::CAP;
+    constexpr int n_pix = M / 2;
+    // staging view of the band's LDS
     int2 *s_g = reinterpret_cast<int2 *>(grid);                   // gu0, gv0: first footprint cell
     float2 *s_val = reinterpret_cast<float2 *>(s_g + CAP);         // Stokes I value
     float *s_w = reinterpret_cast<float *>(s_val + CAP);           // padded wu, then padded wv
@@ -351,9 +413,20 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
 
     const int t = threadIdx.x;
     const int row0 = M / 2 + band * R;  // bands cover the rows v >= 0 of the Hermitian grid
-    const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, LOGM, t, 256);
     const float2 *cv_c = cvis + (size_t)c * n_pairs;
     const int k_begin = band_off[band], k_end = band_off[band + 1];
+    const int n_items = k_end - k_begin;
+    const int n_rounds = (n_items + CAP - 1) / CAP;
+    // Round rr stages list entries rr, rr + n_rounds, ... (sorted by column and spread over the
+    // whole band, so every wave has work in every round); thread t stages entry t n_rounds + rr,
+    // so its entries are contiguous.  The loads run ahead of their use: the entry two rounds
+    // ahead and the staged data of the next round are in flight while a round is gridded.
+    const int *my = band_items + k_begin + t * n_rounds;
+    auto has = [&](int rr) { return rr < n_rounds && t * n_rounds + rr < n_items; };
+    int it_nxt = has(1) ? my[1] : 0;
+    StageIn cur;
+    if (has(0)) cur = stage_load(my[0], cv_c, dxy, bset, c);
+    fill_twiddles<LOGM>(tab, grid, t);  // (the band's LDS is free until staging)
     if constexpr (PREC == NBSI_PREC_FP16) {
         // Scale this workgroup's visibilities by a power of two so the largest |V_I| it grids
         // maps below 2^14: every FP16 product (kernel weights <= 1) stays finite.
@@ -389,24 +462,21 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
     // grid position u / du + M/2 with du = 1/4 wavelength; candidate pairs outside B at this
     // channel's frequency are staged with a zero value
     const double sc = freq[c] / C_LIGHT * 4.0;
-    // when the band holds more baselines than one round stages, round rr takes list entries
-    // rr, rr + n_rounds, ...: still sorted by column, and spread over the whole band, so every
-    // wave has work in every round
-    const int n_items = k_end - k_begin;
-    const int n_rounds = (n_items + CAP - 1) / CAP;
     for (int rr = 0; rr < n_rounds; rr++) {
         const int nk = (n_items - rr + n_rounds - 1) / n_rounds;
-        __syncthreads();
-        for (int i = t; i < nk; i += 256) {
-            const int item = band_items[k_begin + rr + i * n_rounds];
-            const int k = item >> 1;
-            float2 val = bset(c, k) ? cv_c[k] : make_float2(0.f, 0.f);
+        StageIn nxt;
+        if (has(rr + 1)) nxt = stage_load(it_nxt, cv_c, dxy, bset, c);
+        const int it_after = has(rr + 2) ? my[rr + 2] : 0;
+        __syncthreads();  // the previous round's staging area is free
+        if (has(rr)) {
+            const int i = t;
+            const int item = cur.item, k = item >> 1;
+            float2 val = ((cur.word >> (k & 31)) & 1u) ? cur.val : make_float2(0.f, 0.f);
             // mirrored item: conj V at -(u, v)
             const double sgn = (item & 1) ? -sc : sc;
             if (item & 1) val.y = -val.y;
             if constexpr (PREC == NBSI_PREC_FP16) val = make_float2(val.x * vscale, val.y * vscale);
-            const double2 d = dxy[k];
-            const double cu = d.x * sgn + (double)(M / 2), cvv = d.y * sgn + (double)(M / 2);
+            const double cu = cur.d.x * sgn + (double)(M / 2), cvv = cur.d.y * sgn + (double)(M / 2);
             const double fu = floor(cu), fv = floor(cvv);
             s_g[i] = make_int2((int)fu - 3, (int)fv - 3);
             s_val[i] = val;
@@ -466,38 +536,46 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
                     for (int r = 0; r < RPT; r++) acc[q][r] = cadd(acc[q][r], grid_product<PREC>(val, wu[q], wv[r]));
             }
         }
+        cur = nxt;
+        it_nxt = it_after;
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < CPT; q++)
 #pragma unroll
-        for (int r = 0; r < RPT; r++) grid[pidx((rown + r) * M + col0 + q)] = acc[q][r];
+        for (int r = 0; r < RPT; r++) grid[(rown + r) * RS + p8(col0 + q)] = acc[q][r];
     __syncthreads();
-    batched_fft<GE>(grid, t, LOGM, tw, LOGM);
-    // keep image columns x: FFT index (x - n/2) mod M, times (-1)^(x - n/2); undo the FP16 scale
+    fft_rows<LOGM, R, LOGM>(grid, tab, t);
+    // keep image columns x: FFT index (x - n/2) mod M, times (-1)^(x - n/2); undo the FP16 scale;
+    // the tile [x][R rows] is written as two rows per float4, contiguous over the workgroup
     const float unscale = (PREC == NBSI_PREC_FP16) ? 1.f / vscale : 1.f;
-    constexpr int half = R / 2;  // two rows per float4 store
-    for (int e = t; e < n_pix * half; e += 256) {
-        const int lr = 2 * (e % half), x = e / half;
+    constexpr int HALF = R / 2;
+    float4 *dst = reinterpret_cast<float4 *>(inter + (size_t)c * n_pix * n_pix + (size_t)band * n_pix * R);
+    for (int e = t; e < n_pix * HALF; e += 256) {
+        const int x = e / HALF, lr = 2 * (e % HALF);
         const int xp = x - n_pix / 2;
         const int col = xp & (M - 1);
         const float sgn = (xp & 1) ? -unscale : unscale;
-        const float2 f0 = grid[pidx(lr * M + col)], f1 = grid[pidx((lr + 1) * M + col)];
-        float4 o = make_float4(f0.x * sgn, f0.y * sgn, f1.x * sgn, f1.y * sgn);
-        *reinterpret_cast<float4 *>(inter + ((size_t)c * n_pix + x) * n_pix + band * R + lr) = o;
+        const float2 f0 = grid[lr * RS + p8(col)], f1 = grid[(lr + 1) * RS + p8(col)];
+        dst[e] = make_float4(f0.x * sgn, f0.y * sgn, f1.x * sgn, f1.y * sgn);
     }
 }
 
+// Row pass of the chunk's channels: XCD-aware order (all bands of a channel run on one XCD, so
+// its Stokes I row is read into one L2 once).
 template <int LOGM, int PREC, int GE>
-__global__ __launch_bounds__(256) void grid_rows_kernel(
-    const float2 *__restrict__ cvis, const double2 *__restrict__ dxy, const double *__restrict__ freq,
-    const int *__restrict__ band_off, const int *__restrict__ band_items, int n_pairs, int n_pix, SetTest bset,
-    float2 *__restrict__ inter) {
-    __shared__ float2 grid[padded_size(Tile<GE>::CELLS)];
-    __shared__ float2 tw_lo[64], tw_hi[64];
+__global__ __launch_bounds__(256) void grid_rows_kernel(const float2 *__restrict__ cvis, const double2 *__restrict__ dxy,
+                                                        const double *__restrict__ freq, const int *__restrict__ band_off,
+                                                        const int *__restrict__ band_items, int n_pairs, int n_chan,
+                                                        SetTest bset, float2 *__restrict__ inter) {
+    using GS = GridShape<LOGM, GE>;
+    __shared__ float2 grid[GS::BUF];
+    __shared__ float2 tab[1 << (LOGM - 1)];
     __shared__ float vscale;
-    grid_rows<LOGM, PREC, GE>(cvis, dxy, freq, band_off, band_items, n_pairs, n_pix, bset, inter, blockIdx.x,
-                              blockIdx.y, grid, tw_lo, tw_hi, vscale);
+    const int id = blockIdx.x, xcd = id & 7, slot = id >> 3;
+    const int c = ((slot / GS::NB) << 3) + xcd, band = slot % GS::NB;
+    if (c >= n_chan) return;
+    grid_rows<LOGM, PREC, GE>(cvis, dxy, freq, band_off, band_items, n_pairs, bset, inter, band, c, grid, tab, vscale);
 }
 
 // Gridding of channel ranges of several sub-bands of one image size: task -> (job, channel,
@@ -505,8 +583,9 @@ __global__ __launch_bounds__(256) void grid_rows_kernel(
 template <int LOGM, int PREC, int GE>
 __global__ __launch_bounds__(256) void grid_rows_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
                                                               int n_tasks) {
-    __shared__ float2 grid[padded_size(Tile<GE>::CELLS)];
-    __shared__ float2 tw_lo[64], tw_hi[64];
+    using GS = GridShape<LOGM, GE>;
+    __shared__ float2 grid[GS::BUF];
+    __shared__ float2 tab[1 << (LOGM - 1)];
     __shared__ float vscale;
     const int task = blockIdx.x;
     if (task >= n_tasks) return;
@@ -515,8 +594,8 @@ __global__ __launch_bounds__(256) void grid_rows_batch_kernel(const ImgJob *__re
     const ImgJob &jb = jobs[j];
     const int local = task - jb.rows_task0;
     const SetTest bset{jb.inb, (jb.n_pairs + 31) >> 5};
-    grid_rows<LOGM, PREC, GE>(jb.cvis, jb.dxy, jb.freq, jb.band_off, jb.band_items, jb.n_pairs, jb.n_pix, bset,
-                              jb.inter, local % jb.n_bands, local / jb.n_bands, grid, tw_lo, tw_hi, vscale);
+    grid_rows<LOGM, PREC, GE>(jb.cvis, jb.dxy, jb.freq, jb.band_off, jb.band_items, jb.n_pairs, bset, jb.inter,
+                              local % GS::NB, local / GS::NB, grid, tab, vscale);
 }
 
 // Column pass.  After the row pass, column x of the Hermitian grid holds s[i] = H(x, i) for the
@@ -525,64 +604,80 @@ __global__ __launch_bounds__(256) void grid_rows_batch_kernel(const ImgJob *__re
 // real, and one n-point transform gives it: with a[i] = s[i] + s[i + n] and
 // b[i] = (s[i] - s[i + n]) w^i, i < n, the transform Z of z = a + i b has Z[m] = S[2m] + i S[2m+1].
 // The image is S / 2 (the real part of the transform of the half-plane grid), times the kernel
-// correction and 1 / |B|.  A workgroup takes cols_per_band(ge, n) consecutive columns.
+// correction and 1 / |B|.  A workgroup takes NX consecutive columns: one contiguous block of
+// NX x R values from every band's tile.
+template <int LOGM, int GE>
+struct ColShape {
+    static constexpr int M = 1 << LOGM, N = M / 2, LOGN = LOGM - 1;
+    static constexpr int NX = cols_per_band(GE, N);     // columns per workgroup
+    static constexpr int RB = Tile<GE>::CELLS / M;       // rows per band of the row pass
+    static constexpr int NBANDS = N / RB;
+    static constexpr int RS = row_stride(N);
+    static constexpr int E = NX * N / 256;               // values per thread
+    static constexpr int BUF = NX * RS;
+    static constexpr int NXB = N / NX;                   // workgroups per channel
+    static_assert(E >= 2 && E % 2 == 0 && RB >= 2, "float4 loads");
+};
 
-template <int GE>
-__device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, int n_pix, int log_m,
-                                          const float *__restrict__ corr, const int *__restrict__ nb,
-                                          float *__restrict__ img, int xb, int c, float2 *buf, float2 *tw_lo,
-                                          float2 *tw_hi, unsigned *__restrict__ flags) {
+template <int LOGM, int GE>
+__device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, const float *__restrict__ corr,
+                                          const int *__restrict__ nb, float *__restrict__ img, int xb, int c,
+                                          float2 *buf, float2 *tab, unsigned *__restrict__ flags) {
+    using CS = ColShape<LOGM, GE>;
+    constexpr int M = CS::M, n = CS::N, NX = CS::NX, RB = CS::RB, RS = CS::RS, E = CS::E;
     const int t = threadIdx.x;
-    const int n = n_pix, log_n = log_m - 1, M = 1 << log_m;
-    constexpr int CELLS = Tile<GE>::CELLS;
-    const int nx = cols_per_band(GE, n_pix);
-    const int x0 = xb * nx;
-    const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_m, t, 256);
-    // the band's columns are contiguous in the intermediate; a band narrower than the tile
-    // (n = 64, ge = 32) leaves zero columns that are transformed and dropped
-    const float4 *src = reinterpret_cast<const float4 *>(inter + ((size_t)c * n + x0) * n);
-    const int n4 = nx * n / 2;
-    float4 r[CELLS / 2 / 256];
+    const int x0 = xb * NX;
+    // every band's block of these columns: [xl][RB rows], two rows per float4
+    const float4 *src = reinterpret_cast<const float4 *>(inter + (size_t)c * n * n);
+    float4 r[E / 2];
 #pragma unroll
-    for (int q = 0; q < CELLS / 2 / 256; q++) {
+    for (int q = 0; q < E / 2; q++) {
         const int e4 = t + 256 * q;
-        r[q] = e4 < n4 ? src[e4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const int b = e4 / (NX * RB / 2), w = e4 % (NX * RB / 2);
+        r[q] = src[((size_t)b * n + x0) * (RB / 2) + w];
     }
+    fill_twiddles<LOGM>(tab, buf, t);  // (buf is free until the tiles are stored)
 #pragma unroll
-    for (int q = 0; q < CELLS / 2 / 256; q++) {
-        const int e = 2 * (t + 256 * q);  // two consecutive elements never straddle a pad
-        buf[pidx(e)] = make_float2(r[q].x, r[q].y);
-        buf[pidx(e + 1)] = make_float2(r[q].z, r[q].w);
+    for (int q = 0; q < E / 2; q++) {
+        const int e4 = t + 256 * q;
+        const int b = e4 / (NX * RB / 2), w = e4 % (NX * RB / 2);
+        const int xl = w / (RB / 2), lr = 2 * (w % (RB / 2));
+        const int i = b * RB + lr;
+        buf[xl * RS + p8(i)] = make_float2(r[q].x, r[q].y);
+        buf[xl * RS + p8(i + 1)] = make_float2(r[q].z, r[q].w);
     }
     __syncthreads();
-    float2 z[GE];
+    float2 z[E];
 #pragma unroll
-    for (int q = 0; q < GE; q++) {
+    for (int q = 0; q < E; q++) {
         const int e = t + 256 * q;
-        const int i = e & (n - 1);
-        const float2 hi = buf[pidx(e)];  // s[i + n]
+        const int xl = e / n, i = e % n;
+        const float2 hi = buf[xl * RS + p8(i)];  // s[i + n]
         float2 lo = make_float2(0.f, 0.f);
         if (i) {
-            const float2 m = buf[pidx(e - i + n - i)];  // s[i] = conj s[2n - i], stored at row n - i
+            const float2 m = buf[xl * RS + p8(n - i)];  // s[i] = conj s[2n - i], stored at row n - i
             lo = make_float2(m.x, -m.y);
         }
         const float2 a = cadd(lo, hi);
-        const float2 b = cmul(make_float2(lo.x - hi.x, lo.y - hi.y), tw(i));
-        z[q] = make_float2(a.x - b.y, a.y + b.x);
+        const float2 bb = cmul(make_float2(lo.x - hi.x, lo.y - hi.y), tab[i]);  // w^i = W_M^i
+        z[q] = make_float2(a.x - bb.y, a.y + bb.x);
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < GE; q++) buf[pidx(t + 256 * q)] = z[q];
+    for (int q = 0; q < E; q++) {
+        const int e = t + 256 * q;
+        buf[(e / n) * RS + p8(e % n)] = z[q];
+    }
     __syncthreads();
-    batched_fft<GE>(buf, t, log_n, tw, log_m);
+    fft_rows<CS::LOGN, NX, LOGM>(buf, tab, t);
     const int cnt = nb[c];
     const float inv = cnt > 0 ? (float)(0.5 / (double)cnt) : 0.f;
     bool bad = false;
-    for (int e = t; e < n * nx; e += 256) {
-        const int xl = e % nx, y = e / nx;
+    for (int e = t; e < n * NX; e += 256) {
+        const int xl = e % NX, y = e / NX;
         const int yp = y - n / 2;
         const int k = yp & (M - 1);
-        const float2 f = buf[pidx(xl * n + (k >> 1))];
+        const float2 f = buf[xl * RS + p8(k >> 1)];
         const float v = (k & 1) ? f.y : f.x;
         const float sgn = (yp & 1) ? -1.f : 1.f;
         const float o = v * sgn * corr[x0 + xl] * corr[y] * inv;
@@ -592,29 +687,33 @@ __device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, int 
     flag_nonfinite(bad, flags);
 }
 
-template <int GE>
-__global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict__ inter, int n_pix, int log_m,
+// Column pass of the chunk's channels, in the row pass's XCD-aware order.
+template <int LOGM, int GE>
+__global__ __launch_bounds__(256) void grid_cols_kernel(const float2 *__restrict__ inter, int n_chan,
                                                         const float *__restrict__ corr, const int *__restrict__ nb,
                                                         float *__restrict__ img, unsigned *__restrict__ flags) {
-    __shared__ float2 buf[padded_size(Tile<GE>::CELLS)];
-    __shared__ float2 tw_lo[64], tw_hi[64];
-    grid_cols<GE>(inter, n_pix, log_m, corr, nb, img, blockIdx.x, blockIdx.y, buf, tw_lo, tw_hi, flags);
+    using CS = ColShape<LOGM, GE>;
+    __shared__ float2 buf[CS::BUF];
+    __shared__ float2 tab[1 << (LOGM - 1)];
+    const int id = blockIdx.x, xcd = id & 7, slot = id >> 3;
+    const int c = ((slot / CS::NXB) << 3) + xcd, xb = slot % CS::NXB;
+    if (c >= n_chan) return;
+    grid_cols<LOGM, GE>(inter, corr, nb, img, xb, c, buf, tab, flags);
 }
 
-template <int GE>
+template <int LOGM, int GE>
 __global__ __launch_bounds__(256) void grid_cols_batch_kernel(const ImgJob *__restrict__ jobs, int n_jobs,
                                                               int n_tasks) {
-    __shared__ float2 buf[padded_size(Tile<GE>::CELLS)];
-    __shared__ float2 tw_lo[64], tw_hi[64];
+    using CS = ColShape<LOGM, GE>;
+    __shared__ float2 buf[CS::BUF];
+    __shared__ float2 tab[1 << (LOGM - 1)];
     const int task = blockIdx.x;  // one workgroup per (job, channel, column band)
     if (task >= n_tasks) return;
     int j = 0;
     while (j + 1 < n_jobs && jobs[j + 1].cols_task0 <= task) j++;
     const ImgJob &jb = jobs[j];
-    const int n_xb = jb.n_pix / cols_per_band(GE, jb.n_pix);
     const int local = task - jb.cols_task0;
-    grid_cols<GE>(jb.inter, jb.n_pix, jb.log_m, jb.corr, jb.nb, jb.img, local % n_xb, local / n_xb, buf, tw_lo,
-                  tw_hi, jb.flags);
+    grid_cols<LOGM, GE>(jb.inter, jb.corr, jb.nb, jb.img, local % CS::NXB, local / CS::NXB, buf, tab, jb.flags);
 }
 
 // Gather over channel ranges of several sub-bands: one workgroup per (job, channel, 256 pairs).
@@ -653,33 +752,37 @@ hipError_t launch_image_dft(const nbsi_image_plan *p, const void *vis, int vis_d
     return hipGetLastError();
 }
 
-template <int GE>
-static hipError_t launch_grid_ge(const nbsi_image_plan *p, int precision, const float2 *cvis, float2 *inter, float *img,
-                                 int log_m, hipStream_t st, unsigned *flags) {
-    dim3 gr(p->n_bands, p->n_chan);
+template <int LOGM, int GE>
+static hipError_t launch_grid_m(const nbsi_image_plan *p, int precision, const float2 *cvis, float2 *inter, float *img,
+                                hipStream_t st, unsigned *flags) {
+    const int c8 = (p->n_chan + 7) / 8 * 8;  // XCD-aware order: eight channels per round of blocks
     const SetTest bset{p->d_inb, (p->n_pairs + 31) >> 5};
-#define NBSI_ROWS(LM, PR)                                                                                   \
-    hipLaunchKernelGGL((grid_rows_kernel<LM, PR, GE>), gr, dim3(256), 0, st, cvis, p->d_dxy, p->d_freq,     \
-                       p->d_band_off, p->d_band_items, p->n_pairs, p->n_pix, bset, inter)
-#define NBSI_ROWS_P(LM)                                                        \
-    if (precision == NBSI_PREC_FP16) NBSI_ROWS(LM, NBSI_PREC_FP16);             \
-    else if (precision == NBSI_PREC_BF16) NBSI_ROWS(LM, NBSI_PREC_BF16);        \
-    else NBSI_ROWS(LM, NBSI_PREC_FP32)
-    switch (log_m) {
-        case 7: NBSI_ROWS_P(7); break;
-        case 8: NBSI_ROWS_P(8); break;
-        case 9: NBSI_ROWS_P(9); break;
-        case 10: NBSI_ROWS_P(10); break;
-        case 11: NBSI_ROWS_P(11); break;
-        default: return hipErrorInvalidValue;
-    }
-#undef NBSI_ROWS_P
+    const dim3 gr((unsigned)(GridShape<LOGM, GE>::NB * c8));
+#define NBSI_ROWS(PR)                                                                                           \
+    hipLaunchKernelGGL((grid_rows_kernel<LOGM, PR, GE>), gr, dim3(256), 0, st, cvis, p->d_dxy, p->d_freq,      \
+                       p->d_band_off, p->d_band_items, p->n_pairs, p->n_chan, bset, inter)
+    if (precision == NBSI_PREC_FP16) NBSI_ROWS(NBSI_PREC_FP16);
+    else if (precision == NBSI_PREC_BF16) NBSI_ROWS(NBSI_PREC_BF16);
+    else NBSI_ROWS(NBSI_PREC_FP32);
 #undef NBSI_ROWS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(grid_cols_kernel<GE>, dim3(p->n_pix / cols_per_band(GE, p->n_pix), p->n_chan), dim3(256), 0,
-                       st, inter, p->n_pix, log_m, p->d_corr, p->d_nb, img, flags);
+    hipLaunchKernelGGL((grid_cols_kernel<LOGM, GE>), dim3((unsigned)(ColShape<LOGM, GE>::NXB * c8)), dim3(256), 0, st,
+                       inter, p->n_chan, p->d_corr, p->d_nb, img, flags);
     return hipGetLastError();
+}
+
+template <int GE>
+static hipError_t launch_grid_ge(const nbsi_image_plan *p, int precision, const float2 *cvis, float2 *inter, float *img,
+                                 int log_m, hipStream_t st, unsigned *flags) {
+    switch (log_m) {
+        case 7: return launch_grid_m<7, GE>(p, precision, cvis, inter, img, st, flags);
+        case 8: return launch_grid_m<8, GE>(p, precision, cvis, inter, img, st, flags);
+        case 9: return launch_grid_m<9, GE>(p, precision, cvis, inter, img, st, flags);
+        case 10: return launch_grid_m<10, GE>(p, precision, cvis, inter, img, st, flags);
+        case 11: return launch_grid_m<11, GE>(p, precision, cvis, inter, img, st, flags);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_image_grid_stokes(const nbsi_image_plan *p, const float2 *cvis, int precision, float2 *inter,
@@ -737,10 +840,20 @@ hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks
                     : launch_batch_rows_ge<16>(d_jobs, n_jobs, n_tasks, log_m, precision, st);
 }
 
-hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int ge, hipStream_t st) {
-    if (ge == 32)
-        hipLaunchKernelGGL(grid_cols_batch_kernel<32>, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
-    else
-        hipLaunchKernelGGL(grid_cols_batch_kernel<16>, dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks);
+template <int GE>
+static hipError_t launch_batch_cols_ge(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, hipStream_t st) {
+    switch (log_m) {
+        case 7: hipLaunchKernelGGL((grid_cols_batch_kernel<7, GE>), dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks); break;
+        case 8: hipLaunchKernelGGL((grid_cols_batch_kernel<8, GE>), dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks); break;
+        case 9: hipLaunchKernelGGL((grid_cols_batch_kernel<9, GE>), dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks); break;
+        case 10: hipLaunchKernelGGL((grid_cols_batch_kernel<10, GE>), dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks); break;
+        case 11: hipLaunchKernelGGL((grid_cols_batch_kernel<11, GE>), dim3(n_tasks), dim3(256), 0, st, d_jobs, n_jobs, n_tasks); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int ge, hipStream_t st) {
+    return ge == 32 ? launch_batch_cols_ge<32>(d_jobs, n_jobs, n_tasks, log_m, st)
+                    : launch_batch_cols_ge<16>(d_jobs, n_jobs, n_tasks, log_m, st);
 }

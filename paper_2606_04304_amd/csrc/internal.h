@@ -184,7 +184,7 @@ __host__ __device__ constexpr int cols_per_band(int ge, int n_pix) {
 hipError_t launch_image_batch_gather(const ImgJob *d_jobs, int n_jobs, int n_tasks, hipStream_t st);
 hipError_t launch_image_batch_rows(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int precision, int ge,
                                    hipStream_t st);
-hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int ge, hipStream_t st);
+hipError_t launch_image_batch_cols(const ImgJob *d_jobs, int n_jobs, int n_tasks, int log_m, int ge, hipStream_t st);
 
 int channelize_log_m(int log_n, int n_chan);
 int channelize_dyn_elems(int log_n, int log_m);
