@@ -196,8 +196,10 @@ __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int
     const int wr = wave >> 1, wc = wave & 1;
     const bool diag = (I == J);
     const bool active = !(diag && wr < wc);
-    int8_t *sA[2] = {lds, lds + 2 * TILE_LDS};
-    int8_t *sB[2] = {lds + TILE_LDS, lds + 3 * TILE_LDS};
+    // stage buffers by offset (a runtime-indexed table of pointers would make every access a
+    // generic flat instruction, which waits on the global loads in flight)
+    auto sA = [lds](int bi) { return lds + 2 * bi * TILE_LDS; };
+    auto sB = [lds](int bi) { return lds + (2 * bi + 1) * TILE_LDS; };
 
     v16i acc[MI][MI];
 #pragma unroll
@@ -219,8 +221,8 @@ __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int
     v4i ra[STAGE_VECS], rb[STAGE_VECS];
     load_stage<VEC>(ra, Y, rows, T, ldy, I * TILE_I8, 0, t);
     if (!diag) load_stage<VEC>(rb, Y, rows, T, ldy, J * TILE_I8, 0, t);
-    store_stage(sA[0], ra, t);
-    if (!diag) store_stage(sB[0], rb, t);
+    store_stage(sA(0), ra, t);
+    if (!diag) store_stage(sB(0), rb, t);
     __syncthreads();
     for (int st = 0; st < n_st; st++) {
         const int cur = st & 1;
@@ -230,8 +232,8 @@ __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int
             if (!diag) load_stage<VEC>(rb, Y, rows, T, ldy, J * TILE_I8, (st + 1) * KC, t);
         }
         if (active) {
-            const int8_t *a_s = sA[cur] + (wr * WT + (lane & 31)) * LDS_STRIDE;
-            const int8_t *b_s = (diag ? sA[cur] : sB[cur]) + (wc * WT + (lane & 31)) * LDS_STRIDE;
+            const int8_t *a_s = sA(cur) + (wr * WT + (lane & 31)) * LDS_STRIDE;
+            const int8_t *b_s = (diag ? sA(cur) : sB(cur)) + (wc * WT + (lane & 31)) * LDS_STRIDE;
 #pragma unroll
             for (int kk = 0; kk < KC; kk += 32) {
                 const int koff = kk + (lane >> 5) * 16;
@@ -248,8 +250,8 @@ __device__ __forceinline__ void correlate_tile(const int8_t *__restrict__ q, int
             }
         }
         if (more) {
-            store_stage(sA[cur ^ 1], ra, t);
-            if (!diag) store_stage(sB[cur ^ 1], rb, t);
+            store_stage(sA(cur ^ 1), ra, t);
+            if (!diag) store_stage(sB(cur ^ 1), rb, t);
         }
         __syncthreads();
     }
