@@ -154,7 +154,8 @@ int nbsi_correlate(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, in
 
 /* Name of the kernel nbsi_correlate runs for this shape (a static string; host only):
  * "correlate_i8_chan_kernel<32>" / "<64>" (short integrations: one workgroup holds a whole
- * channel) or "correlate_i8_kernel" (128 x 128 tiles). */
+ * channel), "correlate_i8_pipe_kernel<128>" (128 x 128 tiles) or "correlate_i8_pipe_kernel<256>"
+ * (256 x 256 tiles, integrations of 192 spectra and more). */
 const char *nbsi_correlate_kernel(int n_in, int n_spec);
 
 /*

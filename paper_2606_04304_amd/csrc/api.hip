@@ -277,7 +277,8 @@ const char *nbsi_correlate_kernel(int n_in, int n_spec) {
     switch (correlate_default_variant(n_in, n_spec)) {
         case CORR_VARIANT_CHAN32: return "correlate_i8_chan_kernel<32>";
         case CORR_VARIANT_CHAN64: return "correlate_i8_chan_kernel<64>";
-        default: return "correlate_i8_kernel";
+        default:  // 16-byte row strides (other integrations are repacked to one first)
+            return n_spec >= PIPE_BIG_T ? "correlate_i8_pipe_kernel<256>" : "correlate_i8_pipe_kernel<128>";
     }
 }
 

@@ -119,9 +119,14 @@ struct CalIn {
 // so for a quad of lanes 4m .. 4m+3 the XX visibility of antenna pair (A, B) sits in lane 4m
 // (inputs 2A, 2B) and the YY one in lane 4m+3 (inputs 2A+1, 2B+1); within the 8 x 8 antenna
 // block, A % 8 = 2 qq + l / 32 and B % 8 = (l % 32) / 4.
+// stage (optional): write the visibilities to an LDS tile instead, element (ia - stage_r0,
+// b - stage_c0) at stage[(ia - stage_r0) * VIS_LDS_STRIDE + b - stage_c0] (rows outside the packed
+// triangle included; the row writer skips them).
+constexpr int VIS_LDS_STRIDE = 72;  // int2 per staged row: 4 rows of a store fall in different banks
 __device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, int lane, int n_in,
                                                int2 *__restrict__ vc, const StokesOut &so, int c,
-                                               const BlockStokes &bs, bool small_sums, const CalIn &cal) {
+                                               const BlockStokes &bs, bool small_sums, const CalIn &cal,
+                                               int2 *stage = nullptr, int stage_r0 = 0, int stage_c0 = 0) {
     int par[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) par[r] = swap_lanes(a[r]);
@@ -138,16 +143,17 @@ __device__ __forceinline__ void store_tile_i32(const v16i &a, int R0, int C0, in
             re = par[4 * qq + 2] + a[4 * qq + 3];
             im = par[4 * qq + 3] - a[4 * qq + 2];
         }
-        if (ia < n_in && b <= ia) {
+        if (stage || (ia < n_in && b <= ia)) {
+            int2 out = make_int2(re, im);
             if (cal.wr) {
                 const float2 wi = cal.wr[ia - cal.r0], wj = cal.wc[b - cal.c0];
                 const float vr = (float)re, vi = (float)im;
                 const float tr = wi.x * vr - wi.y * vi, ti = wi.x * vi + wi.y * vr;  // w_i V
                 const float2 o = make_float2(tr * wj.x + ti * wj.y, ti * wj.x - tr * wj.y);  // * conj(w_j)
-                reinterpret_cast<float2 *>(vc)[(size_t)ia * (ia + 1) / 2 + b] = o;
-            } else {
-                vc[(size_t)ia * (ia + 1) / 2 + b] = make_int2(re, im);
+                out = make_int2(__float_as_int(o.x), __float_as_int(o.y));
             }
+            if (stage) stage[(ia - stage_r0) * VIS_LDS_STRIDE + (b - stage_c0)] = out;
+            else vc[(size_t)ia * (ia + 1) / 2 + b] = out;
         }
         if (bs.mask) {
             // quad_perm [3, 3, 3, 3]: every lane of the quad reads lane 3's visibility
@@ -288,6 +294,238 @@ __global__ __launch_bounds__(256, 3) void correlate_i8_kernel(const int8_t *__re
     correlate_tile<VEC, STOKES, CAL>(q, n_in, T, ldy, c, pair, vis, lds, so, calw, s_cal);
 }
 
+// Pipelined, persistent form of the tiled kernel for rows of a 16-byte multiple stride (every
+// single-band launch; other integrations are repacked first), on PT x PT tiles of G (PT = 128:
+// four waves, PT = 256: sixteen waves; each wave 64 x 64 of G).  A workgroup takes the tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ... (gridDim.x a multiple of 8, so every tile of a
+// workgroup stays on its XCD) and runs their K stages as one stream: stage g of the workgroup is
+// stage g mod n_st of its tile g / n_st.  A stage holds SK bytes of K of every row (64 for
+// PT = 128, 128 for PT = 256: whole 128-byte lines of L2, read once) and the stages go through a
+// ring of DEPTH LDS buffers (3 x 48 KB for PT = 128, 2 x 64 KB for PT = 256) filled by
+// direct-to-LDS buffer loads (no registers, no LDS store instructions): while stage g is
+// multiplied the loads of the next DEPTH - 1 stages are in flight, also across the end of a tile,
+// so a tile's first loads run under the previous tile's epilogue (with 128 KB of LDS one
+// workgroup holds a CU).  A wave's load writes 1 KB of LDS (1024 / SK rows); row r keeps its
+// 16-byte K chunks in the order slot(j, r), so the fragment reads of 16 consecutive rows at one
+// chunk hit distinct banks.  Reads past the channel's rows or past the row stride go beyond the
+// buffer's range and return 0.  Waits are explicit: each thread waits for its own loads of stage
+// g (later stages may stay outstanding), then a barrier makes every thread's loads visible and
+// frees the buffer that the next loads overwrite (read one stage earlier).  Within a stage the
+// fragments of the next 32-byte K block are read while the current block multiplies.  Long
+// integrations take the 256 x 256 tile, which moves half the operand bytes from L2 per
+// multiply-add.  (Measured at 704 inputs, T = 2,048: neither the barriers nor the waits cost
+// time; eight waves of 128 x 64 are slower than sixteen of 64 x 64; the clock under this load
+// settles near 1.9 GHz.)
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int PT>
+struct PipeShape {
+    static constexpr int SK = PT == 128 ? 64 : 128;   // bytes of K per stage and row
+    static constexpr int DEPTH = PT == 128 ? 3 : 2;   // stages in the LDS ring
+    static constexpr int WPB = PT == 128 ? 3 : 1;     // workgroups per CU
+    static constexpr int WM = 64;                     // rows of G per wave
+    static constexpr int WN = 64;                     // columns of G per wave
+    static constexpr int MI = WM / 32, NI = WN / 32;  // 32 x 32 MFMA blocks per wave
+    static constexpr int WR = PT / WM, WC = PT / WN;  // wave grid WR x WC
+    static constexpr int NW = WR * WC;                // waves
+    static constexpr int CPR = SK / 16;               // 16-byte chunks per row
+    static constexpr int RPK = 1024 / SK;             // rows per 1 KB block
+    static constexpr int OP = PT * SK;                // bytes of one operand's stage
+    static constexpr int STAGE = 2 * OP;              // bytes of a stage
+    static constexpr int BPW = PT / RPK / NW;         // 1 KB blocks per operand and wave
+    static constexpr int LOADS = 2 * BPW;             // direct loads per thread and stage
+    static_assert(BPW >= 1 && (PT / RPK) % NW == 0, "whole blocks per wave");
+    // slot of chunk j in row r: rows r .. r + 255 / SK share the 256 bytes of the 64 banks, and
+    // 16 consecutive rows read at one chunk hit 16 distinct 16-byte bank groups
+    static __device__ __forceinline__ int slot(int j, int r) { return j ^ ((r / (256 / SK)) & (CPR - 1)); }
+};
+
+template <int N>
+__device__ __forceinline__ void wait_vm() {  // s_waitcnt vmcnt(N), other counters untouched
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Wait until at most `stages` stages of this thread's loads (LOADS each) are outstanding.
+template <int LOADS, int MAXST>
+__device__ __forceinline__ void wait_stages(int stages) {
+    if (MAXST >= 2 && stages >= 2) wait_vm<2 * LOADS>();
+    else if (stages >= 1) wait_vm<LOADS>();
+    else wait_vm<0>();
+}
+
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Tile u of workgroup b: tile id b + u gridDim.x -> XCD lane id & 7, pair, channel.
+struct PipeTile {
+    int c, I, J;
+};
+
+__device__ __forceinline__ PipeTile pipe_tile(int rest, int xcd, int n_pairs) {
+    PipeTile p;
+    p.c = (rest / n_pairs) * 8 + xcd;
+    tile_pair(rest % n_pairs, p.I, p.J);
+    return p;
+}
+
+template <int PT, bool STOKES, bool CAL>
+__global__ __launch_bounds__(64 * PipeShape<PT>::NW, PipeShape<PT>::WPB) void correlate_i8_pipe_kernel(
+    const int8_t *__restrict__ q, int n_chan, int n_in, int T, int ldy, int n_pairs, int32_t *__restrict__ vis,
+    StokesOut so, const float2 *__restrict__ calw) {
+    using PS = PipeShape<PT>;
+    __shared__ __attribute__((aligned(16))) int8_t lds[PS::DEPTH * PS::STAGE];
+    __shared__ float2 s_cal[CAL ? PT : 1];
+    const int rows = 2 * n_in;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    // this workgroup's tiles: rest = rest0 + u step for u = 0 .. n_tiles - 1 (the channels of the
+    // last group of eight that do not exist end the list of the XCD lanes past them)
+    const int xcd = blockIdx.x & 7, rest0 = blockIdx.x >> 3, step = gridDim.x >> 3;
+    const int n_groups = (n_chan + 7) / 8;
+    const int rest_end = (xcd < n_chan - 8 * (n_groups - 1) ? n_groups : n_groups - 1) * n_pairs;
+    const int n_tiles = rest0 < rest_end ? (rest_end - 1 - rest0) / step + 1 : 0;
+    const int n_st = (T + PS::SK - 1) / PS::SK;
+    const int n_g = n_tiles * n_st;
+    if (n_g == 0) return;
+
+    // this thread's loads: wave w fills 1 KB blocks BPW w .. BPW w + BPW - 1 of each operand
+    // (rows 16 b .. 16 b + 15: the lane's row l / 4 and slot l % 4 of the block)
+    int rl[PS::BPW], slot_chunk[PS::BPW];
+#pragma unroll
+    for (int i = 0; i < PS::BPW; i++) {
+        rl[i] = (PS::BPW * wave + i) * PS::RPK + lane / PS::CPR;
+        slot_chunk[i] = PS::slot(lane % PS::CPR, rl[i]);  // the K chunk this lane's slot holds (an involution)
+    }
+    // loads of stream stage g: tile ti (stage s of it) into ring buffer g mod DEPTH
+    PipeTile li = pipe_tile(rest0, xcd, n_pairs);
+    int l_tile = 0, l_s = 0;
+    auto issue_next = [&](int g) __attribute__((always_inline)) {
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<int8_t *>(q + (size_t)li.c * rows * ldy), (short)0, rows * ldy, 0x00020000);
+        int8_t *base = lds + (g % PS::DEPTH) * PS::STAGE;
+        const bool ldiag = li.I == li.J;
+#pragma unroll
+        for (int i = 0; i < PS::BPW; i++) {
+            const int k = l_s * PS::SK + 16 * slot_chunk[i];
+            const int ra = li.I * PT + rl[i];
+            const int rb = ldiag ? rows : li.J * PT + rl[i];  // (diagonal tiles read A only)
+            const unsigned va = (ra < rows && k < ldy) ? (unsigned)(ra * ldy + k) : 0x80000000u;
+            const unsigned vb = (rb < rows && k < ldy) ? (unsigned)(rb * ldy + k) : 0x80000000u;
+            int8_t *blk = base + (PS::BPW * wave + i) * 1024;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)blk, 16, va, 0, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_void_t *)(blk + PS::OP), 16, vb, 0, 0, 0);
+        }
+        if (++l_s == n_st) {
+            l_s = 0;
+            if (++l_tile < n_tiles) li = pipe_tile(rest0 + l_tile * step, xcd, n_pairs);
+        }
+    };
+
+    v16i acc[PS::MI][PS::NI];
+#pragma unroll
+    for (int mi = 0; mi < PS::MI; mi++)
+#pragma unroll
+        for (int ni = 0; ni < PS::NI; ni++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[mi][ni][r] = 0;
+#pragma unroll
+    for (int g = 0; g < PS::DEPTH - 1; g++)
+        if (g < n_g) issue_next(g);
+
+    const size_t nprod = (size_t)n_in * (n_in + 1) / 2;
+    PipeTile ct = pipe_tile(rest0, xcd, n_pairs);
+    int c_tile = 0, s = 0;
+    for (int g = 0; g < n_g; g++) {
+        const bool diag = ct.I == ct.J;
+        // the wave's block of the tile (wr, wc); on a diagonal tile of sixteen waves the ten
+        // blocks on or below the diagonal are spread 3, 3, 2, 2 over the SIMDs (wave w runs on
+        // SIMD w mod 4) instead of 4, 3, 2, 1
+        const int pos = (PS::NW == 16 && diag) ? (int)((0xB62173A5FD94EC80ull >> (4 * wave)) & 15) : wave;
+        const int wr = pos / PS::WC, wc = pos % PS::WC;
+        // fragment rows of this wave (A: wr, B: wc); a row's chunk j sits at slot(j, r)
+        const int ra0 = wr * PS::WM + (lane & 31), rb0 = wc * PS::WN + (lane & 31);
+        // waves wholly above the diagonal of a diagonal tile, or wholly past the last row, multiply nothing
+        const bool active = !(diag && wc * PS::WN > wr * PS::WM + PS::WM - 1) && ct.I * PT + wr * PS::WM < rows;
+        // stages g + 1 .. g + DEPTH - 2 may stay in flight
+        wait_stages<PS::LOADS, PS::DEPTH - 2>(min(n_g - 1 - g, PS::DEPTH - 2));
+        lds_barrier();
+        if (g + PS::DEPTH - 1 < n_g) issue_next(g + PS::DEPTH - 1);
+        if (CAL && s == 0) {  // correction factors of the tile's row and column inputs (PT / 2 each)
+            for (int u = t; u < PT; u += 64 * PS::NW) {
+                const int in = u < PT / 2 ? ct.I * (PT / 2) + u : ct.J * (PT / 2) + u - PT / 2;
+                s_cal[u] = in < n_in ? calw[(size_t)ct.c * n_in + in] : make_float2(0.f, 0.f);
+            }
+        }
+        if (active) {
+            const int8_t *sa = lds + (g % PS::DEPTH) * PS::STAGE;
+            const int8_t *sb = diag ? sa : sa + PS::OP;
+            // fragments of K block kk (32 bytes: the lane's half j = 2 kk + l / 32)
+            auto frag = [&](int kk, v4i *a, v4i *b) __attribute__((always_inline)) {
+                const int j = 2 * kk + (lane >> 5);
+#pragma unroll
+                for (int mi = 0; mi < PS::MI; mi++) {
+                    const int r = ra0 + mi * 32;
+                    a[mi] = *reinterpret_cast<const v4i *>(sa + r * PS::SK + (PS::slot(j, r) << 4));
+                }
+#pragma unroll
+                for (int ni = 0; ni < PS::NI; ni++) {
+                    const int r = rb0 + ni * 32;
+                    b[ni] = *reinterpret_cast<const v4i *>(sb + r * PS::SK + (PS::slot(j, r) << 4));
+                }
+            };
+            auto mma = [&](const v4i *a, const v4i *b) __attribute__((always_inline)) {
+#pragma unroll
+                for (int mi = 0; mi < PS::MI; mi++)
+#pragma unroll
+                    for (int ni = 0; ni < PS::NI; ni++)
+                        acc[mi][ni] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+            };
+            constexpr int NK = PS::SK / 32;
+            // the fragments of block kk + 1 load while block kk multiplies (blocks past T hold 0)
+            // (scheduling barriers keep the compiler from pulling the reads back behind the MFMAs)
+            v4i a[2][PS::MI], b[2][PS::NI];
+            frag(0, a[0], b[0]);
+#pragma unroll
+            for (int kk = 0; kk < NK; kk++) {
+                if (kk + 1 < NK) frag(kk + 1, a[(kk + 1) & 1], b[(kk + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                mma(a[kk & 1], b[kk & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (++s < n_st) continue;
+        // the tile's last stage: epilogue (the next tile's first stages are already loading)
+        if (CAL) lds_barrier();  // s_cal visible to every wave
+        if (active) {
+            int2 *vc = reinterpret_cast<int2 *>(vis) + (size_t)ct.c * nprod;
+#pragma unroll
+            for (int mi = 0; mi < PS::MI; mi++)
+#pragma unroll
+                for (int ni = 0; ni < PS::NI; ni++) {
+                    const int R0 = ct.I * PT + wr * PS::WM + mi * 32;
+                    const int C0 = ct.J * PT + wc * PS::WN + ni * 32;
+                    if (R0 < rows && C0 <= R0 + 31) {
+                        const BlockStokes bs = STOKES ? block_stokes(so, R0, C0) : BlockStokes();
+                        CalIn ci;
+                        if (CAL) ci = CalIn{s_cal, ct.I * (PT / 2), s_cal + PT / 2, ct.J * (PT / 2)};
+                        store_tile_i32(acc[mi][ni], R0, C0, lane, n_in, vc, STOKES ? so : StokesOut(), ct.c, bs,
+                                       T <= 256, ci);
+                    }
+                }
+        }
+#pragma unroll
+        for (int mi = 0; mi < PS::MI; mi++)
+#pragma unroll
+            for (int ni = 0; ni < PS::NI; ni++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) acc[mi][ni][r] = 0;
+        s = 0;
+        if (++c_tile < n_tiles) ct = pipe_tile(rest0 + c_tile * step, xcd, n_pairs);
+    }
+}
+
 // Several sub-bands in one launch: task -> (job, channel group of 8, tile pair, XCD lane), one
 // workgroup per task, in the same XCD-preserving order as the single-band launch.
 template <bool VEC>
@@ -312,6 +550,10 @@ __global__ __launch_bounds__(256, 3) void correlate_i8_batch_kernel(const CorrJo
 
 // Repack int8 rows of T bytes to a stride of ldy bytes (ldy >= T, a multiple of 16), zero-filled,
 // so the tiled correlator stages whole 16-byte vectors.  One thread per 16-byte output vector.
+// Repack rows of T bytes to a stride of ldy (a multiple of 16 above T), zero-filled.  One thread
+// per 16-byte output chunk reads the five aligned words around its 16 bytes (the source is
+// 16-byte aligned, so a row starts at any byte of a word) and shifts them into place with
+// v_alignbyte; a row's last, partial chunk is read byte by byte.
 __global__ __launch_bounds__(256) void pad_rows_kernel(const int8_t *__restrict__ src, size_t n_rows, int T,
                                                        int ldy, int8_t *__restrict__ dst) {
     const size_t vpr = (size_t)(ldy / 16);
@@ -319,11 +561,24 @@ __global__ __launch_bounds__(256) void pad_rows_kernel(const int8_t *__restrict_
     if (e >= n_rows * vpr) return;
     const size_t r = e / vpr;
     const int k = (int)(e % vpr) * 16;
-    const int8_t *s = src + r * (size_t)T + k;
-    int8_t tmp[16];
+    const size_t a = r * (size_t)T + k;  // first source byte
+    v4i out;
+    if (k + 16 <= T && (a & ~(size_t)3) + 20 <= n_rows * (size_t)T) {
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(src + (a & ~(size_t)3));
+        const unsigned sh = (unsigned)(a & 3);
+        uint32_t x[5];
 #pragma unroll
-    for (int b = 0; b < 16; b++) tmp[b] = (k + b < T) ? s[b] : (int8_t)0;
-    *reinterpret_cast<v4i *>(dst + r * (size_t)ldy + k) = *reinterpret_cast<v4i *>(tmp);
+        for (int i = 0; i < 5; i++) x[i] = w[i];
+#pragma unroll
+        for (int i = 0; i < 4; i++) out[i] = (int)__builtin_amdgcn_alignbyte(x[i + 1], x[i], sh);
+    } else {
+        int8_t tmp[16];
+        const int8_t *s = src + a;
+#pragma unroll
+        for (int b = 0; b < 16; b++) tmp[b] = (k + b < T) ? s[b] : (int8_t)0;
+        out = *reinterpret_cast<v4i *>(tmp);
+    }
+    *reinterpret_cast<v4i *>(dst + r * (size_t)ldy + k) = out;
 }
 
 // Short integrations (n_spec <= 64): one workgroup per channel keeps the channel's whole
@@ -610,6 +865,18 @@ hipError_t launch_correlate_batch(const CorrJob *d_jobs, int n_jobs, int n_tasks
     return hipGetLastError();
 }
 
+// Compute units of the current device (queried once per device).
+static int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        cus[dev] = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0 ? n : 256;
+    }
+    return cus[dev];
+}
+
 // Single-band launch of one variant (the default path and the autotuner's candidates).
 hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n_spec, int32_t *vis, int variant,
                                     hipStream_t st, StokesOut so, int8_t *pad_scratch, const float2 *calw) {
@@ -641,9 +908,24 @@ hipError_t launch_correlate_variant(const int8_t *q, int n_chan, int n_in, int n
             else if (so.out) NBSI_TILED(false, true, false);
             else NBSI_TILED(false, false, false);
         } else {
-            if (calw) NBSI_TILED(true, false, true);
-            else if (so.out) NBSI_TILED(true, true, false);
-            else NBSI_TILED(true, false, false);
+            const int pt = n_spec >= PIPE_BIG_T ? 256 : 128;
+            const int nt = (2 * n_in + pt - 1) / pt, np = nt * (nt + 1) / 2;
+            // persistent grid: the resident workgroups, a multiple of 8, no more than the tiles
+            const size_t tiles = (size_t)((n_chan + 7) / 8) * 8 * np;
+            const size_t g = std::min(tiles, (size_t)device_cus() * (pt == 256 ? PipeShape<256>::WPB : PipeShape<128>::WPB) / 8 * 8);
+#define NBSI_PIPE(PT, S, CL)                                                                                         \
+    hipLaunchKernelGGL((correlate_i8_pipe_kernel<PT, S, CL>), dim3((unsigned)g), dim3(64 * PipeShape<PT>::NW), 0, st, q, \
+                       n_chan, n_in, n_spec, ldy, np, vis, so, calw)
+            if (pt == 256) {
+                if (calw) NBSI_PIPE(256, false, true);
+                else if (so.out) NBSI_PIPE(256, true, false);
+                else NBSI_PIPE(256, false, false);
+            } else {
+                if (calw) NBSI_PIPE(128, false, true);
+                else if (so.out) NBSI_PIPE(128, true, false);
+                else NBSI_PIPE(128, false, false);
+            }
+#undef NBSI_PIPE
         }
 #undef NBSI_TILED
         return hipGetLastError();

@@ -136,6 +136,8 @@ struct CorrJob {
 enum { CORR_VARIANT_TILED = 0, CORR_VARIANT_CHAN32 = 1, CORR_VARIANT_CHAN64 = 2 };
 int correlate_batch_tasks(const CorrJob &jb, int variant);
 int correlate_default_variant(int n_in, int n_spec);
+// Tiled correlations of at least this many spectra take 256 x 256 tiles (else 128 x 128).
+constexpr int PIPE_BIG_T = 192;
 bool correlate_variant_valid(int n_in, int n_spec, int variant);
 // Optional Stokes-I output of the correlator's epilogue: for the candidate pair (A, B) of an
 // imaging plan with index k (see nbsi_image_plan::d_tmask), out[c * n_pairs + k] =

@@ -122,6 +122,8 @@ def test_correlate_bit_exact(n_chan, n_in, n_spec):
 TILED_CASES = [
     # n_chan, n_in, n_spec
     (17, 704, 298), (9, 704, 1024), (17, 704, 100), (9, 200, 1024), (12, 130, 100),
+    # both sides of the switch to 256 x 256 tiles, and the longest integration timed
+    (9, 704, 176), (9, 704, 192), (9, 704, 2048), (9, 520, 200),
 ]
 
 
@@ -136,6 +138,19 @@ def test_correlate_tiled_sampled_channels_bit_exact(n_chan, n_in, n_spec):
     for c in chans:
         ref = oracle.correlate(q[c:c + 1].numpy())
         assert np.array_equal(got[c], ref[0]), c
+
+
+@pytest.mark.parametrize("n_spec", [297, 298, 299, 300, 301])
+def test_correlate_tiled_repacked_rows(n_spec):
+    """Integrations that are not a multiple of 16 spectra are repacked to a 16-byte row stride
+    first, from word loads shifted by the row's start within its word (every byte offset occurs
+    across these lengths); all channels are compared."""
+    n_chan, n_in = 5, 130
+    print(f"correlate repack n_spec={n_spec}", flush=True)
+    q = synth.random_spectra(n_chan, n_in, n_spec, seed=77 + n_spec, full_range=True)
+    vis = nb.nbsi_correlate(q.to(DEV))
+    torch.cuda.synchronize()
+    assert np.array_equal(vis.cpu().numpy(), oracle.correlate(q.numpy()))
 
 
 def test_correlate_extremes_and_determinism():
