@@ -193,6 +193,9 @@ int detect_run(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode,
         NBSI_TRY_HIP(ctx, hipMemsetAsync(counter, 0, sizeof(int), ctx->stream));
         NBSI_TRY_HIP(ctx, launch_detect_scan(img, n_chan, n_pix, mode, (const float *)stats, thresh, snr,
                                              (nbsi_cand *)cand, cap, counter, ctx->stream, ctx->d_flags));
+        // the usual few candidates are sorted before the count comes back: one wait per call
+        NBSI_TRY_HIP(ctx, launch_detect_sort_small_dev((const nbsi_cand *)cand, counter, cap, n_chan, n_pix, out,
+                                                       max_out, ctx->stream));
         NBSI_TRY_HIP(ctx, hipMemcpyAsync(&count, counter, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
         NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
         if (count <= cap) break;
@@ -205,7 +208,7 @@ int detect_run(nbsi_ctx *ctx, const float *img, int n_chan, int n_pix, int mode,
     }
     *n_out = count;
     const int n_write = std::min(count, max_out);
-    if (count > 0 && n_write > 0) {
+    if (count > detect_sort_small_max() && n_write > 0) {
         int n_pow2 = 1;
         while (n_pow2 < count) n_pow2 <<= 1;
         void *keys = ws ? (void *)ws->keys : nullptr;

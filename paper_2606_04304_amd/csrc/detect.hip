@@ -382,14 +382,27 @@ __device__ float wave_median_fast(ValFn val, int n, float *pool, int lane) {
 
 // ---- spectra held in registers (n_chan <= 64 NR) ----
 // Lane l of a wave holds channels l + 64 j, j < NR, of its pixel in v[j] (NaN past n_chan, which
-// every comparison below treats as false); tf maps a held value to the value being ranked.  The
-// same algorithm as wave_select, with every pass over registers instead of LDS.
-template <int NR, typename TF>
-__device__ float reg_select(const float (&v)[NR], TF tf, int n, int rank, float *pool, int lane) {
+// every comparison below treats as false).  The same algorithm as wave_select, with every pass
+// over registers instead of LDS; a pass costs two compares and a select per held value on the
+// vector unit, while the counts (popcounts of the compare masks) run on the scalar unit.
+// The rank-th smallest held value, and the next one up when the last bracket shows it (NaN
+// otherwise), for held values that are finite or NaN (NaN is never counted).
+template <int NR>
+__device__ float2 reg_select(const float (&v)[NR], int n, int rank, float *pool, int lane) {
     constexpr int D = 8, RESAMPLE_FROM = 4;
     float lo = -INFINITY, hi = INFINITY;
     int c_lt = 0, c_le = n;
-    float smp = lane < n ? tf(v[0]) : INFINITY;
+    // first sample: lane l holds channel l + 64 (l mod NR), spread over the band (NaN past n);
+    // the lanes that take register j form a constant mask
+    float smp = INFINITY;
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        unsigned long long lanes_j = 0ull;
+#pragma unroll
+        for (int l = j % 64; l < 64; l += NR) lanes_j |= 1ull << l;
+        smp = __builtin_amdgcn_inverse_ballot_w64(lanes_j) ? v[j] : smp;
+    }
+    smp = smp == smp ? smp : INFINITY;
     bool pivot = false, resample = false;
     for (int round = 0; round < 2 * n + 2; round++) {
         const int m = c_le - c_lt;
@@ -399,7 +412,7 @@ __device__ float reg_select(const float (&v)[NR], TF tf, int n, int rank, float 
             int k = 0;
 #pragma unroll
             for (int j = 0; j < NR; j++) {
-                const float x = tf(v[j]);
+                const float x = v[j];
                 if (x >= lo && x <= hi) {
                     k++;
                     if ((mix_hash((unsigned)(lane + 64 * j), (unsigned)round) >> 20) * (unsigned)k < 4096u) smp = x;
@@ -407,7 +420,7 @@ __device__ float reg_select(const float (&v)[NR], TF tf, int n, int rank, float 
             }
         }
         const float srt = wave_sort64(smp, lane);
-        const int s_n = uniform_i(wave_sum(smp < INFINITY ? 1 : 0));
+        const int s_n = __popcll(__ballot(smp < INFINITY));
         const int p = min(s_n - 1, (int)(((long long)(rank - c_lt) * s_n) / m));
         float a, b;
         if (pivot) {
@@ -419,18 +432,26 @@ __device__ float reg_select(const float (&v)[NR], TF tf, int n, int rank, float 
         }
         a = uniform_f(a);
         b = uniform_f(b);
+        // count below a and at or below b (popcounts of the compare masks, on the scalar unit);
+        // keep each lane's last held value in [a, b] (selected by the mask le & ~lt)
         int n_lt = 0, n_le = 0;
         float s_in = INFINITY;
 #pragma unroll
         for (int j = 0; j < NR; j++) {
-            const float x = tf(v[j]);
-            n_lt += x < a;
-            n_le += x <= b;
-            s_in = (s_in == INFINITY && x >= a && x <= b) ? x : s_in;
+            const float x = v[j];
+            const unsigned long long m_lt = __ballot(x < a), m_le = __ballot(x <= b);
+            n_lt += __popcll(m_lt);
+            n_le += __popcll(m_le);
+            s_in = __builtin_amdgcn_inverse_ballot_w64(m_le & ~m_lt) ? x : s_in;
+            // (an empty asm that takes s_in makes each select happen here: left alone, the
+            // compiler defers the select chain and keeps every value's masks alive)
+            asm volatile("" : "+v"(s_in));
         }
-        n_lt = uniform_i(wave_sum(n_lt));
-        n_le = uniform_i(wave_sum(n_le));
-        resample = true;
+        // (the next sample is chosen before branching: were s_in needed on one path only, the
+        // compiler would sink its selects there and keep every pass mask alive until then)
+        const bool inside = rank >= n_lt && rank < n_le;
+        smp = inside ? s_in : smp;
+        resample = !inside;
         if (rank < n_lt) {
             hi = float_down(a);
             c_le = n_lt;
@@ -438,105 +459,122 @@ __device__ float reg_select(const float (&v)[NR], TF tf, int n, int rank, float 
             lo = float_up(b);
             c_lt = n_le;
         } else {
-            if (a == b) return a;
+            if (a == b) return make_float2(a, rank + 1 < n_le ? a : NAN);
             lo = a;
             hi = b;
             c_lt = n_lt;
             c_le = n_le;
-            smp = s_in;
-            resample = false;
         }
         pivot = c_le - c_lt == m;
     }
-    if (lo == hi) return lo;
+    if (lo == hi) return make_float2(lo, rank + 1 < c_le ? lo : NAN);
+    // at most 64 values remain in [lo, hi]: gathered one per lane through `pool`, sorted across
+    // the wave, and read at the rank (and the next place, when it is in the bracket)
     int base = 0;
 #pragma unroll
     for (int j = 0; j < NR; j++) {
-        const float x = tf(v[j]);
+        const float x = v[j];
         const bool in = x >= lo && x <= hi;
         const unsigned long long bm = __ballot(in);
+        if (bm == 0ull) continue;  // (most registers hold none of them)
         if (in) pool[base + __popcll(bm & ((1ull << lane) - 1ull))] = x;
         base += __popcll(bm);
     }
     const int m = base;
+    const float srt = wave_sort64(lane < m ? pool[lane] : INFINITY, lane);
     const int k = rank - c_lt;
-    float mine = 0.f;
-    bool hit = false;
-    if (lane < m) {
-        mine = pool[lane];
-        int less = 0, eq = 0;
-        for (int j = 0; j < m; j++) {
-            const float y = pool[j];
-            less += y < mine;
-            eq += y == mine;
-        }
-        hit = less <= k && k < less + eq;
-    }
-    const unsigned long long hb = __ballot(hit);
-    return __shfl(mine, hb ? (int)(__ffsll((long long)hb) - 1) : 0, 64);
+    const float vk = __shfl(srt, k, 64), vk1 = __shfl(srt, min(k + 1, 63), 64);
+    return make_float2(vk, k + 1 < m ? vk1 : NAN);
 }
 
-template <int NR, typename TF>
-__device__ float reg_median(const float (&v)[NR], TF tf, int n, float *pool, int lane) {
-    const float vlo = reg_select<NR>(v, tf, n, (n - 1) / 2, pool, lane);
-    if (n & 1) return vlo;
-    int le = 0;
-    float nxt = INFINITY;
-#pragma unroll
-    for (int j = 0; j < NR; j++) {
-        const float x = tf(v[j]);
-        le += x <= vlo;
-        if (x > vlo) nxt = fminf(nxt, x);
-    }
-    le = wave_sum(le);
-    nxt = wave_min_f(nxt);
-    const float vhi = (le >= n / 2 + 1) ? vlo : nxt;
-    return 0.5f * (vlo + vhi);
-}
-
-// Per-pixel detection for spectra of up to 64 NR channels: a workgroup of 16 waves takes 16
-// adjacent pixels of one row; each staging round loads 512 channels x 16 pixels (64 contiguous
-// bytes per channel row) through an LDS tile, and every wave keeps its pixel's spectrum in
-// registers, so the selections and the scoring run without LDS or barriers.
-constexpr int REG_PX = 16;
 template <int NR>
-__global__ __launch_bounds__(1024) void detect_pixel_reg_kernel(const float *__restrict__ img, int n_chan, int n_pix,
+__device__ float reg_median(const float (&v)[NR], int n, float *pool, int lane) {
+    const float2 r = reg_select<NR>(v, n, (n - 1) / 2, pool, lane);
+    if (n & 1) return r.x;
+    float vhi = r.y;
+    if (vhi != vhi) {  // the upper middle value was not in the last bracket: one more pass
+        int le = 0;
+        float nxt = INFINITY;
+#pragma unroll
+        for (int j = 0; j < NR; j++) {
+            const float x = v[j];
+            le += __popcll(__ballot(x <= r.x));
+            nxt = fminf(nxt, x > r.x ? x : INFINITY);
+        }
+        nxt = wave_min_f(nxt);
+        vhi = (le >= n / 2 + 1) ? r.x : nxt;
+    }
+    return 0.5f * (r.x + vhi);
+}
+
+// Per-pixel detection for spectra of up to 64 NR channels: a workgroup of REG_PX waves takes
+// REG_PX adjacent pixels of one row; each staging round loads 512 channels x REG_PX pixels
+// (4 REG_PX contiguous bytes per channel row) through an LDS tile, and every wave keeps its
+// pixel's spectrum in registers, so the selections and the scoring run without LDS or barriers.
+// Eight-wave workgroups at 128 registers leave room for two per CU, so one workgroup's staging
+// reads run under the other's selections.
+constexpr int REG_PX = 8;
+constexpr int REG_LINE = 128 / (4 * REG_PX);  // workgroups that share a 128-byte line of a row
+template <int NR>
+__global__ __launch_bounds__(64 * REG_PX, 4) void detect_pixel_reg_kernel(const float *__restrict__ img, int n_chan, int n_pix,
                                                                 int mode, const float2 *__restrict__ stats,
                                                                 float thresh, float *__restrict__ snr_out,
                                                                 nbsi_cand *__restrict__ cand, int cap,
                                                                 int *__restrict__ counter, unsigned *__restrict__ flags) {
-    constexpr int CH = 512;  // channels per staging round (8 registers)
-    static_assert(NR % 8 == 0, "staging rounds");
+    constexpr int CH = 1024;              // channels per staging round (16 registers)
+    constexpr int TPC = REG_PX / 4;       // threads per channel row segment (16 bytes each)
+    constexpr int CPS = 64 * REG_PX / TPC;  // channels per load step (256)
+    static_assert(NR % (CH / 64) == 0 && CH % CPS == 0, "staging rounds");
     __shared__ float tile[CH][REG_PX + 1];
     __shared__ float pool_all[REG_PX][64];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int groups_per_row = (n_pix + REG_PX - 1) / REG_PX;
-    const int gy = blockIdx.x / groups_per_row, gx0 = (blockIdx.x % groups_per_row) * REG_PX;
+    // XCD-aware order: workgroups are dealt to the 8 XCDs round robin, so the REG_LINE groups
+    // that split each 128-byte line of a channel row go to blocks b, b + 8, ... of one XCD,
+    // which run together and share the line in that XCD's L2
+    constexpr int RUN = 8 * REG_LINE;
+    const int nbr = (int)gridDim.x / RUN * RUN, b = blockIdx.x;
+    const int grp = b < nbr ? (b / RUN) * RUN + (b & 7) * REG_LINE + ((b >> 3) % REG_LINE) : b;
+    const int gy = grp / groups_per_row, gx0 = (grp % groups_per_row) * REG_PX;
     const size_t npix2 = (size_t)n_pix * n_pix;
-    const int sp = t % REG_PX, sc = t / REG_PX;  // staging: pixel, channel offset (0..63)
-    float v[NR];
+    // staging: thread t loads pixels sp .. sp + 3 (16 bytes; n_pix is a multiple of 8) of
+    // channels sc + CPS q
+    const int sp = 4 * (t % TPC), sc = t / TPC;
+    const bool col_ok = gx0 + sp < n_pix;
+    const float *src = img + (size_t)gy * n_pix + gx0 + sp;
+    // the loads of round k + 1 are issued before round k's tile is read back, so they are in
+    // flight across its barrier
+    auto load = [&](int k, float4 (&r)[CH / CPS]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int k = 0; k < NR / 8; k++) {
-        float r[8];
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int c = k * CH + sc + 64 * q;
-            float x = NAN;
-            if (c < n_chan && gx0 + sp < n_pix) {
-                x = img[(size_t)c * npix2 + (size_t)gy * n_pix + gx0 + sp];
-                if (mode == NBSI_DETECT_PER_IMAGE) {
-                    const float2 st = stats[c];
-                    x = st.y > 0.f ? (x - st.x) / st.y : x * 0.f;  // (x * 0: non-finite stays non-finite)
-                }
-            }
-            r[q] = x;
+        for (int q = 0; q < CH / CPS; q++) {
+            const int c = k * CH + sc + CPS * q;
+            r[q] = (c < n_chan && col_ok) ? *reinterpret_cast<const float4 *>(src + (size_t)c * npix2)
+                                          : make_float4(NAN, NAN, NAN, NAN);
         }
+    };
+    float v[NR];
+    float4 r[CH / CPS];
+    load(0, r);
+#pragma unroll
+    for (int k = 0; k < NR / (CH / 64); k++) {
         __syncthreads();  // the previous round's tile has been read
 #pragma unroll
-        for (int q = 0; q < 8; q++) tile[sc + 64 * q][sp] = r[q];
+        for (int q = 0; q < CH / CPS; q++) {
+            const int c = k * CH + sc + CPS * q;
+            float e[4] = {r[q].x, r[q].y, r[q].z, r[q].w};
+            if (mode == NBSI_DETECT_PER_IMAGE && c < n_chan) {
+                const float2 st = stats[c];
+#pragma unroll
+                for (int i = 0; i < 4; i++)  // (x * 0: non-finite stays non-finite)
+                    e[i] = st.y > 0.f ? (e[i] - st.x) / st.y : e[i] * 0.f;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) tile[sc + CPS * q][sp + i] = e[i];
+        }
+        if (k + 1 < NR / (CH / 64)) load(k + 1, r);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 8; q++) v[8 * k + q] = tile[lane + 64 * q][wave];
+        for (int q = 0; q < CH / 64; q++) v[(CH / 64) * k + q] = tile[lane + 64 * q][wave];
     }
     const int x = gx0 + wave, y = gy;
     if (x >= n_pix) return;  // no barriers below
@@ -549,15 +587,28 @@ __global__ __launch_bounds__(1024) void detect_pixel_reg_kernel(const float *__r
     if (in_hor && !finite && lane == 0 && flags) atomicOr(flags, NBSI_FLAG_CUBE_NONFINITE);
     const bool active = in_hor && finite;
     float *pool = pool_all[wave];
-    float med = 0.f, scale = 1.f;
+    float scale = 1.f;
     bool ok = active;
     if (active) {
-        med = reg_median<NR>(v, [](float a) { return a; }, n_chan, pool, lane);
+        const float med = reg_median<NR>(v, n_chan, pool, lane);
+        // the deviations x - med replace the values (rounded as the score rounds them); for the
+        // MAD their magnitudes, with the signs kept in a bit mask, so that both selections rank
+        // values held in registers (a rank over |x - med| computed on the fly has the compiler
+        // hoist all NR of them out of the selection rounds and spill)
+        unsigned long long neg = 0ull;
+#pragma unroll
+        for (int j = 0; j < NR; j++) {
+            const float d = v[j] - med;
+            neg |= (unsigned long long)(d < 0.f) << j;
+            v[j] = fabsf(d);  // (NaN past n_chan stays NaN)
+        }
         if (mode == NBSI_DETECT_PER_PIXEL) {
-            const float mad = reg_median<NR>(v, [med](float a) { return fabsf(a - med); }, n_chan, pool, lane);
+            const float mad = reg_median<NR>(v, n_chan, pool, lane);
             scale = MAD_K * mad;
             ok = mad > 0.f;
         }
+#pragma unroll
+        for (int j = 0; j < NR; j++) v[j] = ((neg >> j) & 1ull) ? -v[j] : v[j];
     }
     // SNR = (x - med) / scale as a product with the float32 reciprocal; neighbours along
     // frequency come from the adjacent lane (channel c +- 1), across register rows at lanes 0/63
@@ -565,17 +616,19 @@ __global__ __launch_bounds__(1024) void detect_pixel_reg_kernel(const float *__r
 #pragma unroll
     for (int j = 0; j < NR; j++) {
         const int c = lane + 64 * j;
-        const float xv = v[j];
+        const float xv = v[j];  // x - med
+        const float z = ok ? xv * inv : 0.f;
+        if (snr_out && c < n_chan) snr_out[(size_t)c * npix2 + (size_t)y * n_pix + x] = z;
+        const bool hit = ok && c < n_chan && z >= thresh;
+        // the neighbours are fetched (with every lane taking part) only when a lane crosses
+        if (__ballot(hit) == 0ull) continue;
         const float up = __shfl_up(xv, 1, 64), dn = __shfl_down(xv, 1, 64);
         const float prev_row = j > 0 ? __shfl(v[j > 0 ? j - 1 : 0], 63, 64) : 0.f;
         const float next_row = j + 1 < NR ? __shfl(v[j + 1 < NR ? j + 1 : j], 0, 64) : 0.f;
-        if (c >= n_chan) continue;
-        const float z = ok ? (xv - med) * inv : 0.f;
-        if (snr_out) snr_out[(size_t)c * npix2 + (size_t)y * n_pix + x] = z;
-        if (!ok || z < thresh) continue;
+        if (!hit) continue;
         const float xl = lane > 0 ? up : prev_row, xr = lane < 63 ? dn : next_row;
-        if (c > 0 && !(z > (xl - med) * inv)) continue;
-        if (c + 1 < n_chan && !(z >= (xr - med) * inv)) continue;
+        if (c > 0 && !(z > xl * inv)) continue;
+        if (c + 1 < n_chan && !(z >= xr * inv)) continue;
         const int idx = atomicAdd(counter, 1);
         if (idx < cap) {
             nbsi_cand r;
@@ -826,6 +879,40 @@ __global__ __launch_bounds__(1024) void sort_small_kernel(const nbsi_cand *__res
     for (int i = t; i < n_out; i += 1024) out[i] = cand[(int)(s[i] & 0xffffffull)];
 }
 
+// The small sort with the count read on the device: n = *counter candidates (when n <= cap and
+// n <= SORT1_MAX; otherwise the host sorts once it has read n), the first min(n, n_out) of them
+// written to out in (y, x, c) order.
+__global__ __launch_bounds__(1024) void sort_small_dev_kernel(const nbsi_cand *__restrict__ cand,
+                                                              const int *__restrict__ counter, int cap, int n_chan,
+                                                              int n_pix, int n_out, nbsi_cand *__restrict__ out) {
+    __shared__ unsigned long long s[SORT1_MAX];
+    const int n = *counter;
+    if (n <= 0 || n > cap || n > SORT1_MAX) return;
+    int n_pow2 = 1;
+    while (n_pow2 < n) n_pow2 <<= 1;
+    const int t = threadIdx.x;
+    for (int i = t; i < n_pow2; i += 1024)
+        s[i] = (i < n) ? ((cand_key(cand[i], n_chan, n_pix) << 24) | (unsigned long long)i) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= n_pow2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = t; i < n_pow2; i += 1024) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const unsigned long long a = s[i], b = s[p];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) {
+                        s[i] = b;
+                        s[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    const int m = min(n, n_out);
+    for (int i = t; i < m; i += 1024) out[i] = cand[(int)(s[i] & 0xffffffull)];
+}
+
 __global__ void gather_sorted_kernel(const unsigned long long *__restrict__ keys, const nbsi_cand *__restrict__ cand,
                                      int n_out, nbsi_cand *__restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -890,6 +977,16 @@ hipError_t launch_detect_scan(const float *img, int n_chan, int n_pix, int mode,
     }
     return hipGetLastError();
 }
+
+hipError_t launch_detect_sort_small_dev(const nbsi_cand *cand, const int *counter, int cap, int n_chan, int n_pix,
+                                       nbsi_cand *out, int n_out, hipStream_t st) {
+    if (n_out <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sort_small_dev_kernel, dim3(1), dim3(1024), 0, st, cand, counter, cap, n_chan, n_pix, n_out,
+                       out);
+    return hipGetLastError();
+}
+
+int detect_sort_small_max() { return SORT1_MAX; }
 
 hipError_t launch_detect_sort(nbsi_cand *cand, int n, unsigned long long *keys, int n_chan, int n_pix,
                               nbsi_cand *out, int n_out, hipStream_t st) {

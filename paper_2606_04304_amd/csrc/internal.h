@@ -223,5 +223,10 @@ hipError_t launch_detect_stats(const float *img, int n_chan, int n_pix, int mode
 hipError_t launch_detect_scan(const float *img, int n_chan, int n_pix, int mode,
                               const float *stats, float thresh, float *snr, nbsi_cand *cand,
                               int cap, int *counter, hipStream_t st, unsigned *flags = nullptr);
+// Sorts the candidates on the device when their count (read there) is at most
+// detect_sort_small_max() and at most cap; larger counts are left to launch_detect_sort.
+hipError_t launch_detect_sort_small_dev(const nbsi_cand *cand, const int *counter, int cap, int n_chan, int n_pix,
+                                       nbsi_cand *out, int n_out, hipStream_t st);
+int detect_sort_small_max();
 hipError_t launch_detect_sort(nbsi_cand *cand, int n, unsigned long long *keys, int n_chan,
                               int n_pix, nbsi_cand *out, int n_out, hipStream_t st);
