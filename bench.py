@@ -52,8 +52,11 @@ def parse():
     ap.add_argument("--no-deep", action="store_true", help="skip the long-integration correlator leg")
     ap.add_argument("--no-classifier", action="store_true", help="skip the classifier leg")
     ap.add_argument("--no-search", action="store_true", help="skip the full Stage I search leg")
+    ap.add_argument("--no-precision", action="store_true", help="skip the C4 precision leg")
+    ap.add_argument("--no-c5", action="store_true", help="skip the C5 classifier leg (10^5 injections)")
     ap.add_argument("--leg", default=None,
-                    choices=["deep_correlator", "classifier", "stage1_search", "dedoppler", "stage2"],
+                    choices=["deep_correlator", "classifier", "stage1_search", "dedoppler", "stage2", "precision",
+                             "c5"],
                     help="with --legs-only: run this leg alone")
     ap.add_argument("--step-only", action="store_true",
                     help="profiling aid: only the timed step (no legs, no FP32 path, no batch)")
@@ -215,6 +218,18 @@ def batched_leg(args, nb, torch, ctx, dev, synth):
                for bd, o in zip(batch.subbands, outs))
     launches = batch.describe()
     batch.close()
+    # the same batch with FP16 / BF16 gridding (FP32 accumulation), against the FP32 batch's images
+    reduced = {}
+    for prec, name in ((nb.NBSI_PREC_FP16, "fp16"), (nb.NBSI_PREC_BF16, "bf16")):
+        bp = nb.Batch(xyz, subs, precision=prec, graph=True, ctx=ctx)
+        ms_p = timed(bp.run, k)
+        worst = 0.0
+        for bd, o in zip(bp.subbands, outs):
+            peak = o[2].abs().amax(dim=(1, 2))
+            worst = max(worst, float(((bd["img"] - o[2]).abs().amax(dim=(1, 2)) / peak).max()))
+        reduced[name] = {"batched_graph_ms": round(ms_p, 3), "vs_fp32_batch_max_abs_over_peak": worst}
+        bp.close()
+        log(f"[bench] batched graph, {name} gridding: {ms_p:.2f} ms")
     tuned = nb.Batch(xyz, subs, graph=True, autotune=True, ctx=ctx)
     ms_tuned = timed(tuned.run, k)
     desc = json.loads(tuned.describe())
@@ -227,6 +242,23 @@ def batched_leg(args, nb, torch, ctx, dev, synth):
                     for bd, o in zip(over.subbands, outs))
     log(f"[bench] batched, sub-bands overlapped on two streams (default tiles): {ms_over:.2f} ms")
     over.close()
+    # the plain FP32 path per sub-band: float spectra, FP32 correlator, FP32 gridding (last: it
+    # overwrites the per-sub-band images)
+    t_max = max(d["n_spec"] for d in subs)
+    spec_f = torch.empty((1024 * n_in * 2 * t_max,), dtype=torch.float32, device=dev)
+    vis_f = torch.empty((1024, nprod, 2), dtype=torch.float32, device=dev)
+
+    def per_subband_f32():
+        for d, p, (_, _, img) in zip(subs, plans, outs):
+            sf = spec_f[:d["n_chan"] * n_in * 2 * d["n_spec"]].view(d["n_chan"], n_in, 2, d["n_spec"])
+            nb.nbsi_channelize(d["volt"], d["n_fft"], d["n_spec"], d["chan0"], d["n_chan"], d["gain"],
+                               want_q=False, want_f=True, spec_f=sf, ctx=ctx)
+            nb.nbsi_correlate_f32(sf, vis=vis_f[:d["n_chan"]], ctx=ctx)
+            nb.nbsi_image(p, vis_f[:d["n_chan"]], nb.NBSI_PREC_FP32, img=img)
+
+    ms_plain = timed(per_subband_f32, k)
+    log(f"[bench] plain FP32 path per sub-band: {ms_plain:.2f} ms")
+    del spec_f, vis_f
     n_ch = sum(d["n_chan"] for d in subs)
     ops = sum(8.0 * nprod * d["n_spec"] * d["n_chan"] for d in subs)
     return {
@@ -242,6 +274,11 @@ def batched_leg(args, nb, torch, ctx, dev, synth):
         "fine_channels_per_s_autotuned": round(n_ch / (ms_tuned * 1e-3), 1),
         "correlated_tops_autotuned": round(ops / (ms_tuned * 1e-3) / 1e12, 3),
         "batched_equals_per_subband": bool(same),
+        "batched_reduced_precision": reduced,
+        "plain_fp32_path_per_subband_ms": round(ms_plain, 3),
+        "speedup_vs_plain_fp32_path": {"batched_fp32_graph": round(ms_plain / ms_batch, 3),
+                                       **{f"batched_{n}_graph": round(ms_plain / r["batched_graph_ms"], 3)
+                                          for n, r in reduced.items()}},
         "launches": json.loads(launches)["launches"],
         "autotuned_choices": [(s["n_fft"], s["n_spec"], s["n_pix"], s["corr_variant"], s["grid_ge"])
                               for s in desc["subbands"]],
@@ -259,6 +296,129 @@ def _timed(torch, fn, k):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / k
+
+
+def precision_leg(args, nb, torch, ctx, dev, synth):
+    """C4 at full size: 352 antennas x 2 pol, 2^18-point channelizer keeping 16,384 channels, T = 8
+    spectra, 512 x 512 gridded images.  Channelize (int8 codes) and correlate with the Stokes-I
+    epilogue once (exact int32 visibilities), then image every channel from Stokes I by gridding
+    in FP32, FP16 and BF16 (FP32 accumulation, float64 uv); and the plain FP32 path on the same
+    GPU (float spectra, FP32 correlator, FP32 gridding from float visibilities).  FP16 / BF16
+    images are compared with the FP32 ones over every channel (worst channel's max-abs and RMS
+    error relative to its peak; the FP64-oracle errors at sampled pixels are the precision test's)."""
+    cfg = synth.make_config(4)
+    xyz, volt, freq, gain = synth.config_inputs(cfg, device="cuda")
+    n_in, C, T, n_pix = 2 * cfg.n_ant, cfg.n_chan, cfg.n_spec, cfg.n_pix
+    nprod = n_in * (n_in + 1) // 2
+    g = torch.from_numpy(gain).to(dev)
+    plan = nb.ImagePlan(xyz, freq, n_pix, nb.NBSI_IMAGE_GRID, ctx=ctx)
+    n_pairs = plan.n_pairs()
+    k = max(2, args.steps // 4)
+    q = torch.empty((C, n_in, 2, T), dtype=torch.int8, device=dev)
+    ms_chan = _timed(torch, lambda: nb.nbsi_channelize(volt, cfg.n_fft, T, cfg.chan0, C, g, spec_q=q, ctx=ctx), k)
+    vis = torch.empty((C, nprod, 2), dtype=torch.int32, device=dev)
+    st = torch.empty((C, n_pairs, 2), dtype=torch.float32, device=dev)
+    ms_corr = _timed(torch, lambda: nb.nbsi_correlate_stokes(q, plan, vis=vis, stokes_i=st, ctx=ctx), k)
+    del vis
+    torch.cuda.empty_cache()
+    ref = torch.empty((C, n_pix, n_pix), dtype=torch.float32, device=dev)
+    img = torch.empty_like(ref)
+    modes = {}
+    for prec, name in ((nb.NBSI_PREC_FP32, "fp32"), (nb.NBSI_PREC_FP16, "fp16"), (nb.NBSI_PREC_BF16, "bf16")):
+        out = ref if prec == nb.NBSI_PREC_FP32 else img
+        ms = _timed(torch, lambda: nb.nbsi_image_stokes(plan, st, prec, img=out), k)
+        entry = {"image_ms": round(ms, 3), "imaged_channels_per_s": round(C / (ms * 1e-3), 1)}
+        if prec != nb.NBSI_PREC_FP32:
+            worst_max = worst_rms = 0.0
+            for c0 in range(0, C, 1024):
+                r, o = ref[c0:c0 + 1024], img[c0:c0 + 1024]
+                peak = r.abs().amax(dim=(1, 2))
+                d = (o - r).abs()
+                worst_max = max(worst_max, float((d.amax(dim=(1, 2)) / peak).max()))
+                worst_rms = max(worst_rms, float((d.pow(2).mean(dim=(1, 2)).sqrt() / peak).max()))
+            entry.update({"vs_fp32_max_abs_over_peak": worst_max, "vs_fp32_rms_over_peak": worst_rms})
+        modes[name] = entry
+        log(f"[bench] C4 gridding {name}: {ms:.2f} ms")
+    del st
+    torch.cuda.empty_cache()
+    # plain FP32 path: float spectra, FP32 correlator, FP32 gridding of float visibilities
+    spec_f = torch.empty((C, n_in, 2, T), dtype=torch.float32, device=dev)
+    ms_chan_f = _timed(torch, lambda: nb.nbsi_channelize(volt, cfg.n_fft, T, cfg.chan0, C, g, want_q=False,
+                                                         want_f=True, spec_f=spec_f, ctx=ctx), k)
+    vis_f = torch.empty((C, nprod, 2), dtype=torch.float32, device=dev)
+    ms_corr_f = _timed(torch, lambda: nb.nbsi_correlate_f32(spec_f, vis=vis_f, ctx=ctx), k)
+    ms_img_f = _timed(torch, lambda: nb.nbsi_image(plan, vis_f, nb.NBSI_PREC_FP32, img=img), k)
+    log(f"[bench] C4 plain FP32 path: {ms_chan_f + ms_corr_f + ms_img_f:.2f} ms")
+    plan.close()
+    del spec_f, vis_f, ref, img, q, volt
+    torch.cuda.empty_cache()
+    mixed = {n: round(ms_chan + ms_corr + modes[n]["image_ms"], 3) for n in modes}
+    plain = round(ms_chan_f + ms_corr_f + ms_img_f, 3)
+    return {
+        "workload": "C4: 352 ant x 2 pol, 2^18-pt channelizer, T=8, 16384 channels, GRID 512^2",
+        "channelize_ms": round(ms_chan, 3), "correlate_stokes_ms": round(ms_corr, 3),
+        "gridding": modes,
+        "mixed_precision_path_ms": mixed,
+        "plain_fp32_path_ms": {"channelize_f32": round(ms_chan_f, 3), "correlate_f32": round(ms_corr_f, 3),
+                               "image_fp32_from_f32_vis": round(ms_img_f, 3), "total": plain},
+        "speedup_vs_plain_fp32_path": {n: round(plain / v, 3) for n, v in mixed.items()},
+    }
+
+
+def c5_leg(args, nb, torch, ctx, dev, synth):
+    """C5: candidate cubes of the instrument configuration (352 antennas, 65,536-point channelizer,
+    T = 32, 4,096 channels, 256^2 images) with 10^5 synthetic injections through the library's own
+    pipeline: 460 injection sets of 150 sky tones, 50 horizon RFI tracks and 20 broadband spikes,
+    over three noise dumps (training 300 sets, operating point 60, test 100).  The network is
+    trained on the GPU (the library's forward / backward / Adam kernels) on the training dump's
+    candidates, its operating point (95 % of tone candidates kept) set on the second dump, and it
+    is scored on the third against the plain 5 sigma detector (every candidate accepted):
+    precision over accepted candidates, recall over injected tones."""
+    from paper_2606_04304_amd import classifier as cl
+    from synth import injections as inj
+    splits = {"train": (9400, 300), "operating_point": (9500, 60), "test": (9600, 100)}
+    data = {}
+    t0 = time.perf_counter()
+    for name, (seed, n_sets) in splits.items():
+        xyz, freq, vis = inj.noise_visibilities(352, 750.0, 65536, 32, 30720, 4096, seed, ctx=ctx)
+        data[name] = inj.build_dataset(xyz, freq, vis, 256, n_sets, seed + 7, ctx=ctx)
+        del vis
+        torch.cuda.empty_cache()
+        log(f"[bench] C5 {name}: {n_sets} injection sets, {len(data[name]['labels'])} candidates")
+    build_s = time.perf_counter() - t0
+    n_inj = sum(220 * n for _, n in splits.values())
+    net = nb.Net(synth.net_init(9700), max_batch=512)
+    tr = data["train"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = cl.train(net, tr["stamps"], tr["labels"], epochs=3, batch=512, lr=2e-3, seed=9701)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    cut = cl.operating_point(cl.scores(net, data["operating_point"]["stamps"]),
+                             data["operating_point"]["labels"], keep=0.95)
+    te = data["test"]
+    z = cl.scores(net, te["stamps"]) - cut
+    lab, tid, n_t = te["labels"], te["tone_ids"], te["tones_injected"]
+    p_thr, r_thr = cl.precision_recall(np.ones(len(lab), bool), lab, tid, n_t)
+    p_net, r_net = cl.precision_recall(z > 0, lab, tid, n_t)
+    kinds = te["kinds"]
+    names = {synth.KIND_TONE: "tone", synth.KIND_RFI: "rfi", synth.KIND_SPIKE: "spike", synth.KIND_NOISE: "noise"}
+    rej = {names[k]: round(float(np.mean(z[kinds == k] <= 0)), 4) for k in names if np.any(kinds == k)}
+    net.close()
+    log(f"[bench] C5: threshold P {p_thr:.3f} R {r_thr:.3f}; network P {p_net:.3f} R {r_net:.3f}")
+    return {
+        "workload": "C5: instrument-scale candidate cubes, 10^5 injections (tones, horizon RFI, broadband "
+                    "spikes), 33-channel x 9x9 FP16 stamps, 3-layer conv net",
+        "injections": n_inj,
+        "candidates": {k: int(len(d["labels"])) for k, d in data.items()},
+        "tone_candidates": {k: int(np.sum(d["labels"] > 0.5)) for k, d in data.items()},
+        "tones_injected_test": int(n_t),
+        "threshold_detector": {"precision": round(p_thr, 4), "recall": round(r_thr, 4)},
+        "with_network": {"precision": round(p_net, 4), "recall": round(r_net, 4)},
+        "rejected_fraction_by_kind": rej,
+        "train_loss_per_epoch": [round(h, 4) for h in hist],
+        "data_build_s": round(build_s, 2), "train_s": round(train_s, 3),
+    }
 
 
 def deep_correlator_leg(args, nb, torch, ctx, dev, synth):
@@ -459,7 +619,9 @@ def main():
                 "classifier": lambda: classifier_leg(args, nb, torch, c0, dev, synth),
                 "stage1_search": lambda: search_leg(args, nb, torch, c0, dev, 4096, 256),
                 "dedoppler": lambda: dedoppler_leg(args, nb, torch, c0, dev, 4096, 256),
-                "stage2": lambda: stage2_leg(args, nb, torch, c0, dev, 4096, 256)}
+                "stage2": lambda: stage2_leg(args, nb, torch, c0, dev, 4096, 256),
+                "precision": lambda: precision_leg(args, nb, torch, c0, dev, synth),
+                "c5": lambda: c5_leg(args, nb, torch, c0, dev, synth)}
         names = [args.leg] if args.leg else list(legs)
         print(json.dumps({k: legs[k]() for k in names}))
         return
@@ -614,6 +776,7 @@ def main():
 
     if args.step_only:
         args.no_search = args.no_fp32_path = args.no_batch = args.no_deep = args.no_classifier = True
+        args.no_precision = args.no_c5 = True
     if not args.no_search:
         comp["stage1_search"] = search_leg(args, nb, torch, ctx, dev, C, n_pix)
         comp["dedoppler"] = dedoppler_leg(args, nb, torch, ctx, dev, C, n_pix)
@@ -677,6 +840,12 @@ def main():
         comp["deep_correlator"] = deep_correlator_leg(args, nb, torch, ctx, dev, synth)
     if not args.no_classifier:
         comp["classifier"] = classifier_leg(args, nb, torch, ctx, dev, synth)
+        torch.cuda.empty_cache()
+    if not args.no_precision:
+        comp["precision_c4"] = precision_leg(args, nb, torch, ctx, dev, synth)
+        torch.cuda.empty_cache()
+    if not args.no_c5:
+        comp["classifier_c5"] = c5_leg(args, nb, torch, ctx, dev, synth)
         torch.cuda.empty_cache()
 
     out = {

@@ -276,26 +276,59 @@ __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_batch_kernel(cons
 }
 
 // [n_in][n_spec][C] complex int8 -> [C][n_in][2][n_spec] int8, through a 64 x 64 LDS tile:
-// tile (i, channel block cb, spectrum block sb).
+// tile (i, channel block cb, spectrum block sb).  The tile's rows are read as channel pairs
+// (4 bytes) when n_chan is even; each (channel, component) run of spectra is written 16 bytes at
+// a time (one vector store when n_spec is a multiple of 16, so the run is 16-byte aligned).
 __device__ __forceinline__ void corner_turn_q_tile(const int16_t *__restrict__ stage, int n_in, int n_spec,
                                                    int n_chan, int8_t *__restrict__ out, int i, int cb, int sb,
-                                                   int16_t (*tile)[65]) {
+                                                   int16_t (*tile)[66]) {
     const int c0 = cb * 64, s0 = sb * 64;
+    const int S = min(64, n_spec - s0);  // spectra of this tile
     const int t = threadIdx.x;
-    for (int e = t; e < 64 * 64; e += 256) {
-        const int sl = e / 64, cl = e % 64;
-        const int s = s0 + sl, c = c0 + cl;
-        tile[sl][cl] = (s < n_spec && c < n_chan) ? stage[((size_t)i * n_spec + s) * n_chan + c] : 0;
+    const int16_t *src = stage + ((size_t)i * n_spec + s0) * n_chan + c0;
+    if ((n_chan & 1) == 0) {
+        for (int e = t; e < S * 32; e += 256) {
+            const int sl = e >> 5, cp = 2 * (e & 31);
+            int v = 0;
+            if (c0 + cp < n_chan) v = *reinterpret_cast<const int *>(src + (size_t)sl * n_chan + cp);
+            tile[sl][cp] = (int16_t)(v & 0xffff);
+            tile[sl][cp + 1] = (int16_t)(v >> 16);
+        }
+    } else {
+        for (int e = t; e < S * 64; e += 256) {
+            const int sl = e >> 6, cl = e & 63;
+            tile[sl][cl] = c0 + cl < n_chan ? src[(size_t)sl * n_chan + cl] : (int16_t)0;
+        }
     }
     __syncthreads();
-    // write: for each (channel, component), 64 consecutive spectra
-    for (int e = t; e < 64 * 2 * 64; e += 256) {
-        const int sl = e % 64, comp = (e / 64) % 2, cl = e / 128;
-        const int s = s0 + sl, c = c0 + cl;
-        if (s < n_spec && c < n_chan) {
-            const int16_t v = tile[sl][cl];
-            const int8_t b = comp ? (int8_t)(v >> 8) : (int8_t)(v & 0xff);
-            out[(((size_t)c * n_in + i) * 2 + comp) * n_spec + s] = b;
+    // pieces of 16 spectra: piece fastest, then component, then channel (a channel's two runs
+    // are adjacent in the output)
+    const int NP = (S + 15) >> 4;
+    const bool vec = (n_spec & 15) == 0;
+    for (int e = t; e < 128 * NP; e += 256) {
+        const int piece = e % NP, comp = (e / NP) & 1, cl = e / (2 * NP);
+        const int c = c0 + cl;
+        if (c >= n_chan) continue;
+        const int sl0 = 16 * piece;
+        int8_t *dst = out + (((size_t)c * n_in + i) * 2 + comp) * n_spec + s0 + sl0;
+        if (vec && sl0 + 16 <= S) {
+            int w[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                int x = 0;
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int v = tile[sl0 + 4 * q + k][cl];
+                    x |= ((comp ? (v >> 8) : v) & 0xff) << (8 * k);
+                }
+                w[q] = x;
+            }
+            *reinterpret_cast<int4 *>(dst) = make_int4(w[0], w[1], w[2], w[3]);
+        } else {
+            for (int k = 0; k < 16 && sl0 + k < S; k++) {
+                const int16_t v = tile[sl0 + k][cl];
+                dst[k] = comp ? (int8_t)(v >> 8) : (int8_t)(v & 0xff);
+            }
         }
     }
 }
@@ -303,7 +336,7 @@ __device__ __forceinline__ void corner_turn_q_tile(const int16_t *__restrict__ s
 __global__ __launch_bounds__(256) void corner_turn_q_kernel(const int16_t *__restrict__ stage, int n_in,
                                                             int n_spec, int n_chan,
                                                             int8_t *__restrict__ out) {
-    __shared__ int16_t tile[64][65];
+    __shared__ int16_t tile[64][66];
     const int n_cb = (n_chan + 63) / 64;
     corner_turn_q_tile(stage, n_in, n_spec, n_chan, out, blockIdx.y, blockIdx.x % n_cb, blockIdx.x / n_cb, tile);
 }
@@ -312,7 +345,7 @@ __global__ __launch_bounds__(256) void corner_turn_q_kernel(const int16_t *__res
 __global__ __launch_bounds__(256) void corner_turn_q_batch_kernel(const ChanJob *__restrict__ jobs, int n_jobs,
                                                                   const int *__restrict__ task0, int n_tasks,
                                                                   int8_t *const *__restrict__ outs, int n_in) {
-    __shared__ int16_t tile[64][65];
+    __shared__ int16_t tile[64][66];
     const int task = blockIdx.x;
     if (task >= n_tasks) return;
     int j = 0;

@@ -4,11 +4,12 @@
 // conv3x3(33 -> 32) - ReLU - conv3x3(32 -> 64) - ReLU - conv3x3(64 -> 32) - ReLU -
 // global average pool - linear(32 -> 1), trained with binary cross-entropy on the logit.
 //
-// Every convolution is an implicit GEMM on v_mfma_f32_32x32x8_f16: rows are (stamp, position)
-// pairs of the batch (81 positions per 9 x 9 stamp), columns output channels, and the
-// reduction runs over (tap, input channel) with k = tap * CINP + ci (input channels padded to
-// a multiple of 8 with zero weights).  Activations are stored position-major with the channel
-// fastest, [b][81][C], so one lane's four consecutive k are one 8-byte load.
+// Every convolution is an implicit GEMM on gfx950's v_mfma_f32_32x32x16_f16 (K = 16 per
+// instruction: lanes 0-31 carry k 0..7 of their row or column, lanes 32-63 k 8..15): rows are
+// (stamp, position) pairs of the batch (81 positions per 9 x 9 stamp), columns output channels,
+// and the reduction runs over (tap, input channel) with k = tap * CINP + ci (input channels
+// padded to a multiple of 16 with zero weights).  Activations are stored position-major with
+// the channel fastest, [b][81][C], so one lane's eight consecutive k are one 16-byte load.
 //
 // Backward: gradients leave the loss in FP32; before each FP16 product they are scaled by a
 // power of two chosen from their maximum (the first from a bound, later ones from an exact
@@ -27,7 +28,7 @@
 
 namespace {
 
-typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int SC = NBSI_STAMP_CHANNELS;   // 33 spectral channels per stamp
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const _Float16 *__restric
     const int m0 = (blockIdx.x * 4 + wave) * 32;
     if (m0 >= M) return;  // uniform per wave; the kernel has no barriers
     const int co0 = blockIdx.y * 32;
-    const int i = lane & 31, kq = (lane >> 5) * 4;
+    const int i = lane & 31, kq = (lane >> 5) * 8;
     const int m = m0 + i;
     const bool mv = m < M;
     const int b = mv ? m / NPOS : 0, p = mv ? m % NPOS : 0;
@@ -107,19 +108,19 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const _Float16 *__restric
         const bool ok = sv && yy >= 0 && yy < SP && xx >= 0 && xx < SP;
         const int pp = ok ? yy * SP + xx : 0;
 #pragma unroll
-        for (int c0 = 0; c0 < CINP; c0 += 8) {
+        for (int c0 = 0; c0 < CINP; c0 += 16) {
             const int ci = c0 + kq;
-            v4h a = {0, 0, 0, 0};
+            v8h a = {0, 0, 0, 0, 0, 0, 0, 0};
             if (ok) {
                 if constexpr (IN_STAMP) {
 #pragma unroll
-                    for (int e = 0; e < 4; e++) a[e] = (ci + e < CIN) ? src[(ci + e) * NPOS + pp] : (_Float16)0;
+                    for (int e = 0; e < 8; e++) a[e] = (ci + e < CIN) ? src[(ci + e) * NPOS + pp] : (_Float16)0;
                 } else {
-                    a = *reinterpret_cast<const v4h *>(src + pp * CINP + ci);
+                    a = *reinterpret_cast<const v8h *>(src + pp * CINP + ci);
                 }
             }
-            const v4h w = *reinterpret_cast<const v4h *>(wrow + tap * CINP + ci);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a, w, acc, 0, 0, 0);
+            const v8h w = *reinterpret_cast<const v8h *>(wrow + tap * CINP + ci);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, w, acc, 0, 0, 0);
         }
     }
     const int co = co0 + i;
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const _Float16 *__restrict__
     const int split = blockIdx.y;
     const int M = n * NPOS;
     const int mb = split * chunk, me = min(M, mb + chunk);
-    const int i = lane & 31, kq = (lane >> 5) * 4;
+    const int i = lane & 31, kq = (lane >> 5) * 8;
     const int k = k0 + i;
     const bool kv = k < K;
     const int tap = kv ? k / CINP : 0, ci = kv ? k % CINP : 0;
@@ -244,10 +245,10 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const _Float16 *__restrict__
     v16f acc;
 #pragma unroll
     for (int r = 0; r < 16; r++) acc[r] = 0.f;
-    for (int m = mb; m < me; m += 8) {
-        v4h a, xb;
+    for (int m = mb; m < me; m += 16) {
+        v8h a, xb;
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
+        for (int e = 0; e < 8; e++) {
             const int mm = m + kq + e;
             const bool ok = mm < me;
             a[e] = ok ? dZ[(size_t)mm * COUT + co0 + i] : (_Float16)0;
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const _Float16 *__restrict__
             }
             xb[e] = xv;
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a, xb, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, xb, acc, 0, 0, 0);
     }
     if (!kv) return;
 #pragma unroll
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(256) void dgrad_kernel(const _Float16 *__restrict__
     const int m0 = (blockIdx.x * 4 + wave) * 32;
     if (m0 >= M) return;  // uniform per wave; no barriers
     const int ci0 = blockIdx.y * 32;
-    const int i = lane & 31, kq = (lane >> 5) * 4;
+    const int i = lane & 31, kq = (lane >> 5) * 8;
     const int m = m0 + i;
     const bool mv = m < M;
     const int b = mv ? m / NPOS : 0, p = mv ? m % NPOS : 0;
@@ -330,12 +331,12 @@ __global__ __launch_bounds__(256) void dgrad_kernel(const _Float16 *__restrict__
         const bool ok = mv && qy >= 0 && qy < SP && qx >= 0 && qx < SP;
         const _Float16 *zrow = dZ + ((size_t)b * NPOS + (ok ? qy * SP + qx : 0)) * COUT;
 #pragma unroll
-        for (int c0 = 0; c0 < COUT; c0 += 8) {
+        for (int c0 = 0; c0 < COUT; c0 += 16) {
             const int cc = c0 + kq;
-            v4h a = {0, 0, 0, 0};
-            if (ok) a = *reinterpret_cast<const v4h *>(zrow + cc);
-            const v4h w = *reinterpret_cast<const v4h *>(wrow + tap * COUT + cc);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8f16(a, w, acc, 0, 0, 0);
+            v8h a = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (ok) a = *reinterpret_cast<const v8h *>(zrow + cc);
+            const v8h w = *reinterpret_cast<const v8h *>(wrow + tap * COUT + cc);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, w, acc, 0, 0, 0);
         }
     }
     const int c = ci0 + i;
@@ -445,7 +446,7 @@ struct NetDevice {  // current-device guard
 };
 
 hipError_t pack_weights(nbsi_net *net, hipStream_t st) {
-    const int dims[3][3] = {{33, 40, 32}, {32, 32, 64}, {64, 64, 32}};
+    const int dims[3][3] = {{33, 48, 32}, {32, 32, 64}, {64, 64, 32}};
     const int offs[3] = {OFF_W1, OFF_W2, OFF_W3};
     for (int l = 0; l < 3; l++) {
         const int cin = dims[l][0], cinp = dims[l][1], cout = dims[l][2];
@@ -467,7 +468,7 @@ hipError_t forward(nbsi_net *net, const uint16_t *stamps, int n_stamps, const in
     const _Float16 *x = reinterpret_cast<const _Float16 *>(stamps);
     const int M = n * NPOS;
     const dim3 blk(256);
-    hipLaunchKernelGGL((conv_fwd_kernel<33, 40, 32, true, false>), dim3(blocks(M, 128), 1), blk, 0, st, x, index,
+    hipLaunchKernelGGL((conv_fwd_kernel<33, 48, 32, true, false>), dim3(blocks(M, 128), 1), blk, 0, st, x, index,
                        n_stamps, n, net->w16[0], net->theta + OFF_B1, (void *)net->a1);
     hipLaunchKernelGGL((conv_fwd_kernel<32, 32, 64, false, false>), dim3(blocks(M, 128), 2), blk, 0, st,
                        (const _Float16 *)net->a1, nullptr, 0, n, net->w16[1], net->theta + OFF_B2, (void *)net->a2);
@@ -516,7 +517,7 @@ hipError_t backward(nbsi_net *net, const uint16_t *stamps, int n_stamps, const i
     hipLaunchKernelGGL(dz_convert_kernel, dim3(blocks((long)M * 32)), blk, 0, st, net->dA, (long)M * 32,
                        net->maxbits + 1, net->scale, 2, 1, net->dZ);
     // layer 1 (input: the stamps, 33 -> 32)
-    weight_grads<33, 40, 32, true>(net, reinterpret_cast<const _Float16 *>(stamps), index, n_stamps, n, 1, OFF_W1,
+    weight_grads<33, 48, 32, true>(net, reinterpret_cast<const _Float16 *>(stamps), index, n_stamps, n, 1, OFF_W1,
                                    OFF_B1, grad, st);
     return hipGetLastError();
 }
@@ -576,7 +577,7 @@ int nbsi_net_create(nbsi_ctx *ctx, const float *params_host, int max_batch, nbsi
     rc = rc ? rc : net_alloc(net, B * NPOS * 32, &net->a1);
     rc = rc ? rc : net_alloc(net, B * NPOS * 64, &net->a2);
     rc = rc ? rc : net_alloc(net, B * NPOS * 64, &net->dZ);
-    rc = rc ? rc : net_alloc(net, (size_t)32 * 9 * 40, &net->w16[0]);
+    rc = rc ? rc : net_alloc(net, (size_t)32 * 9 * 48, &net->w16[0]);
     rc = rc ? rc : net_alloc(net, (size_t)64 * 9 * 32, &net->w16[1]);
     rc = rc ? rc : net_alloc(net, (size_t)32 * 9 * 64, &net->w16[2]);
     rc = rc ? rc : net_alloc(net, (size_t)33 * 9 * 32, &net->wt16[0]);

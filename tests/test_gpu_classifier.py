@@ -23,12 +23,13 @@ if not torch.cuda.is_available():
 
 import paper_2606_04304_amd as nb  # noqa: E402
 from paper_2606_04304_amd import classifier as cl  # noqa: E402
+from synth import injections as inj  # noqa: E402
 import synth  # noqa: E402
 
 
 def _data(seed, n_sets):
-    xyz, freq, vis = cl.noise_visibilities(352, 750.0, 65536, 32, 30720, 4096, seed)
-    d = cl.build_dataset(xyz, freq, vis, 256, n_sets, seed + 7, log=lambda m: print(m, flush=True))
+    xyz, freq, vis = inj.noise_visibilities(352, 750.0, 65536, 32, 30720, 4096, seed)
+    d = inj.build_dataset(xyz, freq, vis, 256, n_sets, seed + 7, log=lambda m: print(m, flush=True))
     del vis
     torch.cuda.empty_cache()
     return d

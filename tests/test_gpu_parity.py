@@ -49,6 +49,10 @@ CHAN_CASES = [
     (1, 65536, 1, 65536 - 100, 100),  # band at the top edge (wraps below k = 0)
     (1, 1 << 18, 1, (1 << 17) - 8192, 16384),  # P = 16 sub-transforms of 16384
     (1, 1 << 18, 2, (1 << 17) - 512, 1024),    # P = 64 sub-transforms of 4096
+    # corner turns that write whole 16-spectrum runs: an odd band (byte-wide tile reads) and a
+    # second, partial tile of spectra
+    (3, 4096, 32, 1000, 77),
+    (2, 8192, 80, 100, 256),
 ]
 
 
