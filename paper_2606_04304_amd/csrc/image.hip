@@ -233,9 +233,28 @@ __device__ __forceinline__ float2 grid_product(float2 val, float wu, float wv) {
 // every 8 values and 2 more per row.  With it the Stockham passes' loads (consecutive lanes,
 // consecutive values) and strided stores (strides of 1, 2, 4, 8 and 64 values x the radix) fall
 // in distinct banks, and values of one column in consecutive rows do not share a bank.
-__device__ __forceinline__ int p8(int i) { return i + (i >> 3); }
-__host__ __device__ constexpr int p8_size(int n) { return n + n / 8; }
-__host__ __device__ constexpr int row_stride(int l) { return p8_size(l) + 2; }
+// LDS layout of rows of L complex values (L >= 64): element i of row r sits at
+//   r RS + (i & ~31) + ((i & 31) ^ (((i >> 5) C1 ^ r C2) & 31)),
+// an XOR swizzle of the 32 values (64 banks) of each aligned run.  A run read or written
+// contiguously stays conflict-free; the strided accesses of the Stockham passes, the gridding
+// accumulators' store, the kept-column read-out and the column pass's tile store and Hermitian
+// fold are spread over the banks by the run index and the row.  The constants were chosen per L
+// with a bank model of every access pattern of both passes (the eight-byte accesses of a wave in
+// two halves of 32 lanes over 64 four-byte banks): about 1.1x the conflict-free cycles, where a
+// padding of one value per eight had 1.7-2x.
+template <int L>
+struct RowLayout {
+    static constexpr int C1 = (L == 256 || L >= 1024) ? 9 : 5;
+    static constexpr int C2 = L == 128 ? 25 : (L == 2048 ? 0 : 1);
+    static constexpr int RS = L + (L == 128 ? 0 : ((L == 512 || L == 1024) ? 4 : 8));
+    static_assert(L >= 64, "swizzle runs of 32");
+};
+
+template <int L>
+__device__ __forceinline__ int lds_at(int row, int i) {
+    using RL = RowLayout<L>;
+    return row * RL::RS + ((i & ~31) | ((i & 31) ^ ((((i >> 5) * RL::C1) ^ (row * RL::C2)) & 31)));
+}
 
 // Radix of pass p of a 2^LOGL-point transform: 8 throughout, after one radix-2 or radix-4 pass
 // when LOGL is not a multiple of 3.
@@ -263,7 +282,6 @@ __device__ __forceinline__ float2 twid(const float2 *tab, int m) {
 template <int LOGL, int NROWS, int LOGR, int LOGNS, int LOGT>
 __device__ __forceinline__ void fft_pass(float2 *buf, const float2 *tab, int t) {
     constexpr int L = 1 << LOGL, R = 1 << LOGR, NS = 1 << LOGNS;
-    constexpr int RS = row_stride(L);
     constexpr int E = NROWS * L / 256, NB = E / R, PER_ROW = L / R;
     static_assert(E % R == 0, "whole butterflies per thread");
     static_assert(NS == 1 || 256 % PER_ROW == 0, "shared twiddles");
@@ -272,7 +290,7 @@ __device__ __forceinline__ void fft_pass(float2 *buf, const float2 *tab, int t) 
     for (int b = 0; b < NB; b++) {
         const int g = t + 256 * b, row = g / PER_ROW, j = g % PER_ROW;
 #pragma unroll
-        for (int r = 0; r < R; r++) v[b * R + r] = buf[row * RS + p8(j + r * PER_ROW)];
+        for (int r = 0; r < R; r++) v[b * R + r] = buf[lds_at<L>(row, j + r * PER_ROW)];
     }
     __syncthreads();
     float2 w[R];
@@ -291,7 +309,7 @@ __device__ __forceinline__ void fft_pass(float2 *buf, const float2 *tab, int t) 
         const int g = t + 256 * b, row = g / PER_ROW, j = g % PER_ROW;
         const int base = ((j >> LOGNS) << (LOGNS + LOGR)) + (j & (NS - 1));
 #pragma unroll
-        for (int r = 0; r < R; r++) buf[row * RS + p8(base + r * NS)] = v[b * R + r];
+        for (int r = 0; r < R; r++) buf[lds_at<L>(row, base + r * NS)] = v[b * R + r];
     }
     __syncthreads();
 }
@@ -355,7 +373,7 @@ struct GridShape {
     static constexpr int CELLS = Tile<GE>::CELLS;
     static constexpr int R = CELLS / M;              // rows of a band
     static constexpr int NB = M / 2 / R;             // bands of the half plane
-    static constexpr int RS = row_stride(M);
+    static constexpr int RS = RowLayout<M>::RS;
     static constexpr int BUF = R * RS;               // LDS complex values of the band
     // owned columns per thread: 4 x 4 cells at M = 512 (measured 3.5% faster than 2 x 8 there),
     // else one column per 256 of M
@@ -543,7 +561,7 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
 #pragma unroll
     for (int q = 0; q < CPT; q++)
 #pragma unroll
-        for (int r = 0; r < RPT; r++) grid[(rown + r) * RS + p8(col0 + q)] = acc[q][r];
+        for (int r = 0; r < RPT; r++) grid[lds_at<M>(rown + r, col0 + q)] = acc[q][r];
     __syncthreads();
     fft_rows<LOGM, R, LOGM>(grid, tab, t);
     // keep image columns x: FFT index (x - n/2) mod M, times (-1)^(x - n/2); undo the FP16 scale;
@@ -556,7 +574,7 @@ __device__ __forceinline__ void grid_rows(const float2 *__restrict__ cvis, const
         const int xp = x - n_pix / 2;
         const int col = xp & (M - 1);
         const float sgn = (xp & 1) ? -unscale : unscale;
-        const float2 f0 = grid[lr * RS + p8(col)], f1 = grid[(lr + 1) * RS + p8(col)];
+        const float2 f0 = grid[lds_at<M>(lr, col)], f1 = grid[lds_at<M>(lr + 1, col)];
         dst[e] = make_float4(f0.x * sgn, f0.y * sgn, f1.x * sgn, f1.y * sgn);
     }
 }
@@ -612,7 +630,7 @@ struct ColShape {
     static constexpr int NX = cols_per_band(GE, N);     // columns per workgroup
     static constexpr int RB = Tile<GE>::CELLS / M;       // rows per band of the row pass
     static constexpr int NBANDS = N / RB;
-    static constexpr int RS = row_stride(N);
+    static constexpr int RS = RowLayout<N>::RS;
     static constexpr int E = NX * N / 256;               // values per thread
     static constexpr int BUF = NX * RS;
     static constexpr int NXB = N / NX;                   // workgroups per channel
@@ -643,8 +661,8 @@ __device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, cons
         const int b = e4 / (NX * RB / 2), w = e4 % (NX * RB / 2);
         const int xl = w / (RB / 2), lr = 2 * (w % (RB / 2));
         const int i = b * RB + lr;
-        buf[xl * RS + p8(i)] = make_float2(r[q].x, r[q].y);
-        buf[xl * RS + p8(i + 1)] = make_float2(r[q].z, r[q].w);
+        buf[lds_at<n>(xl, i)] = make_float2(r[q].x, r[q].y);
+        buf[lds_at<n>(xl, i + 1)] = make_float2(r[q].z, r[q].w);
     }
     __syncthreads();
     float2 z[E];
@@ -652,10 +670,10 @@ __device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, cons
     for (int q = 0; q < E; q++) {
         const int e = t + 256 * q;
         const int xl = e / n, i = e % n;
-        const float2 hi = buf[xl * RS + p8(i)];  // s[i + n]
+        const float2 hi = buf[lds_at<n>(xl, i)];  // s[i + n]
         float2 lo = make_float2(0.f, 0.f);
         if (i) {
-            const float2 m = buf[xl * RS + p8(n - i)];  // s[i] = conj s[2n - i], stored at row n - i
+            const float2 m = buf[lds_at<n>(xl, n - i)];  // s[i] = conj s[2n - i], stored at row n - i
             lo = make_float2(m.x, -m.y);
         }
         const float2 a = cadd(lo, hi);
@@ -666,7 +684,7 @@ __device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, cons
 #pragma unroll
     for (int q = 0; q < E; q++) {
         const int e = t + 256 * q;
-        buf[(e / n) * RS + p8(e % n)] = z[q];
+        buf[lds_at<n>(e / n, e % n)] = z[q];
     }
     __syncthreads();
     fft_rows<CS::LOGN, NX, LOGM>(buf, tab, t);
@@ -677,7 +695,7 @@ __device__ __forceinline__ void grid_cols(const float2 *__restrict__ inter, cons
         const int xl = e % NX, y = e / NX;
         const int yp = y - n / 2;
         const int k = yp & (M - 1);
-        const float2 f = buf[xl * RS + p8(k >> 1)];
+        const float2 f = buf[lds_at<n>(xl, k >> 1)];
         const float v = (k & 1) ? f.y : f.x;
         const float sgn = (yp & 1) ? -1.f : 1.f;
         const float o = v * sgn * corr[x0 + xl] * corr[y] * inv;
