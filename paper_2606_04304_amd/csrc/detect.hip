@@ -554,10 +554,15 @@ __global__ __launch_bounds__(64 * REG_PX, 4) void detect_pixel_reg_kernel(const 
     };
     float v[NR];
     float4 r[CH / CPS];
+    // pixels of the workgroup whose spectrum holds a non-finite value (bit = pixel), gathered
+    // while staging
+    __shared__ unsigned s_bad;
+    if (t == 0) s_bad = 0u;
     load(0, r);
 #pragma unroll
     for (int k = 0; k < NR / (CH / 64); k++) {
-        __syncthreads();  // the previous round's tile has been read
+        __syncthreads();  // the previous round's tile has been read (and s_bad is cleared)
+        unsigned bad_px = 0u;
 #pragma unroll
         for (int q = 0; q < CH / CPS; q++) {
             const int c = k * CH + sc + CPS * q;
@@ -569,8 +574,12 @@ __global__ __launch_bounds__(64 * REG_PX, 4) void detect_pixel_reg_kernel(const 
                     e[i] = st.y > 0.f ? (e[i] - st.x) / st.y : e[i] * 0.f;
             }
 #pragma unroll
-            for (int i = 0; i < 4; i++) tile[sc + CPS * q][sp + i] = e[i];
+            for (int i = 0; i < 4; i++) {
+                tile[sc + CPS * q][sp + i] = e[i];
+                if (c < n_chan && !__builtin_isfinite(e[i])) bad_px |= 1u << (sp + i);
+            }
         }
+        if (bad_px) atomicOr(&s_bad, bad_px);
         if (k + 1 < NR / (CH / 64)) load(k + 1, r);
         __syncthreads();
 #pragma unroll
@@ -579,10 +588,7 @@ __global__ __launch_bounds__(64 * REG_PX, 4) void detect_pixel_reg_kernel(const 
     const int x = gx0 + wave, y = gy;
     if (x >= n_pix) return;  // no barriers below
     // a spectrum holding a non-finite value is not searched (wave-uniform: one pixel per wave)
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < NR; j++) bad |= (lane + 64 * j < n_chan) && !__builtin_isfinite(v[j]);
-    const bool finite = __ballot(bad) == 0ull;
+    const bool finite = ((s_bad >> wave) & 1u) == 0u;
     const bool in_hor = in_horizon(x, y, n_pix);
     if (in_hor && !finite && lane == 0 && flags) atomicOr(flags, NBSI_FLAG_CUBE_NONFINITE);
     const bool active = in_hor && finite;
