@@ -154,8 +154,9 @@ int nbsi_correlate(nbsi_ctx *ctx, const int8_t *spec_q, int n_chan, int n_in, in
 
 /* Name of the kernel nbsi_correlate runs for this shape (a static string; host only):
  * "correlate_i8_chan_kernel<32>" / "<64>" (short integrations: one workgroup holds a whole
- * channel), "correlate_i8_pipe_kernel<128>" (128 x 128 tiles) or "correlate_i8_pipe_kernel<256>"
- * (256 x 256 tiles, integrations of 192 spectra and more). */
+ * channel), "correlate_i8_pipe_kernel<256>" (256 x 256 tiles, integrations of more than 64
+ * spectra) or "correlate_i8_pipe_kernel<128>" (128 x 128 tiles: up to 64 spectra of more inputs
+ * than the whole-channel kernels hold in LDS). */
 const char *nbsi_correlate_kernel(int n_in, int n_spec);
 
 /*

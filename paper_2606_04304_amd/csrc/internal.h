@@ -136,8 +136,10 @@ struct CorrJob {
 enum { CORR_VARIANT_TILED = 0, CORR_VARIANT_CHAN32 = 1, CORR_VARIANT_CHAN64 = 2 };
 int correlate_batch_tasks(const CorrJob &jb, int variant);
 int correlate_default_variant(int n_in, int n_spec);
-// Tiled correlations of at least this many spectra take 256 x 256 tiles (else 128 x 128).
-constexpr int PIPE_BIG_T = 192;
+// Tiled correlations of at least this many spectra take 256 x 256 tiles, the rest (at most 64
+// spectra: whole-channel shapes too large for LDS) 128 x 128 tiles.  (Measured at 704 inputs:
+// the 256 tiles are faster from T = 80 on, 0.50 vs 0.71 ms at T = 80 and 1.04 vs 1.34 at 298.)
+constexpr int PIPE_BIG_T = 65;
 bool correlate_variant_valid(int n_in, int n_spec, int variant);
 // Optional Stokes-I output of the correlator's epilogue: for the candidate pair (A, B) of an
 // imaging plan with index k (see nbsi_image_plan::d_tmask), out[c * n_pairs + k] =

@@ -126,8 +126,9 @@ def test_correlate_bit_exact(n_chan, n_in, n_spec):
 TILED_CASES = [
     # n_chan, n_in, n_spec
     (17, 704, 298), (9, 704, 1024), (17, 704, 100), (9, 200, 1024), (12, 130, 100),
-    # both sides of the switch to 256 x 256 tiles, and the longest integration timed
-    (9, 704, 176), (9, 704, 192), (9, 704, 2048), (9, 520, 200),
+    # 256 x 256 tiles over more lengths, the longest integration timed, and 128 x 128 tiles (64
+    # spectra of more inputs than the whole-channel kernel holds in LDS)
+    (9, 704, 176), (9, 704, 192), (9, 704, 2048), (9, 520, 200), (9, 704, 80), (9, 800, 64),
 ]
 
 
