@@ -6,9 +6,11 @@
 // captured once into a hipGraph and replayed.  A persistent form with a device work queue was
 // measured slower here: the tasks are small and uneven, and the hardware dispatcher spreads
 // them better than an atomic counter per task.
-// An autotuner chooses the correlator variant (128 x 128 tiles or whole-channel panels) per
-// integration length and the gridding tile height (16 or 32 cells per thread) per image shape by
-// timing replays of the whole batch, and caches the choices in a text file.
+// An autotuner chooses the correlator variant (tiles or whole-channel panels) per integration
+// length and the gridding tile height (16 or 32 cells per thread) per image shape by timing
+// replays of the whole batch, and caches the choices in a text file.  Tiled sub-bands whose rows
+// are whole 16-byte vectors take the single-band persistent kernel, one launch per sub-band (each
+// fills the GPU); the others the batched tiled kernel.
 #include "internal.h"
 
 #include <stdio.h>
@@ -38,13 +40,16 @@ struct nbsi_batch {
     size_t cvis_bytes = 0, inter_bytes = 0;
 
     struct Launch {  // one batched launch: kind, shape key, job array on the device
-        int kind;    // 0 channelize, 1 corner turn, 2 correlate, 3 gather, 4 rows, 5 cols
+        // 0 channelize, 1 corner turn, 2 correlate, 3 gather, 4 rows, 5 cols, 6 correlate with the
+        // single-band tiled kernel once per job (h_corr)
+        int kind;
         int a = 0, b = 0;  // kind-specific shape (log_m/g, variant, log_m/ge)
         int group = 0;     // sub-band group (one group per sub-band with NBSI_BATCH_OVERLAP)
         int n_jobs = 0, n_tasks = 0, max_dyn = 0;
         void *d_jobs = nullptr;
         int *d_task0 = nullptr;
         int8_t **d_outs = nullptr;
+        std::vector<CorrJob> h_corr;
     };
     std::vector<Launch> launches;
 
@@ -139,6 +144,13 @@ hipError_t launch_one(const nbsi_batch *b, const nbsi_batch::Launch &L, hipStrea
         case 3: return launch_image_batch_gather((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, st);
         case 4: return launch_image_batch_rows((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, b->precision, L.b, st);
         case 5: return launch_image_batch_cols((const ImgJob *)L.d_jobs, L.n_jobs, L.n_tasks, L.a, L.b, st);
+        case 6:
+            for (const CorrJob &j : L.h_corr) {
+                const hipError_t e = launch_correlate_variant(j.q, j.n_chan, j.n_in, j.n_spec, j.vis, CORR_VARIANT_TILED,
+                                                              st, StokesOut(), nullptr, nullptr);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
     }
     return hipErrorInvalidValue;
 }
@@ -236,6 +248,19 @@ int build_group_launches(nbsi_batch *b, const std::vector<int> &members, int gro
         kg[{v, v == CORR_VARIANT_TILED && (b->sb[s].n_spec & 15) == 0 ? 1 : 0}].push_back(s);
     }
     for (auto &kv : kg) {
+        if (kv.first.first == CORR_VARIANT_TILED && kv.first.second) {
+            // whole 16-byte rows: the persistent, pipelined single-band kernel, one launch per
+            // sub-band (each fills the GPU on its own)
+            nbsi_batch::Launch L;
+            L.kind = 6;
+            for (int s : kv.second) {
+                const nbsi_subband &x = b->sb[s];
+                L.h_corr.push_back(CorrJob{x.spec_q, x.vis, b->n_in, x.n_spec, x.n_chan, 0});
+            }
+            L.n_jobs = (int)L.h_corr.size();
+            b->launches.push_back(L);
+            continue;
+        }
         std::vector<CorrJob> jobs;
         int tasks = 0;
         for (int s : kv.second) {
@@ -595,7 +620,7 @@ int nbsi_batch_plan(nbsi_ctx *ctx, const double *ant_xyz_host, int n_ant, const 
         char tmp[256];
         snprintf(tmp, sizeof tmp, "%s{\"n_fft\": %d, \"n_spec\": %d, \"n_chan\": %d, \"n_pix\": %d, \"corr_variant\": \"%s\", \"grid_ge\": %d}",
                  s ? ", " : "", b->sb[s].n_fft, b->sb[s].n_spec, b->sb[s].n_chan, b->sb[s].n_pix,
-                 b->corr_variant[s] == CORR_VARIANT_TILED ? "tiled128" : (b->corr_variant[s] == CORR_VARIANT_CHAN32 ? "channel32" : "channel64"),
+                 b->corr_variant[s] == CORR_VARIANT_TILED ? "tiled" : (b->corr_variant[s] == CORR_VARIANT_CHAN32 ? "channel32" : "channel64"),
                  b->grid_ge[s]);
         d += tmp;
     }
