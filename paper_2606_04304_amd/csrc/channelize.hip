@@ -4,11 +4,21 @@
 // Design.  Only a contiguous band of C fine channels is kept out of each N-point spectrum,
 // so the transform is evaluated as P = N / M sub-transforms of size M >= C on the
 // decimated sequences x[p + P m] (m < M):
-//     X[k] = sum_p W_N^{p k} Y_p[k mod M],   Y_p = FFT_M(w x)[p + P m]
+//     X[k] = sum_p W_N^{p k} Y_p[k mod M],   Y_p = FFT_M(x)[p + P m]
 // Each sub-transform lives in LDS + registers of one workgroup (M/16 threads, 16 complex
-// values per thread, radix-16 Stockham passes), and every thread accumulates the kept outputs
-// it owns in registers; nothing of the N-point spectrum ever goes to HBM.  Twiddles and the
-// window come from a two-level table of float32 roundings of float64 roots (~1.5 ulp).
+// values per thread, radix-16 Stockham passes after a first pass of radix R0), and every
+// thread accumulates the band bins it owns in registers; nothing of the N-point spectrum ever
+// goes to HBM.  A thread loads the samples of G sub-transforms at a time (one load of 2G
+// bytes per element).
+//
+// The periodic Hann window w[n] = 1/2 - 1/2 cos(2 pi n / N) is the sum of three complex
+// exponentials, so windowing the samples equals the three-tap kernel (-1/4, 1/2, -1/4) over
+// adjacent bins of the unwindowed spectrum.  The kernel therefore transforms the raw int8
+// samples, accumulates the C + 2 bins klo - 1 .. klo + C, and applies the window once per
+// spectrum in LDS: no per-sample window arithmetic (the kernel is bound by vector
+// instruction issue).  Twiddles are float32 roundings of float64 roots: per-pass tables
+// (0.5 ulp) for every pass but the last, a two-level table (~1.5 ulp) and short running
+// products for the last pass and the accumulation.
 //
 // The workgroup of input i, spectrum s writes its kept band to a staging array
 // [n_in][n_spec][C] (coalesced); a corner-turn kernel then produces the correlator layout
@@ -17,6 +27,7 @@
 #include "fft_dev.h"
 
 #include <algorithm>
+#include <type_traits>
 
 
 namespace {
@@ -28,93 +39,188 @@ struct Plan {
     static constexpr int M = 1 << LOGM;
     static constexpr int NT = M / E;
     static constexpr int R0 = (LOGM % 4 == 0) ? 16 : (1 << (LOGM % 4));  // first radix
-    static constexpr int NPASS16 = (LOGM % 4 == 0) ? LOGM / 4 - 1 : LOGM / 4;
+    static constexpr int NPASS = (LOGM % 4 == 0) ? LOGM / 4 - 1 : LOGM / 4;  // radix-16 passes
+    // transforms of 4096 points or more can be split (P > 1); the last pass then carries the
+    // factor W_N^{p t} of the accumulation
+    static constexpr bool FOLD = LOGM >= 12;
 };
 
-// W_16^e = exp(-2 pi i e / 16)
-__device__ __forceinline__ float2 w16(int e) {
-    constexpr float c[16] = {1.f, 0.92387953251128675613f, 0.70710678118654752440f, 0.38268343236508977173f,
-                             0.f, -0.38268343236508977173f, -0.70710678118654752440f, -0.92387953251128675613f,
-                             -1.f, -0.92387953251128675613f, -0.70710678118654752440f, -0.38268343236508977173f,
-                             0.f, 0.38268343236508977173f, 0.70710678118654752440f, 0.92387953251128675613f};
-    return make_float2(c[e & 15], -c[(e + 12) & 15]);  // sin(2 pi e/16) = cos(2 pi (e - 4)/16)
+// acc + a * b with two fused multiply-adds per component
+__device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 b) {
+    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
 }
 
-// One radix-16 Stockham pass for one butterfly per thread (j = t).  The twiddles w^r,
-// w = W_{16 ns}^{j mod ns}, come from one table entry: w^1..w^7 by a running product and
-// w^8..w^15 from w^8 = ((w^2)^2)^2, so no chain is longer than about ten roundings.
-__device__ __forceinline__ void pass16(float2 *v, int t, int ns, int log_n, const TwiddleTable &tw) {
-    if (ns > 1) {
-        const int k = t & (ns - 1);
-        const int sh = log_n - (31 - __clz(ns * 16));
-        const float2 w = tw(k << sh);
-        float2 cur = w;
+// Dynamic LDS of one sub-band, in float2 elements: the two-level W_N table (lo at 0, hi), the
+// twiddles of the radix-16 passes but the last (tab; pass q, of span 16 ns_q, at
+// tab + sum_{q' < q} 16 ns_q'), and for split transforms the accumulation twiddles
+// (acc, [P][16][2]), the edge-bin twiddles (ext, [P][2]) and a 2 x 16 exchange slot (eb).
+struct ChanLds {
+    int hi, tab, acc, ext, eb, total;
+};
+
+__host__ __device__ inline ChanLds chan_lds(int log_n, int log_m) {
+    constexpr int e = E;
+    const int lo_bits = (log_n + 1) >> 1;
+    const int r0 = (log_m % 4 == 0) ? 16 : 1 << (log_m % 4);
+    const int npass = (log_m % 4 == 0) ? log_m / 4 - 1 : log_m / 4;
+    const int P = 1 << (log_n - log_m);
+    int ntab = 0;
+    for (int q = 0, ns = r0; q + 1 < npass; q++, ns *= e) ntab += e * ns;
+    ChanLds l;
+    l.hi = 1 << lo_bits;
+    l.tab = l.hi + (1 << (log_n - lo_bits));
+    l.acc = l.tab + ntab;
+    l.ext = l.acc + (P > 1 ? 2 * e * P : 0);
+    l.eb = l.ext + (P > 1 ? 2 * P : 0);
+    l.total = l.eb + (P > 1 ? 2 * e : 0);
+    return l;
+}
+
+// A radix-R pass from a table: v[r] *= col[r * ns] (col = table + (t mod ns), entries
+// W_{R ns}^{k r} at [r][k]), then the R-point DFT.
+template <int R>
+__device__ __forceinline__ void pass_tab(float2 *v, const float2 *col, int ns) {
 #pragma unroll
-        for (int r = 1; r < 8; r++) {
-            v[r] = cmul(v[r], cur);
-            cur = cmul(cur, w);
-        }
+    for (int r = 1; r < R; r++) v[r] = cmul(v[r], col[r * ns]);
+    dft_r<R>(v);
+}
+
+// The last radix-R pass, for one butterfly per thread (j = t): v[r] *= c w^r with
+// w = W_{R ns}^{j mod ns}, then the R-point DFT.  Since the DFT is linear, c scales all R
+// outputs (FOLD; otherwise c = 1).  w^1..w^7 come by a running product and, for R = 16,
+// w^8 = ((w^2)^2)^2, so no chain is longer than about ten roundings.
+template <int R, bool FOLD>
+__device__ __forceinline__ void pass_run(float2 *v, int t, int ns, int log_n, const TwiddleTable &tw, float2 c) {
+    const int k = t & (ns - 1);
+    const int sh = log_n - (31 - __clz(ns * R));
+    const float2 w = tw(k << sh);
+    float2 cur = w;
+    if constexpr (FOLD) {
+        v[0] = cmul(v[0], c);
+        cur = cmul(c, w);
+    }
+#pragma unroll
+    for (int r = 1; r < 8; r++) {
+        v[r] = cmul(v[r], cur);
+        cur = cmul(cur, w);
+    }
+    if constexpr (R == 16) {
         const float2 w2 = cmul(w, w), w4 = cmul(w2, w2);
         cur = cmul(w4, w4);
+        if constexpr (FOLD) cur = cmul(c, cur);
 #pragma unroll
         for (int r = 8; r < 16; r++) {
             v[r] = cmul(v[r], cur);
             cur = cmul(cur, w);
         }
     }
-    dft16(v);
+    dft_r<R>(v);
 }
 
-// Build the transform tables of one sub-band in LDS: the two-level table of W_N and the
-// [P][16][2] accumulation twiddles W_N^{p (NT r + M j_sel)}.  The kept output of residue
-// k1 = t + NT r is k = k1 + M j with j = jl (k1 >= klo mod M) or jl + 1 (k1 < klo mod M), so
-// W_N^{p k} = W_N^{p t} * W_N^{p (NT r + M j)}.
+// Build the tables of one sub-band in LDS (layout chan_lds).  The unwindowed band starts at
+// blo = klo - 1; residue k1 = t + NT r holds band bin k = k1 + M j with j = jl (k1 >= blo
+// mod M) or jl + 1 (k1 < blo mod M), so W_N^{p k} = W_N^{p t} * acc[p][r][j - jl], the first
+// factor folded into the last pass.  The band's last min(C + 2 - M, 2) bins blo + M + x share
+// residue blo + x with the first ones and get their own accumulators; the thread holding that
+// residue, t_x = (blo + x) mod NT, carries W_N^{p t_x}, so ext[p][x] = W_N^{p (blo + M + x - t_x)}.
 template <int LOGM>
 __device__ __forceinline__ TwiddleTable chan_tables(float2 *dyn, int log_n, int klo, int t) {
     using PL = Plan<LOGM>;
     constexpr int M = PL::M, NT = PL::NT;
     const int N = 1 << log_n, P = N >> LOGM;
-    const int lo_bits = (log_n + 1) >> 1;
-    float2 *tw_lo = dyn, *tw_hi = dyn + (1 << lo_bits);
-    float2 *acc_tw = tw_hi + (1 << (log_n - lo_bits));
-    const TwiddleTable tw = build_twiddles(tw_lo, tw_hi, log_n, t, NT);
+    const ChanLds L = chan_lds(log_n, LOGM);
+    const TwiddleTable tw = build_twiddles(dyn, dyn + L.hi, log_n, t, NT);
+    {
+        int off = L.tab;
+#pragma unroll
+        for (int q = 0, ns = PL::R0; q + 1 < PL::NPASS; q++, ns *= E) {
+            for (int e = t; e < E * ns; e += NT) {
+                const int r = e / ns, k = e % ns;
+                double s, c;
+                sincospi(-2.0 * (double)(k * r) / (double)(E * ns), &s, &c);
+                dyn[off + e] = make_float2((float)c, (float)s);
+            }
+            off += E * ns;
+        }
+    }
     __syncthreads();
-    const int jl = klo >> LOGM;
     if (P > 1) {
-        for (int e = t; e < P * 32; e += NT) {
-            const int p = e >> 5, r = (e >> 1) & 15, sel = e & 1;
+        const int blo = (klo - 1) & (N - 1);
+        const int jl = blo >> LOGM;
+        for (int e = t; e < P * 2 * E; e += NT) {
+            const int p = e / (2 * E), r = (e >> 1) % E, sel = e & 1;
             const int j = (jl + sel) & (P - 1);
-            acc_tw[e] = tw((p * (NT * r + M * j)) & (N - 1));
+            dyn[L.acc + e] = tw((p * (NT * r + M * j)) & (N - 1));
+        }
+        for (int e = t; e < 2 * P; e += NT) {
+            const int p = e >> 1, x = e & 1;
+            const int tx = (blo + x) & (NT - 1);
+            dyn[L.ext + e] = tw((p * (blo + M + x - tx)) & (N - 1));
         }
     }
     __syncthreads();
     return tw;
 }
 
-// size in float2 of the dynamic LDS of one sub-band's tables
-__host__ __device__ inline int chan_dyn_elems(int log_n, int log_m) {
-    const int lo_bits = (log_n + 1) >> 1;
-    const int P = 1 << (log_n - log_m);
-    return (1 << lo_bits) + (1 << (log_n - lo_bits)) + (P > 1 ? 32 * P : 0);
+// The raw samples of sub-transform p from half H of word W of each element (H = 0: the low 16
+// bits), the first pass and the radix-16 passes; on return v[r] = c Y_p[t + r NT].
+template <int LOGM, int H, int W, int DW>
+__device__ __forceinline__ void sub_transform(float2 *v, const unsigned (&raw)[E][DW], float2 *buf,
+                                              const float2 *tab, const TwiddleTable &tw, int log_n, float2 c) {
+    using PL = Plan<LOGM>;
+    constexpr int NT = PL::NT, R0 = PL::R0;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const unsigned s = raw[e][W] >> (16 * H);
+        v[e] = make_float2((float)(int8_t)(s & 0xff), (float)(int8_t)((s >> 8) & 0xff));
+    }
+    // first pass (radix R0, no twiddles)
+#pragma unroll
+    for (int b = 0; b < E / R0; b++) dft_r<R0>(v + b * R0);
+    __syncthreads();  // buf free (previous sub-transform done reading)
+    stockham_store<R0, E>(buf, v, t, NT, 1);
+    __syncthreads();
+    int ns = R0;
+    const float2 *tq = tab;
+#pragma unroll
+    for (int pass = 0; pass < PL::NPASS; pass++) {
+        stockham_load<E, E>(buf, v, t, NT, LOGM);
+        if (pass + 1 < PL::NPASS) {
+            pass_tab<E>(v, tq + (t & (ns - 1)), ns);
+            tq += E * ns;
+            __syncthreads();
+            stockham_store<E, E>(buf, v, t, NT, ns);
+            __syncthreads();
+        } else {
+            pass_run<E, PL::FOLD>(v, t, ns, log_n, tw, c);
+        }
+        ns *= E;
+    }
 }
 
-// One spectrum (input i, spectrum s) of one sub-band: window, P sub-transforms, twiddled
-// accumulation of the kept band, gain, float32 and int8 outputs to the staging arrays.
+// One spectrum (input i, spectrum s) of one sub-band: P sub-transforms of the raw samples,
+// twiddled accumulation of the band bins klo - 1 .. klo + C, the window as a three-tap kernel
+// over them, gain, float32 and int8 outputs to the staging arrays.
 template <int LOGM, int G>
 __device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, int s, float2 *buf, const float2 *dyn,
                                                     const TwiddleTable &tw) {
     using PL = Plan<LOGM>;
     constexpr int M = PL::M, NT = PL::NT, R0 = PL::R0;
-    constexpr int DW = G >= 4 ? G / 2 : 1;  // dwords of raw samples per element
+    constexpr int DW = G >= 4 ? G / 2 : 1;  // words of raw samples per element
     static_assert(G == 1 || G == 2 || G == 4 || G == 8, "load grouping");
     const int t = threadIdx.x;
     const int log_n = jb.log_n, n_spec = jb.n_spec, klo = jb.klo, n_chan = jb.n_chan;
     const int N = 1 << log_n;
     const int P = N >> LOGM;
     const int log_p = log_n - LOGM;
-    const int lo_bits = (log_n + 1) >> 1;
-    const float2 *acc_tw = dyn + (1 << lo_bits) + (1 << (log_n - lo_bits));
-    const int rl = klo & (M - 1);
+    const ChanLds L = chan_lds(log_n, LOGM);
+    const float2 *tab = dyn + L.tab;
+    const int blo = (klo - 1) & (N - 1);
+    const int rl = blo & (M - 1);
+    const int n_edge = P > 1 ? min(max(n_chan + 2 - M, 0), 2) : 0;
+    const int tx0 = blo & (NT - 1), tx1 = (blo + 1) & (NT - 1);
+    const int rx0 = rl / NT, rx1 = ((blo + 1) & (M - 1)) / NT;
     // raw buffer over this spectrum's samples: one per-thread offset plus scalar offsets per
     // element, with hardware range checking (reads past the spectrum return 0)
     const int16_t *x = reinterpret_cast<const int16_t *>(jb.volt) + ((size_t)i * n_spec + s) * (size_t)N;
@@ -133,12 +239,54 @@ __device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, in
     float2 acc[E];
 #pragma unroll
     for (int r = 0; r < E; r++) acc[r] = make_float2(0.f, 0.f);
+    float2 xa0 = make_float2(0.f, 0.f), xa1 = make_float2(0.f, 0.f);  // edge bins (lanes tx0, tx1)
+
+    // accumulate sub-transform p (v = W_N^{p t} Y_p[t + r NT] when split)
+    auto accumulate = [&](const float2 *v, int p) {
+        if (P == 1) {
+#pragma unroll
+            for (int r = 0; r < E; r++) acc[r] = v[r];
+            return;
+        }
+        const float2 *row = dyn + L.acc + p * 2 * E;
+#pragma unroll
+        for (int r = 0; r < E; r++) acc[r] = cmac(acc[r], v[r], row[2 * r + ((sel >> r) & 1)]);
+        if (n_edge > 0) {
+            // the edge residue's register is chosen by a uniform index: its lane passes all E
+            // values through LDS and reads the one it needs back
+            float2 *eb = const_cast<float2 *>(dyn) + L.eb;
+            if (t == tx0) {
+#pragma unroll
+                for (int r = 0; r < E; r++) eb[r] = v[r];
+                xa0 = cmac(xa0, eb[rx0], dyn[L.ext + 2 * p]);
+            }
+            if (n_edge > 1 && t == tx1) {
+#pragma unroll
+                for (int r = 0; r < E; r++) eb[E + r] = v[r];
+                xa1 = cmac(xa1, eb[E + rx1], dyn[L.ext + 2 * p + 1]);
+            }
+        }
+    };
+    // sub-transforms p (low half of word W) and p + 1 (high half)
+    auto pair = [&](auto wc, const unsigned (&raw)[E][DW], int p) {
+        constexpr int W = decltype(wc)::value;
+        float2 v[E];
+        const float2 one = make_float2(1.f, 0.f);
+        sub_transform<LOGM, 0, W, DW>(v, raw, buf, tab, tw, log_n,
+                                         PL::FOLD && P > 1 ? tw((p * t) & (N - 1)) : one);
+        accumulate(v, p);
+        if constexpr (G >= 2) {
+            sub_transform<LOGM, 1, W, DW>(v, raw, buf, tab, tw, log_n,
+                                             PL::FOLD && P > 1 ? tw(((p + 1) * t) & (N - 1)) : one);
+            accumulate(v, p + 1);
+        }
+    };
 
     for (int p0 = 0; p0 < P; p0 += G) {
-        // raw samples of G consecutive sub-transforms (one 2G-byte load per element: the G
-        // samples x[p0 .. p0 + G - 1 + P m] are adjacent), element m = t + NT b + (M/R0) r.
-        // Loading G sub-transforms' samples at once means each 32-byte segment of the spectrum
-        // is fetched P/G times rather than P/2 times when the workgroups' spectra overflow L2.
+        // raw samples of G consecutive sub-transforms (2G bytes per element: the G samples
+        // x[p0 .. p0 + G - 1 + P m] are adjacent), element m = t + NT b + (M/R0) r.  Loading
+        // the samples of G sub-transforms at once means each 32-byte segment of the spectrum is
+        // fetched P/G times rather than P/2 times when the workgroups' spectra overflow L2.
         unsigned raw[E][DW];
 #pragma unroll
         for (int b = 0; b < E / R0; b++)
@@ -162,67 +310,28 @@ __device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, in
                     w[0] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, voff, soff, 0);
                 }
             }
+        // two sub-transforms per step from word 0, then the next word moves down
 #pragma unroll 1
-        for (int g = 0; g < G; g++) {
-            const int p = p0 + g;
-            float2 v[E];
-            // window w[n] = 1/2 - 1/2 cos(2 pi n / N), n = p + P t + (N/16) b + (N/R0) r:
-            // cos from W_N^{p + P t} times the constant W_16^{b + (16/R0) r}
-            const float2 wb = tw(p + (t << log_p));
+        for (int g = 0; g < G; g += 2) {
+            pair(std::integral_constant<int, 0>{}, raw, p0 + g);
 #pragma unroll
-            for (int b = 0; b < E / R0; b++)
+            for (int e = 0; e < E; e++)
 #pragma unroll
-                for (int r = 0; r < R0; r++) {
-                    const float2 wc = w16(b + (16 / R0) * r);
-                    const float cs = wb.x * wc.x - wb.y * wc.y;
-                    const float w = 0.5f - 0.5f * cs;
-                    const int sample = (int)raw[b * R0 + r][0];  // low 16 bits: sub-transform p
-                    const float re = (float)(int8_t)(sample & 0xff), im = (float)(int8_t)((sample >> 8) & 0xff);
-                    v[b * R0 + r] = make_float2(w * re, w * im);
-                }
-            // move the next sub-transform's samples into the low 16 bits
-            if constexpr (G >= 2) {
-#pragma unroll
-                for (int e = 0; e < E; e++) {
-#pragma unroll
-                    for (int w = 0; w + 1 < DW; w++) raw[e][w] = __builtin_amdgcn_alignbit(raw[e][w + 1], raw[e][w], 16);
-                    raw[e][DW - 1] >>= 16;
-                }
-            }
-            // first pass (radix R0, no twiddles)
-#pragma unroll
-            for (int b = 0; b < E / R0; b++) dft_r<R0>(v + b * R0);
-            __syncthreads();  // buf free (previous sub-transform done reading)
-            stockham_store<R0, E>(buf, v, t, NT, 1);
-            __syncthreads();
-            int ns = R0;
-#pragma unroll
-            for (int pass = 0; pass < PL::NPASS16; pass++) {
-                stockham_load<16, E>(buf, v, t, NT, LOGM);
-                pass16(v, t, ns, log_n, tw);
-                if (pass + 1 < PL::NPASS16) {
-                    __syncthreads();
-                    stockham_store<16, E>(buf, v, t, NT, ns);
-                    __syncthreads();
-                }
-                ns *= 16;
-            }
-            // v[r] = Y_p[t + r NT]
-            if (P == 1) {
-#pragma unroll
-                for (int r = 0; r < E; r++) acc[r] = v[r];
-            } else {
-                const float2 bp = tw((p * t) & (N - 1));
-                const float2 *row = acc_tw + p * 32;
-                // every register accumulates (branch-free); only kept outputs are stored
-#pragma unroll
-                for (int r = 0; r < E; r++) {
-                    const float2 tr = cmul(bp, row[2 * r + ((sel >> r) & 1)]);
-                    acc[r] = cadd(acc[r], cmul(v[r], tr));
-                }
-            }
+                for (int w = 0; w + 1 < DW; w++) raw[e][w] = raw[e][w + 1];
         }
     }
+
+    // unwindowed band in LDS: band[q] = X[blo + q] for q < C + 2 (positions M, M + 1 are the
+    // edge bins; with P = 1 the spectrum is M-periodic and they wrap to 0, 1)
+    __syncthreads();  // every wave is done with buf
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+        const int q = (t + r * NT - blo) & (M - 1);
+        if (q < n_chan + 2) buf[q] = acc[r];
+    }
+    if (n_edge > 0 && t == tx0) buf[M] = xa0;
+    if (n_edge > 1 && t == tx1) buf[M + 1] = xa1;
+    __syncthreads();
 
     const float g = jb.gain[i];
     const size_t rowo = ((size_t)i * n_spec + s) * (size_t)n_chan;
@@ -231,8 +340,13 @@ __device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, in
     for (int r = 0; r < E; r++) {
         if (!(kept & (1u << r))) continue;
         const int k1 = t + r * NT;
-        const int d = (k1 - klo) & (M - 1);
-        const float2 gx = make_float2(acc[r].x * g, acc[r].y * g);
+        const int d = (k1 - klo) & (M - 1);  // output channel; bins d, d + 1, d + 2 of the band
+        int qp = d + 2;
+        if (P == 1 && qp >= M) qp -= M;
+        const float2 xm = buf[d], x0 = buf[d + 1 == M && P == 1 ? 0 : d + 1], xp = buf[qp];
+        // window: X_w[k] = X[k] / 2 - (X[k - 1] + X[k + 1]) / 4
+        const float2 xw = make_float2(fmaf(-0.25f, xm.x + xp.x, 0.5f * x0.x), fmaf(-0.25f, xm.y + xp.y, 0.5f * x0.y));
+        const float2 gx = make_float2(xw.x * g, xw.y * g);
         const bool fin = __builtin_isfinite(gx.x) && __builtin_isfinite(gx.y);
         fl |= fin ? 0u : NBSI_FLAG_SPEC_NONFINITE;
         if (jb.stage_f) jb.stage_f[rowo + d] = gx;
@@ -249,8 +363,17 @@ __device__ __forceinline__ void channelize_spectrum(const ChanJob &jb, int i, in
     if (fl && jb.flags) atomicOr(jb.flags, fl);
 }
 
+// threads per workgroup, and the waves per SIMD the register budget is built for: three
+// 256-thread workgroups per CU for 4096-point sub-transforms loaded four at a time (168 VGPRs;
+// at 16 sub-transforms per spectrum 8% faster than two workgroups loading eight at a time),
+// else the compiler's choice
 template <int LOGM, int G>
-__global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(ChanJob jb) {
+constexpr int chan_threads() { return (1 << LOGM) / E; }
+template <int LOGM, int G>
+constexpr int chan_waves() { return LOGM == 12 && G <= 4 ? 3 : 1; }
+
+template <int LOGM, int G>
+__global__ __launch_bounds__((chan_threads<LOGM, G>()), (chan_waves<LOGM, G>())) void channelize_kernel(ChanJob jb) {
     __shared__ float2 buf[padded_size(1 << LOGM)];
     extern __shared__ float2 dyn[];  // tables (chan_tables)
     const TwiddleTable tw = chan_tables<LOGM>(dyn, jb.log_n, jb.klo, threadIdx.x);
@@ -261,8 +384,8 @@ __global__ __launch_bounds__((1 << LOGM) / 16) void channelize_kernel(ChanJob jb
 // [task0, task0 + n_in n_spec), one workgroup per task, so the kernel keeps the register
 // budget and occupancy of the single-band kernel and the dispatcher balances the workgroups.
 template <int LOGM, int G>
-__global__ __launch_bounds__((1 << LOGM) / 16) void channelize_batch_kernel(const ChanJob *__restrict__ jobs,
-                                                                            int n_jobs, int n_tasks) {
+__global__ __launch_bounds__((chan_threads<LOGM, G>()), (chan_waves<LOGM, G>())) void channelize_batch_kernel(
+    const ChanJob *__restrict__ jobs, int n_jobs, int n_tasks) {
     __shared__ float2 buf[padded_size(1 << LOGM)];
     extern __shared__ float2 dyn[];
     const int task = blockIdx.x;
@@ -384,37 +507,52 @@ __global__ __launch_bounds__(256) void corner_turn_f_kernel(const float2 *__rest
     }
 }
 
+// Sub-transforms whose samples one load covers (never more than P).  Each element's 2P bytes
+// of samples are fetched P/G times (a spectrum's lines leave L2 between its load groups), so G
+// trades fetches against registers: for 4096-point sub-transforms G = 4 (the 168-VGPR budget of
+// three workgroups per CU) while P <= 16, and G = 8 (two workgroups) beyond, where the fetches
+// of G = 4 bound the kernel (measured at P = 32 / 64: 3.28 / 6.96 ms against 2.48 / 3.34 ms);
+// 2 for 16384-point sub-transforms (1024 threads leave 128 VGPRs: wider loads would spill);
+// else 8.
+int chan_group(int log_n, int log_m) {
+    const int P = 1 << (log_n - log_m);
+    if (log_m == 12) return std::min(P <= 16 ? 4 : 8, P);
+    return std::min(log_m >= 14 ? 2 : 8, P);
+}
+
+template <int LOGM, int G>
+hipError_t launch_g(const ChanJob &jb, int n_in, hipStream_t st) {
+    const size_t lds = sizeof(float2) * chan_lds(jb.log_n, LOGM).total;
+    hipLaunchKernelGGL((channelize_kernel<LOGM, G>), dim3((unsigned)n_in * (unsigned)jb.n_spec),
+                       dim3(chan_threads<LOGM, G>()), lds, st, jb);
+    return hipGetLastError();
+}
+
 template <int LOGM>
 hipError_t launch_logm(const ChanJob &jb, int n_in, hipStream_t st) {
-    dim3 grid((unsigned)n_in * (unsigned)jb.n_spec);
-    const int P = 1 << (jb.log_n - LOGM);
-    const size_t lds = sizeof(float2) * chan_dyn_elems(jb.log_n, LOGM);
-    if constexpr (LOGM >= 14) {  // 1024 threads leave 128 VGPRs: wider loads would spill
-        if (P >= 2)
-            hipLaunchKernelGGL((channelize_kernel<LOGM, 2>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
-        else
-            hipLaunchKernelGGL((channelize_kernel<LOGM, 1>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
-    } else if constexpr (LOGM >= 12) {
-        if (P >= 8)
-            hipLaunchKernelGGL((channelize_kernel<LOGM, 8>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
-        else if (P == 4)
-            hipLaunchKernelGGL((channelize_kernel<LOGM, 4>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
-        else if (P == 2)
-            hipLaunchKernelGGL((channelize_kernel<LOGM, 2>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
-        else
-            hipLaunchKernelGGL((channelize_kernel<LOGM, 1>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+    if constexpr (LOGM < 12) {
+        if (jb.log_n != LOGM) return hipErrorInvalidValue;  // a transform shorter than 4096 is never split
+        return launch_g<LOGM, 1>(jb, n_in, st);
     } else {
-        if (P != 1) return hipErrorInvalidValue;  // a transform shorter than 4096 is never split
-        hipLaunchKernelGGL((channelize_kernel<LOGM, 1>), grid, dim3((1 << LOGM) / 16), lds, st, jb);
+        switch (chan_group(jb.log_n, LOGM)) {
+            case 1: return launch_g<LOGM, 1>(jb, n_in, st);
+            case 2: return launch_g<LOGM, 2>(jb, n_in, st);
+            case 4:
+                if constexpr (LOGM < 14) return launch_g<LOGM, 4>(jb, n_in, st);
+                return hipErrorInvalidValue;
+            case 8:
+                if constexpr (LOGM < 14) return launch_g<LOGM, 8>(jb, n_in, st);
+                return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
+        }
     }
-    return hipGetLastError();
 }
 
 template <int LOGM, int G>
 hipError_t launch_batch_logm(const ChanJob *d_jobs, int n_jobs, int n_tasks, size_t lds,
                              hipStream_t st) {
-    hipLaunchKernelGGL((channelize_batch_kernel<LOGM, G>), dim3(n_tasks), dim3((1 << LOGM) / 16), lds, st, d_jobs,
-                       n_jobs, n_tasks);
+    hipLaunchKernelGGL((channelize_batch_kernel<LOGM, G>), dim3(n_tasks), dim3(chan_threads<LOGM, G>()), lds, st,
+                       d_jobs, n_jobs, n_tasks);
     return hipGetLastError();
 }
 
@@ -473,10 +611,9 @@ hipError_t launch_channelize_batch(const ChanJob *d_jobs, int n_jobs, int n_task
 #undef NBSI_CBG
 }
 
-int channelize_dyn_elems(int log_n, int log_m) { return chan_dyn_elems(log_n, log_m); }
+int channelize_dyn_elems(int log_n, int log_m) { return chan_lds(log_n, log_m).total; }
 
-// Sub-transforms whose samples one load covers: min(8, P) (min(2, P) for 16384-point sub-transforms).
-int channelize_group(int log_n, int log_m) { return std::min(log_m >= 14 ? 2 : 8, 1 << (log_n - log_m)); }
+int channelize_group(int log_n, int log_m) { return chan_group(log_n, log_m); }
 
 int corner_turn_tasks(int n_in, int n_spec, int n_chan) { return n_in * ((n_chan + 63) / 64) * ((n_spec + 63) / 64); }
 

@@ -61,51 +61,91 @@ __device__ __forceinline__ void dft4(float2 &x0, float2 &x1, float2 &x2, float2 
     x3 = csub(t1, cmul_negi(t3));
 }
 
-// radix-8 = 4 x 2: n = 2 n1 + n2, k = k1 + 4 k2
+// radix-8 = 4 x 2: n = 2 n1 + n2, k = k1 + 4 k2.  The twiddles W8^k1 of the odd half enter
+// the combining sums as fused multiply-adds: (x + i y) W8 = r (x + y) + i r (y - x), so
+// a +- that costs one add per component for x + y (or y - x) and one FMA per output.
 __device__ __forceinline__ void dft8(float2 *v) {
     const float r = 0.70710678118654752440f;
-    dft4(v[0], v[2], v[4], v[6]);  // n2 = 0 -> y0[k1]
-    dft4(v[1], v[3], v[5], v[7]);  // n2 = 1 -> y1[k1]
-    // twiddle y1[k1] *= W8^k1
-    v[3] = cmul(v[3], make_float2(r, -r));
-    v[5] = cmul_negi(v[5]);
-    v[7] = cmul(v[7], make_float2(-r, -r));
+    dft4(v[0], v[2], v[4], v[6]);  // n2 = 0 -> y0[k1] at v[2 k1]
+    dft4(v[1], v[3], v[5], v[7]);  // n2 = 1 -> y1[k1] at v[2 k1 + 1]
     float2 o[8];
-#pragma unroll
-    for (int k1 = 0; k1 < 4; k1++) {
-        float2 a = v[2 * k1], b = v[2 * k1 + 1];
-        o[k1] = cadd(a, b);
-        o[k1 + 4] = csub(a, b);
+    o[0] = cadd(v[0], v[1]);
+    o[4] = csub(v[0], v[1]);
+    {  // k1 = 1: y1 W8 = r (s, d)
+        const float s = v[3].x + v[3].y, d = v[3].y - v[3].x;
+        o[1] = make_float2(fmaf(r, s, v[2].x), fmaf(r, d, v[2].y));
+        o[5] = make_float2(fmaf(-r, s, v[2].x), fmaf(-r, d, v[2].y));
+    }
+    o[2] = cadd(v[4], cmul_negi(v[5]));  // k1 = 2: y1 W8^2 = -i y1
+    o[6] = csub(v[4], cmul_negi(v[5]));
+    {  // k1 = 3: y1 W8^3 = r (d, -s)
+        const float s = v[7].x + v[7].y, d = v[7].y - v[7].x;
+        o[3] = make_float2(fmaf(r, d, v[6].x), fmaf(-r, s, v[6].y));
+        o[7] = make_float2(fmaf(-r, d, v[6].x), fmaf(r, s, v[6].y));
     }
 #pragma unroll
     for (int k = 0; k < 8; k++) v[k] = o[k];
 }
 
-// radix-16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+// radix-16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.  The inner twiddles W16^(n2 k1) are folded
+// into the second stage's sums as fused multiply-adds: W^2 and W^6 terms are r (x +- y); the
+// W^1/W^3 and W^3/W^9 pairs combine into sums c (A + tau B) with c = cos(pi/8) and
+// tau = tan(pi/8), so every scaled term costs one FMA to form and one per output.
 __device__ __forceinline__ void dft16(float2 *v) {
 #pragma unroll
     for (int n2 = 0; n2 < 4; n2++) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
-    // element (n2, k1) now sits at v[4 k1 + n2]; twiddle by W16^(n2 k1)
-    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+    // element (n2, k1) now sits at v[4 k1 + n2]; output k1 + 4 k2 goes to o[k1 + 4 k2]
+    const float c = 0.92387953251128675613f;    // cos(pi/8)
+    const float tau = 0.41421356237309504880f;  // tan(pi/8)
     const float r = 0.70710678118654752440f;
-    v[4 + 1] = cmul(v[4 + 1], make_float2(c1, -s1));   // k1=1,n2=1: W^1
-    v[4 + 2] = cmul(v[4 + 2], make_float2(r, -r));     // W^2
-    v[4 + 3] = cmul(v[4 + 3], make_float2(s1, -c1));   // W^3
-    v[8 + 1] = cmul(v[8 + 1], make_float2(r, -r));     // k1=2: W^2
-    v[8 + 2] = cmul_negi(v[8 + 2]);                    // W^4
-    v[8 + 3] = cmul(v[8 + 3], make_float2(-r, -r));    // W^6
-    v[12 + 1] = cmul(v[12 + 1], make_float2(s1, -c1)); // k1=3: W^3
-    v[12 + 2] = cmul(v[12 + 2], make_float2(-r, -r));  // W^6
-    v[12 + 3] = cmul(v[12 + 3], make_float2(-c1, s1)); // W^9
     float2 o[16];
-#pragma unroll
-    for (int k1 = 0; k1 < 4; k1++) {
-        float2 a = v[4 * k1], b = v[4 * k1 + 1], c = v[4 * k1 + 2], d = v[4 * k1 + 3];
-        dft4(a, b, c, d);
-        o[k1] = a;
-        o[k1 + 4] = b;
-        o[k1 + 8] = c;
-        o[k1 + 12] = d;
+    {  // k1 = 0: no twiddles
+        float2 a = v[0], b = v[1], cc = v[2], d = v[3];
+        dft4(a, b, cc, d);
+        o[0] = a;
+        o[4] = b;
+        o[8] = cc;
+        o[12] = d;
+    }
+    {  // k1 = 1: a = v4, x1 = v5 W^1, x2 = v6 W^2, x3 = v7 W^3
+        const float2 a = v[4], p = v[5], q = v[7];
+        const float s6 = v[6].x + v[6].y, d6 = v[6].y - v[6].x;
+        const float2 t0 = make_float2(fmaf(r, s6, a.x), fmaf(r, d6, a.y));
+        const float2 t1 = make_float2(fmaf(-r, s6, a.x), fmaf(-r, d6, a.y));
+        const float A = p.x + q.y, B = p.y + q.x, C = p.y - q.x, D = p.x - q.y;
+        // x1 + x3 = c (A + tau B, C - tau D), x1 - x3 = c (D + tau C, B - tau A)
+        const float2 u2 = make_float2(fmaf(tau, B, A), fmaf(-tau, D, C));
+        const float2 u3 = make_float2(fmaf(tau, C, D), fmaf(-tau, A, B));
+        o[1] = make_float2(fmaf(c, u2.x, t0.x), fmaf(c, u2.y, t0.y));
+        o[9] = make_float2(fmaf(-c, u2.x, t0.x), fmaf(-c, u2.y, t0.y));
+        o[5] = make_float2(fmaf(c, u3.y, t1.x), fmaf(-c, u3.x, t1.y));
+        o[13] = make_float2(fmaf(-c, u3.y, t1.x), fmaf(c, u3.x, t1.y));
+    }
+    {  // k1 = 2: a = v8, x1 = v9 W^2, x2 = v10 W^4 = -i v10, x3 = v11 W^6
+        const float2 a = v[8], x2 = cmul_negi(v[10]);
+        const float2 t0 = cadd(a, x2), t1 = csub(a, x2);
+        const float s9 = v[9].x + v[9].y, d9 = v[9].y - v[9].x;
+        const float s11 = v[11].x + v[11].y, d11 = v[11].y - v[11].x;
+        // x1 = r (s9, d9), x3 = r (d11, -s11)
+        const float2 P = make_float2(s9 + d11, d9 - s11), Q = make_float2(s9 - d11, d9 + s11);
+        o[2] = make_float2(fmaf(r, P.x, t0.x), fmaf(r, P.y, t0.y));
+        o[10] = make_float2(fmaf(-r, P.x, t0.x), fmaf(-r, P.y, t0.y));
+        o[6] = make_float2(fmaf(r, Q.y, t1.x), fmaf(-r, Q.x, t1.y));
+        o[14] = make_float2(fmaf(-r, Q.y, t1.x), fmaf(r, Q.x, t1.y));
+    }
+    {  // k1 = 3: a = v12, x1 = v13 W^3, x2 = v14 W^6, x3 = v15 W^9
+        const float2 a = v[12], p = v[13], q = v[15];
+        const float s14 = v[14].x + v[14].y, d14 = v[14].y - v[14].x;  // x2 = r (d14, -s14)
+        const float2 t0 = make_float2(fmaf(r, d14, a.x), fmaf(-r, s14, a.y));
+        const float2 t1 = make_float2(fmaf(-r, d14, a.x), fmaf(r, s14, a.y));
+        const float A = p.x - q.y, B = p.y - q.x, C = p.y + q.x, D = p.x + q.y;
+        // x1 + x3 = (c (B + tau A), -c (D - tau C)), x1 - x3 = (c (C + tau D), -c (A - tau B))
+        const float2 u2 = make_float2(fmaf(tau, A, B), fmaf(-tau, C, D));
+        const float2 u3 = make_float2(fmaf(tau, D, C), fmaf(-tau, B, A));
+        o[3] = make_float2(fmaf(c, u2.x, t0.x), fmaf(-c, u2.y, t0.y));
+        o[11] = make_float2(fmaf(-c, u2.x, t0.x), fmaf(c, u2.y, t0.y));
+        o[7] = make_float2(fmaf(-c, u3.y, t1.x), fmaf(-c, u3.x, t1.y));
+        o[15] = make_float2(fmaf(c, u3.y, t1.x), fmaf(c, u3.x, t1.y));
     }
 #pragma unroll
     for (int k = 0; k < 16; k++) v[k] = o[k];
