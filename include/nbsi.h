@@ -312,6 +312,24 @@ int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pix, const in
                 int max_out, int *n_out, float *thresh_host, int64_t *n_provisional_host);
 
 /*
+ * The Stage I search of nbsi_search on a cube whose noise is correlated across channels (Sec.
+ * 2.4's unit-normalised boxcars read as unit variance under that correlation).  rho_host (host,
+ * n_rho values, NULL when n_rho = 0) holds the correlation of the cube's noise at lags of
+ * 1 .. n_rho channels (zero beyond); every window sum of width w is divided by
+ *   sigma_w = sqrt(w + 2 sum_{l=1}^{min(w-1, n_rho)} (w - l) rho_l)
+ * in place of sqrt(w), in step 1 and in the re-evaluation of step 4.  The images of this library
+ * (periodic Hann window, cross-correlations of independent inputs) have rho = (4/9, 1/36).
+ * n_rho in [0, NBSI_SEARCH_MAX_LAG], each rho in (-1, 1), and sigma_w^2 > 0 for every width of
+ * the bank, else NBSI_EINVAL.  n_rho = 0 is nbsi_search.  Other arguments, layouts, ownership
+ * and errors as nbsi_search.
+ */
+#define NBSI_SEARCH_MAX_LAG 8
+int nbsi_search_corr(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pix, const int32_t *widths_host,
+                     int n_widths, const double *rho_host, int n_rho, double fdr_q, float *best_snr,
+                     uint8_t *best_width, nbsi_cand *out, int max_out, int *n_out, float *thresh_host,
+                     int64_t *n_provisional_host);
+
+/*
  * Drift-rate search (the paper's Doppler-drift discussion, Sec. 2: a search over drifts of tens
  * of Hz per dump): snr_sub [n_sub][n_chan][n_pix][n_pix] float32 holds the standardised residual
  * cubes of n_sub sub-integrations of one dump (each channelised, correlated, imaged and

@@ -9,7 +9,13 @@ width-1 detector: unit-variance noise, spectral median removed):
    of 10 (26 widths).  "Unit-normalised" is read as unit energy, so unit-variance white noise
    gives unit-variance filtered output:
        S_w[c] = (1/sqrt(w)) * sum_{j=0}^{w-1} r[c - floor(w/2) + j],
-   evaluated only where the window lies inside the band.
+   evaluated only where the window lies inside the band.  When the channels of the noise are
+   correlated (rho_l = correlation at a lag of l channels, l = 1..L), unit-normalised is read
+   as unit variance under that correlation: the window sum is divided by
+       sigma_w = sqrt(w + 2 sum_{l=1}^{min(w-1, L)} (w - l) rho_l)
+   (the standard deviation of a sum of w consecutive unit-variance samples), which is sqrt(w)
+   for white noise.  The paper does not say how its SNRs treat the correlation that its window
+   puts between adjacent fine channels; without it the bank's noise is not unit-normal.
 2. For every pixel and channel the highest SNR over the widths and its width are kept (on ties
    the narrower width).
 3. SNR -> p-value under the standardised (unit normal) noise model, one-sided:
@@ -27,7 +33,7 @@ width-1 detector: unit-variance noise, spectral median removed):
    s = c - floor(w/2), guard g = w and flank length L = max(16, 2 w), the flanks
    [s - g - L, s - g) and [s + w + g, s + w + g + L) inside the band give a baseline b (median)
    and noise sigma = 1.482602218505602 * MAD; the re-evaluated SNR is
-   sum_{window}(r - b) / (sqrt(w) sigma).  The detection is kept when that is >= S*; with
+   sum_{window}(r - b) / (sigma_w sigma).  The detection is kept when that is >= S*; with
    fewer than 8 flank channels or sigma = 0 it is discarded.
 
 Medians of even counts are the mean of the two central order statistics.  Output records
@@ -42,11 +48,28 @@ import numpy as np
 from .detect import MAD_K, horizon_mask, median_even_mean
 
 WIDTHS = tuple(list(range(1, 11)) + list(range(12, 49, 4)) + list(range(50, 101, 10)))
+
+# Channel correlations of the imaged cube's noise.  The periodic Hann window is the three-tap
+# kernel (-1/4, 1/2, -1/4) over the bins of the unwindowed spectrum, so windowed white noise has
+# correlation (-1/4 * 1/2 + 1/2 * -1/4) / (1/16 + 1/4 + 1/16) = -2/3 at a lag of one channel and
+# (1/16) / (3/8) = 1/6 at two; a cross-correlation product of two independent inputs then has
+# the squared magnitudes, 4/9 and 1/36, and so do the images built from such products.
+HANN_CROSS_RHO = (4.0 / 9.0, 1.0 / 36.0)
 REEVAL_MIN_FLANK = 8
 
 
-def boxcar_bank(r: np.ndarray, widths=WIDTHS) -> tuple[np.ndarray, np.ndarray]:
-    """(S, W): highest unit-energy boxcar SNR over the widths and its width, for r [C][...]."""
+def boxcar_sigma(w: int, rho=()) -> float:
+    """Standard deviation of the sum of w consecutive unit-variance samples whose correlation at
+    a lag of l channels is rho[l - 1] (zero beyond len(rho)): sqrt(w) for white noise."""
+    var = float(w)
+    for l in range(1, min(w - 1, len(rho)) + 1):
+        var += 2.0 * (w - l) * float(rho[l - 1])
+    return math.sqrt(var)
+
+
+def boxcar_bank(r: np.ndarray, widths=WIDTHS, rho=()) -> tuple[np.ndarray, np.ndarray]:
+    """(S, W): highest unit-variance boxcar SNR over the widths and its width, for r [C][...]
+    (noise channel correlations rho, see boxcar_sigma)."""
     r = np.asarray(r, dtype=np.float64)
     n_chan = r.shape[0]
     flat = r.reshape(n_chan, -1)
@@ -60,7 +83,7 @@ def boxcar_bank(r: np.ndarray, widths=WIDTHS) -> tuple[np.ndarray, np.ndarray]:
         sw = np.zeros((c1 - c0 + 1, flat.shape[1]))
         for j in range(w):                   # the window sum, term by term
             sw += flat[c0 - h + j:c1 - h + j + 1]
-        sw /= math.sqrt(w)
+        sw /= boxcar_sigma(w, rho)
         upd = sw > best[c0:c1 + 1]           # strict: the narrower width wins ties
         best[c0:c1 + 1][upd] = sw[upd]
         wbest[c0:c1 + 1][upd] = w
@@ -106,7 +129,7 @@ def nms(S: np.ndarray, W: np.ndarray, accepted: np.ndarray) -> np.ndarray:
     return keep
 
 
-def reevaluate(r_pix: np.ndarray, c: int, w: int) -> float:
+def reevaluate(r_pix: np.ndarray, c: int, w: int, rho=()) -> float:
     """Re-evaluated SNR of a detection at channel c with width w in one pixel's spectrum."""
     n_chan = r_pix.shape[0]
     s = c - w // 2
@@ -120,17 +143,17 @@ def reevaluate(r_pix: np.ndarray, c: int, w: int) -> float:
     mad = float(median_even_mean(np.abs(flank - b), axis=0))
     if mad <= 0.0:
         return -math.inf
-    return float(np.sum(r_pix[s:s + w] - b) / (math.sqrt(w) * MAD_K * mad))
+    return float(np.sum(r_pix[s:s + w] - b) / (boxcar_sigma(w, rho) * MAD_K * mad))
 
 
-def search(r: np.ndarray, q: float = 0.01, widths=WIDTHS, valid: np.ndarray | None = None):
+def search(r: np.ndarray, q: float = 0.01, widths=WIDTHS, valid: np.ndarray | None = None, rho=()):
     """Stage I over r [C][N][N]: (records, S, W, k*, S*).  valid [N][N] marks searched pixels
-    (default: the visible hemisphere)."""
+    (default: the visible hemisphere); rho the noise's channel correlations (white: empty)."""
     r = np.asarray(r, dtype=np.float64)
     n_chan, n_pix, _ = r.shape
     if valid is None:
         valid = horizon_mask(n_pix)
-    S, W = boxcar_bank(r, widths)
+    S, W = boxcar_bank(r, widths, rho)
     Sv = S[:, valid]
     m = int(valid.sum()) * n_chan
     kstar, sstar = bh_threshold(Sv.ravel(), m, q)
@@ -141,7 +164,7 @@ def search(r: np.ndarray, q: float = 0.01, widths=WIDTHS, valid: np.ndarray | No
     keep = []
     rf = r.reshape(n_chan, -1)
     for c, p in zip(c_idx, p_idx):
-        keep.append(reevaluate(rf[:, p], int(c), int(flatW[c, p])) >= sstar)
+        keep.append(reevaluate(rf[:, p], int(c), int(flatW[c, p]), rho) >= sstar)
     keep = np.asarray(keep, dtype=bool)
     c_idx, p_idx = c_idx[keep], p_idx[keep]
     y, x = p_idx // n_pix, p_idx % n_pix

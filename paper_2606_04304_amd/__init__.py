@@ -42,7 +42,7 @@ EXPORTS = [
     "nbsi_batch_describe", "nbsi_batch_destroy", "nbsi_stamps", "nbsi_net_create", "nbsi_net_destroy",
     "nbsi_net_set_params", "nbsi_net_get_params", "nbsi_net_forward", "nbsi_net_grad", "nbsi_net_adam",
     "nbsi_net_train_step", "nbsi_correlate_kernel", "nbsi_image_plan_pairs", "nbsi_correlate_stokes",
-    "nbsi_image_stokes", "nbsi_correlate_image", "nbsi_search", "nbsi_correlate_cal", "nbsi_dedoppler", "nbsi_beam", "nbsi_stage2",
+    "nbsi_image_stokes", "nbsi_correlate_image", "nbsi_search", "nbsi_search_corr", "nbsi_correlate_cal", "nbsi_dedoppler", "nbsi_beam", "nbsi_stage2",
     "nbsi_detect_noalloc", "nbsi_status",
 ]
 NBSI_FLAG_SPEC_NONFINITE = 0x1
@@ -59,6 +59,12 @@ NBSI_S2_MAX_CANDS = 1 << 22
 NBSI_BEAM_HALF = 2
 NBSI_SEARCH_MAX_WIDTHS = 32
 NBSI_SEARCH_MAX_WIDTH = 128
+NBSI_SEARCH_MAX_LAG = 8
+# Channel correlations of the noise of this library's images (periodic Hann window: the windowed
+# spectra's neighbouring channels correlate at -2/3 and 1/6 at lags 1 and 2, so the
+# cross-correlations of independent inputs, and the images made of them, at 4/9 and 1/36):
+# nbsi_search(..., rho=HANN_CROSS_RHO) on an SNR cube of those images.
+HANN_CROSS_RHO = (4.0 / 9.0, 1.0 / 36.0)
 NBSI_STAMP_CHANNELS = 33
 NBSI_STAMP_PIXELS = 9
 NBSI_NET_NPARAM = 46529
@@ -128,6 +134,8 @@ def lib():
         L.nbsi_correlate_image.argtypes = [P, P, I, I, I, P, I, I, P, P, P]
         L.nbsi_search.argtypes = [P, P, I, I, P, I, D, P, P, P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_float),
                                   ctypes.POINTER(ctypes.c_int64)]
+        L.nbsi_search_corr.argtypes = [P, P, I, I, P, I, P, I, D, P, P, P, I, ctypes.POINTER(I),
+                                       ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int64)]
         L.nbsi_detect.argtypes = [P, P, I, I, I, ctypes.c_float, P, P, I, P]
         L.nbsi_detect_noalloc.argtypes = [P, P, I, I, I, ctypes.c_float, P, P, I, P]
         L.nbsi_batch_plan.argtypes = [P, P, I, P, I, I, I, ctypes.c_char_p, ctypes.POINTER(P)]
@@ -437,10 +445,12 @@ def nbsi_correlate_image(spec_q, plan: ImagePlan, precision: int = NBSI_PREC_FP3
 
 
 def nbsi_search(snr, fdr_q: float = 0.01, widths=None, max_out: int = 1 << 20, want_cubes: bool = False,
-                ctx: Context | None = None):
+                ctx: Context | None = None, rho=None):
     """Full Stage I search of a standardised residual cube snr [n_chan][n_pix][n_pix] float32:
     (candidate records sorted by (y, x, c), BH threshold S* (inf if none), provisional count k*,
-    best-SNR cube or None, best-width cube (uint8) or None).  Blocks until done."""
+    best-SNR cube or None, best-width cube (uint8) or None).  rho: the noise's channel
+    correlations at lags 1, 2, ... (None or empty: white; HANN_CROSS_RHO for this library's
+    images), through nbsi_search_corr.  Blocks until done."""
     torch = _torch()
     ctx = ctx or nbsi_create(snr.device.index or 0)
     _need(snr, torch.float32, "snr", ctx.device)
@@ -457,9 +467,12 @@ def nbsi_search(snr, fdr_q: float = 0.01, widths=None, max_out: int = 1 << 20, w
     thr = ctypes.c_float()
     kprov = ctypes.c_int64()
     ctx._sync_stream()
-    st = lib().nbsi_search(ctx._h, _ptr(snr), n_chan, n_pix, wl.ctypes.data_as(ctypes.c_void_p) if wl is not None else None,
-                           n_w, float(fdr_q), _ptr(S), _ptr(W), _ptr(out), max_out, ctypes.byref(n_out),
-                           ctypes.byref(thr), ctypes.byref(kprov))
+    rl = np.ascontiguousarray(rho if rho is not None else (), dtype=np.float64)
+    st = lib().nbsi_search_corr(ctx._h, _ptr(snr), n_chan, n_pix,
+                                wl.ctypes.data_as(ctypes.c_void_p) if wl is not None else None, n_w,
+                                rl.ctypes.data_as(ctypes.c_void_p) if rl.size else None, int(rl.size), float(fdr_q),
+                                _ptr(S), _ptr(W), _ptr(out), max_out, ctypes.byref(n_out), ctypes.byref(thr),
+                                ctypes.byref(kprov))
     if st not in (0, NBSI_ETRUNC):
         _check(st, ctx)
     n = min(n_out.value, max_out)

@@ -1,7 +1,9 @@
 // Full Stage I search (Sec. 2.4): matched filtering of every pixel's spectrum with a bank of
-// unit-energy boxcars, the best SNR and width per voxel, a Benjamini-Hochberg threshold over all
-// searched voxels, width-aware non-maximum suppression along frequency and a local
-// re-evaluation of every survivor against its flanks.
+// unit-variance boxcars (the window sum over its noise standard deviation: sqrt(w) for white
+// noise, sqrt(w + 2 sum_l (w - l) rho_l) when the caller gives the noise's channel correlations
+// rho_l, e.g. those the periodic Hann window puts into imaged cubes), the best SNR and width per
+// voxel, a Benjamini-Hochberg threshold over all searched voxels, width-aware non-maximum
+// suppression along frequency and a local re-evaluation of every survivor against its flanks.
 //
 // Kernels:
 //  * search_bank_kernel: a workgroup takes 64 consecutive pixels (one per lane) and 128
@@ -9,7 +11,7 @@
 //    window's halo (64 below, 63 above) into registers with coalesced 256-byte row loads, all in
 //    flight at once, scans them there and writes exclusive prefix sums along frequency to LDS
 //    once (relative to the staged block, so window sums never carry the rounding of a long
-//    running sum); for every channel it takes the maximum of (P[s + w] - P[s]) / sqrt(w) over
+//    running sum); for every channel it takes the maximum of (P[s + w] - P[s]) / sigma_w over
 //    the widths whose window fits in the band (a test skipped for channels at least 64 from
 //    both band edges, where every window fits).  It writes the
 //    best SNR and width cubes and adds the in-horizon SNRs at or above a floor F to a histogram
@@ -46,10 +48,14 @@ constexpr int FLANK_MAX = 4 * NBSI_SEARCH_MAX_WIDTH;         // two flanks of at
 constexpr int REEVAL_MIN_FLANK = 8;
 constexpr float MAD_TO_SIGMA = 1.482602218505602f;
 
+// The width bank: widths ascending, and per width the standard deviation sigma_w of the window
+// sum of unit-variance noise with the caller's channel correlations (sqrt(w) when white) and its
+// reciprocal.
 struct Widths {
     int n;
     int w[NBSI_SEARCH_MAX_WIDTHS];
-    float inv_sqrt[NBSI_SEARCH_MAX_WIDTHS];
+    float inv_sqrt[NBSI_SEARCH_MAX_WIDTHS];  // 1 / sigma_w
+    float sigma[NBSI_SEARCH_MAX_WIDTHS];     // sigma_w
 };
 
 struct Cand {  // an accepted voxel
@@ -275,7 +281,7 @@ __device__ float median_lds(const float *vals, int n, float *slot) {
 // flanks reproduces at or above S*.
 __global__ __launch_bounds__(256) void search_refine_kernel(const float *__restrict__ r, int n_chan, int n_pix,
                                                             const Cand *__restrict__ cands, float sstar,
-                                                            int *__restrict__ keep) {
+                                                            Widths W, int *__restrict__ keep) {
     __shared__ float flank[FLANK_MAX];
     __shared__ float dev[FLANK_MAX];
     __shared__ float red[256];
@@ -311,7 +317,10 @@ __global__ __launch_bounds__(256) void search_refine_kernel(const float *__restr
     }
     if (t == 0) {
         const float sigma = MAD_TO_SIGMA * mad;
-        const float snr2 = sigma > 0.f ? red[0] / (sqrtf((float)w) * sigma) : -INFINITY;
+        float sw = sqrtf((float)w);  // (every candidate's width is one of the bank's)
+        for (int k = 0; k < W.n; k++)
+            if (W.w[k] == w) sw = W.sigma[k];
+        const float snr2 = sigma > 0.f ? red[0] / (sw * sigma) : -INFINITY;
         keep[blockIdx.x] = snr2 >= sstar ? 1 : 0;
     }
 }
@@ -320,9 +329,10 @@ double q_tail(double s) { return 0.5 * erfc(s / sqrt(2.0)); }
 
 }  // namespace
 
-extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pix, const int32_t *widths_host,
-                           int n_widths, double fdr_q, float *best_snr, uint8_t *best_width, nbsi_cand *out,
-                           int max_out, int *n_out, float *thresh_host, int64_t *n_provisional_host) {
+extern "C" int nbsi_search_corr(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pix, const int32_t *widths_host,
+                                int n_widths, const double *rho_host, int n_rho, double fdr_q, float *best_snr,
+                                uint8_t *best_width, nbsi_cand *out, int max_out, int *n_out, float *thresh_host,
+                                int64_t *n_provisional_host) {
     if (!ctx) return NBSI_EINVAL;
     int rc = nbsi_check_detect(n_chan, n_pix, NBSI_DETECT_PER_PIXEL, max_out);
     if (rc) return nbsi_fail(ctx, rc, "nbsi_search: bad shape");
@@ -331,6 +341,11 @@ extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pi
         (best_width && !aligned16(best_width)))
         return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_search: misaligned pointer");
     if (!(fdr_q > 0.0 && fdr_q < 1.0)) return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_search: fdr_q must be in (0, 1)");
+    if (n_rho < 0 || n_rho > NBSI_SEARCH_MAX_LAG || (n_rho > 0 && !rho_host))
+        return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_search: n_rho out of range or rho missing");
+    for (int l = 0; l < n_rho; l++)
+        if (!(rho_host[l] > -1.0 && rho_host[l] < 1.0))
+            return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_search: channel correlations must be in (-1, 1)");
     static const int kDefault[] = {1,  2,  3,  4,  5,  6,  7,  8,  9,  10, 12, 16, 20,
                                    24, 28, 32, 36, 40, 44, 48, 50, 60, 70, 80, 90, 100};
     std::vector<int> ws;
@@ -348,8 +363,15 @@ extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pi
     Widths W{};
     W.n = (int)ws.size();
     for (int k = 0; k < W.n; k++) {
-        W.w[k] = ws[k];
-        W.inv_sqrt[k] = (float)(1.0 / sqrt((double)ws[k]));
+        // variance of the sum of w consecutive unit-variance samples: w + 2 sum_l (w - l) rho_l
+        const int w = ws[k];
+        double var = (double)w;
+        for (int l = 1; l <= std::min(w - 1, n_rho); l++) var += 2.0 * (double)(w - l) * rho_host[l - 1];
+        if (!(var > 0.0))
+            return nbsi_fail(ctx, NBSI_EINVAL, "nbsi_search: channel correlations give a window sum of no variance");
+        W.w[k] = w;
+        W.inv_sqrt[k] = (float)(1.0 / sqrt(var));
+        W.sigma[k] = (float)sqrt(var);
     }
     // histogram floor F = f32 / 32: a whole bin below Q^-1(q) (q_tail(f32 / 32 + 1 / 32) > q), far
     // beyond erfc's rounding, so every voxel BH can accept is counted
@@ -459,7 +481,7 @@ extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pi
     NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (n_surv > 0)
         hipLaunchKernelGGL(search_refine_kernel, dim3((unsigned)n_surv), dim3(256), 0, ctx->stream, snr, n_chan, n_pix,
-                           (const Cand *)surv, sstar, (int *)keep);
+                           (const Cand *)surv, sstar, W, (int *)keep);
     NBSI_TRY_HIP(ctx, hipGetLastError());
     std::vector<Cand> hc(n_surv);
     std::vector<int> hk(n_surv);
@@ -479,4 +501,11 @@ extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pi
         NBSI_TRY_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }
     return (int)rec.size() > max_out ? NBSI_ETRUNC : NBSI_OK;
+}
+
+extern "C" int nbsi_search(nbsi_ctx *ctx, const float *snr, int n_chan, int n_pix, const int32_t *widths_host,
+                           int n_widths, double fdr_q, float *best_snr, uint8_t *best_width, nbsi_cand *out,
+                           int max_out, int *n_out, float *thresh_host, int64_t *n_provisional_host) {
+    return nbsi_search_corr(ctx, snr, n_chan, n_pix, widths_host, n_widths, nullptr, 0, fdr_q, best_snr, best_width,
+                            out, max_out, n_out, thresh_host, n_provisional_host);
 }

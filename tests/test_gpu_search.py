@@ -27,15 +27,15 @@ def _cube(n_chan, n_pix, seed, lines=(), sigma=1.0):
     return r.astype(np.float32)
 
 
-def _window_snr(r64, p, c, w):
+def _window_snr(r64, p, c, w, rho=()):
     s = c - w // 2
-    return float(r64[s:s + w, p].sum() / math.sqrt(w))
+    return float(r64[s:s + w, p].sum() / osr.boxcar_sigma(w, rho))
 
 
-def _check_bank(r, S, W, widths=osr.WIDTHS, tol=3e-5):
+def _check_bank(r, S, W, widths=osr.WIDTHS, tol=3e-5, rho=()):
     n_chan = r.shape[0]
     r64 = r.astype(np.float64).reshape(n_chan, -1)
-    S_ref, W_ref = osr.boxcar_bank(r64, widths)
+    S_ref, W_ref = osr.boxcar_bank(r64, widths, rho)
     Sg = S.cpu().numpy().reshape(n_chan, -1).astype(np.float64)
     Wg = W.cpu().numpy().reshape(n_chan, -1).astype(np.int32)
     assert np.abs(Sg - S_ref).max() <= tol
@@ -43,7 +43,7 @@ def _check_bank(r, S, W, widths=osr.WIDTHS, tol=3e-5):
     bad = np.argwhere(Wg != W_ref)
     for c, p in bad[:2000]:
         assert Wg[c, p] in widths
-        assert abs(_window_snr(r64, p, c, int(Wg[c, p])) - S_ref[c, p]) <= tol
+        assert abs(_window_snr(r64, p, c, int(Wg[c, p]), rho) - S_ref[c, p]) <= tol
     return Sg, Wg
 
 
@@ -57,7 +57,7 @@ def test_bank_matches_oracle(n_chan, n_pix):
     _check_bank(r, S, W)
 
 
-def _expected_records(r, Sg, Wg, sstar, n_pix):
+def _expected_records(r, Sg, Wg, sstar, n_pix, rho=()):
     """The oracle's suppression and re-evaluation on the GPU's S and W (float64), with the
     re-evaluated SNRs, to judge decisions near S*."""
     n_chan = r.shape[0]
@@ -67,7 +67,7 @@ def _expected_records(r, Sg, Wg, sstar, n_pix):
     r64 = r.astype(np.float64).reshape(n_chan, -1)
     out = {}
     for c, p in zip(*np.nonzero(surv)):
-        out[(int(p % n_pix), int(p // n_pix), int(c))] = osr.reevaluate(r64[:, p], int(c), int(Wg[c, p]))
+        out[(int(p % n_pix), int(p // n_pix), int(c))] = osr.reevaluate(r64[:, p], int(c), int(Wg[c, p]), rho)
     return out
 
 
@@ -139,3 +139,69 @@ def test_search_custom_widths_and_errors():
     rec_ref, _, _, k_ref, s_ref = osr.search(np.full((64, 16, 16), 4.0), q=0.05)
     assert kprov == k_ref == m and len(rec) == len(rec_ref) == 0
     assert np.float32(thr) == np.float32(S4.cpu().numpy()[:, horizon_mask(16)].min())
+
+
+# ---- noise correlated across channels (nbsi_search_corr) ----
+
+def _hann_ma2():
+    """MA(2) coefficients (unit variance) whose channel correlations are the images' (4/9, 1/36)."""
+    from scipy.optimize import fsolve
+
+    def eq(v):
+        a0, a1, a2 = v
+        S = a0 * a0 + a1 * a1 + a2 * a2
+        return [a0 * a2 / S - nb.HANN_CROSS_RHO[1], (a0 * a1 + a1 * a2) / S - nb.HANN_CROSS_RHO[0], S - 1.0]
+
+    return fsolve(eq, [0.8, 0.5, 0.05])
+
+
+def _corr_cube(n_chan, n_pix, seed, lines=()):
+    a = _hann_ma2()
+    rng = np.random.default_rng(seed)
+    e = rng.standard_normal((n_chan + 2, n_pix, n_pix))
+    r = a[0] * e[2:] + a[1] * e[1:-1] + a[2] * e[:-2]
+    for (x, y, c0, w, snr) in lines:
+        r[c0:c0 + w, y, x] += snr * osr.boxcar_sigma(w, nb.HANN_CROSS_RHO) / w
+    return r.astype(np.float32)
+
+
+@pytest.mark.parametrize("seed,q", [(21, 0.01), (22, 0.1)])
+def test_search_corr_matches_oracle(seed, q):
+    """Hann-correlated noise with lines: the bank under rho, BH, suppression and the rho-aware
+    re-evaluation against the oracle; every line found."""
+    n_chan, n_pix = 640, 32
+    lines = [(9, 7, 300, 12, 14.0), (20, 12, 100, 1, 10.0), (14, 20, 500, 40, 16.0), (16, 16, 600, 3, 9.0)]
+    print(f"search corr seed={seed} q={q}", flush=True)
+    r = _corr_cube(n_chan, n_pix, seed, lines)
+    rec, thr, kprov, S, W = nb.nbsi_search(torch.from_numpy(r).to(DEV), fdr_q=q, want_cubes=True,
+                                           rho=nb.HANN_CROSS_RHO)
+    torch.cuda.synchronize()
+    print(f"  k* {kprov} S* {thr:.4f} records {len(rec)}", flush=True)
+    Sg, Wg = _check_bank(r, S, W, rho=osr.HANN_CROSS_RHO)
+    valid = horizon_mask(n_pix).ravel()
+    k_ref, s_ref = osr.bh_threshold(Sg[:, valid].ravel(), int(valid.sum()) * n_chan, q)
+    assert kprov == k_ref and np.float32(thr) == np.float32(s_ref)
+    exp = _expected_records(r, Sg, Wg, thr, n_pix, rho=osr.HANN_CROSS_RHO)
+    got = {(int(a["x"]), int(a["y"]), int(a["c"])): a for a in rec}
+    for key, snr2 in exp.items():
+        if abs(snr2 - thr) < 1e-4 * max(1.0, thr):
+            continue  # a float32 re-evaluation may fall on either side of S*
+        assert (key in got) == (snr2 >= thr), (key, snr2, thr)
+    for key in got:
+        assert key in exp
+    for (x, y, c0, w, snr) in lines:
+        hits = [k for k in got if k[0] == x and k[1] == y and abs(k[2] - (c0 + w // 2)) <= max(2, w // 2)]
+        assert hits, (x, y, c0, w)
+
+
+def test_search_corr_noise_only_and_errors():
+    """Correlated noise alone: BH admits nothing under the matching rho and a great many voxels
+    under the white-noise scale; invalid correlations are rejected."""
+    r = torch.from_numpy(_corr_cube(512, 32, 23)).to(DEV)
+    rec, thr, kprov, _, _ = nb.nbsi_search(r, fdr_q=0.01, rho=nb.HANN_CROSS_RHO)
+    assert kprov == 0 and len(rec) == 0 and math.isinf(thr)
+    _, _, k_white, _, _ = nb.nbsi_search(r, fdr_q=0.01)
+    assert k_white > 100
+    for bad in ([0.5] * 9, [1.0], [-1.0], [float("nan")], [-0.99]):
+        with pytest.raises(nb.NbsiError):
+            nb.nbsi_search(r, rho=bad)

@@ -194,3 +194,71 @@ def test_search_accepts_every_voxel_when_all_are_significant():
     m = int(oracle.detect.horizon_mask(8).sum()) * 64
     assert kstar == m and sstar == S[:, oracle.detect.horizon_mask(8)].min()
     assert len(rec) == 0
+
+
+# ---- correlated channels (unit-variance boxcars under a channel correlation) ----
+
+@pytest.mark.parametrize("a", [(1.0, 0.8, 0.3), (1.0, -0.5, 0.2)])
+def test_boxcar_sigma_unit_variance_of_ma2_noise(a):
+    """Monte Carlo: an MA(2) process x_k = a0 e_k + a1 e_{k-1} + a2 e_{k-2} has correlations
+    rho1 = (a0 a1 + a1 a2) / sum a^2, rho2 = a0 a2 / sum a^2; its window sums divided by
+    boxcar_sigma have unit variance, while sqrt(w) (the white-noise scale) does not."""
+    a0, a1, a2 = a
+    var = a0 * a0 + a1 * a1 + a2 * a2
+    rho = ((a0 * a1 + a1 * a2) / var, a0 * a2 / var)
+    rng = np.random.Generator(np.random.PCG64(11))
+    e = rng.standard_normal((1 << 21) + 2)
+    x = (a0 * e[2:] + a1 * e[1:-1] + a2 * e[:-2]) / math.sqrt(var)
+    for w in (1, 2, 3, 10, 50):
+        n = x.size // w
+        sums = x[:n * w].reshape(n, w).sum(axis=1)
+        v = float(np.var(sums / osr.boxcar_sigma(w, rho)))
+        assert abs(v - 1.0) < 0.04, (w, v)
+        if w > 1:
+            assert abs(float(np.var(sums / math.sqrt(w))) - 1.0) > 0.15
+    assert osr.boxcar_sigma(7, ()) == math.sqrt(7)
+
+
+def test_hann_cross_product_channel_correlations():
+    """The cross-correlation products of two independent white inputs, windowed with the periodic
+    Hann window and transformed (numpy FFT), have the channel correlations HANN_CROSS_RHO."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    n = 4096
+    win = 0.5 - 0.5 * np.cos(2 * np.pi * np.arange(n) / n)
+    acc = np.zeros(3)
+    for _ in range(64):
+        z = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+        X = np.fft.fft(z * win, axis=1)
+        v = (X[0] * np.conj(X[1])).real
+        v = v / v.std()
+        acc += [np.mean(v * v), np.mean(v[:-1] * v[1:]), np.mean(v[:-2] * v[2:])]
+    acc /= 64
+    assert abs(acc[1] / acc[0] - osr.HANN_CROSS_RHO[0]) < 0.01
+    assert abs(acc[2] / acc[0] - osr.HANN_CROSS_RHO[1]) < 0.01
+
+
+def test_search_with_channel_correlation_keeps_noise_unit_normal():
+    """A noise-only cube with the Hann cross-product correlations: under the matching rho the
+    best-over-widths statistic of a single width is unit normal, and BH admits nothing at
+    q = 0.01; with the white-noise scale the same cube overflows BH."""
+    # an MA(2) process with rho = HANN_CROSS_RHO: a0 a2 / S = 1/36, (a0 + a2) a1 / S = 4/9
+    from scipy.optimize import fsolve
+
+    def eq(v):
+        a0, a1, a2 = v
+        S = a0 * a0 + a1 * a1 + a2 * a2
+        return [a0 * a2 / S - osr.HANN_CROSS_RHO[1], (a0 * a1 + a1 * a2) / S - osr.HANN_CROSS_RHO[0], S - 1.0]
+
+    a = fsolve(eq, [0.8, 0.5, 0.05])
+    rng = np.random.Generator(np.random.PCG64(13))
+    n_chan, n_pix = 600, 8
+    e = rng.standard_normal((n_chan + 2, n_pix, n_pix))
+    r = a[0] * e[2:] + a[1] * e[1:-1] + a[2] * e[:-2]
+    valid = np.ones((n_pix, n_pix), dtype=bool)
+    S1, _ = osr.boxcar_bank(r, widths=(20,), rho=osr.HANN_CROSS_RHO)
+    s = S1[np.isfinite(S1)]
+    assert abs(float(np.var(s)) - 1.0) < 0.1
+    rec, _, _, kstar, _ = osr.search(r, q=0.01, widths=(1, 2, 5, 10, 20), valid=valid, rho=osr.HANN_CROSS_RHO)
+    assert kstar == 0 and len(rec) == 0
+    _, _, _, k_white, _ = osr.search(r, q=0.01, widths=(1, 2, 5, 10, 20), valid=valid)
+    assert k_white > 0
