@@ -8,7 +8,8 @@ back-propagated gradients (relative rounding <= 2^-11 each, a few roundings deep
 accumulation.  Bars (derived from that, with margin for cancellation in the sums):
   logits      |dz| <= 4e-3 max|z| + 1e-4
   loss        relative 1e-3
-  gradients   per tensor: max-abs <= 2e-2 of the tensor's largest |g|, L2 <= 1e-2 relative
+  gradients   per tensor: max-abs <= 1e-2 of the tensor's largest |g|, L2 <= 1e-2 relative
+              (measured worst over the cases: 6.0e-3 and 5.1e-3)
   Adam        relative 1e-5 (FP32 against FP64 arithmetic on the same inputs)
 """
 import numpy as np
@@ -96,7 +97,9 @@ def _check_grads(g, gr):
         if peak == 0:
             assert np.abs(a).max() == 0, name
             continue
-        assert np.abs(a - b).max() <= 2e-2 * peak, (name, np.abs(a - b).max() / peak)
+        print(f"  {name}: max-abs {np.abs(a - b).max() / peak:.2e} of peak, "
+              f"L2 {np.linalg.norm(a - b) / np.linalg.norm(b):.2e}", flush=True)
+        assert np.abs(a - b).max() <= 1e-2 * peak, (name, np.abs(a - b).max() / peak)
         assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b), (name, np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
