@@ -53,6 +53,13 @@ CHAN_CASES = [
     # second, partial tile of spectra
     (3, 4096, 32, 1000, 77),
     (2, 8192, 80, 100, 256),
+    # the window's neighbour bins: C = M - 1 (one bin past the residues: one edge accumulator),
+    # C = M - 1 and C = M at P = 1 (the neighbours wrap around the M-periodic spectrum), and a
+    # split transform whose band starts at bin 0 (its lower neighbour is bin N - 1)
+    (2, 16384, 2, 100, 4095),
+    (2, 4096, 2, 1, 4095),
+    (1, 4096, 3, 0, 4096),
+    (2, 65536, 2, 32768, 4096),
 ]
 
 
