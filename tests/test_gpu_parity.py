@@ -302,6 +302,12 @@ def _compare_candidates(rec, ref, snr_ref, tau, tol=1e-4):
     (5000, 8, nb.NBSI_DETECT_PER_PIXEL), (32, 256, nb.NBSI_DETECT_PER_IMAGE), (16, 128, nb.NBSI_DETECT_PER_IMAGE), (12, 512, nb.NBSI_DETECT_PER_IMAGE),
 ])
 def test_detect_matches_oracle(n_chan, n_pix, mode):
+    assert detect_parity(n_chan, n_pix, mode) >= 3
+
+
+def detect_parity(n_chan, n_pix, mode):
+    """Every SNR and candidate of a cube with planted spikes against the oracle; returns the
+    oracle's candidate count (short spectra can leave the weaker spikes below 5 sigma)."""
     print(f"detect n_chan={n_chan} n_pix={n_pix} mode={mode}", flush=True)
     # per-image mode standardises by the spread of whole images, which the per-pixel offsets
     # below widen, so its spikes are made louder
@@ -318,7 +324,7 @@ def test_detect_matches_oracle(n_chan, n_pix, mode):
     d = np.abs(snr_got - snr_ref)[:, valid]
     assert d.max() <= 1e-4 * max(1.0, np.abs(snr_ref).max())
     _compare_candidates(rec, ref, snr_ref, 5.0)
-    assert len(ref) >= 3
+    return len(ref)
 
 
 def test_per_image_statistics_adversarial():
