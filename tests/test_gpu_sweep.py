@@ -1,9 +1,11 @@
 """GPU parity over seeded random shapes: the channelizer (every transform size from 256 to 2^18
 points, bands anywhere in the spectrum, 1 to 16,384 channels), the correlator (1 to 420 inputs,
 1 to 400 spectra: whole-channel and tiled kernels, repacked rows), the detector (12 to 6,000
-channels, both noise models) and the gridded imager, each against the oracle with the fixed
-cases' own checks and bars.  The shapes come from a fixed seed, so the cases are the same on
-every run."""
+channels, both noise models) and the gridded imager; then the correlator's Stokes-I epilogue
+and its overlap with imaging, the tiled correlator up to 800 inputs and 1,100 spectra,
+de-Doppler, the Stage I boxcar bank and the Stage II fits; each against the oracle (or the
+separate calls it must equal) with the fixed cases' own checks and bars.  The shapes come from
+fixed seeds, so the cases are the same on every run."""
 import random
 
 import pytest
@@ -15,7 +17,10 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_2606_04304_amd as nb  # noqa: E402
+import test_gpu_drift as tdr  # noqa: E402
 import test_gpu_parity as tp  # noqa: E402
+import test_gpu_search as tse  # noqa: E402
+import test_gpu_stage2 as ts2  # noqa: E402
 
 
 def _shapes(seed):
@@ -64,3 +69,57 @@ def test_sweep_detect(n_chan, n_pix, mode):
 @pytest.mark.parametrize("n_pix,n_ant,radius", IMG)
 def test_sweep_image_grid(n_pix, n_ant, radius):
     tp.test_image_grid_matches_dft_oracle(n_pix, n_ant, radius)
+
+
+def _shapes2(seed):
+    rng = random.Random(seed)
+    stokes, overlap, tiled, drift, bank, fits = [], [], [], [], [], []
+    for _ in range(10):
+        n_pix = rng.choice([64, 128, 256])
+        stokes.append((rng.randint(3, 90), rng.choice([rng.randint(1, 32), rng.randint(33, 64), rng.randint(65, 320)]),
+                       rng.randint(1, 13), n_pix, rng.uniform(0.5, 1.5) * n_pix))
+    for _ in range(6):
+        overlap.append((rng.randint(3, 48), rng.choice([rng.randint(1, 32), rng.randint(33, 130)]),
+                        rng.choice([64, 128, 256, 512]), rng.randint(1, 40)))
+    for _ in range(8):
+        tiled.append((rng.randint(1, 20), rng.randint(30, 800), rng.randint(65, 1100)))
+    for _ in range(8):
+        drift.append((rng.randint(1, 8), rng.randint(16, 500), 8 * rng.randint(1, 5), rng.randint(0, 16)))
+    for _ in range(6):
+        bank.append((rng.randint(60, 900), 8 * rng.randint(2, 6)))
+    for _ in range(5):
+        fits.append((rng.randint(1, 1000), rng.randint(8, 50), rng.choice([48, 64, 96, 128]), rng.randint(2, 5)))
+    return stokes, overlap, tiled, drift, bank, fits
+
+
+STOKES, OVERLAP, TILED, DRIFT, BANK, FITS = _shapes2(1)
+
+
+@pytest.mark.parametrize("n_ant,n_spec,n_chan,n_pix,radius", STOKES)
+def test_sweep_correlate_stokes(n_ant, n_spec, n_chan, n_pix, radius):
+    tp.stokes_parity(n_ant, n_spec, n_chan, n_pix, radius)
+
+
+@pytest.mark.parametrize("n_ant,n_spec,n_pix,n_chan", OVERLAP)
+def test_sweep_correlate_image_overlapped(n_ant, n_spec, n_pix, n_chan):
+    tp.test_correlate_image_overlapped_matches_sequential(n_ant, n_spec, n_pix, n_chan)
+
+
+@pytest.mark.parametrize("n_chan,n_in,n_spec", TILED)
+def test_sweep_correlate_tiled(n_chan, n_in, n_spec):
+    tp.test_correlate_tiled_sampled_channels_bit_exact(n_chan, n_in, n_spec)
+
+
+@pytest.mark.parametrize("n_sub,n_chan,n_pix,max_drift", DRIFT)
+def test_sweep_dedoppler(n_sub, n_chan, n_pix, max_drift):
+    tdr.test_dedoppler_matches_oracle(n_sub, n_chan, n_pix, max_drift)
+
+
+@pytest.mark.parametrize("n_chan,n_pix", BANK)
+def test_sweep_search_bank(n_chan, n_pix):
+    tse.test_bank_matches_oracle(n_chan, n_pix)
+
+
+@pytest.mark.parametrize("seed,n_chan,n_pix,half", FITS)
+def test_sweep_stage2(seed, n_chan, n_pix, half):
+    ts2.test_stage2_matches_oracle(seed, n_chan, n_pix, half)
