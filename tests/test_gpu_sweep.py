@@ -3,8 +3,9 @@ points, bands anywhere in the spectrum, 1 to 16,384 channels), the correlator (1
 1 to 400 spectra: whole-channel and tiled kernels, repacked rows), the detector (12 to 6,000
 channels, both noise models) and the gridded imager; then the correlator's Stokes-I epilogue
 and its overlap with imaging, the tiled correlator up to 800 inputs and 1,100 spectra,
-de-Doppler, the Stage I boxcar bank and the Stage II fits; each against the oracle (or the
-separate calls it must equal) with the fixed cases' own checks and bars.  The shapes come from
+de-Doppler, the Stage I boxcar bank and the Stage II fits, and the batch runner over random
+sub-band sets; each against the oracle (or the separate calls it must equal) with the fixed
+cases' own checks and bars.  The shapes come from
 fixed seeds, so the cases are the same on every run."""
 import random
 
@@ -17,6 +18,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_2606_04304_amd as nb  # noqa: E402
+import test_gpu_batch as tb  # noqa: E402
 import test_gpu_drift as tdr  # noqa: E402
 import test_gpu_parity as tp  # noqa: E402
 import test_gpu_search as tse  # noqa: E402
@@ -123,3 +125,34 @@ def test_sweep_search_bank(n_chan, n_pix):
 @pytest.mark.parametrize("seed,n_chan,n_pix,half", FITS)
 def test_sweep_stage2(seed, n_chan, n_pix, half):
     ts2.test_stage2_matches_oracle(seed, n_chan, n_pix, half)
+
+
+def _batches(seed, n):
+    rng = random.Random(seed)
+    out = []
+    for case in range(n):
+        shapes = []
+        for _ in range(rng.randint(1, 6)):
+            n_fft = 1 << rng.randint(10, 18)
+            n_chan = min(rng.choice([rng.randint(1, 100), rng.randint(100, 2000), rng.randint(2000, 16384)]), n_fft, 16384)
+            chan0 = rng.randint(0, n_fft - n_chan)
+            n_spec = max(1, min(rng.randint(1, 40), (1 << 19) // n_fft))
+            shapes.append((n_fft, n_spec, chan0, n_chan, rng.choice([64, 128, 256])))
+        out.append((rng.randint(4, 40), rng.random() < 0.5, rng.random() < 0.5, tuple(shapes), 1000 + case))
+    return out
+
+
+@pytest.mark.parametrize("n_ant,graph,overlap,shapes,seed", _batches(1, 6))
+def test_sweep_batch(n_ant, graph, overlap, shapes, seed):
+    """A random set of sub-bands through the batch runner (twice, outputs poisoned in between)
+    gives the per-sub-band calls' spectra, visibilities and images bit for bit."""
+    print(f"batch n_ant={n_ant} graph={graph} overlap={overlap} shapes={shapes}", flush=True)
+    xyz, subs = tb._subbands(n_ant, list(shapes), seed=seed)
+    ref = tb._per_subband(xyz, subs)
+    b = nb.Batch(xyz, subs, graph=graph, overlap=overlap)
+    for _ in range(2):
+        tb._poison(b)
+        b.run()
+        torch.cuda.synchronize()
+        tb._same(b, ref)
+    b.close()
