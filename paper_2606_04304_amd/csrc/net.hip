@@ -275,33 +275,71 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const _Float16 *__restrict__
 }
 
 // Sum the partials in split order, undo the gradient scale, write the oracle layout [o][i][dy][dx].
+// Threads run along the partials' own layout (co, k), so the ksplit reads of a wave are
+// contiguous; padded input channels (ci >= cin) are skipped.
 __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float *__restrict__ partial, int ksplit, int cout,
                                                            int cin, int cinp, const float *__restrict__ scale, int slot,
                                                            float *__restrict__ grad, int off) {
+    const int K = 9 * cinp;
     const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= cout * cin * 9) return;
-    const int co = e / (cin * 9), rem = e % (cin * 9), ci = rem / 9, tap = rem % 9;
-    const int K = 9 * cinp, k = tap * cinp + ci;
+    if (e >= cout * K) return;
+    const int co = e / K, k = e % K, tap = k / cinp, ci = k % cinp;
+    if (ci >= cin) return;
     float s = 0.f;
+    // (unrolled so that the loads are issued ahead of the in-order additions)
+#pragma unroll 8
     for (int q = 0; q < ksplit; q++) s += partial[((size_t)q * cout + co) * K + k];
-    grad[off + e] = s / scale[slot];
+    grad[off + (co * cin + ci) * 9 + tap] = s / scale[slot];
 }
 
-// Bias gradient: one workgroup per output channel, fixed-order tree.
-__global__ __launch_bounds__(256) void bgrad_kernel(const _Float16 *__restrict__ dZ, int M, int cout,
-                                                    const float *__restrict__ scale, int slot, float *__restrict__ grad,
-                                                    int off) {
+// Bias gradient, first level: workgroup q sums dZ over its rows [q rows, (q + 1) rows).  A
+// thread reads 8 channels of a row with one 16-byte load; the row lanes of each channel are
+// summed in a fixed order, so the result is deterministic.
+template <int COUT>
+__global__ __launch_bounds__(256) void bgrad_partial_kernel(const _Float16 *__restrict__ dZ, int M, int rows,
+                                                            float *__restrict__ partial) {
+    constexpr int CG = COUT / 8, RL = 256 / CG;  // 8-channel groups per row, row lanes
+    static_assert(COUT % 8 == 0 && 256 % CG == 0, "whole 16-byte groups");
+    __shared__ float red[RL][COUT + 1];
+    const int t = threadIdx.x, g = t % CG, rl = t / CG;
+    const int m0 = blockIdx.x * rows, m1 = min(M, m0 + rows);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int m = m0 + rl; m < m1; m += RL) {
+        const v8h x = *reinterpret_cast<const v8h *>(dZ + (size_t)m * COUT + 8 * g);
+#pragma unroll
+        for (int i = 0; i < 8; i++) s[i] += (float)x[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++) red[rl][8 * g + i] = s[i];
+    __syncthreads();
+    if (t < COUT) {
+        float a = 0.f;
+        for (int r = 0; r < RL; r++) a += red[r][t];
+        partial[(size_t)blockIdx.x * COUT + t] = a;
+    }
+}
+
+// Bias gradient, second level: each channel's partials over RL lanes, the lanes in a fixed
+// order, the gradient scale undone.
+template <int COUT>
+__global__ __launch_bounds__(256) void bgrad_final_kernel(const float *__restrict__ partial, int n_part,
+                                                          const float *__restrict__ scale, int slot,
+                                                          float *__restrict__ grad, int off) {
+    constexpr int RL = 256 / COUT;
     __shared__ float red[256];
-    const int co = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x, co = t % COUT, rl = t / COUT;
     float s = 0.f;
-    for (int m = t; m < M; m += 256) s += (float)dZ[(size_t)m * cout + co];
+#pragma unroll 8
+    for (int q = rl; q < n_part; q += RL) s += partial[(size_t)q * COUT + co];
     red[t] = s;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
-        __syncthreads();
+    if (t < COUT) {
+        float a = 0.f;
+#pragma unroll
+        for (int r = 0; r < RL; r++) a += red[r * COUT + t];
+        grad[off + t] = a / scale[slot];
     }
-    if (t == 0) grad[off + co] = red[0] / scale[slot];
 }
 
 // Data gradient of a convolution, masked by the previous ReLU:
@@ -417,6 +455,7 @@ struct nbsi_net {
 namespace {
 
 constexpr int MAX_KSPLIT = 64;
+constexpr int BIAS_PARTS = 256;  // workgroups of the bias gradient's first level
 constexpr size_t PARTIAL_FLOATS = (size_t)MAX_KSPLIT * 64 * 9 * 64;
 
 template <typename T>
@@ -488,10 +527,17 @@ void weight_grads(nbsi_net *net, const _Float16 *x, const int32_t *index, int n_
     constexpr int KT = (9 * CINP + 31) / 32;
     hipLaunchKernelGGL((wgrad_kernel<CIN, CINP, COUT, IN_STAMP>), dim3(blocks((COUT / 32) * KT, 4), ks), dim3(256), 0,
                        st, (const _Float16 *)net->dZ, x, index, n_stamps, n, chunk, net->partial);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks(COUT * CIN * 9)), dim3(256), 0, st, net->partial, ks, COUT,
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks(COUT * 9 * CINP)), dim3(256), 0, st, net->partial, ks, COUT,
                        CIN, CINP, net->scale, slot, grad, off_w);
-    hipLaunchKernelGGL(bgrad_kernel, dim3(COUT), dim3(256), 0, st, (const _Float16 *)net->dZ, M, COUT, net->scale,
-                       slot, grad, off_b);
+    // the bias partials (up to BIAS_PARTS per channel) reuse the weight partials' buffer, which
+    // the reduction above has read
+    static_assert(256 % COUT == 0 && (size_t)BIAS_PARTS * COUT <= PARTIAL_FLOATS, "bias partials");
+    const int n_part = std::max(1, std::min(BIAS_PARTS, M / 64));
+    const int rows = (M + n_part - 1) / n_part;
+    hipLaunchKernelGGL(bgrad_partial_kernel<COUT>, dim3(n_part), dim3(256), 0, st, (const _Float16 *)net->dZ, M, rows,
+                       net->partial);
+    hipLaunchKernelGGL(bgrad_final_kernel<COUT>, dim3(1), dim3(256), 0, st, net->partial, n_part, net->scale, slot,
+                       grad, off_b);
 }
 
 // Backward pass after forward(..., labels): every parameter's gradient into grad.
