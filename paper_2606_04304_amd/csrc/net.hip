@@ -175,6 +175,8 @@ __global__ __launch_bounds__(256) void head_reduce_kernel(const float *__restric
     __shared__ float r_w[8][32], r_d[8], r_l[8], r_m[8];
     const int t = threadIdx.x, c = t & 31, j = t >> 5;
     float sw = 0.f, sd = 0.f, sl = 0.f, mx = 0.f;
+    // (unrolled so that the loads are issued ahead of the in-order sums)
+#pragma unroll 8
     for (int b = j; b < n; b += 8) {
         const float d = dz[b];
         sw += d * feat[b * 32 + c];
@@ -281,22 +283,31 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const _Float16 *__restrict__
     for (int r = 0; r < 16; r++) partial[((size_t)split * COUT + co0 + acc_row(r, lane)) * K + k] = acc[r];
 }
 
-// Sum the partials in split order, undo the gradient scale, write the oracle layout [o][i][dy][dx].
-// Threads run along the partials' own layout (co, k), so the ksplit reads of a wave are
-// contiguous; padded input channels (ci >= cin) are skipped.
+// Sum the partials, undo the gradient scale, write the oracle layout [o][i][dy][dx].  A
+// workgroup takes 64 consecutive (co, k) of the partials' own layout (contiguous reads); its
+// four waves sum the splits q = w, w + 4, ... and are then added in wave order, so the result
+// is deterministic.  Padded input channels (ci >= cin) are skipped.
 __global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float *__restrict__ partial, int ksplit, int cout,
                                                            int cin, int cinp, const float *__restrict__ scale, int slot,
                                                            float *__restrict__ grad, int off) {
+    __shared__ float red[4][64];
     const int K = 9 * cinp;
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= cout * K) return;
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int e = blockIdx.x * 64 + l;
+    const bool ev = e < cout * K;
+    float s = 0.f;
+    if (ev) {
+        // (unrolled so that the loads are issued ahead of the in-order additions)
+#pragma unroll 8
+        for (int q = w; q < ksplit; q += 4) s += partial[(size_t)q * cout * K + e];
+    }
+    red[w][l] = s;
+    __syncthreads();
+    if (w != 0 || !ev) return;
     const int co = e / K, k = e % K, tap = k / cinp, ci = k % cinp;
     if (ci >= cin) return;
-    float s = 0.f;
-    // (unrolled so that the loads are issued ahead of the in-order additions)
-#pragma unroll 8
-    for (int q = 0; q < ksplit; q++) s += partial[((size_t)q * cout + co) * K + k];
-    grad[off + (co * cin + ci) * 9 + tap] = s / scale[slot];
+    const float a = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+    grad[off + (co * cin + ci) * 9 + tap] = a / scale[slot];
 }
 
 // Bias gradient, first level: workgroup q sums dZ over its rows [q rows, (q + 1) rows).  A
@@ -539,7 +550,7 @@ void weight_grads(nbsi_net *net, const _Float16 *x, const int32_t *index, int n_
     constexpr int KT = (9 * CINP + 31) / 32;
     hipLaunchKernelGGL((wgrad_kernel<CIN, CINP, COUT, IN_STAMP>), dim3(blocks((COUT / 32) * KT, 4), ks), dim3(256), 0,
                        st, (const _Float16 *)net->dZ, x, index, n_stamps, n, chunk, net->partial);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks(COUT * 9 * CINP)), dim3(256), 0, st, net->partial, ks, COUT,
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks(COUT * 9 * CINP, 64)), dim3(256), 0, st, net->partial, ks, COUT,
                        CIN, CINP, net->scale, slot, grad, off_w);
     // the bias partials (up to BIAS_PARTS per channel) reuse the weight partials' buffer, which
     // the reduction above has read
