@@ -508,12 +508,14 @@ __device__ float reg_median(const float (&v)[NR], int n, float *pool, int lane) 
 }
 
 // Per-pixel detection for spectra of up to 64 NR channels: a workgroup of REG_PX waves takes
-// REG_PX adjacent pixels of one row; each staging round loads 512 channels x REG_PX pixels
+// REG_PX adjacent pixels of one row; each staging round loads 1,024 channels x REG_PX pixels
 // (4 REG_PX contiguous bytes per channel row) through an LDS tile, and every wave keeps its
 // pixel's spectrum in registers, so the selections and the scoring run without LDS or barriers.
-// Eight-wave workgroups at 128 registers leave room for two per CU, so one workgroup's staging
-// reads run under the other's selections.
-constexpr int REG_PX = 8;
+// Four-wave workgroups (four per CU at 128 registers, so staging reads run under other
+// workgroups' selections) free their slot as soon as their slowest pixel is done: the rounds a
+// selection needs vary from pixel to pixel, and eight-wave workgroups, which wait for the
+// slowest of eight, were 5% slower (sixteen-wave ones 17%).
+constexpr int REG_PX = 4;
 constexpr int REG_LINE = 128 / (4 * REG_PX);  // workgroups that share a 128-byte line of a row
 template <int NR>
 __global__ __launch_bounds__(64 * REG_PX, 4) void detect_pixel_reg_kernel(const float *__restrict__ img, int n_chan, int n_pix,
