@@ -3,10 +3,11 @@ points, bands anywhere in the spectrum, 1 to 16,384 channels), the correlator (1
 1 to 400 spectra: whole-channel and tiled kernels, repacked rows), the detector (12 to 6,000
 channels, both noise models) and the gridded imager; then the correlator's Stokes-I epilogue
 and its overlap with imaging, the tiled correlator up to 800 inputs and 1,100 spectra,
-de-Doppler, the Stage I boxcar bank and the Stage II fits, and the batch runner over random
-sub-band sets; each against the oracle (or the separate calls it must equal) with the fixed
+de-Doppler, the Stage I boxcar bank, the whole Stage I search (random FDR levels and noise
+widths) and the Stage II fits, and the batch runner over random sub-band sets; each against the oracle (or the separate calls it must equal) with the fixed
 cases' own checks and bars.  The shapes come from
 fixed seeds, so the cases are the same on every run."""
+import math
 import random
 
 import pytest
@@ -156,3 +157,14 @@ def test_sweep_batch(n_ant, graph, overlap, shapes, seed):
         torch.cuda.synchronize()
         tb._same(b, ref)
     b.close()
+
+
+def _searches(seed, n):
+    rng = random.Random(seed)
+    return [(rng.randint(1, 10 ** 6), round(10 ** rng.uniform(math.log10(0.002), math.log10(0.6)), 4),
+             rng.choice([1.0, 1.2, 1.4])) for _ in range(n)]
+
+
+@pytest.mark.parametrize("seed,q,sigma", _searches(1, 6))
+def test_sweep_search(seed, q, sigma):
+    tse.search_parity(seed, q, sigma)
