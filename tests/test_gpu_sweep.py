@@ -4,7 +4,8 @@ points, bands anywhere in the spectrum, 1 to 16,384 channels), the correlator (1
 channels, both noise models) and the gridded imager; then the correlator's Stokes-I epilogue
 and its overlap with imaging, the tiled correlator up to 800 inputs and 1,100 spectra,
 de-Doppler, the Stage I boxcar bank, the whole Stage I search (random FDR levels and noise
-widths) and the Stage II fits, and the batch runner over random sub-band sets; each against the oracle (or the separate calls it must equal) with the fixed
+widths) and the Stage II fits, the calibrated and the FP32 correlators, and the batch runner over
+random sub-band sets; each against the oracle (or the separate calls it must equal) with the fixed
 cases' own checks and bars.  The shapes come from
 fixed seeds, so the cases are the same on every run."""
 import math
@@ -20,6 +21,7 @@ if not torch.cuda.is_available():
 
 import paper_2606_04304_amd as nb  # noqa: E402
 import test_gpu_batch as tb  # noqa: E402
+import test_gpu_calibrate as tca  # noqa: E402
 import test_gpu_drift as tdr  # noqa: E402
 import test_gpu_parity as tp  # noqa: E402
 import test_gpu_search as tse  # noqa: E402
@@ -168,3 +170,20 @@ def _searches(seed, n):
 @pytest.mark.parametrize("seed,q,sigma", _searches(1, 6))
 def test_sweep_search(seed, q, sigma):
     tse.search_parity(seed, q, sigma)
+
+
+def _corr_shapes(seed, n, max_spec):
+    rng = random.Random(seed)
+    return [(rng.randint(1, 6), rng.choice([rng.randint(1, 64), rng.randint(64, 420)]), rng.randint(1, max_spec))
+            for _ in range(n)]
+
+
+@pytest.mark.parametrize("n_chan,n_in,n_spec", _corr_shapes(1, 6, 400))
+def test_sweep_correlate_cal(n_chan, n_in, n_spec):
+    tca.test_correlate_cal_matches_oracle(n_chan, n_in, n_spec)
+
+
+# (int8 products summed over at most 200 spectra stay integers below 2^24: exact in float32)
+@pytest.mark.parametrize("n_chan,n_in,n_spec", _corr_shapes(2, 6, 200))
+def test_sweep_correlate_f32(n_chan, n_in, n_spec):
+    tp.test_correlate_f32_matches_oracle(n_chan, n_in, n_spec)
